@@ -1,0 +1,177 @@
+"""Pins of the oracle's solves and whole time step: dense direct solves on
+tiny grids, divergence after projection, residual-corrected solute and
+energy conservation (with the printed A_g order as a planted defect), and
+the Neumann closed-form solution of the one-dimensional Stefan problem."""
+import math
+
+import numpy as np
+import pytest
+from scipy.optimize import brentq
+from scipy.special import erf, erfc
+
+import oracle
+import workloads as W
+
+
+def _perturbed_fields(case, seed=2):
+    rng = np.random.default_rng(seed)
+    o = oracle.Oracle(case)
+    f = o.fields()
+    for k in ("u", "v", "w"):
+        f[k] = rng.uniform(-1e-3, 1e-3, f[k].size)
+    f["gl"] = rng.uniform(0.0, 1.0, f["gl"].size)
+    f["p"] = rng.uniform(-1.0, 1.0, f["p"].size)
+    return f
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_krylov_matches_dense_direct(dim):
+    case = W.cavity_2d(6, 5) if dim == 2 else W.box_3d(4, 3, 3, lx=0.04, ly=0.03, lz=0.03)
+    f = _perturbed_fields(case)
+    o = oracle.Oracle(case, fields=f)
+    rng = np.random.default_rng(4)
+    vel = tuple(rng.uniform(-1e-3, 1e-3, max(1, f[k].size)) for k in ("u", "v", "w"))
+    for sys in range(6):
+        if dim == 2 and sys == oracle.SYS_W:
+            continue
+        v = vel if sys in (oracle.SYS_P, oracle.SYS_C, oracle.SYS_T) else None
+        A, b, _, _ = o.assemble(sys, vel=v)
+        Ad = A.toarray()
+        if sys == oracle.SYS_P:
+            x, it, rel = oracle.solve(A, b, kind="cg", tol=1e-14)
+            x = x - x.mean()
+            ref = np.linalg.lstsq(Ad, b, rcond=None)[0]
+            ref = ref - ref.mean()
+        else:
+            x, it, rel = oracle.solve(A, b, kind="bicgstab", tol=1e-14)
+            ref = np.linalg.solve(Ad, b)
+        assert it >= 0
+        assert np.linalg.norm(x - ref) <= 1e-11 * np.linalg.norm(ref)
+
+
+def test_projection_divergence_bound_and_tight_tolerance():
+    """D u^{n+1} = -(dt/rho) r_p (up to the mean of D u*, which is zero), so
+    ||D u^{n+1}|| equals (dt/rho) ||r_p||; at tight tolerance the projected
+    field is divergence free to 1e-12 relative to D u*."""
+    case = W.cavity_2d(12, 8, tol=1e-10)
+    o = oracle.Oracle(case)
+    st = o.step(3)
+    rho, dt = case["alloy"]["rho"], case["numerics"]["dt"]
+    for s in st:
+        assert abs(s["div_new"] - dt / rho * s["poisson_resid"]) <= 1e-6 * s["div_new"] + 1e-12 * s["div_star"]
+    case2 = W.cavity_2d(12, 8, tol=1e-14)
+    st2 = oracle.Oracle(case2).step(3)
+    for s in st2:
+        assert s["div_new"] <= 1e-12 * s["div_star"]
+
+
+def _sums(f, case):
+    lam = case["alloy"]["latent"] / case["alloy"]["cp"]
+    return f["C"].sum(), (f["T"] + lam * f["gl"]).sum()
+
+
+@pytest.mark.parametrize("tol", [1e-10, 1e-14])
+def test_conservation_residual_corrected(tol):
+    """Solute: sum C^{n+1} - sum C^n + dt sum r_C = 0; energy:
+    sum(T + L/c_p g)^{n+1} - sum(...)^n + dt sum_walls U/(rho c_p h)(T* - T_ext)
+    + dt sum r_T = 0, both to 1e-12 relative, at any solver tolerance."""
+    case = W.cavity_2d(20, 12, tol=tol)
+    o = oracle.Oracle(case)
+    dt = case["numerics"]["dt"]
+    for _ in range(6):
+        C0, H0 = _sums(o.fields(), case)
+        s = o.step(1)[0]
+        C1, H1 = _sums(o.fields(), case)
+        assert abs(C1 - C0 + dt * s["sum_resid"][oracle.SYS_C]) <= 1e-12 * abs(C0)
+        assert abs(H1 - H0 + dt * s["wall_flux"] + dt * s["sum_resid"][oracle.SYS_T]) <= 1e-12 * abs(H0)
+        assert abs(s["sum_C"] - C1) <= 1e-13 * abs(C1)
+
+
+def test_printed_Ag_order_breaks_solute_conservation():
+    """Planted defect: the row-scaled A_g*A_con does not conserve solute once
+    a non-uniform composition is carried through mushy cells (it does while
+    g_l = 1 everywhere)."""
+    case = W.cavity_2d(16, 10, tol=1e-13)
+    f = oracle.Oracle(case).fields()
+    rng = np.random.default_rng(9)
+    f["gl"] = rng.uniform(0.2, 1.0, f["gl"].size)
+    f["u"] = rng.uniform(-1e-3, 1e-3, f["u"].size)
+    f["v"] = rng.uniform(-1e-3, 1e-3, f["v"].size)
+    f["C"] = rng.uniform(8.0, 12.0, f["C"].size)
+    good = oracle.Oracle(case, fields=f)
+    bad = oracle.Oracle(case, fields=f, literal_ag_order=True)
+    dt = case["numerics"]["dt"]
+    C0 = f["C"].sum()
+    sg = good.step(1)[0]
+    sb = bad.step(1)[0]
+    eg = abs(good.fields()["C"].sum() - C0 + dt * sg["sum_resid"][oracle.SYS_C]) / C0
+    eb = abs(bad.fields()["C"].sum() - C0 + dt * sb["sum_resid"][oracle.SYS_C]) / C0
+    assert eg < 1e-12
+    assert eb > 1e-9
+
+
+def _neumann_lambda(St_s, St_l):
+    """Root of St_s/(e^{l^2} erf l) - St_l/(e^{l^2} erfc l) = l sqrt(pi)
+    (two-phase Stefan problem, equal diffusivities; Carslaw & Jaeger)."""
+    f = lambda l: St_s / (math.exp(l * l) * erf(l)) - St_l / (math.exp(l * l) * erfc(l)) - l * math.sqrt(math.pi)
+    return brentq(f, 1e-6, 3.0)
+
+
+def _stefan_case(nx, dt, Tw, dTl, lx=0.1):
+    al = W.sn10pb_alloy(beta_T=0.0, beta_C=0.0)
+    Te = al["T_m"] + al["m_sp"] * al["C_e"]
+    case = W.make_case(2, nx, 1, 1, lx, 0.01, 1.0, C0=al["C_e"], alloy=al,
+                       T0=Te + dTl, dT_amp=0.0, dt=dt, tol_p=1e-13, tol_t=1e-13)
+    case["bcs"][0] = W.face_bc(W.THERMAL_DIRICHLET, T0=Tw, b=0.0)
+    return case, Te
+
+
+def test_neumann_stefan_first_order():
+    """Isothermal (eutectic-composition) solidification from a cold wall in a
+    still melt: front s(t) = 2 lam_N sqrt(alpha t) and the erf/erfc
+    temperature profiles.  The latent-heat split lags the front by O(dt), so
+    h and dt are refined together with dt = 3 h^2/alpha; the front error then
+    falls first order in h."""
+    Tw, dTl, t_end = 400.0, 5.0, 20.0
+    errs, terrs = [], []
+    for nx, dt in ((100, 0.1), (200, 0.025), (400, 0.00625)):
+        case, Te = _stefan_case(nx, dt, Tw, dTl)
+        al = case["alloy"]
+        alpha = al["k"] / (al["rho"] * al["cp"])
+        St_s = al["cp"] * (Te - Tw) / al["latent"]
+        St_l = al["cp"] * dTl / al["latent"]
+        lamN = _neumann_lambda(St_s, St_l)
+        o = oracle.Oracle(case)
+        nsteps = int(round(t_end / dt))
+        o.step(nsteps)
+        f = o.fields()
+        h = 0.1 / nx
+        s_num = h * np.sum(1.0 - f["gl"])
+        s_ex = 2 * lamN * math.sqrt(alpha * t_end)
+        errs.append(abs(s_num - s_ex) / s_ex)
+        x = (np.arange(nx) + 0.5) * h
+        eta = x / (2 * math.sqrt(alpha * t_end))
+        Tex = np.where(x < s_ex, Tw + (Te - Tw) * erf(eta) / erf(lamN),
+                       Te + dTl - dTl * erfc(eta) / erfc(lamN))
+        terrs.append(np.abs(f["T"] - Tex).max())
+    assert abs(lamN - 0.1769) < 2e-3
+    assert errs[0] > errs[1] > errs[2], errs
+    assert errs[-1] < 0.012, errs
+    assert errs[0] / errs[-1] > 3.5, errs           # first order over 4x refinement of h
+    assert terrs[-1] < 0.3 * terrs[0] and terrs[-1] < 1.0, terrs    # max |T - T_exact| in K
+
+
+def test_still_melt_without_buoyancy_stays_at_rest():
+    """beta_T = beta_C = 0 (hydrostatic part dropped): the velocity stays
+    exactly zero and C stays uniform while the cavity loses heat."""
+    al = W.sn10pb_alloy(beta_T=0.0, beta_C=0.0)
+    case = W.make_case(2, 10, 6, 1, 0.1, 0.06, 1.0, alloy=al,
+                       bcs=W.west_cooled_bcs())
+    o = oracle.Oracle(case)
+    o.step(5)
+    f = o.fields()
+    assert not f["u"].any() and not f["v"].any()
+    assert np.all(f["C"] == 10.0)
+    lam = case["alloy"]["latent"] / case["alloy"]["cp"]
+    H0 = (case["init"]["T"] + lam * case["init"]["gl"]).sum()
+    assert (f["T"] + lam * f["gl"]).sum() < H0 and (f["gl"] < 1.0).any()
