@@ -1,0 +1,218 @@
+/*
+ * sol.h -- C ABI of the MI355X solidification / macro-segregation step library.
+ *
+ * One time step is the fully decoupled operator-splitting scheme of
+ * arXiv 2303.10783 (Algorithm 1): momentum predictor (eq. 3.3), pressure
+ * correction (eq. 3.4) and projection (eq. 3.5), matrix-based solute
+ * transport (eq. 3.10), split energy equation (eqs. 3.11-3.12) and the
+ * lever-rule phase / concentration update (eqs. 3.13-3.18), on a uniform
+ * staggered grid (Section 3, spatial discretization) with the systems
+ * assembled term-wise (Section 4): constant-coefficient terms (transient,
+ * diffusion, wall terms, the pressure Laplacian) once at creation, upwind
+ * convection, Carman-Kozeny drag and the right-hand sides every step.
+ * Linear systems: Jacobi-preconditioned CG (pressure) and BiCGSTAB
+ * (momentum, solute, energy), stopped on the true residual
+ * ||b - A x||_2 <= tol ||b||_2.  Every step of the path runs in HIP kernels
+ * on one gfx950 device; the library never computes a step on the host.
+ *
+ * Conventions
+ *  - All functions return an int status (SOL_OK or a negative SOL_E* code);
+ *    sol_last_error() returns a thread-local message owned by the library.
+ *  - Every argument is validated before any device work; on an error nothing
+ *    partial is visible (state stays at the last completed step).
+ *  - Layouts: FP64, lexicographic, x fastest (Section 4, eq. 4.2).
+ *      cells  : nx*ny*nz, index i + nx*(j + ny*k)            (p, T, C, gl, Cl, Cs)
+ *      u faces: interior x-faces, (nx-1)*ny*nz, index (i-1) + (nx-1)*(j + ny*k), i = 1..nx-1
+ *      v faces: interior y-faces, nx*(ny-1)*nz
+ *      w faces: interior z-faces, nx*ny*(nz-1) (3D only; 2D has none)
+ *    Wall faces are impermeable and carry no unknown.  In 2D nz = 1, gravity
+ *    acts along -y; in 3D along -z.
+ *  - Ownership: a handle owns all device memory of its case, allocated with
+ *    ctx->alloc (e.g. a framework's caching allocator) when given, else
+ *    hipMalloc; work is queued on ctx->stream (default stream when NULL).
+ *    Host buffers are always caller-owned.
+ *  - Threading: a handle is not thread-safe; distinct handles may be used
+ *    from distinct threads on distinct streams.
+ */
+#ifndef SOL_H
+#define SOL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SOL_OK          0
+#define SOL_EINVAL     -1   /* invalid argument                                  */
+#define SOL_ENOMEM     -2   /* device allocation failed                          */
+#define SOL_ENOCONV    -3   /* a Krylov solve reached max_iter; state rolled back */
+#define SOL_ENONFINITE -4   /* non-finite input field or solver breakdown         */
+#define SOL_EDEVICE    -5   /* HIP runtime error                                  */
+#define SOL_EBUSY      -6   /* handle is part of a live batch                     */
+
+/* systems (matrix rows); also the order of per-system statistics */
+#define SOL_SYS_U 0
+#define SOL_SYS_V 1
+#define SOL_SYS_W 2
+#define SOL_SYS_P 3   /* pressure correction phi (eq. 3.4), cells          */
+#define SOL_SYS_C 4   /* solute C^{n+1} (eq. 3.10), cells                   */
+#define SOL_SYS_T 5   /* intermediate temperature T* (eq. 3.11), cells      */
+
+/* field mask bits; host_src / host_dst arrays are indexed by bit position */
+#define SOL_F_U      (1u << 0)
+#define SOL_F_V      (1u << 1)
+#define SOL_F_W      (1u << 2)
+#define SOL_F_P      (1u << 3)
+#define SOL_F_T      (1u << 4)
+#define SOL_F_C      (1u << 5)
+#define SOL_F_GL     (1u << 6)
+#define SOL_F_CL     (1u << 7)
+#define SOL_F_CS     (1u << 8)
+/* read-only intermediates of the last completed step */
+#define SOL_F_USTAR  (1u << 9)    /* u* (face layout of u)  */
+#define SOL_F_VSTAR  (1u << 10)
+#define SOL_F_WSTAR  (1u << 11)
+#define SOL_F_PHI    (1u << 12)   /* zero-mean pressure correction (cells) */
+#define SOL_F_TSTAR  (1u << 13)   /* T* before the latent correction (cells) */
+#define SOL_NFIELDS  14
+
+#define SOL_THERMAL_ADIABATIC 0
+#define SOL_THERMAL_ROBIN     1   /* q = h (T - T_ext), film in series with the half cell */
+#define SOL_THERMAL_DIRICHLET 2   /* wall temperature T(t) = T0 - b t                     */
+#define SOL_VELOCITY_NOSLIP   0
+#define SOL_VELOCITY_FREESLIP 1
+
+#define SOL_PRECISION_FP64  0
+#define SOL_PRECISION_MIXED 1     /* FP32 Krylov inside FP64 iterative refinement */
+
+typedef struct sol_handle sol_handle;
+typedef struct sol_batch sol_batch;
+
+typedef struct { int32_t dim, nx, ny, nz; double lx, ly, lz; } sol_grid;  /* dim 2|3; 2D: nz=1 */
+
+/* Alloy and model constants (SI units, K, wt%).  Phase diagram: liquidus
+   T = T_m + m_sp C_l (eq. 2.20), partition k_p (eq. 2.19), eutectic C_e.
+   Boussinesq reference state T_ref, C_ref (eq. 2.9).  Carman-Kozeny drag
+   with secondary arm spacing lambda2 and g^3 regularised by darcy_eps
+   (eq. 2.8).  D_l must be 0 (minimal model, eq. 3.6). */
+typedef struct {
+    double rho, mu, cp, k, latent, beta_T, beta_C, lambda2;
+    double T_m, m_sp, k_p, C_e, T_ref, C_ref, g, D_l, darcy_eps;
+} sol_alloy;
+
+typedef struct {
+    int32_t thermal;            /* SOL_THERMAL_*                    */
+    double h, T_ext, T0, b;     /* Robin: h, T_ext; Dirichlet: T0, b */
+    int32_t velocity;           /* SOL_VELOCITY_*                   */
+} sol_face_bc;
+
+typedef struct { sol_face_bc face[6]; } sol_bcs;   /* W E S N B T; 2D uses the first four */
+
+typedef struct {
+    double dt, tol_p, tol_t;    /* time step; relative tolerances (pressure, transport) */
+    int32_t max_iter;           /* per solve                                            */
+    int32_t precision;          /* SOL_PRECISION_*                                       */
+} sol_numerics;
+
+typedef struct {
+    void *stream;                          /* hipStream_t or NULL          */
+    void *(*alloc)(size_t bytes, void *user);
+    void (*free)(void *ptr, void *user);
+    void *user;
+} sol_device_ctx;
+
+typedef struct {
+    int32_t iters[6];            /* Krylov iterations per system, last step      */
+    int64_t iters_total[6];      /* summed over the steps of this call            */
+    double rel_resid[6];         /* final true ||b - A x|| / ||b|| per system      */
+    double sum_resid[6];         /* sum of the final true residual vector          */
+    double sum_C;                /* sum over cells of C^{n+1}                      */
+    double sum_H;                /* sum over cells of T + (L/c_p) g_l at n+1       */
+    double wall_flux;            /* sum over cooled-wall cells of U/(rho c_p h)(T* - T_wall) */
+    double div_star;             /* ||D u*||_2                                     */
+    double div_new;              /* ||D u^{n+1}||_2                                */
+    int64_t step;                /* completed steps of the handle                  */
+} sol_step_stats;
+
+/* Create a case: validates every argument (e.g. nx < 2, dt <= 0,
+   k_p outside (0,1), m_sp >= 0, D_l != 0 -> SOL_EINVAL), allocates device
+   memory, builds the constant-coefficient systems (transient, diffusion,
+   wall terms, pressure Laplacian) on the device, and sets the initial state
+   u = v = w = p = 0, C = C_ref, g_l = 1, C_l = C_ref, C_s = 0,
+   T = T_ref.  ctx may be NULL.  *out receives the handle. */
+int sol_create(const sol_grid *grid, const sol_alloy *alloy, const sol_bcs *bcs,
+               const sol_numerics *num, const sol_device_ctx *ctx, sol_handle **out);
+void sol_destroy(sol_handle *h);
+
+/* Copy host fields (SOL_F_U..SOL_F_CS bits only) into the handle.  host_src is
+   an array of SOL_NFIELDS pointers indexed by bit position; entries for unset
+   bits are ignored.  Non-finite values -> SOL_ENONFINITE (nothing written).
+   Synchronous with respect to the caller's buffers. */
+int sol_write_fields(sol_handle *h, uint32_t mask, const double *const *host_src);
+
+/* Copy fields to host buffers (synchronous).  Intermediates (SOL_F_USTAR ..
+   SOL_F_TSTAR) are those of the last completed step or sol_assemble call. */
+int sol_read_fields(sol_handle *h, uint32_t mask, double *const *host_dst);
+
+/* Number of rows and structural nonzeros of a system (5- / 7-point pattern,
+   in-domain neighbours only). */
+int sol_system_size(const sol_handle *h, int32_t system, int32_t *rows, int32_t *nnz);
+
+/* Assemble, for the current state, the systems in system_mask (bit s =
+   SOL_SYS_s) without solving.  The momentum systems use the level-n fields;
+   the pressure system takes the current velocity as u*; the solute and
+   energy systems take the current velocity as the advecting field and the
+   next time level for prescribed wall temperatures. */
+int sol_assemble(sol_handle *h, uint32_t system_mask);
+
+/* Export the last assembled system as CSR (int32 row_ptr[rows+1],
+   col_idx[nnz] ascending per row, val[nnz], rhs[rows]; host buffers). */
+int sol_read_matrix(sol_handle *h, int32_t system, int32_t *row_ptr, int32_t *col_idx,
+                    double *val, double *rhs);
+
+/* Advance nsteps time steps (Algorithm 1).  stats may be NULL.  On
+   SOL_ENOCONV / SOL_ENONFINITE the handle stays at the last completed step. */
+int sol_step(sol_handle *h, int32_t nsteps, sol_step_stats *stats);
+
+/* Device bytes a case of this size would allocate (admission control). */
+int sol_footprint_bytes(const sol_grid *grid, const sol_numerics *num, size_t *out);
+
+/* Batches: n handles advanced together, every kernel of the step launched
+   once for all cases (uneven sizes allowed).  The handles keep their state
+   and may not be stepped alone while the batch lives (SOL_EBUSY).  All
+   handles must share one stream.  nsteps_per_case[i] steps for case i (a
+   case with 0 sits out); per-case stats optional (array of n). */
+int sol_batch_create(sol_handle *const *cases, int32_t n, sol_batch **out);
+int sol_batch_step(sol_batch *b, const int32_t *nsteps_per_case, sol_step_stats *stats);
+void sol_batch_destroy(sol_batch *b);
+
+/* Kernel timing for roofline reports.  When enabled, HIP events on the
+   handle's stream bracket sampled launches of the kernel classes below (every
+   8th Krylov iteration, every assembly / phase launch); a sample counts only
+   if the solve was still iterating at that launch.  sol_get_timing returns
+   the number of timed launches, their summed duration and the algorithmic
+   bytes those launches move (matrix values + vectors read and written once,
+   per row of the systems that were iterating).  Enabling or disabling
+   resets the counters. */
+#define SOL_KCLASS_CG_A      0   /* CG: p = Mr + beta p, q = A p, (p,q)        */
+#define SOL_KCLASS_CG_B      1   /* CG: x, r update, (r,Mr), (r,r)             */
+#define SOL_KCLASS_BICG_A    2   /* BiCGSTAB: p, v = A M p, (rh,v)              */
+#define SOL_KCLASS_BICG_B    3   /* BiCGSTAB: t = A M s, (t,s), (t,t)           */
+#define SOL_KCLASS_BICG_C    4   /* BiCGSTAB: x, r update, (rh,r), (r,r)        */
+#define SOL_KCLASS_ASM_MOM   5   /* momentum assembly                           */
+#define SOL_KCLASS_ASM_TRN   6   /* solute + energy assembly                    */
+#define SOL_KCLASS_PHASE     7   /* phase update + commit                       */
+#define SOL_NKCLASS          8
+int sol_set_timing(sol_handle *h, int32_t enable);
+int sol_get_timing(sol_handle *h, int32_t kclass, int64_t *launches, double *total_ms,
+                   double *bytes);
+
+const char *sol_last_error(void);
+const char *sol_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SOL_H */

@@ -1,0 +1,1040 @@
+// Host side of the solidification step library: argument validation, device
+// memory, the time-step driver of Algorithm 1, the Krylov orchestration and
+// the C ABI declared in sol.h.
+//
+// Krylov orchestration: convergence is decided on the device (KState::status
+// written by the last workgroup of each iteration kernel; every kernel of a
+// solve that is no longer RUNNING returns at once).  The host queues
+// iterations in chunks and reads the status array through one lagging
+// event: while it inspects chunk k the device already runs chunk k+1, so the
+// GPU never waits for the host; the price is at most one chunk of no-op
+// launches after convergence.  Chunk sizes follow the iteration count of the
+// same solve in the previous step.
+#include "sol.h"
+#include "sol_dev.hpp"
+#include "kernels.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace sol;
+
+static thread_local std::string g_err;
+
+static int fail(int code, const char *fmt, ...)
+{
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess) return fail(SOL_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+#define RCHK(expr)                  \
+    do {                            \
+        int r_ = (expr);            \
+        if (r_ != SOL_OK) return r_; \
+    } while (0)
+
+// ------------------------------------------------------------------ memory
+
+struct Mem {
+    sol_device_ctx ctx{};
+    bool has_ctx = false;
+    std::vector<void *> blocks;
+    size_t bytes = 0;
+    void *get(size_t n)
+    {
+        n = (std::max<size_t>(n, 256) + 255) & ~size_t(255);
+        void *p = nullptr;
+        if (has_ctx) p = ctx.alloc(n, ctx.user);
+        else if (hipMalloc(&p, n) != hipSuccess) p = nullptr;
+        if (p) { blocks.push_back(p); bytes += n; }
+        return p;
+    }
+    void release()
+    {
+        for (void *p : blocks) {
+            if (has_ctx) ctx.free(p, ctx.user);
+            else (void)hipFree(p);
+        }
+        blocks.clear();
+        bytes = 0;
+    }
+};
+
+// ------------------------------------------------------------------ sizes
+
+struct Sizes {
+    int dim, nx, ny, nz, ncell, nd, maxn, ntile_cell;
+    int nsys[NSYS], sdim[NSYS][3];
+};
+
+static void compute_sizes(const sol_grid &g, Sizes &z)
+{
+    z.dim = g.dim;
+    z.nx = g.nx;
+    z.ny = g.ny;
+    z.nz = g.dim == 3 ? g.nz : 1;
+    z.ncell = z.nx * z.ny * z.nz;
+    z.nd = 2 * z.dim + 1;
+    z.maxn = 0;
+    for (int s = 0; s < NSYS; ++s) {
+        int d[3] = {z.nx, z.ny, z.nz};
+        if (s <= SW) d[s] -= 1;
+        if (s == SW && z.dim != 3) d[0] = d[1] = d[2] = 0;
+        for (int a = 0; a < 3; ++a) { if (d[a] < 0) d[a] = 0; z.sdim[s][a] = d[a]; }
+        z.nsys[s] = d[0] * d[1] * d[2];
+        z.maxn = std::max(z.maxn, z.nsys[s]);
+    }
+    z.ntile_cell = ceil_div(z.ncell, TILE);
+}
+
+// total device bytes of one case (matches the allocations in sol_create)
+static size_t footprint(const Sizes &z, int precision)
+{
+    auto al = [](size_t n) { return (std::max<size_t>(n, 256) + 255) & ~size_t(255); };
+    size_t b = 0;
+    const size_t D = sizeof(double), F = sizeof(float);
+    size_t nf = 0;
+    for (int s = 0; s < 3; ++s) nf += std::max(z.nsys[s], 1);
+    b += 3 * (al(nf * D));                                       // u,v,w / us / un (per component)
+    b += 9 * al((size_t)z.ncell * D);                           // p T C gl Cl Cs phi Cnew Tstar
+    for (int s = 0; s < NSYS; ++s) {
+        const size_t n = std::max(z.nsys[s], 1);
+        b += al(z.nd * n * D) + 2 * al(n * D);                   // A, b, minv
+        if (s != SP && s != SC) b += al(z.nd * n * D);           // constant parts
+        if (precision) b += al(z.nd * n * F) + al(n * F);
+    }
+    b += 3 * 7 * al((size_t)z.maxn * D);                        // Krylov work vectors
+    if (precision) b += 3 * 8 * al((size_t)z.maxn * F) + 3 * 2 * al((size_t)z.maxn * D);
+    b += al((size_t)z.ntile_cell * 4 * D) + 2 * al(256);         // reductions, counters, step
+    return b;
+}
+
+// ------------------------------------------------------------------ timing
+
+struct TSample { int cls; int64_t iter; int phase; hipEvent_t a, b; };
+struct TAcc { int64_t n = 0; double ms = 0.0, bytes = 0.0; };
+
+// algorithmic bytes per row of one launch (FP64): matrix values and every
+// vector element read or written once
+static double row_bytes(int cls, int nd, int dim)
+{
+    switch (cls) {
+    case SOL_KCLASS_CG_A: return 8.0 * nd + 40.0;   // A, r, p_old, M; p, q
+    case SOL_KCLASS_CG_B: return 56.0;              // x, p, r, q, M; x, r
+    case SOL_KCLASS_BICG_A: return 8.0 * nd + 56.0; // A, r, p, v, M, rh; p, v
+    case SOL_KCLASS_BICG_B: return 8.0 * nd + 32.0; // A, r, v, M; t
+    case SOL_KCLASS_BICG_C: return 72.0;            // x, r, v, p, M, t, rh; x, r
+    case SOL_KCLASS_ASM_MOM: return 16.0 * nd + 8.0 * dim + 48.0;
+    case SOL_KCLASS_ASM_TRN: return 24.0 * nd + 8.0 * dim + 56.0;
+    case SOL_KCLASS_PHASE: return 96.0 + 16.0 * dim;
+    }
+    return 0.0;
+}
+
+// ------------------------------------------------------------------ handle
+
+struct Group;
+
+struct sol_handle {
+    sol_grid grid{};
+    sol_alloy al{};
+    sol_bcs bcs{};
+    sol_numerics num{};
+    Sizes z{};
+    hipStream_t stream = nullptr;
+    Mem mem;
+    CaseDev cd{};
+    double *work[3][7] = {};
+    float *work32[3][8] = {};
+    double *work64x[3][2] = {};
+    int32_t *csr_cnt = nullptr, *csr_rp[NSYS] = {}, *csr_col[NSYS] = {};
+    double *csr_val[NSYS] = {};
+    Group *solo = nullptr;
+    sol_batch *batch = nullptr;
+    bool timing = false;
+    TAcc tacc[SOL_NKCLASS];
+    std::vector<TSample> samples;
+    std::vector<hipEvent_t> event_pool;
+    int64_t last_iters[NSYS] = {};
+};
+
+// ------------------------------------------------------------------ groups
+
+struct Phase {
+    int kind = K_BICGSTAB;
+    int tcls0 = SOL_KCLASS_BICG_A;       // timing class of the first iteration kernel
+    std::vector<KJob> jobs;
+    std::vector<int> st_index;          // KState index (case * NSYS + system)
+    std::vector<int> case_of, sys_of;
+    KJob *jobs_d = nullptr;
+    JTile *tiles_d[2] = {nullptr, nullptr};   // [0] 5-point jobs, [1] 7-point jobs
+    int nt[2] = {0, 0};
+    int pred = 1;
+    int64_t launched = 0;
+};
+
+struct Group {
+    std::vector<sol_handle *> cs;
+    hipStream_t stream = nullptr;
+    std::vector<void *> dmem;            // hipMalloc'd group arrays
+    CaseDev *cases_d = nullptr;
+    KState *ks_d = nullptr;
+    double *red_d = nullptr;
+    Tile *t_mom[2] = {}, *t_cell[2] = {}, *t_const[2] = {};
+    int n_mom[2] = {}, n_cell[2] = {}, n_const[2] = {};
+    Phase ph[3];                          // momentum, pressure, solute + energy
+    KState *ks_h[2] = {nullptr, nullptr};  // pinned poll buffers
+    double *red_h = nullptr;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    int nks = 0;
+    sol_handle *timer = nullptr;          // handle that collects kernel timing (solo groups)
+};
+
+static void *gmalloc(Group &g, size_t bytes)
+{
+    void *p = nullptr;
+    if (hipMalloc(&p, std::max<size_t>(bytes, 256)) != hipSuccess) return nullptr;
+    g.dmem.push_back(p);
+    return p;
+}
+
+static void group_free(Group *g)
+{
+    if (!g) return;
+    for (void *p : g->dmem) (void)hipFree(p);
+    for (int i = 0; i < 2; ++i) {
+        if (g->ks_h[i]) (void)hipHostFree(g->ks_h[i]);
+        if (g->ev[i]) (void)hipEventDestroy(g->ev[i]);
+    }
+    if (g->red_h) (void)hipHostFree(g->red_h);
+    delete g;
+}
+
+template <class T>
+static int upload(Group &g, T **dst, const std::vector<T> &src)
+{
+    *dst = nullptr;
+    if (src.empty()) return SOL_OK;
+    *dst = (T *)gmalloc(g, sizeof(T) * src.size());
+    if (!*dst) return fail(SOL_ENOMEM, "group allocation failed");
+    HIPCHK(hipMemcpy(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice));
+    return SOL_OK;
+}
+
+static int group_build(Group &g)
+{
+    const int n = (int)g.cs.size();
+    g.nks = n * NSYS;
+    g.ks_d = (KState *)gmalloc(g, sizeof(KState) * g.nks);
+    g.red_d = (double *)gmalloc(g, sizeof(double) * 16 * n);
+    if (!g.ks_d || !g.red_d) return fail(SOL_ENOMEM, "group allocation failed");
+    HIPCHK(hipMemset(g.red_d, 0, sizeof(double) * 16 * n));
+    std::vector<CaseDev> cdv(n);
+    std::vector<KState> ksv(g.nks);
+    for (auto &k : ksv) { std::memset(&k, 0, sizeof(k)); k.status = K_IDLE; }
+    std::vector<Tile> mom[2], cell[2], cst[2];
+    for (int c = 0; c < n; ++c) {
+        sol_handle *h = g.cs[c];
+        CaseDev d = h->cd;
+        d.ks = g.ks_d + c * NSYS;
+        d.red = g.red_d + 16 * c;
+        cdv[c] = d;
+        const int gi = h->z.dim == 3 ? 1 : 0;
+        for (int s = 0; s < h->z.dim; ++s)
+            for (int t = 0; t < ceil_div(h->z.nsys[s], TILE); ++t) mom[gi].push_back({c, s, t, 0});
+        for (int t = 0; t < h->z.ntile_cell; ++t) cell[gi].push_back({c, SC, t, 0});
+        const int cs_list[5] = {SU, SV, SW, SP, ST};
+        for (int s : cs_list)
+            for (int t = 0; t < ceil_div(h->z.nsys[s], TILE); ++t) cst[gi].push_back({c, s, t, 0});
+        for (int s = 0; s < NSYS; ++s) {
+            KState &k = ksv[c * NSYS + s];
+            const double tol = s == SP ? h->num.tol_p : h->num.tol_t;
+            k.tol2 = tol * tol;
+            k.max_iter = h->num.max_iter;
+        }
+    }
+    RCHK(upload(g, &g.cases_d, cdv));
+    HIPCHK(hipMemcpy(g.ks_d, ksv.data(), sizeof(KState) * g.nks, hipMemcpyHostToDevice));
+    for (int gi = 0; gi < 2; ++gi) {
+        RCHK(upload(g, &g.t_mom[gi], mom[gi]));
+        RCHK(upload(g, &g.t_cell[gi], cell[gi]));
+        RCHK(upload(g, &g.t_const[gi], cst[gi]));
+        g.n_mom[gi] = (int)mom[gi].size();
+        g.n_cell[gi] = (int)cell[gi].size();
+        g.n_const[gi] = (int)cst[gi].size();
+    }
+    // solve phases
+    const int phase_sys[3][3] = {{SU, SV, SW}, {SP, -1, -1}, {SC, ST, -1}};
+    for (int p = 0; p < 3; ++p) {
+        Phase &P = g.ph[p];
+        P.kind = p == 1 ? K_CG : K_BICGSTAB;
+        P.tcls0 = p == 1 ? SOL_KCLASS_CG_A : SOL_KCLASS_BICG_A;
+        std::vector<JTile> jt[2];
+        size_t part_total = 0;
+        for (int c = 0; c < n; ++c) {
+            sol_handle *h = g.cs[c];
+            for (int k = 0; k < 3; ++k) {
+                const int s = phase_sys[p][k];
+                if (s < 0 || h->z.nsys[s] == 0) continue;
+                KJob J;
+                std::memset(&J, 0, sizeof(J));
+                J.n = h->z.nsys[s];
+                J.sx = h->z.sdim[s][0];
+                J.sxy = h->z.sdim[s][0] * h->z.sdim[s][1];
+                J.ntile = ceil_div(J.n, TILE);
+                J.kind = P.kind;
+                J.A = h->cd.A[s];
+                J.b = h->cd.b[s];
+                J.minv = h->cd.minv[s];
+                const int ws = p == 0 ? s : (p == 1 ? 0 : (s == SC ? 0 : 1));
+                if (p == 0) { J.x = h->cd.us[s]; J.x0 = s == SU ? h->cd.u : (s == SV ? h->cd.v : h->cd.w); }
+                else if (p == 1) { J.x = h->cd.phi; J.x0 = nullptr; }
+                else if (s == SC) { J.x = h->cd.Cnew; J.x0 = h->cd.C; }
+                else { J.x = h->cd.Tstar; J.x0 = h->cd.T; }
+                J.r = h->work[ws][0]; J.rh = h->work[ws][1];
+                J.p0 = h->work[ws][2]; J.p1 = h->work[ws][3];
+                J.v0 = h->work[ws][4]; J.v1 = h->work[ws][5];
+                J.t = h->work[ws][6];
+                J.st = g.ks_d + c * NSYS + s;
+                part_total += (size_t)J.ntile * 4;
+                const int gi = h->z.nd == 7 ? 1 : 0;
+                const int jidx = (int)P.jobs.size();
+                for (int t = 0; t < J.ntile; ++t) jt[gi].push_back({jidx, t});
+                P.jobs.push_back(J);
+                P.st_index.push_back(c * NSYS + s);
+                P.case_of.push_back(c);
+                P.sys_of.push_back(s);
+            }
+        }
+        double *part = (double *)gmalloc(g, sizeof(double) * std::max<size_t>(part_total, 1));
+        if (!part) return fail(SOL_ENOMEM, "group allocation failed");
+        size_t off = 0;
+        for (auto &J : P.jobs) { J.part = part + off; off += (size_t)J.ntile * 4; }
+        RCHK(upload(g, &P.jobs_d, P.jobs));
+        for (int gi = 0; gi < 2; ++gi) {
+            RCHK(upload(g, &P.tiles_d[gi], jt[gi]));
+            P.nt[gi] = (int)jt[gi].size();
+        }
+        P.pred = p == 1 ? 64 : 2;
+    }
+    for (int i = 0; i < 2; ++i) {
+        HIPCHK(hipHostMalloc((void **)&g.ks_h[i], sizeof(KState) * g.nks, hipHostMallocDefault));
+        HIPCHK(hipEventCreateWithFlags(&g.ev[i], hipEventDisableTiming));
+    }
+    HIPCHK(hipHostMalloc((void **)&g.red_h, sizeof(double) * 16 * n, hipHostMallocDefault));
+    return SOL_OK;
+}
+
+static int group_create(const std::vector<sol_handle *> &cs, Group **out)
+{
+    Group *g = new Group();
+    g->cs = cs;
+    g->stream = cs[0]->stream;
+    int rc = group_build(*g);
+    if (rc != SOL_OK) { group_free(g); return rc; }
+    *out = g;
+    return SOL_OK;
+}
+
+// ------------------------------------------------------------ timing helpers
+
+static hipEvent_t take_event(sol_handle *h)
+{
+    if (!h->event_pool.empty()) {
+        hipEvent_t e = h->event_pool.back();
+        h->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Turn the samples of a finished solve phase (or of a fixed launch) into
+// durations; a Krylov sample counts only for jobs still iterating at that
+// launch (its iteration index below the job's final count, no restart).
+static void collect_samples(Group &g, Phase *P, const KState *ks)
+{
+    sol_handle *h = g.timer;
+    if (!h) return;
+    for (auto &s : h->samples) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, s.a, s.b) != hipSuccess) continue;
+        double bytes = 0.0;
+        bool valid = true;
+        if (s.phase >= 0 && P) {
+            double rows = 0.0;
+            int nd = 5, dim = 2;
+            for (size_t j = 0; j < P->jobs.size(); ++j) {
+                const KState &k = ks[P->st_index[j]];
+                if (k.restarts != 0) valid = false;
+                if (s.iter < k.it) { rows += P->jobs[j].n; nd = g.cs[P->case_of[j]]->z.nd; dim = g.cs[P->case_of[j]]->z.dim; }
+            }
+            if (rows == 0.0) valid = false;
+            bytes = rows * row_bytes(s.cls, nd, dim);
+        } else {
+            for (auto *c : g.cs) {
+                const double rows = s.cls == SOL_KCLASS_ASM_MOM
+                                        ? (double)(c->z.nsys[0] + c->z.nsys[1] + c->z.nsys[2])
+                                        : (double)c->z.ncell;
+                bytes += rows * row_bytes(s.cls, c->z.nd, c->z.dim);
+            }
+        }
+        if (valid) {
+            h->tacc[s.cls].n += 1;
+            h->tacc[s.cls].ms += ms;
+            h->tacc[s.cls].bytes += bytes;
+        }
+        h->event_pool.push_back(s.a);
+        h->event_pool.push_back(s.b);
+    }
+    h->samples.clear();
+}
+
+// ------------------------------------------------------------------ solves
+
+static void enqueue_iters(Group &g, Phase &P, int k, int &flip, int phase_id)
+{
+    sol_handle *tm = g.timer;
+    for (int it = 0; it < k; ++it) {
+        const bool sample = tm && (P.launched % 8 == 0);
+        const int nk = P.kind == K_CG ? 2 : 3;
+        for (int q = 0; q < nk; ++q) {
+            const int which = (P.kind == K_CG ? KI_CG_A : KI_BICG_A) + q;
+            hipEvent_t a = nullptr, b = nullptr;
+            if (sample) { a = take_event(tm); b = take_event(tm); }
+            if (a && b) (void)hipEventRecord(a, g.stream);
+            for (int gi = 0; gi < 2; ++gi)
+                launch_kiter(which, gi ? 7 : 5, P.jobs_d, P.tiles_d[gi], P.nt[gi], flip, g.stream);
+            if (a && b) {
+                (void)hipEventRecord(b, g.stream);
+                tm->samples.push_back({P.tcls0 + q, P.launched, phase_id, a, b});
+            }
+        }
+        flip ^= 1;
+        P.launched += 1;
+    }
+}
+
+static int poll_enqueue(Group &g, int slot)
+{
+    HIPCHK(hipMemcpyAsync(g.ks_h[slot], g.ks_d, sizeof(KState) * g.nks, hipMemcpyDeviceToHost, g.stream));
+    HIPCHK(hipEventRecord(g.ev[slot], g.stream));
+    return SOL_OK;
+}
+
+static int poll_wait(Group &g, int slot)
+{
+    HIPCHK(hipEventSynchronize(g.ev[slot]));
+    return SOL_OK;
+}
+
+static bool any_status(const Group &g, const Phase &P, int slot, int status)
+{
+    for (int idx : P.st_index)
+        if (g.ks_h[slot][idx].status == status) return true;
+    return false;
+}
+
+static int group_solve(Group &g, Phase &P, int phase_id)
+{
+    if (P.jobs.empty()) return SOL_OK;
+    int flip = 0;
+    P.launched = 0;
+    for (int gi = 0; gi < 2; ++gi)
+        launch_kinit(gi ? 7 : 5, P.jobs_d, P.tiles_d[gi], P.nt[gi], flip, 0, g.stream);
+    int rc = SOL_OK;
+    for (int round = 0; round < 64; ++round) {
+        int slot = 0;
+        const int first = round == 0 ? std::max(1, P.pred - P.pred / 8) : std::max(2, P.pred / 8);
+        const int later = std::max(2, P.pred / 16);
+        enqueue_iters(g, P, first, flip, phase_id);
+        RCHK(poll_enqueue(g, slot));
+        for (;;) {
+            enqueue_iters(g, P, later, flip, phase_id);
+            RCHK(poll_enqueue(g, slot ^ 1));
+            RCHK(poll_wait(g, slot));
+            if (!any_status(g, P, slot, K_RUNNING)) { RCHK(poll_wait(g, slot ^ 1)); break; }
+            slot ^= 1;
+        }
+        for (int gi = 0; gi < 2; ++gi)
+            launch_kfinish(gi ? 7 : 5, P.jobs_d, P.tiles_d[gi], P.nt[gi], g.stream);
+        RCHK(poll_enqueue(g, 0));
+        RCHK(poll_wait(g, 0));
+        HIPCHK(hipGetLastError());
+        if (any_status(g, P, 0, K_NONFINITE)) { rc = fail(SOL_ENONFINITE, "non-finite value in a linear solve"); break; }
+        if (any_status(g, P, 0, K_FAILED)) { rc = fail(SOL_ENOCONV, "linear solve did not converge within max_iter"); break; }
+        if (!any_status(g, P, 0, K_RESTART)) break;
+        for (int gi = 0; gi < 2; ++gi)
+            launch_kinit(gi ? 7 : 5, P.jobs_d, P.tiles_d[gi], P.nt[gi], flip, 1, g.stream);
+        if (round == 63) rc = fail(SOL_ENOCONV, "linear solve kept restarting");
+    }
+    int mx = 1;
+    for (size_t j = 0; j < P.jobs.size(); ++j) {
+        const KState &k = g.ks_h[0][P.st_index[j]];
+        mx = std::max(mx, (int)k.it);
+        g.cs[P.case_of[j]]->last_iters[P.sys_of[j]] = k.it;
+    }
+    P.pred = mx;
+    if (g.timer) collect_samples(g, &P, g.ks_h[0]);
+    return rc;
+}
+
+template <class F>
+static void timed(Group &g, int cls, F launch)
+{
+    sol_handle *tm = g.timer;
+    hipEvent_t a = nullptr, b = nullptr;
+    if (tm) { a = take_event(tm); b = take_event(tm); }
+    if (a && b) (void)hipEventRecord(a, g.stream);
+    launch();
+    if (a && b) {
+        (void)hipEventRecord(b, g.stream);
+        tm->samples.push_back({cls, 0, -1, a, b});
+    }
+}
+
+// one time step (Algorithm 1) for every case of the group
+static int group_step(Group &g)
+{
+    hipStream_t s = g.stream;
+    // 1: momentum predictor
+    timed(g, SOL_KCLASS_ASM_MOM, [&] {
+        for (int gi = 0; gi < 2; ++gi) launch_asm_momentum(gi ? 3 : 2, g.cases_d, g.t_mom[gi], g.n_mom[gi], s);
+    });
+    RCHK(group_solve(g, g.ph[0], 0));
+    // 2: pressure correction
+    for (int gi = 0; gi < 2; ++gi) {
+        launch_div_rhs(gi ? 3 : 2, g.cases_d, g.t_cell[gi], g.n_cell[gi], 1, s);
+        launch_sub_mean(g.cases_d, g.t_cell[gi], g.n_cell[gi], s);
+    }
+    RCHK(group_solve(g, g.ph[1], 1));
+    // 3: projection
+    for (int gi = 0; gi < 2; ++gi) launch_project(g.cases_d, g.t_mom[gi], g.n_mom[gi], s);
+    // 4-6: solute and energy systems (both only need u^{n+1})
+    timed(g, SOL_KCLASS_ASM_TRN, [&] {
+        for (int gi = 0; gi < 2; ++gi) launch_asm_transport(gi ? 3 : 2, g.cases_d, g.t_cell[gi], g.n_cell[gi], 1, s);
+    });
+    RCHK(group_solve(g, g.ph[2], 2));
+    // 7-8: phase update, C_l, C_s; commit level n+1
+    timed(g, SOL_KCLASS_PHASE, [&] {
+        for (int gi = 0; gi < 2; ++gi) launch_phase_commit(gi ? 3 : 2, g.cases_d, g.t_cell[gi], g.n_cell[gi], s);
+    });
+    HIPCHK(hipGetLastError());
+    return SOL_OK;
+}
+
+// ------------------------------------------------------------- validation
+
+static int check_finite(double x, const char *what)
+{
+    if (!std::isfinite(x)) return fail(SOL_EINVAL, "%s is not finite", what);
+    return SOL_OK;
+}
+
+static int validate(const sol_grid *g, const sol_alloy *a, const sol_bcs *b, const sol_numerics *n)
+{
+    if (!g || !a || !b || !n) return fail(SOL_EINVAL, "NULL argument");
+    if (g->dim != 2 && g->dim != 3) return fail(SOL_EINVAL, "dim must be 2 or 3 (got %d)", g->dim);
+    if (g->nx < 2 || g->ny < 1) return fail(SOL_EINVAL, "need nx >= 2 and ny >= 1 (got %d, %d)", g->nx, g->ny);
+    if (g->dim == 3 && g->nz < 1) return fail(SOL_EINVAL, "need nz >= 1 in 3D");
+    if (g->dim == 2 && g->nz != 1) return fail(SOL_EINVAL, "2D grids need nz = 1");
+    const double cells = (double)g->nx * g->ny * (g->dim == 3 ? g->nz : 1);
+    if (cells * 7.0 > 2.0e9) return fail(SOL_EINVAL, "grid too large for 32-bit indices");
+    if (!(g->lx > 0) || !(g->ly > 0) || (g->dim == 3 && !(g->lz > 0)))
+        return fail(SOL_EINVAL, "domain lengths must be > 0");
+    const double v[] = {a->rho, a->mu, a->cp, a->k, a->latent, a->beta_T, a->beta_C, a->lambda2, a->T_m,
+                        a->m_sp, a->k_p, a->C_e, a->T_ref, a->C_ref, a->g, a->D_l, a->darcy_eps};
+    for (double x : v) RCHK(check_finite(x, "alloy constant"));
+    if (!(a->rho > 0) || !(a->mu > 0) || !(a->cp > 0) || !(a->k > 0) || !(a->latent > 0))
+        return fail(SOL_EINVAL, "rho, mu, cp, k, latent must be > 0");
+    if (!(a->lambda2 > 0)) return fail(SOL_EINVAL, "lambda2 must be > 0");
+    if (!(a->k_p > 0 && a->k_p < 1)) return fail(SOL_EINVAL, "k_p must lie in (0,1)");
+    if (!(a->m_sp < 0)) return fail(SOL_EINVAL, "liquidus slope m_sp must be < 0");
+    if (!(a->C_e > 0)) return fail(SOL_EINVAL, "C_e must be > 0");
+    if (a->D_l != 0.0) return fail(SOL_EINVAL, "liquid diffusion D_l is not supported (minimal model)");
+    if (!(a->darcy_eps >= 0)) return fail(SOL_EINVAL, "darcy_eps must be >= 0");
+    if (a->g < 0) return fail(SOL_EINVAL, "g must be >= 0");
+    const int nf = g->dim == 3 ? 6 : 4;
+    for (int f = 0; f < 6; ++f) {
+        const sol_face_bc &fb = b->face[f];
+        if (f >= nf) continue;
+        if (fb.thermal < 0 || fb.thermal > 2) return fail(SOL_EINVAL, "face %d: bad thermal type", f);
+        if (fb.velocity < 0 || fb.velocity > 1) return fail(SOL_EINVAL, "face %d: bad velocity type", f);
+        if (fb.thermal == 1 && !(fb.h > 0 && std::isfinite(fb.h) && std::isfinite(fb.T_ext)))
+            return fail(SOL_EINVAL, "face %d: Robin wall needs h > 0 and finite T_ext", f);
+        if (fb.thermal == 2 && !(std::isfinite(fb.T0) && std::isfinite(fb.b)))
+            return fail(SOL_EINVAL, "face %d: prescribed wall temperature needs finite T0, b", f);
+    }
+    if (!(n->dt > 0) || !std::isfinite(n->dt)) return fail(SOL_EINVAL, "dt must be > 0");
+    if (!(n->tol_p > 0 && n->tol_p < 1) || !(n->tol_t > 0 && n->tol_t < 1))
+        return fail(SOL_EINVAL, "tolerances must lie in (0,1)");
+    if (n->max_iter < 1) return fail(SOL_EINVAL, "max_iter must be >= 1");
+    if (n->precision != SOL_PRECISION_FP64 && n->precision != SOL_PRECISION_MIXED)
+        return fail(SOL_EINVAL, "precision must be SOL_PRECISION_FP64 or SOL_PRECISION_MIXED");
+    if (n->precision == SOL_PRECISION_MIXED)
+        return fail(SOL_EINVAL, "mixed precision is not built into this library version");
+    return SOL_OK;
+}
+
+static void make_phys(const sol_handle &h, Phys &P)
+{
+    std::memset(&P, 0, sizeof(P));
+    const Sizes &z = h.z;
+    P.dim = z.dim; P.nx = z.nx; P.ny = z.ny; P.nz = z.nz;
+    P.ncell = z.ncell;
+    for (int s = 0; s < NSYS; ++s) {
+        P.nsys[s] = z.nsys[s];
+        for (int a = 0; a < 3; ++a) P.sdim[s][a] = z.sdim[s][a];
+    }
+    const double L[3] = {h.grid.lx, h.grid.ly, z.dim == 3 ? h.grid.lz : 1.0};
+    const int N[3] = {z.nx, z.ny, z.nz};
+    for (int a = 0; a < 3; ++a) {
+        P.h[a] = L[a] / N[a];
+        P.ih[a] = 1.0 / P.h[a];
+        P.ih2[a] = 1.0 / (P.h[a] * P.h[a]);
+    }
+    const sol_alloy &a = h.al;
+    P.rho = a.rho; P.mu = a.mu; P.nu = a.mu / a.rho;
+    P.dt = h.num.dt; P.idt = 1.0 / h.num.dt;
+    P.alpha = a.k / (a.rho * a.cp);
+    P.lam = a.latent / a.cp;
+    P.kp = a.k_p; P.Tm = a.T_m; P.msp = a.m_sp; P.Ce = a.C_e;
+    P.Tref = a.T_ref; P.Cref = a.C_ref; P.grav = a.g;
+    P.betaT = a.beta_T; P.betaC = a.beta_C; P.lambda2 = a.lambda2; P.eps = a.darcy_eps;
+    P.rcp = a.rho * a.cp; P.kcond = a.k;
+    for (int f = 0; f < 6; ++f) {
+        const sol_face_bc &fb = h.bcs.face[f];
+        const bool used = f < 2 * z.dim;
+        P.thermal[f] = used ? fb.thermal : 0;
+        P.slip[f] = used ? fb.velocity : 0;
+        P.hc[f] = fb.h; P.Text[f] = fb.T_ext; P.Tw0[f] = fb.T0; P.Tramp[f] = fb.b;
+    }
+}
+
+// ------------------------------------------------------------------ C ABI
+
+extern "C" {
+
+const char *sol_last_error(void) { return g_err.c_str(); }
+const char *sol_version(void) { return "solidify-mi355x 0.1 (gfx950)"; }
+
+int sol_footprint_bytes(const sol_grid *grid, const sol_numerics *num, size_t *out)
+{
+    if (!grid || !num || !out) return fail(SOL_EINVAL, "NULL argument");
+    if ((grid->dim != 2 && grid->dim != 3) || grid->nx < 2 || grid->ny < 1 || (grid->dim == 3 && grid->nz < 1))
+        return fail(SOL_EINVAL, "bad grid");
+    Sizes z;
+    compute_sizes(*grid, z);
+    *out = footprint(z, num->precision);
+    return SOL_OK;
+}
+
+static int alloc_case(sol_handle *h)
+{
+    const Sizes &z = h->z;
+    Mem &m = h->mem;
+    const size_t D = sizeof(double);
+    CaseDev &d = h->cd;
+    std::memset(&d, 0, sizeof(d));
+    make_phys(*h, d.ph);
+    auto dal = [&](size_t n) { return (double *)m.get(std::max<size_t>(n, 1) * D); };
+    // face arrays: one block per set, components back to back
+    size_t nf[3];
+    for (int s = 0; s < 3; ++s) nf[s] = std::max(z.nsys[s], 1);
+    double *fu = dal(nf[0] + nf[1] + nf[2]), *fs = dal(nf[0] + nf[1] + nf[2]), *fn = dal(nf[0] + nf[1] + nf[2]);
+    if (!fu || !fs || !fn) return fail(SOL_ENOMEM, "device allocation failed");
+    d.u = fu; d.v = fu + nf[0]; d.w = fu + nf[0] + nf[1];
+    d.us[0] = fs; d.us[1] = fs + nf[0]; d.us[2] = fs + nf[0] + nf[1];
+    d.un[0] = fn; d.un[1] = fn + nf[0]; d.un[2] = fn + nf[0] + nf[1];
+    double **cellf[] = {&d.p, &d.T, &d.C, &d.gl, &d.Cl, &d.Cs, &d.phi, &d.Cnew, &d.Tstar};
+    for (double **pp : cellf) if (!(*pp = dal(z.ncell))) return fail(SOL_ENOMEM, "device allocation failed");
+    for (int s = 0; s < NSYS; ++s) {
+        const size_t n = std::max(z.nsys[s], 1);
+        d.A[s] = dal(z.nd * n);
+        d.b[s] = dal(n);
+        d.minv[s] = dal(n);
+        if (!d.A[s] || !d.b[s] || !d.minv[s]) return fail(SOL_ENOMEM, "device allocation failed");
+        if (s != SP && s != SC) {
+            d.Ac[s] = dal(z.nd * n);
+            if (!d.Ac[s]) return fail(SOL_ENOMEM, "device allocation failed");
+        }
+    }
+    for (int w = 0; w < 3; ++w)
+        for (int k = 0; k < 7; ++k)
+            if (!(h->work[w][k] = dal(z.maxn))) return fail(SOL_ENOMEM, "device allocation failed");
+    d.red_part = dal((size_t)z.ntile_cell * 4);
+    d.red_cnt = (uint32_t *)m.get(256);
+    d.step = (int64_t *)m.get(256);
+    if (!d.red_part || !d.red_cnt || !d.step) return fail(SOL_ENOMEM, "device allocation failed");
+    d.ntile_cell = z.ntile_cell;
+    return SOL_OK;
+}
+
+static int init_state(sol_handle *h)
+{
+    CaseDev &d = h->cd;
+    hipStream_t s = h->stream;
+    const Sizes &z = h->z;
+    const int nf = std::max(z.nsys[0], 1) + std::max(z.nsys[1], 1) + std::max(z.nsys[2], 1);
+    launch_fill(d.u, 0.0, nf, s);
+    launch_fill(d.us[0], 0.0, nf, s);
+    launch_fill(d.un[0], 0.0, nf, s);
+    launch_fill(d.p, 0.0, z.ncell, s);
+    launch_fill(d.T, h->al.T_ref, z.ncell, s);
+    launch_fill(d.C, h->al.C_ref, z.ncell, s);
+    launch_fill(d.gl, 1.0, z.ncell, s);
+    launch_fill(d.Cl, h->al.C_ref, z.ncell, s);
+    launch_fill(d.Cs, 0.0, z.ncell, s);
+    launch_fill(d.phi, 0.0, z.ncell, s);
+    launch_fill(d.Cnew, h->al.C_ref, z.ncell, s);
+    launch_fill(d.Tstar, h->al.T_ref, z.ncell, s);
+    for (int w = 0; w < 3; ++w)
+        for (int k = 0; k < 7; ++k) launch_fill(h->work[w][k], 0.0, z.maxn, s);
+    HIPCHK(hipMemsetAsync(d.red_cnt, 0, 256, s));
+    HIPCHK(hipMemsetAsync(d.step, 0, 256, s));
+    HIPCHK(hipGetLastError());
+    return SOL_OK;
+}
+
+int sol_create(const sol_grid *grid, const sol_alloy *alloy, const sol_bcs *bcs, const sol_numerics *num,
+               const sol_device_ctx *ctx, sol_handle **out)
+{
+    if (!out) return fail(SOL_EINVAL, "NULL out");
+    *out = nullptr;
+    RCHK(validate(grid, alloy, bcs, num));
+    if (ctx && ((ctx->alloc == nullptr) != (ctx->free == nullptr)))
+        return fail(SOL_EINVAL, "ctx->alloc and ctx->free must both be set or both be NULL");
+    sol_handle *h = new sol_handle();
+    h->grid = *grid;
+    if (h->grid.dim == 2) { h->grid.nz = 1; h->grid.lz = 1.0; }
+    h->al = *alloy;
+    h->bcs = *bcs;
+    h->num = *num;
+    compute_sizes(h->grid, h->z);
+    if (ctx) {
+        h->stream = (hipStream_t)ctx->stream;
+        if (ctx->alloc) { h->mem.ctx = *ctx; h->mem.has_ctx = true; }
+    }
+    int rc = alloc_case(h);
+    if (rc == SOL_OK) rc = init_state(h);
+    if (rc == SOL_OK) rc = group_create({h}, &h->solo);
+    if (rc == SOL_OK) {
+        Group &g = *h->solo;
+        for (int gi = 0; gi < 2; ++gi) launch_asm_const(gi ? 3 : 2, g.cases_d, g.t_const[gi], g.n_const[gi], h->stream);
+        if (hipGetLastError() != hipSuccess || hipStreamSynchronize(h->stream) != hipSuccess)
+            rc = fail(SOL_EDEVICE, "offline assembly failed");
+    }
+    if (rc != SOL_OK) {
+        group_free(h->solo);
+        h->mem.release();
+        delete h;
+        return rc;
+    }
+    *out = h;
+    return SOL_OK;
+}
+
+void sol_destroy(sol_handle *h)
+{
+    if (!h) return;
+    (void)hipStreamSynchronize(h->stream);
+    group_free(h->solo);
+    for (int s = 0; s < NSYS; ++s) {
+        if (h->csr_rp[s]) (void)hipFree(h->csr_rp[s]);
+        if (h->csr_col[s]) (void)hipFree(h->csr_col[s]);
+        if (h->csr_val[s]) (void)hipFree(h->csr_val[s]);
+    }
+    if (h->csr_cnt) (void)hipFree(h->csr_cnt);
+    for (auto &s : h->samples) { (void)hipEventDestroy(s.a); (void)hipEventDestroy(s.b); }
+    for (auto e : h->event_pool) (void)hipEventDestroy(e);
+    h->mem.release();
+    delete h;
+}
+
+static double *field_ptr(sol_handle *h, int bit, size_t *n)
+{
+    const Sizes &z = h->z;
+    CaseDev &d = h->cd;
+    switch (bit) {
+    case 0: *n = z.nsys[0]; return d.u;
+    case 1: *n = z.nsys[1]; return d.v;
+    case 2: *n = z.nsys[2]; return d.w;
+    case 3: *n = z.ncell; return d.p;
+    case 4: *n = z.ncell; return d.T;
+    case 5: *n = z.ncell; return d.C;
+    case 6: *n = z.ncell; return d.gl;
+    case 7: *n = z.ncell; return d.Cl;
+    case 8: *n = z.ncell; return d.Cs;
+    case 9: *n = z.nsys[0]; return d.us[0];
+    case 10: *n = z.nsys[1]; return d.us[1];
+    case 11: *n = z.nsys[2]; return d.us[2];
+    case 12: *n = z.ncell; return d.phi;
+    case 13: *n = z.ncell; return d.Tstar;
+    }
+    *n = 0;
+    return nullptr;
+}
+
+int sol_write_fields(sol_handle *h, uint32_t mask, const double *const *src)
+{
+    if (!h || !src) return fail(SOL_EINVAL, "NULL argument");
+    if (mask & ~((1u << 9) - 1)) return fail(SOL_EINVAL, "only state fields (SOL_F_U..SOL_F_CS) can be written");
+    if (h->batch) return fail(SOL_EBUSY, "handle is part of a batch");
+    for (int bit = 0; bit < 9; ++bit) {
+        if (!(mask & (1u << bit))) continue;
+        size_t n;
+        field_ptr(h, bit, &n);
+        if (n && !src[bit]) return fail(SOL_EINVAL, "field %d: NULL source", bit);
+        for (size_t i = 0; i < n; ++i)
+            if (!std::isfinite(src[bit][i])) return fail(SOL_ENONFINITE, "field %d: non-finite value at %zu", bit, i);
+    }
+    for (int bit = 0; bit < 9; ++bit) {
+        if (!(mask & (1u << bit))) continue;
+        size_t n;
+        double *d = field_ptr(h, bit, &n);
+        if (n) HIPCHK(hipMemcpyAsync(d, src[bit], n * sizeof(double), hipMemcpyHostToDevice, h->stream));
+    }
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return SOL_OK;
+}
+
+int sol_read_fields(sol_handle *h, uint32_t mask, double *const *dst)
+{
+    if (!h || !dst) return fail(SOL_EINVAL, "NULL argument");
+    if (mask & ~((1u << SOL_NFIELDS) - 1)) return fail(SOL_EINVAL, "unknown field bits");
+    for (int bit = 0; bit < SOL_NFIELDS; ++bit) {
+        if (!(mask & (1u << bit))) continue;
+        size_t n;
+        field_ptr(h, bit, &n);
+        if (n && !dst[bit]) return fail(SOL_EINVAL, "field %d: NULL destination", bit);
+    }
+    for (int bit = 0; bit < SOL_NFIELDS; ++bit) {
+        if (!(mask & (1u << bit))) continue;
+        size_t n;
+        double *d = field_ptr(h, bit, &n);
+        if (n) HIPCHK(hipMemcpyAsync(dst[bit], d, n * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    }
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return SOL_OK;
+}
+
+int sol_system_size(const sol_handle *h, int32_t system, int32_t *rows, int32_t *nnz)
+{
+    if (!h || !rows || !nnz) return fail(SOL_EINVAL, "NULL argument");
+    if (system < 0 || system >= NSYS) return fail(SOL_EINVAL, "bad system %d", system);
+    const Sizes &z = h->z;
+    const int *d = z.sdim[system];
+    const int64_t n = (int64_t)d[0] * d[1] * d[2];
+    int64_t k = n;
+    if (n) {
+        k += 2 * ((int64_t)(d[0] - 1) * d[1] * d[2] + (int64_t)d[0] * (d[1] - 1) * d[2]);
+        if (z.dim == 3) k += 2 * (int64_t)d[0] * d[1] * (d[2] - 1);
+    }
+    *rows = (int32_t)n;
+    *nnz = (int32_t)k;
+    return SOL_OK;
+}
+
+int sol_assemble(sol_handle *h, uint32_t mask)
+{
+    if (!h) return fail(SOL_EINVAL, "NULL handle");
+    if (mask & ~((1u << NSYS) - 1)) return fail(SOL_EINVAL, "unknown system bits");
+    if (h->batch) return fail(SOL_EBUSY, "handle is part of a batch");
+    Group &g = *h->solo;
+    hipStream_t s = h->stream;
+    const int gi = h->z.dim == 3 ? 1 : 0;
+    const int dim = h->z.dim;
+    if (mask & 7u) launch_asm_momentum(dim, g.cases_d, g.t_mom[gi], g.n_mom[gi], s);
+    if (mask & (1u << SP)) {
+        launch_div_rhs(dim, g.cases_d, g.t_cell[gi], g.n_cell[gi], 0, s);
+        launch_sub_mean(g.cases_d, g.t_cell[gi], g.n_cell[gi], s);
+    }
+    if (mask & ((1u << SC) | (1u << ST))) launch_asm_transport(dim, g.cases_d, g.t_cell[gi], g.n_cell[gi], 0, s);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));
+    return SOL_OK;
+}
+
+int sol_read_matrix(sol_handle *h, int32_t system, int32_t *row_ptr, int32_t *col_idx, double *val, double *rhs)
+{
+    if (!h || !row_ptr || !col_idx || !val || !rhs) return fail(SOL_EINVAL, "NULL argument");
+    if (system < 0 || system >= NSYS) return fail(SOL_EINVAL, "bad system %d", system);
+    int32_t n, nnz;
+    RCHK(sol_system_size(h, system, &n, &nnz));
+    if (n == 0) { row_ptr[0] = 0; return SOL_OK; }
+    const bool build = h->csr_rp[system] == nullptr;
+    if (build) {
+        if (!h->csr_cnt) HIPCHK(hipMalloc(&h->csr_cnt, sizeof(int32_t) * h->z.maxn));
+        HIPCHK(hipMalloc(&h->csr_rp[system], sizeof(int32_t) * (n + 1)));
+        HIPCHK(hipMalloc(&h->csr_col[system], sizeof(int32_t) * nnz));
+        HIPCHK(hipMalloc(&h->csr_val[system], sizeof(double) * nnz));
+    }
+    // device descriptor of this case (solo group entry 0)
+    launch_csr(h->z.dim, h->solo->cases_d, system, n, h->csr_cnt, h->csr_rp[system], h->csr_col[system],
+               h->csr_val[system], build ? 1 : 0, h->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(row_ptr, h->csr_rp[system], sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipMemcpyAsync(col_idx, h->csr_col[system], sizeof(int32_t) * nnz, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipMemcpyAsync(val, h->csr_val[system], sizeof(double) * nnz, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipMemcpyAsync(rhs, h->cd.b[system], sizeof(double) * n, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return SOL_OK;
+}
+
+static int fill_stats(Group &g, int c, sol_step_stats *st, const int64_t *tot)
+{
+    sol_handle *h = g.cs[c];
+    KState ks[NSYS];
+    double red[16];
+    int64_t step = 0;
+    HIPCHK(hipMemcpyAsync(ks, g.ks_d + c * NSYS, sizeof(ks), hipMemcpyDeviceToHost, g.stream));
+    HIPCHK(hipMemcpyAsync(red, g.red_d + 16 * c, sizeof(red), hipMemcpyDeviceToHost, g.stream));
+    HIPCHK(hipMemcpyAsync(&step, h->cd.step, sizeof(step), hipMemcpyDeviceToHost, g.stream));
+    HIPCHK(hipStreamSynchronize(g.stream));
+    std::memset(st, 0, sizeof(*st));
+    for (int s = 0; s < NSYS; ++s) {
+        if (h->z.nsys[s] == 0) continue;
+        st->iters[s] = ks[s].it;
+        st->iters_total[s] = tot ? tot[s] : ks[s].it;
+        st->rel_resid[s] = ks[s].bb > 0 ? std::sqrt(ks[s].tr2 / ks[s].bb) : 0.0;
+        st->sum_resid[s] = ks[s].tsum;
+    }
+    st->sum_C = red[R_SUMC];
+    st->sum_H = red[R_SUMH];
+    st->wall_flux = red[R_WALL];
+    st->div_star = red[R_DIVSTAR];
+    st->div_new = red[R_DIVNEW];
+    st->step = step;
+    return SOL_OK;
+}
+
+int sol_step(sol_handle *h, int32_t nsteps, sol_step_stats *stats)
+{
+    if (!h) return fail(SOL_EINVAL, "NULL handle");
+    if (nsteps < 0) return fail(SOL_EINVAL, "nsteps must be >= 0");
+    if (h->batch) return fail(SOL_EBUSY, "handle is part of a batch");
+    Group &g = *h->solo;
+    g.timer = h->timing ? h : nullptr;
+    int64_t tot[NSYS] = {};
+    for (int k = 0; k < nsteps; ++k) {
+        int rc = group_step(g);
+        if (rc != SOL_OK) {
+            (void)hipStreamSynchronize(h->stream);
+            return rc;
+        }
+        for (int s = 0; s < NSYS; ++s) tot[s] += h->last_iters[s];
+        if (g.timer) {
+            HIPCHK(hipStreamSynchronize(h->stream));
+            collect_samples(g, nullptr, nullptr);
+        }
+    }
+    if (stats) RCHK(fill_stats(g, 0, stats, tot));
+    else HIPCHK(hipStreamSynchronize(h->stream));
+    return SOL_OK;
+}
+
+int sol_set_timing(sol_handle *h, int32_t enable)
+{
+    if (!h) return fail(SOL_EINVAL, "NULL handle");
+    h->timing = enable != 0;
+    for (auto &t : h->tacc) t = TAcc();
+    return SOL_OK;
+}
+
+int sol_get_timing(sol_handle *h, int32_t kclass, int64_t *launches, double *total_ms, double *bytes)
+{
+    if (!h || !launches || !total_ms || !bytes) return fail(SOL_EINVAL, "NULL argument");
+    if (kclass < 0 || kclass >= SOL_NKCLASS) return fail(SOL_EINVAL, "bad kernel class");
+    *launches = h->tacc[kclass].n;
+    *total_ms = h->tacc[kclass].ms;
+    *bytes = h->tacc[kclass].bytes;
+    return SOL_OK;
+}
+
+// ------------------------------------------------------------------ batches
+
+struct sol_batch {
+    std::vector<sol_handle *> cs;
+    Group *g = nullptr;                  // group over the currently active cases
+    std::vector<int> active;
+};
+
+int sol_batch_create(sol_handle *const *cases, int32_t n, sol_batch **out)
+{
+    if (!cases || !out || n < 1) return fail(SOL_EINVAL, "bad batch arguments");
+    *out = nullptr;
+    for (int i = 0; i < n; ++i) {
+        if (!cases[i]) return fail(SOL_EINVAL, "NULL handle %d", i);
+        if (cases[i]->batch) return fail(SOL_EBUSY, "handle %d already in a batch", i);
+        if (cases[i]->stream != cases[0]->stream) return fail(SOL_EINVAL, "handles must share one stream");
+        for (int j = 0; j < i; ++j)
+            if (cases[j] == cases[i]) return fail(SOL_EINVAL, "handle %d given twice", i);
+    }
+    sol_batch *b = new sol_batch();
+    b->cs.assign(cases, cases + n);
+    for (auto *h : b->cs) h->batch = b;
+    *out = b;
+    return SOL_OK;
+}
+
+void sol_batch_destroy(sol_batch *b)
+{
+    if (!b) return;
+    if (!b->cs.empty()) (void)hipStreamSynchronize(b->cs[0]->stream);
+    group_free(b->g);
+    for (auto *h : b->cs) h->batch = nullptr;
+    delete b;
+}
+
+int sol_batch_step(sol_batch *b, const int32_t *nsteps, sol_step_stats *stats)
+{
+    if (!b || !nsteps) return fail(SOL_EINVAL, "NULL argument");
+    const int n = (int)b->cs.size();
+    int mx = 0;
+    for (int i = 0; i < n; ++i) {
+        if (nsteps[i] < 0) return fail(SOL_EINVAL, "nsteps[%d] < 0", i);
+        mx = std::max(mx, (int)nsteps[i]);
+    }
+    std::vector<int64_t> tot((size_t)n * NSYS, 0);
+    for (int k = 0; k < mx; ++k) {
+        std::vector<int> act;
+        for (int i = 0; i < n; ++i) if (nsteps[i] > k) act.push_back(i);
+        if (act != b->active || !b->g) {
+            if (b->g) { (void)hipStreamSynchronize(b->cs[0]->stream); group_free(b->g); b->g = nullptr; }
+            std::vector<sol_handle *> hs;
+            for (int i : act) hs.push_back(b->cs[i]);
+            RCHK(group_create(hs, &b->g));
+            b->active = act;
+        }
+        b->g->timer = nullptr;
+        int rc = group_step(*b->g);
+        if (rc != SOL_OK) { (void)hipStreamSynchronize(b->cs[0]->stream); return rc; }
+        for (size_t a = 0; a < act.size(); ++a)
+            for (int s = 0; s < NSYS; ++s) tot[(size_t)act[a] * NSYS + s] += b->cs[act[a]]->last_iters[s];
+    }
+    if (stats && b->g) {
+        for (size_t a = 0; a < b->active.size(); ++a)
+            RCHK(fill_stats(*b->g, (int)a, &stats[b->active[a]], &tot[(size_t)b->active[a] * NSYS]));
+    }
+    HIPCHK(hipStreamSynchronize(b->cs[0]->stream));
+    return SOL_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,25 @@
+// Launchers of the step kernels (defined in kernels.hip).
+#pragma once
+#include "sol_dev.hpp"
+
+namespace sol {
+
+void launch_asm_const(int dim, const CaseDev *c, const Tile *t, int nt, hipStream_t s);
+void launch_asm_momentum(int dim, const CaseDev *c, const Tile *t, int nt, hipStream_t s);
+void launch_asm_transport(int dim, const CaseDev *c, const Tile *t, int nt, int vel_src, hipStream_t s);
+void launch_div_rhs(int dim, const CaseDev *c, const Tile *t, int nt, int vel_src, hipStream_t s);
+void launch_sub_mean(const CaseDev *c, const Tile *t, int nt, hipStream_t s);
+void launch_project(const CaseDev *c, const Tile *t, int nt, hipStream_t s);
+void launch_phase_commit(int dim, const CaseDev *c, const Tile *t, int nt, hipStream_t s);
+
+void launch_kinit(int nd, const KJob *j, const JTile *t, int nt, int flip, int mode, hipStream_t s);
+void launch_kfinish(int nd, const KJob *j, const JTile *t, int nt, hipStream_t s);
+enum KIter { KI_CG_A = 0, KI_CG_B = 1, KI_BICG_A = 2, KI_BICG_B = 3, KI_BICG_C = 4 };
+void launch_kiter(int which, int nd, const KJob *j, const JTile *t, int nt, int flip, hipStream_t s);
+
+void launch_csr(int dim, const CaseDev *cd, int s, int n, int32_t *cnt, int32_t *row_ptr, int32_t *col,
+                double *val, int build_pattern, hipStream_t st);
+void launch_fill(double *x, double v, int n, hipStream_t s);
+void launch_set_status(KState *st, int n, int status, hipStream_t s);
+
+}  // namespace sol

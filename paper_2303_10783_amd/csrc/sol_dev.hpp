@@ -1,0 +1,95 @@
+// Internal descriptors shared by the kernels and the host engine of the
+// solidification step library (gfx950).  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sol {
+
+constexpr int TILE = 256;          // rows per workgroup (4 wave64)
+constexpr int NXCD = 8;            // MI355X: 8 XCDs, workgroups dealt round-robin
+
+enum System { SU = 0, SV = 1, SW = 2, SP = 3, SC = 4, ST = 5, NSYS = 6 };
+
+// Krylov status codes (KState::status)
+enum KStatus {
+    K_RUNNING = 0, K_CONVERGED = 1, K_FAILED = 2, K_RESTART = 3, K_DONE = 4,
+    K_ZERO = 5,      // ||b|| = 0: x = 0 by definition
+    K_IDLE = 6,      // not part of the current solve
+    K_NONFINITE = 7
+};
+
+enum KKind { K_CG = 0, K_BICGSTAB = 1 };
+
+// Per-solve device scalars.  Written only by the last-arriving workgroup of
+// a kernel (or by init kernels), read by the next kernel on the stream.
+struct KState {
+    double rho, rho_old, alpha, omega, beta;
+    double bb, rr, tr2, tsum, xsum, bmean;
+    double tol2;
+    int32_t it, status, max_iter, restarts;
+    uint32_t cnt;      // arrival counter of the last-block reduction
+    int32_t pad[3];
+};
+
+// Physical / geometric constants of one case (immutable after create).
+struct Phys {
+    int32_t dim, nx, ny, nz;
+    int32_t ncell;
+    int32_t nsys[NSYS];
+    int32_t sdim[NSYS][3];
+    double h[3], ih[3], ih2[3];
+    double rho, mu, nu, dt, idt, alpha, lam, kp, Tm, msp, Ce, Tref, Cref;
+    double grav, betaT, betaC, lambda2, eps, rcp, kcond;
+    int32_t thermal[6], slip[6];
+    double hc[6], Text[6], Tw0[6], Tramp[6];
+};
+
+// Device pointers of one case.
+struct CaseDev {
+    Phys ph;
+    // level-n state (updated in place by the commit at the end of a step)
+    double *u, *v, *w, *p, *T, *C, *gl, *Cl, *Cs;
+    // step intermediates
+    double *us[3];            // u* (momentum predictor)
+    double *un[3];            // u^{n+1} (projected), committed to u, v, w
+    double *phi, *Cnew, *Tstar;
+    // systems, DIA storage: A[s][slot*n + row], slot order -sxy,-sx,-1,0,+1,+sx,+sxy
+    double *A[NSYS], *b[NSYS], *minv[NSYS];
+    double *Ac[NSYS];         // constant (offline) parts of U, V, W, T; P uses A[SP]
+    // mixed precision copies (FP32) of matrices and inverse diagonals
+    float *A32[NSYS], *minv32[NSYS];
+    int64_t *step;            // completed steps (device counter)
+    KState *ks;               // [NSYS] solver states of this case
+    double *red;              // [16] per-case reduction results
+    double *red_part;         // [ntile_cell * 4] reduction partials
+    uint32_t *red_cnt;        // [2] arrival counters
+    int32_t ntile_cell;
+};
+
+// Reduction result slots in CaseDev::red
+enum RedSlot { R_SUMB = 0, R_DIVSTAR = 1, R_SUMC = 2, R_SUMH = 3, R_WALL = 4, R_DIVNEW = 5 };
+
+// One linear solve.
+struct KJob {
+    int32_t n, sx, sxy, ntile;
+    int32_t kind;             // KKind
+    int32_t pad;
+    const double *A, *b, *minv;
+    double *x;
+    const double *x0;         // initial guess copied into x on a fresh start (NULL: x = 0)
+    double *r, *rh, *p0, *p1, *v0, *v1, *t;
+    double *part;             // [ntile * 4]
+    KState *st;
+    // mixed precision: FP32 operator and work vectors for the inner solve
+    const float *A32, *minv32;
+    float *r32, *rh32, *p032, *p132, *v032, *v132, *t32, *x32;
+};
+
+// Tile of a per-row kernel: case, system (or component), tile within it.
+struct Tile { int32_t c, s, t, pad; };
+struct JTile { int32_t j, t; };
+
+__host__ __device__ inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
+
+}  // namespace sol

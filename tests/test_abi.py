@@ -1,0 +1,90 @@
+"""CPU checks of the C ABI: the library loads, exports every symbol the header
+declares, and rejects invalid arguments before any device work."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sol.h")
+
+
+@pytest.fixture(scope="module")
+def sol():
+    import paper_2303_10783_amd as sol
+    from paper_2303_10783_amd import build as b
+    if not os.path.exists(b.OUT):
+        b.build()
+    sol.load()
+    return sol
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(sol_[a-z_]+)\s*\(", txt)))
+
+
+def test_exports_every_declared_symbol(sol):
+    L = sol.load()
+    names = _declared()
+    assert "sol_create" in names and "sol_step" in names and "sol_batch_step" in names
+    for n in names:
+        assert hasattr(L, n), n
+    from paper_2303_10783_amd import binding
+    assert sorted(binding.exported_symbols()) == names
+
+
+def _structs(sol, case):
+    from paper_2303_10783_amd import binding
+    return binding.make_structs(case)
+
+
+@pytest.mark.parametrize("mutate,field", [
+    (lambda c: c["grid"].update(nx=1), "nx"),
+    (lambda c: c["grid"].update(dim=4), "dim"),
+    (lambda c: c["numerics"].update(dt=0.0), "dt"),
+    (lambda c: c["numerics"].update(dt=float("nan")), "dt"),
+    (lambda c: c["numerics"].update(tol_p=0.0), "tolerance"),
+    (lambda c: c["numerics"].update(max_iter=0), "max_iter"),
+    (lambda c: c["alloy"].update(k_p=1.2), "k_p"),
+    (lambda c: c["alloy"].update(m_sp=2.33), "m_sp"),
+    (lambda c: c["alloy"].update(rho=-1.0), "rho"),
+    (lambda c: c["alloy"].update(D_l=1e-9), "D_l"),
+    (lambda c: c["bcs"][0].update(h=-5.0), "Robin"),
+    (lambda c: c["grid"].update(lx=0.0), "lengths"),
+])
+def test_invalid_arguments_rejected_before_device_work(sol, mutate, field):
+    from paper_2303_10783_amd import binding
+    case = W.cavity_2d(8, 6)
+    mutate(case)
+    grid, alloy, bcs, num = binding.make_structs(case)
+    h = C.c_void_p()
+    rc = sol.load().sol_create(C.byref(grid), C.byref(alloy), C.byref(bcs), C.byref(num), None, C.byref(h))
+    assert rc == binding.SOL_EINVAL
+    assert h.value is None
+    assert sol.load().sol_last_error().decode()
+
+
+def test_null_arguments(sol):
+    from paper_2303_10783_amd import binding
+    L = sol.load()
+    h = C.c_void_p()
+    assert L.sol_create(None, None, None, None, None, C.byref(h)) == binding.SOL_EINVAL
+    assert L.sol_step(None, 1, None) == binding.SOL_EINVAL
+    assert L.sol_read_fields(None, 1, None) == binding.SOL_EINVAL
+    assert L.sol_batch_create(None, 0, C.byref(h)) == binding.SOL_EINVAL
+    L.sol_destroy(None)
+    L.sol_batch_destroy(None)
+
+
+def test_footprint_scales_with_cells(sol):
+    f1 = sol.sol_footprint_bytes(W.cavity_2d(100, 60))
+    f2 = sol.sol_footprint_bytes(W.cavity_2d(200, 120))
+    f3 = sol.sol_footprint_bytes(W.box_3d(32, 32, 32))
+    assert 3.5 < f2 / f1 < 4.5
+    assert 300 < f2 / (200 * 120) < 1500          # bytes per cell, 2D
+    assert f3 / 32 ** 3 > f2 / (200 * 120)         # 3D stores 7 diagonals

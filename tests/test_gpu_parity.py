@@ -1,0 +1,327 @@
+"""GPU parity of the HIP path (through the C ABI) against the FP64 oracle.
+
+Bars: sparsity patterns bit-exact; assembled values within 16 ulp of the row
+scale (same formulas, different summation order); fields after N steps
+within 1e-9 relative L2 (solver tolerance 1e-13 on both sides, so the
+Krylov stopping points cannot separate them); full-size workloads checked
+stage by stage on the oracle's own assembly of the GPU's inputs."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+EPS = np.finfo(float).eps
+FIELDS = ("u", "v", "w", "p", "T", "C", "gl", "Cl", "Cs")
+
+
+@pytest.fixture(scope="module")
+def sol():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_2303_10783_amd as sol
+    sol.load()
+    return sol
+
+
+@pytest.fixture(scope="module")
+def dev(sol):
+    return sol.TorchDevice(0)
+
+
+def rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    if a.size == 0:
+        return 0.0
+    den = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / den if den > 0 else np.linalg.norm(a - b)
+
+
+def field_errors(got, ref):
+    out = {}
+    for k in FIELDS:
+        a, b = got[k], ref[k]
+        if len(b) == 0 or (k == "w" and len(a) == 0):
+            continue
+        if k == "p":
+            a, b = a - a.mean(), b - b.mean()
+        out[k] = rel(a, b)
+    return out
+
+
+def perturbed(case, seed=11):
+    rng = np.random.default_rng(seed)
+    f = {k: np.array(v, dtype=np.float64, copy=True) for k, v in case["init"].items()}
+    for k in ("u", "v", "w"):
+        f[k] = rng.uniform(-2e-3, 2e-3, f[k].size)
+    n = f["T"].size
+    f["gl"] = rng.uniform(0.0, 1.0, n)
+    f["p"] = rng.uniform(-2.0, 2.0, n)
+    f["T"] = f["T"] + rng.uniform(-20.0, 5.0, n)
+    f["C"] = f["C"] + rng.uniform(-1.0, 1.0, n)
+    f["Cl"] = f["C"] / (f["gl"] + case["alloy"]["k_p"] * (1 - f["gl"]))
+    return f
+
+
+def compare_system(sol_case, orc, sysid, vel):
+    rp, ci, va, rhs = sol_case.read_matrix(sysid)
+    A, b, orp, oci = orc.assemble(sysid, vel=vel)
+    assert np.array_equal(rp, orp), f"row_ptr differs for system {sysid}"
+    assert np.array_equal(ci, oci), f"col_idx differs for system {sysid}"
+    scale = np.add.reduceat(np.abs(A.data), A.indptr[:-1]) + np.abs(b) if A.shape[0] else np.zeros(0)
+    dv = np.abs(va - A.data)
+    drow = np.add.reduceat(dv, A.indptr[:-1]) if A.shape[0] else np.zeros(0)
+    assert np.all(drow <= 16 * EPS * scale), (sysid, (drow / scale).max())
+    assert np.all(np.abs(rhs - b) <= 16 * EPS * scale), (sysid, (np.abs(rhs - b) / scale).max())
+
+
+def _cases_small():
+    c2 = W.cavity_2d(37, 23, seed=5)
+    c2fs = W.cavity_2d(19, 11, seed=6)
+    for bc in c2fs["bcs"]:
+        bc["velocity"] = W.VELOCITY_FREESLIP
+    c2fs["bcs"][3] = W.face_bc(W.THERMAL_DIRICHLET, T0=470.0, b=0.3, velocity=W.VELOCITY_FREESLIP)
+    c3 = W.box_3d(13, 9, 6, lx=0.013, ly=0.009, lz=0.006, seed=7)
+    c3["bcs"][5] = W.face_bc(W.THERMAL_ROBIN, h=150.0, T_ext=350.0)
+    return [c2, c2fs, c3]
+
+
+@pytest.mark.parametrize("case", _cases_small(), ids=["2d-37x23", "2d-freeslip-dirichlet", "3d-13x9x6"])
+def test_assembly_pattern_and_values(sol, dev, case):
+    f = perturbed(case)
+    g = sol.Case(case, device=dev, write_init=False)
+    g.write_fields(f)
+    g.assemble(0x3F)
+    orc = oracle.Oracle(case, fields=f)
+    vel = (f["u"], f["v"], f["w"] if f["w"].size else np.zeros(1))
+    for s in range(6):
+        if case["grid"]["dim"] == 2 and s == 2:
+            continue
+        compare_system(g, orc, s, vel if s >= 3 else None)
+    g.close()
+
+
+def _step_cases():
+    out = []
+    c = W.cavity_2d(37, 23, tol=1e-13, seed=1)
+    out.append(("2d-37x23", c, 6))
+    c = W.cavity_2d(19, 11, tol=1e-13, seed=2)
+    for bc in c["bcs"]:
+        bc["velocity"] = W.VELOCITY_FREESLIP
+    c["bcs"][2] = W.face_bc(W.THERMAL_DIRICHLET, T0=440.0, b=1.0, velocity=W.VELOCITY_FREESLIP)
+    out.append(("2d-freeslip-ramp", c, 5))
+    c = W.make_case(2, 40, 1, 1, 0.04, 0.001, 1.0, dT_amp=0.0, tol_p=1e-13, tol_t=1e-13)
+    c["bcs"][0] = W.face_bc(W.THERMAL_DIRICHLET, T0=400.0, b=0.0)
+    out.append(("1d-ny1", c, 8))
+    c = W.cavity_2d(2, 3, lx=0.004, ly=0.006, tol=1e-13, seed=4)
+    out.append(("2d-min-2x3", c, 4))
+    c = W.box_3d(9, 7, 5, lx=0.009, ly=0.007, lz=0.005, tol=1e-13, seed=3)
+    out.append(("3d-9x7x5", c, 4))
+    c = W.box_3d(17, 11, 6, lx=0.017, ly=0.011, lz=0.006, tol=1e-13, seed=8)
+    out.append(("3d-17x11x6", c, 3))
+    return out
+
+
+@pytest.mark.parametrize("name,case,nsteps", _step_cases(), ids=[x[0] for x in _step_cases()])
+def test_steps_match_oracle(sol, dev, name, case, nsteps):
+    print(f"[gpu] step parity {name}: {nsteps} steps", flush=True)
+    g = sol.Case(case, device=dev)
+    o = oracle.Oracle(case)
+    st = g.step(nsteps - 1)
+    o.step(nsteps - 1)
+    st = g.step(1)
+    o.step(1, keep_intermediate=True)
+    errs = field_errors(g.read_fields(), o.fields())
+    assert max(errs.values()) < 1e-9, errs
+    inter = g.read_fields(("ustar", "vstar", "wstar", "phi", "Tstar"))
+    oi = o.intermediate
+    assert rel(inter["ustar"], oi["u"]) < 1e-9
+    assert rel(inter["vstar"], oi["v"]) < 1e-9 or oi["v"].size == 0
+    if case["grid"]["dim"] == 3:
+        assert rel(inter["wstar"], oi["w"]) < 1e-9
+    assert rel(inter["Tstar"], oi["Tstar"]) < 1e-12
+    # converged on the true residual
+    for s in range(6):
+        assert st["rel_resid"][s] <= 1e-13 * (1 + 1e-6)
+    g.close()
+
+
+def test_cavity_50x30_200_steps(sol, dev):
+    """The 50x30 cavity (cooled west wall, Sn-10%Pb-type constants), 200 steps:
+    GPU vs oracle at solver tolerance 1e-12 (gate 1e-9), and the spread at the
+    workload tolerance 1e-10 reported (bounded by 1e-6)."""
+    case = W.cavity_2d(50, 30, tol=1e-12, seed=0)
+    print("[gpu] 50x30 cavity, 200 steps, tol 1e-12", flush=True)
+    g = sol.Case(case, device=dev)
+    o = oracle.Oracle(case)
+    st = g.step(200)
+    o.step(200)
+    errs = field_errors(g.read_fields(), o.fields())
+    print("rel L2 (tol 1e-12):", {k: f"{v:.1e}" for k, v in errs.items()})
+    assert max(errs.values()) < 1e-9, errs
+    assert (g.read_fields()["gl"] < 1).any()        # solidification has started
+    g.close()
+    case = W.cavity_2d(50, 30, tol=1e-10, seed=0)
+    g = sol.Case(case, device=dev)
+    o = oracle.Oracle(case)
+    g.step(200)
+    o.step(200)
+    errs = field_errors(g.read_fields(), o.fields())
+    print("rel L2 (tol 1e-10):", {k: f"{v:.1e}" for k, v in errs.items()})
+    assert max(errs.values()) < 1e-6, errs
+    g.close()
+
+
+def test_conservation_and_divergence_on_gpu(sol, dev):
+    """Residual-corrected solute and energy balances per step to 1e-12 from
+    the GPU's own reductions; ||D u^{n+1}|| = (dt/rho) ||r_p|| bound."""
+    case = W.cavity_2d(64, 40, tol=1e-10, seed=9)
+    g = sol.Case(case, device=dev)
+    lam = case["alloy"]["latent"] / case["alloy"]["cp"]
+    dt = case["numerics"]["dt"]
+    f = g.read_fields()
+    C0, H0 = f["C"].sum(), (f["T"] + lam * f["gl"]).sum()
+    for _ in range(8):
+        st = g.step(1)
+        assert abs(st["sum_C"] - C0 + dt * st["sum_resid"][4]) <= 1e-12 * abs(C0)
+        assert abs(st["sum_H"] - H0 + dt * st["wall_flux"] + dt * st["sum_resid"][5]) <= 1e-12 * abs(H0)
+        f = g.read_fields()
+        assert abs(f["C"].sum() - st["sum_C"]) <= 1e-13 * abs(C0)
+        C0, H0 = st["sum_C"], st["sum_H"]
+        assert st["div_new"] <= 1e-9 * max(st["div_star"], 1e-300) + 1e-300
+    g.close()
+
+
+def test_zero_rhs_and_rest_state(sol, dev):
+    """No buoyancy: the momentum right-hand sides vanish (x = 0 by
+    definition), the melt stays at rest and C stays uniform."""
+    al = W.sn10pb_alloy(beta_T=0.0, beta_C=0.0)
+    case = W.make_case(2, 20, 12, 1, 0.02, 0.012, 1.0, alloy=al, bcs=W.west_cooled_bcs())
+    g = sol.Case(case, device=dev)
+    st = g.step(3)
+    f = g.read_fields()
+    assert not f["u"].any() and not f["v"].any()
+    assert np.all(f["C"] == case["C0"])
+    assert st["iters"][0] == 0 and st["iters"][1] == 0
+    g.close()
+
+
+def test_no_convergence_rolls_back(sol, dev):
+    import paper_2303_10783_amd.binding as B
+    case = W.cavity_2d(30, 20, max_iter=1)
+    g = sol.Case(case, device=dev)
+    before = g.read_fields()
+    with pytest.raises(B.SolError) as e:
+        g.step(1)
+    assert e.value.code == B.SOL_ENOCONV
+    after = g.read_fields()
+    for k in FIELDS:
+        assert np.array_equal(before[k], after[k]), k
+    g.close()
+
+
+def test_nonfinite_input_rejected(sol, dev):
+    import paper_2303_10783_amd.binding as B
+    case = W.cavity_2d(10, 8)
+    g = sol.Case(case, device=dev)
+    f = dict(case["init"])
+    f["T"] = f["T"].copy()
+    f["T"][17] = np.nan
+    with pytest.raises(B.SolError) as e:
+        g.write_fields({"T": f["T"]})
+    assert e.value.code == B.SOL_ENONFINITE
+    assert np.array_equal(g.read_fields(("T",))["T"], case["init"]["T"])
+    g.close()
+
+
+def test_batched_equals_alone_bitwise(sol, dev):
+    """Cases advanced together in one launch per kernel give bit-identical
+    fields to the same cases advanced alone (same tiles, same reduction
+    order)."""
+    cases = [W.cavity_2d(23, 17, seed=1), W.cavity_2d(41, 9, lx=0.041, ly=0.009, seed=2),
+             W.box_3d(8, 6, 5, lx=0.008, ly=0.006, lz=0.005, seed=3), W.cavity_2d(64, 30, seed=4)]
+    nsteps = [3, 2, 3, 1]
+    alone = []
+    for c, n in zip(cases, nsteps):
+        g = sol.Case(c, device=dev)
+        g.step(n)
+        alone.append(g.read_fields())
+        g.close()
+    gs = [sol.Case(c, device=dev) for c in cases]
+    b = sol.Batch(gs)
+    b.step(nsteps)
+    b.close()
+    for g, ref in zip(gs, alone):
+        got = g.read_fields()
+        for k in FIELDS:
+            assert np.array_equal(got[k], ref[k]), k
+        g.close()
+
+
+def test_torch_allocator_and_hipmalloc_agree(sol, dev):
+    case = W.cavity_2d(30, 20, seed=12)
+    a = sol.Case(case, device=dev)
+    b = sol.Case(case, device=None)
+    a.step(2)
+    b.step(2)
+    fa, fb = a.read_fields(), b.read_fields()
+    for k in FIELDS:
+        assert np.array_equal(fa[k], fb[k]), k
+    a.close()
+    b.close()
+
+
+def _stagewise(sol, dev, case, tag):
+    """One step of a full-size workload; each stage checked against the
+    oracle's assembly of the GPU's own inputs: momentum, pressure, solute and
+    energy residuals within the solver tolerance, the projection through the
+    divergence bound, and the phase update cell by cell."""
+    print(f"[gpu] stage-wise parity {tag}", flush=True)
+    g = sol.Case(case, device=dev)
+    g.step(2)                                    # develop a flow first
+    fn = g.read_fields()
+    st = g.step(1)
+    f1 = g.read_fields()
+    inter = g.read_fields(("ustar", "vstar", "wstar", "phi", "Tstar"))
+    orc = oracle.Oracle(case, fields=fn)
+    orc.step_index = st["step"] - 1
+    tol = case["numerics"]["tol_t"]
+    for s, xs in ((0, inter["ustar"]), (1, inter["vstar"]), (2, inter["wstar"])):
+        if case["grid"]["dim"] == 2 and s == 2:
+            continue
+        A, b, _, _ = orc.assemble(s)
+        assert np.linalg.norm(b - A @ xs) <= tol * np.linalg.norm(b) * (1 + 1e-6) + 1e-300
+    ustar = (inter["ustar"], inter["vstar"], inter["wstar"] if inter["wstar"].size else np.zeros(1))
+    A, b, _, _ = orc.assemble(3, vel=ustar)
+    phi = inter["phi"]
+    assert np.linalg.norm(b - A @ phi) <= case["numerics"]["tol_p"] * np.linalg.norm(b) * (1 + 1e-6)
+    unew = (f1["u"], f1["v"], f1["w"] if f1["w"].size else np.zeros(1))
+    A, b, _, _ = orc.assemble(4, vel=unew)
+    assert np.linalg.norm(b - A @ f1["C"]) <= tol * np.linalg.norm(b) * (1 + 1e-6)
+    A, b, _, _ = orc.assemble(5, vel=unew)
+    assert np.linalg.norm(b - A @ inter["Tstar"]) <= tol * np.linalg.norm(b) * (1 + 1e-6)
+    T, gl, Cl, Cs, br = orc.phase(inter["Tstar"], fn["gl"], f1["C"])
+    assert rel(f1["T"], T) < 1e-14 and np.abs(f1["gl"] - gl).max() < 1e-12
+    assert rel(f1["Cl"], Cl) < 1e-13 and rel(f1["Cs"], Cs) < 1e-13
+    np.testing.assert_allclose(f1["p"] - fn["p"], phi, rtol=0, atol=1e-12 * np.abs(fn["p"]).max() + 1e-300)
+    assert st["div_new"] <= 1e-9 * st["div_star"] + 1e-300
+    # assembly of the developed state, all systems, full size
+    g.assemble(0x3F)
+    orc2 = oracle.Oracle(case, fields=f1)
+    orc2.step_index = st["step"]
+    vel = (f1["u"], f1["v"], f1["w"] if f1["w"].size else np.zeros(1))
+    for s in range(6):
+        if case["grid"]["dim"] == 2 and s == 2:
+            continue
+        compare_system(g, orc2, s, vel if s >= 3 else None)
+    g.close()
+
+
+def test_full_size_500x300_stagewise(sol, dev):
+    _stagewise(sol, dev, W.workload_case("C2"), "500x300")
+
+
+def test_full_size_128x128x64_stagewise(sol, dev):
+    _stagewise(sol, dev, W.workload_case("C3"), "128x128x64")
