@@ -1,0 +1,138 @@
+"""Throughput of the full time step on one MI355X.
+
+Default workload: the 500x300 2D cavity (Sn-10%Pb-type alloy, west wall
+cooled by h = 400 W/m^2K to 298 K, PCG / BiCGSTAB tolerance 1e-10), FP64.
+A step is one pass of Algorithm 1 (momentum predictor, pressure
+correction, projection, solute, energy, phase update) through the HIP
+library; value = cells x steps / wall time of the timed steps, with the
+state resident on the device.
+
+Also printed in the same JSON line:
+  roofline      achieved algorithmic GB/s of the dominant kernel (HIP events
+                on the library's stream, sampled launches) against 8 TB/s;
+  cpu_baseline  the FP64 oracle on the host for a bounded number of steps.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "cell-updates/s per full time step (1 GPU), mixed vs FP64; p50/p99 case latency"
+HBM_PEAK_GBS = 8000.0
+
+
+def roofline(g, ncell_rows):
+    """Dominant kernel class by estimated time per step, from sampled events."""
+    best = None
+    for cls in ("cg_a", "cg_b", "bicg_a", "bicg_b", "bicg_c", "asm_mom", "asm_trn", "phase"):
+        t = g.timing(cls)
+        if t["launches"] == 0:
+            continue
+        t["avg_ms"] = t["ms"] / t["launches"]
+        t["bytes_per_launch"] = t["bytes"] / t["launches"]
+        t["gbs"] = t["bytes"] / (t["ms"] * 1e-3) / 1e9
+        t["cls"] = cls
+        # estimated share of the step: avg duration x launches per step
+        per_step = ncell_rows.get(cls, 1.0)
+        t["est_ms_per_step"] = t["avg_ms"] * per_step
+        if best is None or t["est_ms_per_step"] > best["est_ms_per_step"]:
+            best = t
+    return best
+
+
+def cpu_baseline(case, budget_s=12.0, max_steps=20):
+    import oracle
+    threads = min(16, os.cpu_count() or 1)
+    o = oracle.Oracle(case, threads=threads)
+    n = case["grid"]["nx"] * case["grid"]["ny"] * (case["grid"]["nz"] if case["grid"]["dim"] == 3 else 1)
+    t0 = time.perf_counter()
+    steps = 0
+    while steps < max_steps:
+        o.step(1)
+        steps += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return dict(value=n * steps / dt, unit="cell-updates/s", cores=threads, kind="oracle",
+                sample=f"first {steps} steps of the same workload from its initial state, "
+                       f"FP64 C oracle, {threads} OpenMP threads, {dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="C2", choices=["C1", "C2", "C3"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-roofline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(independent cases shard across GPUs without communication; not built here)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2303_10783_amd as sol
+    import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    case = W.workload_case(args.workload)
+    grid = case["grid"]
+    ncell = grid["nx"] * grid["ny"] * (grid["nz"] if grid["dim"] == 3 else 1)
+    dev = sol.TorchDevice(0)
+    g = sol.Case(case, device=dev)
+    if args.warmup:
+        g.step(args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = g.step(args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    secs = t1 - t0
+    value = ncell * args.steps / secs
+    iters = st["iters_total"]
+
+    roof = None
+    if not args.no_roofline:
+        g.set_timing(True)
+        st2 = g.step(2)
+        per = {k: max(1, st2["iters_total"][3] / 2) for k in ("cg_a", "cg_b")}
+        other = sum(st2["iters_total"][s] for s in (0, 1, 2, 4, 5)) / 2
+        per.update({k: max(1, other) for k in ("bicg_a", "bicg_b", "bicg_c")})
+        best = roofline(g, per)
+        g.set_timing(False)
+        if best:
+            roof = dict(bound="hbm", achieved=round(best["gbs"], 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                        frac=round(best["gbs"] / HBM_PEAK_GBS, 4), traffic=None,
+                        kernel=best["cls"], avg_us=round(best["avg_ms"] * 1e3, 2),
+                        bytes_per_launch=int(best["bytes_per_launch"]),
+                        timed_launches=int(best["launches"]))
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(case)
+    g.close()
+    out = dict(
+        metric=METRIC, value=value, unit="cell-updates/s", n_gpus=1, steps=args.steps,
+        warmup=args.warmup, ms_per_step=1e3 * secs / args.steps, higher_is_better=True,
+        scaling="weak", vs_baseline=None, dtype="f64", data="synthetic",
+        config=dict(workload=f"{args.workload}: 2D cavity {grid['nx']}x{grid['ny']}" if grid["dim"] == 2
+                    else f"{args.workload}: 3D box {grid['nx']}x{grid['ny']}x{grid['nz']}",
+                    cells=ncell, dt=case["numerics"]["dt"], tol=case["numerics"]["tol_p"],
+                    precision=args.precision, krylov_iters_per_step={
+                        n: round(iters[i] / args.steps, 1) for i, n in enumerate("uvwpCT")}),
+        roofline=roof, cpu_baseline=cpu,
+    )
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -2,9 +2,11 @@
 // memory, the time-step driver of Algorithm 1, the Krylov orchestration and
 // the C ABI declared in sol.h.
 //
-// Krylov orchestration: convergence is decided on the device (KState::status
-// written by the last workgroup of each iteration kernel; every kernel of a
-// solve that is no longer RUNNING returns at once).  The host queues
+// Krylov orchestration: convergence is decided on the device (every
+// workgroup of an iteration kernel totals the partial sums of the previous
+// kernel and takes the same decision; workgroup 0 records it in
+// KState::status; every kernel of a solve that is no longer RUNNING returns
+// at once).  The host queues
 // iterations in chunks and reads the status array through one lagging
 // event: while it inspects chunk k the device already runs chunk k+1, so the
 // GPU never waits for the host; the price is at most one chunk of no-op
@@ -125,6 +127,14 @@ static size_t footprint(const Sizes &z, int precision)
     return b;
 }
 
+// rows per tile of a solve: 1..8 rows per thread, aiming at <= ~384 tiles so
+// that the per-kernel totals of the partial sums stay cheap
+static int rows_per_tile(int n)
+{
+    const int m = std::max(1, std::min(8, ceil_div(n, TILE * 384)));
+    return TILE * m;
+}
+
 // ------------------------------------------------------------------ timing
 
 struct TSample { int cls; int64_t iter; int phase; hipEvent_t a, b; };
@@ -196,6 +206,7 @@ struct Group {
     CaseDev *cases_d = nullptr;
     KState *ks_d = nullptr;
     double *red_d = nullptr;
+    int32_t *cidx_d = nullptr;           // 0..n-1 (per-case one-workgroup kernels)
     Tile *t_mom[2] = {}, *t_cell[2] = {}, *t_const[2] = {};
     int n_mom[2] = {}, n_cell[2] = {}, n_const[2] = {};
     Phase ph[3];                          // momentum, pressure, solute + energy
@@ -270,6 +281,11 @@ static int group_build(Group &g)
         }
     }
     RCHK(upload(g, &g.cases_d, cdv));
+    {
+        std::vector<int32_t> ci(n);
+        for (int c = 0; c < n; ++c) ci[c] = c;
+        RCHK(upload(g, &g.cidx_d, ci));
+    }
     HIPCHK(hipMemcpy(g.ks_d, ksv.data(), sizeof(KState) * g.nks, hipMemcpyHostToDevice));
     for (int gi = 0; gi < 2; ++gi) {
         RCHK(upload(g, &g.t_mom[gi], mom[gi]));
@@ -297,7 +313,8 @@ static int group_build(Group &g)
                 J.n = h->z.nsys[s];
                 J.sx = h->z.sdim[s][0];
                 J.sxy = h->z.sdim[s][0] * h->z.sdim[s][1];
-                J.ntile = ceil_div(J.n, TILE);
+                J.rpt = rows_per_tile(J.n);
+                J.ntile = ceil_div(J.n, J.rpt);
                 J.kind = P.kind;
                 J.A = h->cd.A[s];
                 J.b = h->cd.b[s];
@@ -312,7 +329,7 @@ static int group_build(Group &g)
                 J.v0 = h->work[ws][4]; J.v1 = h->work[ws][5];
                 J.t = h->work[ws][6];
                 J.st = g.ks_d + c * NSYS + s;
-                part_total += (size_t)J.ntile * 4;
+                part_total += (size_t)J.ntile * 2 * NSLOT;
                 const int gi = h->z.nd == 7 ? 1 : 0;
                 const int jidx = (int)P.jobs.size();
                 for (int t = 0; t < J.ntile; ++t) jt[gi].push_back({jidx, t});
@@ -325,7 +342,7 @@ static int group_build(Group &g)
         double *part = (double *)gmalloc(g, sizeof(double) * std::max<size_t>(part_total, 1));
         if (!part) return fail(SOL_ENOMEM, "group allocation failed");
         size_t off = 0;
-        for (auto &J : P.jobs) { J.part = part + off; off += (size_t)J.ntile * 4; }
+        for (auto &J : P.jobs) { J.part = part + off; off += (size_t)J.ntile * 2 * NSLOT; }
         RCHK(upload(g, &P.jobs_d, P.jobs));
         for (int gi = 0; gi < 2; ++gi) {
             RCHK(upload(g, &P.tiles_d[gi], jt[gi]));
@@ -409,10 +426,10 @@ static void collect_samples(Group &g, Phase *P, const KState *ks)
 
 // ------------------------------------------------------------------ solves
 
-static void enqueue_iters(Group &g, Phase &P, int k, int &flip, int phase_id)
+static void enqueue_iters(Group &g, Phase &P, int nits, int &k, int phase_id)
 {
     sol_handle *tm = g.timer;
-    for (int it = 0; it < k; ++it) {
+    for (int it = 0; it < nits; ++it) {
         const bool sample = tm && (P.launched % 8 == 0);
         const int nk = P.kind == K_CG ? 2 : 3;
         for (int q = 0; q < nk; ++q) {
@@ -421,13 +438,13 @@ static void enqueue_iters(Group &g, Phase &P, int k, int &flip, int phase_id)
             if (sample) { a = take_event(tm); b = take_event(tm); }
             if (a && b) (void)hipEventRecord(a, g.stream);
             for (int gi = 0; gi < 2; ++gi)
-                launch_kiter(which, gi ? 7 : 5, P.jobs_d, P.tiles_d[gi], P.nt[gi], flip, g.stream);
+                launch_kiter(which, gi ? 7 : 5, P.jobs_d, P.tiles_d[gi], P.nt[gi], k, g.stream);
             if (a && b) {
                 (void)hipEventRecord(b, g.stream);
                 tm->samples.push_back({P.tcls0 + q, P.launched, phase_id, a, b});
             }
         }
-        flip ^= 1;
+        k += 1;
         P.launched += 1;
     }
 }
@@ -455,19 +472,19 @@ static bool any_status(const Group &g, const Phase &P, int slot, int status)
 static int group_solve(Group &g, Phase &P, int phase_id)
 {
     if (P.jobs.empty()) return SOL_OK;
-    int flip = 0;
+    int k = 0;                       // host iteration index of the next launch
     P.launched = 0;
     for (int gi = 0; gi < 2; ++gi)
-        launch_kinit(gi ? 7 : 5, P.jobs_d, P.tiles_d[gi], P.nt[gi], flip, 0, g.stream);
+        launch_kinit(gi ? 7 : 5, P.jobs_d, P.tiles_d[gi], P.nt[gi], k, 0, g.stream);
     int rc = SOL_OK;
     for (int round = 0; round < 64; ++round) {
         int slot = 0;
         const int first = round == 0 ? std::max(1, P.pred - P.pred / 8) : std::max(2, P.pred / 8);
         const int later = std::max(2, P.pred / 16);
-        enqueue_iters(g, P, first, flip, phase_id);
+        enqueue_iters(g, P, first, k, phase_id);
         RCHK(poll_enqueue(g, slot));
         for (;;) {
-            enqueue_iters(g, P, later, flip, phase_id);
+            enqueue_iters(g, P, later, k, phase_id);
             RCHK(poll_enqueue(g, slot ^ 1));
             RCHK(poll_wait(g, slot));
             if (!any_status(g, P, slot, K_RUNNING)) { RCHK(poll_wait(g, slot ^ 1)); break; }
@@ -475,6 +492,7 @@ static int group_solve(Group &g, Phase &P, int phase_id)
         }
         for (int gi = 0; gi < 2; ++gi)
             launch_kfinish(gi ? 7 : 5, P.jobs_d, P.tiles_d[gi], P.nt[gi], g.stream);
+        launch_kdecide(P.jobs_d, (int)P.jobs.size(), g.stream);
         RCHK(poll_enqueue(g, 0));
         RCHK(poll_wait(g, 0));
         HIPCHK(hipGetLastError());
@@ -482,14 +500,14 @@ static int group_solve(Group &g, Phase &P, int phase_id)
         if (any_status(g, P, 0, K_FAILED)) { rc = fail(SOL_ENOCONV, "linear solve did not converge within max_iter"); break; }
         if (!any_status(g, P, 0, K_RESTART)) break;
         for (int gi = 0; gi < 2; ++gi)
-            launch_kinit(gi ? 7 : 5, P.jobs_d, P.tiles_d[gi], P.nt[gi], flip, 1, g.stream);
+            launch_kinit(gi ? 7 : 5, P.jobs_d, P.tiles_d[gi], P.nt[gi], k, 1, g.stream);
         if (round == 63) rc = fail(SOL_ENOCONV, "linear solve kept restarting");
     }
     int mx = 1;
     for (size_t j = 0; j < P.jobs.size(); ++j) {
-        const KState &k = g.ks_h[0][P.st_index[j]];
-        mx = std::max(mx, (int)k.it);
-        g.cs[P.case_of[j]]->last_iters[P.sys_of[j]] = k.it;
+        const KState &ks = g.ks_h[0][P.st_index[j]];
+        mx = std::max(mx, (int)ks.it);
+        g.cs[P.case_of[j]]->last_iters[P.sys_of[j]] = ks.it;
     }
     P.pred = mx;
     if (g.timer) collect_samples(g, &P, g.ks_h[0]);
@@ -536,6 +554,7 @@ static int group_step(Group &g)
     timed(g, SOL_KCLASS_PHASE, [&] {
         for (int gi = 0; gi < 2; ++gi) launch_phase_commit(gi ? 3 : 2, g.cases_d, g.t_cell[gi], g.n_cell[gi], s);
     });
+    launch_case_stats(g.cases_d, g.cidx_d, (int)g.cs.size(), s);
     HIPCHK(hipGetLastError());
     return SOL_OK;
 }

@@ -5,9 +5,9 @@
 // Launch model: every per-row kernel walks a table of tiles (256 rows each)
 // covering one or many cases; workgroup b takes tile xcd_tile(b) so that the
 // tiles one XCD executes are contiguous in memory (its L2 then holds the
-// y/z neighbour rows of its own tiles).  Reductions finish in the
-// last-arriving workgroup of the tile range of each case / solve, in a fixed
-// order (deterministic, independent of which workgroup arrives last).
+// y/z neighbour rows of its own tiles).  Reductions: per-workgroup partial
+// sums, totalled in a fixed order by the next kernel (deterministic; no
+// device-scope fences, which on gfx950 would write back the whole L2).
 #include "sol_dev.hpp"
 #include "kernels.hpp"
 
@@ -48,44 +48,46 @@ __device__ __forceinline__ void block_sum(double (&v)[K], double *sh)
     __syncthreads();
 }
 
-// Block partial sums -> part[ltile]; the last of `ntile` arriving workgroups
-// sums all partials in tile order and returns true with the totals in tot
-// (valid in every thread of that workgroup).  The arrival counter is reset
-// by the last workgroup.
+// Reductions.  A kernel writes one partial sum per workgroup (plain stores);
+// the next kernel on the stream (kernel boundaries make them visible) sums
+// the partials of the tiles it needs in tile order, every workgroup in the
+// same order, so all workgroups obtain bit-identical totals and no
+// device-scope fence or atomic is needed.
+
+// block totals of K values -> part[off[k] + t] (written by thread 0)
 template <int K>
-__device__ bool arrive(double (&v)[K], double *part, uint32_t *cnt, int ntile, int ltile, double (&tot)[K])
+__device__ __forceinline__ void put_partials(double (&v)[K], double *part, const int (&off)[K], int t)
 {
     __shared__ double sh[4 * K];
-    __shared__ int last;
     block_sum<K>(v, sh);
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int k = 0; k < K; ++k) part[ltile * K + k] = v[k];
-        __threadfence();
-        const uint32_t prev = atomicAdd(cnt, 1u);
-        last = (prev == (uint32_t)(ntile - 1));
+        for (int k = 0; k < K; ++k) part[off[k] + t] = v[k];
     }
-    __syncthreads();
-    if (!last) return false;
-    __threadfence();
+}
+
+// out[k] = sum_{q < ntile} part[off[k] + q], identical in every thread and
+// every workgroup
+template <int K>
+__device__ __forceinline__ void sum_partials(const double *part, const int (&off)[K], int ntile, double (&out)[K])
+{
+    __shared__ double sh[4 * K];
     double acc[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) acc[k] = 0.0;
     for (int q = threadIdx.x; q < ntile; q += TILE) {
 #pragma unroll
-        for (int k = 0; k < K; ++k)
-            acc[k] += __hip_atomic_load(part + q * K + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        for (int k = 0; k < K; ++k) acc[k] += part[off[k] + q];
     }
     block_sum<K>(acc, sh);
     if (threadIdx.x == 0) {
 #pragma unroll
         for (int k = 0; k < K; ++k) sh[k] = acc[k];
-        *cnt = 0u;
     }
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < K; ++k) tot[k] = sh[k];
-    return true;
+    for (int k = 0; k < K; ++k) out[k] = sh[k];
+    __syncthreads();
 }
 
 // neighbour offset of DIA slot s (slot order -sxy, -sx, -1, 0, +1, +sx, +sxy)
@@ -392,8 +394,7 @@ __global__ __launch_bounds__(TILE) void k_asm_transport(const CaseDev *__restric
 }
 
 // ---------------------------------------------- pressure-correction rhs
-// b = -(rho/dt) D u* (eq. 3.4); partial sums give the mean (removed by
-// k_sub_mean) and ||D u*||.
+// b = -(rho/dt) D u* (eq. 3.4); partial sums of b and (D u*)^2 per tile.
 template <int DIM>
 __global__ __launch_bounds__(TILE) void k_div_rhs(const CaseDev *__restrict__ cases, const Tile *__restrict__ tiles, int vel_src)
 {
@@ -415,23 +416,29 @@ __global__ __launch_bounds__(TILE) void k_div_rhs(const CaseDev *__restrict__ ca
         v[0] = b;
         v[1] = dv * dv;
     }
-    double tot[2];
-    if (arrive<2>(v, c.red_part, &c.red_cnt[0], c.ntile_cell, tl.t, tot)) {
-        if (threadIdx.x == 0) {
-            c.red[R_SUMB] = tot[0];
-            c.red[R_DIVSTAR] = sqrt(tot[1]);
-            c.ks[SP].bmean = tot[0] / (double)P.ncell;
-        }
-    }
+    const int nt = c.ntile_cell;
+    const int off[2] = {0, nt};
+    put_partials<2>(v, c.red_part, off, tl.t);
 }
 
-// remove the mean of the pressure rhs (consistency of the Neumann problem)
+// remove the mean of the pressure rhs (consistency of the Neumann problem);
+// workgroup 0 of each case records the mean and ||D u*||
 __global__ __launch_bounds__(TILE) void k_sub_mean(const CaseDev *__restrict__ cases, const Tile *__restrict__ tiles)
 {
     const Tile tl = tiles[xcd_tile(blockIdx.x, gridDim.x)];
     const CaseDev &c = cases[tl.c];
+    const int nt = c.ntile_cell;
+    const int off[2] = {0, nt};
+    double tot[2];
+    sum_partials<2>(c.red_part, off, nt, tot);
+    const double mean = tot[0] / (double)c.ph.ncell;
     const int ci = tl.t * TILE + threadIdx.x;
-    if (ci < c.ph.ncell) c.b[SP][ci] -= c.ks[SP].bmean;
+    if (ci < c.ph.ncell) c.b[SP][ci] -= mean;
+    if (tl.t == 0 && threadIdx.x == 0) {
+        c.red[R_SUMB] = tot[0];
+        c.red[R_DIVSTAR] = sqrt(tot[1]);
+        c.ks[SP].bmean = mean;
+    }
 }
 
 // ------------------------------------------------------------ projection
@@ -547,25 +554,49 @@ __global__ __launch_bounds__(TILE) void k_phase_commit(const CaseDev *__restrict
         v[2] = wall;
         v[3] = dv * dv;
     }
+    const int nt = c.ntile_cell;
+    const int off[4] = {0, nt, 2 * nt, 3 * nt};
+    put_partials<4>(v, c.red_part, off, tl.t);
+}
+
+// per-case totals of the committed step (one workgroup per case); advances
+// the step counter after every workgroup of k_phase_commit has read it
+__global__ __launch_bounds__(TILE) void k_case_stats(const CaseDev *__restrict__ cases, const int32_t *__restrict__ cidx)
+{
+    const CaseDev &c = cases[cidx[blockIdx.x]];
+    const int nt = c.ntile_cell;
+    const int off[4] = {0, nt, 2 * nt, 3 * nt};
     double tot[4];
-    if (arrive<4>(v, c.red_part, &c.red_cnt[1], c.ntile_cell, tl.t, tot)) {
-        if (threadIdx.x == 0) {
-            c.red[R_SUMC] = tot[0];
-            c.red[R_SUMH] = tot[1];
-            c.red[R_WALL] = tot[2];
-            c.red[R_DIVNEW] = sqrt(tot[3]);
-            *c.step += 1;
-        }
+    sum_partials<4>(c.red_part, off, nt, tot);
+    if (threadIdx.x == 0) {
+        c.red[R_SUMC] = tot[0];
+        c.red[R_SUMH] = tot[1];
+        c.red[R_WALL] = tot[2];
+        c.red[R_DIVNEW] = sqrt(tot[3]);
+        *c.step += 1;
     }
 }
 
 // ------------------------------------------------------------- Krylov
 // Jacobi-preconditioned CG (pressure) and BiCGSTAB (transport).  Each
-// iteration is split at its global reductions; the preconditioned vector
-// that the matrix product needs at neighbour rows is recomputed there from
-// the (unchanged) vectors of the previous kernel, so no extra pass writes
-// it.  Vectors that are overwritten while neighbours still read them are
-// ping-ponged (flip).  A solve that is not RUNNING skips every kernel.
+// iteration is split at its global reductions.  A kernel of iteration k
+// first totals the partial sums the previous kernels left (iteration k-1 in
+// the buffers of parity (k-1)&1, iteration k in parity k&1), derives the
+// scalars (alpha, beta, omega) and the convergence decision, identically in
+// every workgroup, then works on its rows and writes its own partials.
+// The preconditioned vector the matrix product needs at neighbour rows is
+// recomputed there from vectors the previous kernel left unchanged, so no
+// extra pass writes it; vectors overwritten while neighbours still read them
+// are ping-ponged by iteration parity.  Workgroup 0 of a solve records a
+// status change (converged, failed, restart); every other workgroup reaches
+// the same decision from the same totals and stops with it.
+
+typedef __attribute__((address_space(1))) double gdbl;
+
+template <class T>
+__device__ __forceinline__ gdbl *G(T *p) { return (gdbl *)p; }
+template <class T>
+__device__ __forceinline__ const gdbl *GC(const T *p) { return (const gdbl *)p; }
 
 __device__ __forceinline__ const KJob &job_of(const KJob *jobs, const JTile *tiles, JTile &tl)
 {
@@ -573,258 +604,340 @@ __device__ __forceinline__ const KJob &job_of(const KJob *jobs, const JTile *til
     return jobs[tl.j];
 }
 
-// fresh start (mode 0: every job; x = x0 or 0) or restart (mode 1: jobs in
-// K_RESTART; keeps x).  r = b - A x, rh = r, p = v = 0.
+__device__ __forceinline__ int poff(const KJob &J, int par, int slot) { return (par * NSLOT + slot) * J.ntile; }
+
+// status of a solve as seen by iteration k: RUNNING, or a (re)start whose
+// first iteration is k
+__device__ __forceinline__ bool active(const KState *st, int k)
+{
+    const int s = st->status;
+    return s == K_RUNNING || (s == K_RESTART && k == st->k0);
+}
+
+// record a terminal (or restart) status: workgroup 0 of the solve only
+__device__ __forceinline__ void set_status(const JTile &tl, KState *st, int status, int it, double rr)
+{
+    if (tl.t == 0 && threadIdx.x == 0) {
+        st->status = status;
+        st->it = it;
+        st->rr = rr;
+    }
+}
+
+// Start of a solve at host iteration index k (mode 0: every solve, x = x0 or
+// 0; mode 1: solves in K_RESTART, keep x).  r = b - A x, rh = r, p = v = 0;
+// partials (r,Mr) or (rh,r), (r,r), (b,b) for iteration k.
 template <int ND>
-__global__ __launch_bounds__(TILE) void k_kinit(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles, int flip, int mode)
+__global__ __launch_bounds__(TILE) void k_kinit(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles, int k, int mode)
 {
     JTile tl;
     const KJob &J = job_of(jobs, tiles, tl);
     KState *st = J.st;
     if (mode == 1 && st->status != K_RESTART) return;
-    const int i = tl.t * TILE + threadIdx.x;
     const int n = J.n;
+    const int flip = k & 1;
+    const gdbl *A = GC(J.A), *b = GC(J.b), *mi = GC(J.minv);
+    gdbl *x = G(J.x), *r = G(J.r), *rh = G(J.rh);
+    gdbl *po = G(flip ? J.p1 : J.p0), *vo = G(flip ? J.v1 : J.v0);
+    const gdbl *x0 = GC(J.x0);
     double v[3] = {0.0, 0.0, 0.0};
-    if (i < n) {
-        double r;
+    const int i0 = tl.t * J.rpt;
+    const int i1 = min(n, i0 + J.rpt);
+    for (int i = i0 + threadIdx.x; i < i1; i += TILE) {
+        double ri;
         if (mode == 0) {
-            const double *x0 = J.x0;
             if (x0) {
-                r = J.b[i] - stencil<ND>(J.A, n, i, J.sx, J.sxy, [&](int j) { return x0[j]; });
-                J.x[i] = x0[i];
+                ri = b[i] - stencil<ND>(A, n, i, J.sx, J.sxy, [&](int j) { return x0[j]; });
+                x[i] = x0[i];
             } else {
-                r = J.b[i];
-                J.x[i] = 0.0;
+                ri = b[i];
+                x[i] = 0.0;
             }
         } else {
-            const double *x = J.x;
-            r = J.b[i] - stencil<ND>(J.A, n, i, J.sx, J.sxy, [&](int j) { return x[j]; });
+            ri = b[i] - stencil<ND>(A, n, i, J.sx, J.sxy, [&](int j) { return x[j]; });
         }
-        J.r[i] = r;
-        J.rh[i] = r;
-        (flip ? J.p1 : J.p0)[i] = 0.0;
-        (flip ? J.v1 : J.v0)[i] = 0.0;
-        v[0] = r * r;
-        v[1] = J.b[i] * J.b[i];
-        v[2] = r * J.minv[i] * r;
+        r[i] = ri;
+        rh[i] = ri;
+        po[i] = 0.0;
+        vo[i] = 0.0;
+        v[0] += J.kind == K_CG ? ri * mi[i] * ri : ri * ri;
+        v[1] += ri * ri;
+        v[2] += b[i] * b[i];
     }
-    double tot[3];
-    if (arrive<3>(v, J.part, &st->cnt, J.ntile, tl.t, tot)) {
-        if (threadIdx.x == 0) {
-            if (mode == 0) { st->bb = tot[1]; st->it = 0; st->restarts = 0; }
-            st->rr = tot[0];
-            st->rho = J.kind == K_CG ? tot[2] : tot[0];
-            st->rho_old = 1.0; st->alpha = 1.0; st->omega = 1.0; st->beta = 0.0;
-            if (!finite(tot[0]) || !finite(tot[1])) st->status = K_NONFINITE;
-            else if (st->bb == 0.0) st->status = K_ZERO;
-            else if (tot[0] <= st->tol2 * st->bb) st->status = K_CONVERGED;
-            else st->status = K_RUNNING;
-        }
+    const int par = (k + 1) & 1;               // = parity of iteration k-1
+    const int off[3] = {poff(J, par, PS_RHO), poff(J, par, PS_RR), poff(J, par, PS_BB)};
+    put_partials<3>(v, J.part, off, tl.t);
+    if (tl.t == 0 && threadIdx.x == 0) {
+        st->k0 = k;
+        if (mode == 0) { st->it_base = 0; st->restarts = 0; st->status = K_RUNNING; }
+        else { st->it_base = st->it; st->restarts += 1; }
     }
 }
 
-// CG, first half: p = M r + beta p_old; q = A p; alpha = rho / (p, q)
+// convergence test at the start of iteration k (shared by CG and BiCGSTAB);
+// returns false when the solve stops here
+__device__ __forceinline__ bool test_convergence(const KJob &J, const JTile &tl, KState *st, int k,
+                                                 double rr, double &bb)
+{
+    const int it = st->it_base + (k - st->k0);
+    if (k == st->k0) {
+        const int off[1] = {poff(J, (k + 1) & 1, PS_BB)};
+        double t[1];
+        sum_partials<1>(J.part, off, J.ntile, t);
+        bb = t[0];
+        if (tl.t == 0 && threadIdx.x == 0) st->bb = bb;
+    } else {
+        bb = st->bb;
+    }
+    if (!finite(rr) || !finite(bb)) { set_status(tl, st, K_NONFINITE, it, rr); return false; }
+    if (bb == 0.0) { set_status(tl, st, K_ZERO, it, rr); return false; }
+    if (rr <= st->tol2 * bb) { set_status(tl, st, K_CONVERGED, it, rr); return false; }
+    if (it >= st->max_iter) { set_status(tl, st, K_FAILED, it, rr); return false; }
+    if (k == st->k0 && tl.t == 0 && threadIdx.x == 0) st->status = K_RUNNING;
+    return true;
+}
+
+// CG, first half of iteration k: beta = rho_k / rho_{k-1}; p = M r + beta p;
+// q = A p; partial (p, q)
 template <int ND>
-__global__ __launch_bounds__(TILE) void k_cg_a(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles, int flip)
+__global__ __launch_bounds__(TILE) void k_cg_a(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles, int k)
 {
     JTile tl;
     const KJob &J = job_of(jobs, tiles, tl);
     KState *st = J.st;
-    if (st->status != K_RUNNING) return;
-    const int i = tl.t * TILE + threadIdx.x;
+    if (!active(st, k)) return;
+    const int pk = k & 1, pm = (k + 1) & 1;
+    double s2[2];
+    {
+        const int off[2] = {poff(J, pm, PS_RHO), poff(J, pm, PS_RR)};
+        sum_partials<2>(J.part, off, J.ntile, s2);
+    }
+    double bb;
+    if (!test_convergence(J, tl, st, k, s2[1], bb)) return;
+    double beta = 0.0;
+    if (k != st->k0) {
+        const int off[1] = {poff(J, pk, PS_RHO)};
+        double t[1];
+        sum_partials<1>(J.part, off, J.ntile, t);
+        beta = s2[0] / t[0];
+    }
     const int n = J.n;
-    const double beta = st->beta;
-    const double *po = flip ? J.p1 : J.p0;
-    double *pn = flip ? J.p0 : J.p1;
-    const double *r = J.r, *mi = J.minv;
+    const gdbl *A = GC(J.A), *r = GC(J.r), *mi = GC(J.minv);
+    const gdbl *po = GC(pk ? J.p1 : J.p0);
+    gdbl *pn = G(pk ? J.p0 : J.p1), *q = G(J.t);
     double v[1] = {0.0};
-    if (i < n) {
+    const int i0 = tl.t * J.rpt, i1 = min(n, i0 + J.rpt);
+    for (int i = i0 + threadIdx.x; i < i1; i += TILE) {
         const double pi = mi[i] * r[i] + beta * po[i];
-        const double qi = stencil<ND>(J.A, n, i, J.sx, J.sxy, [&](int j) { return mi[j] * r[j] + beta * po[j]; });
+        const double qi = stencil<ND>(A, n, i, J.sx, J.sxy, [&](int j) { return mi[j] * r[j] + beta * po[j]; });
         pn[i] = pi;
-        J.t[i] = qi;
-        v[0] = pi * qi;
+        q[i] = qi;
+        v[0] += pi * qi;
     }
-    double tot[1];
-    if (arrive<1>(v, J.part, &st->cnt, J.ntile, tl.t, tot)) {
-        if (threadIdx.x == 0) {
-            if (!(tot[0] > 0.0) || !finite(tot[0])) st->status = finite(tot[0]) ? K_RESTART : K_NONFINITE;
-            else st->alpha = st->rho / tot[0];
-        }
-    }
+    const int off[1] = {poff(J, pk, PS_Q)};
+    put_partials<1>(v, J.part, off, tl.t);
 }
 
-// CG, second half: x += alpha p; r -= alpha q; rho' = (r, M r); beta = rho'/rho
+// CG, second half: alpha = rho_k / (p, q); x += alpha p; r -= alpha q;
+// partials (r, M r), (r, r) for iteration k+1
 template <int ND>
-__global__ __launch_bounds__(TILE) void k_cg_b(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles, int flip)
+__global__ __launch_bounds__(TILE) void k_cg_b(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles, int k)
 {
     JTile tl;
     const KJob &J = job_of(jobs, tiles, tl);
     KState *st = J.st;
     if (st->status != K_RUNNING) return;
-    const int i = tl.t * TILE + threadIdx.x;
-    const double alpha = st->alpha;
-    const double *pn = flip ? J.p0 : J.p1;
+    const int pk = k & 1, pm = (k + 1) & 1;
+    double s2[2];
+    {
+        const int off[2] = {poff(J, pm, PS_RHO), poff(J, pk, PS_Q)};
+        sum_partials<2>(J.part, off, J.ntile, s2);
+    }
+    if (!(s2[1] > 0.0) || !finite(s2[1])) {
+        set_status(tl, st, finite(s2[1]) ? K_RESTART : K_NONFINITE, st->it_base + (k - st->k0), 0.0);
+        return;
+    }
+    const double alpha = s2[0] / s2[1];
+    const gdbl *pn = GC(pk ? J.p0 : J.p1), *q = GC(J.t), *mi = GC(J.minv);
+    gdbl *x = G(J.x), *r = G(J.r);
     double v[2] = {0.0, 0.0};
-    if (i < J.n) {
-        const double xi = J.x[i] + alpha * pn[i];
-        const double ri = J.r[i] - alpha * J.t[i];
-        J.x[i] = xi;
-        J.r[i] = ri;
-        v[0] = ri * J.minv[i] * ri;
-        v[1] = ri * ri;
+    const int i0 = tl.t * J.rpt, i1 = min(J.n, i0 + J.rpt);
+    for (int i = i0 + threadIdx.x; i < i1; i += TILE) {
+        x[i] = x[i] + alpha * pn[i];
+        const double ri = r[i] - alpha * q[i];
+        r[i] = ri;
+        v[0] += ri * mi[i] * ri;
+        v[1] += ri * ri;
     }
-    double tot[2];
-    if (arrive<2>(v, J.part, &st->cnt, J.ntile, tl.t, tot)) {
-        if (threadIdx.x == 0) {
-            st->beta = tot[0] / st->rho;
-            st->rho = tot[0];
-            st->rr = tot[1];
-            st->it += 1;
-            if (!finite(tot[1])) st->status = K_NONFINITE;
-            else if (tot[1] <= st->tol2 * st->bb) st->status = K_CONVERGED;
-            else if (st->it >= st->max_iter) st->status = K_FAILED;
-        }
-    }
+    const int off[2] = {poff(J, pk, PS_RHO), poff(J, pk, PS_RR)};
+    put_partials<2>(v, J.part, off, tl.t);
 }
 
 // BiCGSTAB (van der Vorst), right Jacobi preconditioning.
-// a: p = r + beta (p_old - omega v_old); v = A M p; alpha = rho / (rh, v)
+// a: beta = (rho_k/rho_{k-1})(alpha_{k-1}/omega_{k-1});
+//    p = r + beta (p - omega v); v = A M p; partial (rh, v)
 template <int ND>
-__global__ __launch_bounds__(TILE) void k_bicg_a(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles, int flip)
+__global__ __launch_bounds__(TILE) void k_bicg_a(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles, int k)
 {
     JTile tl;
     const KJob &J = job_of(jobs, tiles, tl);
     KState *st = J.st;
-    if (st->status != K_RUNNING) return;
-    const int i = tl.t * TILE + threadIdx.x;
+    if (!active(st, k)) return;
+    const int pk = k & 1, pm = (k + 1) & 1;
+    double s2[2];
+    {
+        const int off[2] = {poff(J, pm, PS_RHO), poff(J, pm, PS_RR)};
+        sum_partials<2>(J.part, off, J.ntile, s2);
+    }
+    double bb;
+    if (!test_convergence(J, tl, st, k, s2[1], bb)) return;
+    const double rho = s2[0];
+    double beta = 0.0, omega = 0.0;
+    if (k != st->k0) {
+        double s4[4];
+        const int off[4] = {poff(J, pk, PS_RHO), poff(J, pm, PS_Q), poff(J, pm, PS_TS), poff(J, pm, PS_TT)};
+        sum_partials<4>(J.part, off, J.ntile, s4);
+        const double rho_prev = s4[0];
+        const double alpha_prev = rho_prev / s4[1];
+        omega = s4[3] > 0.0 ? s4[2] / s4[3] : 0.0;
+        if (omega == 0.0 || rho == 0.0 || rho_prev == 0.0) {
+            set_status(tl, st, K_RESTART, st->it_base + (k - st->k0), s2[1]);
+            return;
+        }
+        beta = (rho / rho_prev) * (alpha_prev / omega);
+    }
     const int n = J.n;
-    const double omega = st->omega;
-    const double beta = (st->rho / st->rho_old) * (st->alpha / omega);
-    const double *po = flip ? J.p1 : J.p0, *vo = flip ? J.v1 : J.v0;
-    double *pn = flip ? J.p0 : J.p1, *vn = flip ? J.v0 : J.v1;
-    const double *r = J.r, *mi = J.minv;
+    const gdbl *A = GC(J.A), *r = GC(J.r), *mi = GC(J.minv), *rh = GC(J.rh);
+    const gdbl *po = GC(pk ? J.p1 : J.p0), *vo = GC(pk ? J.v1 : J.v0);
+    gdbl *pn = G(pk ? J.p0 : J.p1), *vn = G(pk ? J.v0 : J.v1);
     double v[1] = {0.0};
-    if (i < n) {
+    const int i0 = tl.t * J.rpt, i1 = min(n, i0 + J.rpt);
+    for (int i = i0 + threadIdx.x; i < i1; i += TILE) {
         const double pi = r[i] + beta * (po[i] - omega * vo[i]);
-        const double vi = stencil<ND>(J.A, n, i, J.sx, J.sxy,
+        const double vi = stencil<ND>(A, n, i, J.sx, J.sxy,
                                       [&](int j) { return mi[j] * (r[j] + beta * (po[j] - omega * vo[j])); });
         pn[i] = pi;
         vn[i] = vi;
-        v[0] = J.rh[i] * vi;
+        v[0] += rh[i] * vi;
     }
-    double tot[1];
-    if (arrive<1>(v, J.part, &st->cnt, J.ntile, tl.t, tot)) {
-        if (threadIdx.x == 0) {
-            if (!finite(tot[0])) st->status = K_NONFINITE;
-            else if (tot[0] == 0.0) st->status = K_RESTART;
-            else st->alpha = st->rho / tot[0];
-        }
-    }
+    const int off[1] = {poff(J, pk, PS_Q)};
+    put_partials<1>(v, J.part, off, tl.t);
 }
 
-// b: s = r - alpha v; t = A M s; omega = (t, s) / (t, t)
+// b: alpha = rho_k / (rh, v); s = r - alpha v; t = A M s; partials (t,s), (t,t)
 template <int ND>
-__global__ __launch_bounds__(TILE) void k_bicg_b(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles, int flip)
+__global__ __launch_bounds__(TILE) void k_bicg_b(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles, int k)
 {
     JTile tl;
     const KJob &J = job_of(jobs, tiles, tl);
     KState *st = J.st;
     if (st->status != K_RUNNING) return;
-    const int i = tl.t * TILE + threadIdx.x;
+    const int pk = k & 1, pm = (k + 1) & 1;
+    double s2[2];
+    {
+        const int off[2] = {poff(J, pm, PS_RHO), poff(J, pk, PS_Q)};
+        sum_partials<2>(J.part, off, J.ntile, s2);
+    }
+    if (s2[1] == 0.0 || !finite(s2[1])) {
+        set_status(tl, st, finite(s2[1]) ? K_RESTART : K_NONFINITE, st->it_base + (k - st->k0), 0.0);
+        return;
+    }
+    const double alpha = s2[0] / s2[1];
     const int n = J.n;
-    const double alpha = st->alpha;
-    const double *vn = flip ? J.v0 : J.v1;
-    const double *r = J.r, *mi = J.minv;
+    const gdbl *A = GC(J.A), *r = GC(J.r), *mi = GC(J.minv);
+    const gdbl *vn = GC(pk ? J.v0 : J.v1);
+    gdbl *t = G(J.t);
     double v[2] = {0.0, 0.0};
-    if (i < n) {
+    const int i0 = tl.t * J.rpt, i1 = min(n, i0 + J.rpt);
+    for (int i = i0 + threadIdx.x; i < i1; i += TILE) {
         const double si = r[i] - alpha * vn[i];
-        const double ti = stencil<ND>(J.A, n, i, J.sx, J.sxy, [&](int j) { return mi[j] * (r[j] - alpha * vn[j]); });
-        J.t[i] = ti;
-        v[0] = ti * si;
-        v[1] = ti * ti;
+        const double ti = stencil<ND>(A, n, i, J.sx, J.sxy, [&](int j) { return mi[j] * (r[j] - alpha * vn[j]); });
+        t[i] = ti;
+        v[0] += ti * si;
+        v[1] += ti * ti;
     }
-    double tot[2];
-    if (arrive<2>(v, J.part, &st->cnt, J.ntile, tl.t, tot)) {
-        if (threadIdx.x == 0) {
-            if (!finite(tot[0]) || !finite(tot[1])) st->status = K_NONFINITE;
-            else st->omega = tot[1] > 0.0 ? tot[0] / tot[1] : 0.0;
-        }
-    }
+    const int off[2] = {poff(J, pk, PS_TS), poff(J, pk, PS_TT)};
+    put_partials<2>(v, J.part, off, tl.t);
 }
 
-// c: x += alpha M p + omega M s; r = s - omega t; rho' = (rh, r)
+// c: omega = (t,s)/(t,t); x += M (alpha p + omega s); r = s - omega t;
+// partials (rh, r), (r, r) for iteration k+1
 template <int ND>
-__global__ __launch_bounds__(TILE) void k_bicg_c(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles, int flip)
+__global__ __launch_bounds__(TILE) void k_bicg_c(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles, int k)
 {
     JTile tl;
     const KJob &J = job_of(jobs, tiles, tl);
     KState *st = J.st;
     if (st->status != K_RUNNING) return;
-    const int i = tl.t * TILE + threadIdx.x;
-    const double alpha = st->alpha, omega = st->omega;
-    const double *pn = flip ? J.p0 : J.p1, *vn = flip ? J.v0 : J.v1;
+    const int pk = k & 1, pm = (k + 1) & 1;
+    double s4[4];
+    {
+        const int off[4] = {poff(J, pm, PS_RHO), poff(J, pk, PS_Q), poff(J, pk, PS_TS), poff(J, pk, PS_TT)};
+        sum_partials<4>(J.part, off, J.ntile, s4);
+    }
+    const double alpha = s4[0] / s4[1];
+    const double omega = s4[3] > 0.0 ? s4[2] / s4[3] : 0.0;
+    const gdbl *pn = GC(pk ? J.p0 : J.p1), *vn = GC(pk ? J.v0 : J.v1), *t = GC(J.t);
+    const gdbl *mi = GC(J.minv), *rh = GC(J.rh);
+    gdbl *x = G(J.x), *r = G(J.r);
     double v[2] = {0.0, 0.0};
-    if (i < J.n) {
-        const double mi = J.minv[i];
-        const double si = J.r[i] - alpha * vn[i];
-        J.x[i] += mi * (alpha * pn[i] + omega * si);
-        const double ri = si - omega * J.t[i];
-        J.r[i] = ri;
-        v[0] = J.rh[i] * ri;
-        v[1] = ri * ri;
+    const int i0 = tl.t * J.rpt, i1 = min(J.n, i0 + J.rpt);
+    for (int i = i0 + threadIdx.x; i < i1; i += TILE) {
+        const double si = r[i] - alpha * vn[i];
+        x[i] = x[i] + mi[i] * (alpha * pn[i] + omega * si);
+        const double ri = si - omega * t[i];
+        r[i] = ri;
+        v[0] += rh[i] * ri;
+        v[1] += ri * ri;
     }
-    double tot[2];
-    if (arrive<2>(v, J.part, &st->cnt, J.ntile, tl.t, tot)) {
-        if (threadIdx.x == 0) {
-            st->rho_old = st->rho;
-            st->rho = tot[0];
-            st->rr = tot[1];
-            st->it += 1;
-            if (!finite(tot[1])) st->status = K_NONFINITE;
-            else if (tot[1] <= st->tol2 * st->bb) st->status = K_CONVERGED;
-            else if (st->it >= st->max_iter) st->status = K_FAILED;
-            else if (omega == 0.0 || tot[0] == 0.0) st->status = K_RESTART;
-        }
-    }
+    const int off[2] = {poff(J, pk, PS_RHO), poff(J, pk, PS_RR)};
+    put_partials<2>(v, J.part, off, tl.t);
 }
 
-// Verification of a converged solve on the true residual b - A x; also the
-// sums the step reports (sum of the residual, sum of x).  K_ZERO: x = 0.
+// True residual b - A x of a solve that stopped as converged (or x = 0 when
+// ||b|| = 0); partials of ||b - A x||^2, sum(b - A x), sum(x) into parity 0.
 template <int ND>
 __global__ __launch_bounds__(TILE) void k_kfinish(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles)
 {
     JTile tl;
     const KJob &J = job_of(jobs, tiles, tl);
+    const int status = J.st->status;
+    if (status != K_CONVERGED && status != K_ZERO) return;
+    const int n = J.n;
+    const gdbl *A = GC(J.A), *b = GC(J.b);
+    gdbl *x = G(J.x);
+    double v[3] = {0.0, 0.0, 0.0};
+    const int i0 = tl.t * J.rpt, i1 = min(n, i0 + J.rpt);
+    for (int i = i0 + threadIdx.x; i < i1; i += TILE) {
+        if (status == K_ZERO) {
+            x[i] = 0.0;
+        } else {
+            const double rt = b[i] - stencil<ND>(A, n, i, J.sx, J.sxy, [&](int j) { return x[j]; });
+            v[0] += rt * rt;
+            v[1] += rt;
+            v[2] += x[i];
+        }
+    }
+    const int off[3] = {poff(J, 0, PS_Q), poff(J, 0, PS_TS), poff(J, 0, PS_TT)};
+    put_partials<3>(v, J.part, off, tl.t);
+}
+
+// one workgroup per solve: totals of k_kfinish, verdict on the true residual
+__global__ __launch_bounds__(TILE) void k_kdecide(const KJob *__restrict__ jobs, int njobs)
+{
+    const KJob &J = jobs[blockIdx.x];
     KState *st = J.st;
     const int status = st->status;
     if (status != K_CONVERGED && status != K_ZERO) return;
-    const int i = tl.t * TILE + threadIdx.x;
-    const int n = J.n;
-    double v[3] = {0.0, 0.0, 0.0};
-    if (i < n) {
-        if (status == K_ZERO) {
-            J.x[i] = 0.0;
-        } else {
-            const double *x = J.x;
-            const double rt = J.b[i] - stencil<ND>(J.A, n, i, J.sx, J.sxy, [&](int j) { return x[j]; });
-            v[0] = rt * rt;
-            v[1] = rt;
-            v[2] = x[i];
-        }
-    }
+    const int off[3] = {poff(J, 0, PS_Q), poff(J, 0, PS_TS), poff(J, 0, PS_TT)};
     double tot[3];
-    if (arrive<3>(v, J.part, &st->cnt, J.ntile, tl.t, tot)) {
-        if (threadIdx.x == 0) {
-            st->tr2 = tot[0];
-            st->tsum = tot[1];
-            st->xsum = tot[2];
-            if (status == K_ZERO || tot[0] <= st->tol2 * st->bb) st->status = K_DONE;
-            else {
-                st->restarts += 1;
-                st->status = st->restarts > 20 ? K_FAILED : K_RESTART;
-            }
-        }
+    sum_partials<3>(J.part, off, J.ntile, tot);
+    if (threadIdx.x == 0) {
+        st->tr2 = tot[0];
+        st->tsum = tot[1];
+        st->xsum = tot[2];
+        if (status == K_ZERO || tot[0] <= st->tol2 * st->bb) st->status = K_DONE;
+        else st->status = st->restarts >= 20 ? K_FAILED : K_RESTART;
     }
 }
 
@@ -953,11 +1066,21 @@ void launch_phase_commit(int dim, const CaseDev *c, const Tile *t, int nt, hipSt
     else hipLaunchKernelGGL(k_phase_commit<3>, GRID(nt), 0, s, c, t);
 }
 
-void launch_kinit(int nd, const KJob *j, const JTile *t, int nt, int flip, int mode, hipStream_t s)
+void launch_kinit(int nd, const KJob *j, const JTile *t, int nt, int k, int mode, hipStream_t s)
 {
     if (nt <= 0) return;
-    if (nd == 5) hipLaunchKernelGGL(k_kinit<5>, GRID(nt), 0, s, j, t, flip, mode);
-    else hipLaunchKernelGGL(k_kinit<7>, GRID(nt), 0, s, j, t, flip, mode);
+    if (nd == 5) hipLaunchKernelGGL(k_kinit<5>, GRID(nt), 0, s, j, t, k, mode);
+    else hipLaunchKernelGGL(k_kinit<7>, GRID(nt), 0, s, j, t, k, mode);
+}
+void launch_kdecide(const KJob *j, int njobs, hipStream_t s)
+{
+    if (njobs <= 0) return;
+    hipLaunchKernelGGL(k_kdecide, dim3(njobs), dim3(TILE), 0, s, j, njobs);
+}
+void launch_case_stats(const CaseDev *c, const int32_t *cidx, int ncase, hipStream_t s)
+{
+    if (ncase <= 0) return;
+    hipLaunchKernelGGL(k_case_stats, dim3(ncase), dim3(TILE), 0, s, c, cidx);
 }
 void launch_kfinish(int nd, const KJob *j, const JTile *t, int nt, hipStream_t s)
 {
@@ -965,24 +1088,24 @@ void launch_kfinish(int nd, const KJob *j, const JTile *t, int nt, hipStream_t s
     if (nd == 5) hipLaunchKernelGGL(k_kfinish<5>, GRID(nt), 0, s, j, t);
     else hipLaunchKernelGGL(k_kfinish<7>, GRID(nt), 0, s, j, t);
 }
-void launch_kiter(int which, int nd, const KJob *j, const JTile *t, int nt, int flip, hipStream_t s)
+void launch_kiter(int which, int nd, const KJob *j, const JTile *t, int nt, int k, hipStream_t s)
 {
     if (nt <= 0) return;
     if (nd == 5) {
         switch (which) {
-        case KI_CG_A: hipLaunchKernelGGL(k_cg_a<5>, GRID(nt), 0, s, j, t, flip); break;
-        case KI_CG_B: hipLaunchKernelGGL(k_cg_b<5>, GRID(nt), 0, s, j, t, flip); break;
-        case KI_BICG_A: hipLaunchKernelGGL(k_bicg_a<5>, GRID(nt), 0, s, j, t, flip); break;
-        case KI_BICG_B: hipLaunchKernelGGL(k_bicg_b<5>, GRID(nt), 0, s, j, t, flip); break;
-        default: hipLaunchKernelGGL(k_bicg_c<5>, GRID(nt), 0, s, j, t, flip); break;
+        case KI_CG_A: hipLaunchKernelGGL(k_cg_a<5>, GRID(nt), 0, s, j, t, k); break;
+        case KI_CG_B: hipLaunchKernelGGL(k_cg_b<5>, GRID(nt), 0, s, j, t, k); break;
+        case KI_BICG_A: hipLaunchKernelGGL(k_bicg_a<5>, GRID(nt), 0, s, j, t, k); break;
+        case KI_BICG_B: hipLaunchKernelGGL(k_bicg_b<5>, GRID(nt), 0, s, j, t, k); break;
+        default: hipLaunchKernelGGL(k_bicg_c<5>, GRID(nt), 0, s, j, t, k); break;
         }
     } else {
         switch (which) {
-        case KI_CG_A: hipLaunchKernelGGL(k_cg_a<7>, GRID(nt), 0, s, j, t, flip); break;
-        case KI_CG_B: hipLaunchKernelGGL(k_cg_b<7>, GRID(nt), 0, s, j, t, flip); break;
-        case KI_BICG_A: hipLaunchKernelGGL(k_bicg_a<7>, GRID(nt), 0, s, j, t, flip); break;
-        case KI_BICG_B: hipLaunchKernelGGL(k_bicg_b<7>, GRID(nt), 0, s, j, t, flip); break;
-        default: hipLaunchKernelGGL(k_bicg_c<7>, GRID(nt), 0, s, j, t, flip); break;
+        case KI_CG_A: hipLaunchKernelGGL(k_cg_a<7>, GRID(nt), 0, s, j, t, k); break;
+        case KI_CG_B: hipLaunchKernelGGL(k_cg_b<7>, GRID(nt), 0, s, j, t, k); break;
+        case KI_BICG_A: hipLaunchKernelGGL(k_bicg_a<7>, GRID(nt), 0, s, j, t, k); break;
+        case KI_BICG_B: hipLaunchKernelGGL(k_bicg_b<7>, GRID(nt), 0, s, j, t, k); break;
+        default: hipLaunchKernelGGL(k_bicg_c<7>, GRID(nt), 0, s, j, t, k); break;
         }
     }
 }

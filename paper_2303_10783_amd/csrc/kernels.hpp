@@ -12,10 +12,12 @@ void launch_sub_mean(const CaseDev *c, const Tile *t, int nt, hipStream_t s);
 void launch_project(const CaseDev *c, const Tile *t, int nt, hipStream_t s);
 void launch_phase_commit(int dim, const CaseDev *c, const Tile *t, int nt, hipStream_t s);
 
-void launch_kinit(int nd, const KJob *j, const JTile *t, int nt, int flip, int mode, hipStream_t s);
+void launch_kinit(int nd, const KJob *j, const JTile *t, int nt, int k, int mode, hipStream_t s);
+void launch_kdecide(const KJob *j, int njobs, hipStream_t s);
+void launch_case_stats(const CaseDev *c, const int32_t *cidx, int ncase, hipStream_t s);
 void launch_kfinish(int nd, const KJob *j, const JTile *t, int nt, hipStream_t s);
 enum KIter { KI_CG_A = 0, KI_CG_B = 1, KI_BICG_A = 2, KI_BICG_B = 3, KI_BICG_C = 4 };
-void launch_kiter(int which, int nd, const KJob *j, const JTile *t, int nt, int flip, hipStream_t s);
+void launch_kiter(int which, int nd, const KJob *j, const JTile *t, int nt, int k, hipStream_t s);
 
 void launch_csr(int dim, const CaseDev *cd, int s, int n, int32_t *cnt, int32_t *row_ptr, int32_t *col,
                 double *val, int build_pattern, hipStream_t st);

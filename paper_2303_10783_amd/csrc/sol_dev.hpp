@@ -21,16 +21,26 @@ enum KStatus {
 
 enum KKind { K_CG = 0, K_BICGSTAB = 1 };
 
-// Per-solve device scalars.  Written only by the last-arriving workgroup of
-// a kernel (or by init kernels), read by the next kernel on the stream.
+// Per-solve device state.  Iteration kernels read it at their start; only
+// workgroup 0 of a solve writes it, and only the fields no other workgroup
+// of the same kernel reads (status changes are taken by every workgroup from
+// the same reduced partials, so all of them stop together).
 struct KState {
-    double rho, rho_old, alpha, omega, beta;
-    double bb, rr, tr2, tsum, xsum, bmean;
-    double tol2;
-    int32_t it, status, max_iter, restarts;
-    uint32_t cnt;      // arrival counter of the last-block reduction
-    int32_t pad[3];
+    double bb;                 // ||b||^2 of the current solve
+    double rr;                 // ||r||^2 at the last convergence test
+    double tr2, tsum, xsum;    // true residual ||b - A x||^2, sum(b - A x), sum(x)
+    double bmean;              // mean of the pressure rhs (removed before the solve)
+    double tol2;               // tol^2
+    int32_t status;            // KStatus
+    int32_t it;                // iterations done (valid once not RUNNING)
+    int32_t it_base;           // iterations done before the current (re)start
+    int32_t k0;                // host iteration index of the current (re)start
+    int32_t max_iter, restarts;
 };
+
+// Partial-sum slots of a solve: part[(par * NSLOT + slot) * ntile + tile],
+// par = parity of the iteration that produced them.
+enum PSlot { PS_Q = 0, PS_TS = 1, PS_TT = 2, PS_RHO = 3, PS_RR = 4, PS_BB = 5, NSLOT = 6 };
 
 // Physical / geometric constants of one case (immutable after create).
 struct Phys {
@@ -72,14 +82,15 @@ enum RedSlot { R_SUMB = 0, R_DIVSTAR = 1, R_SUMC = 2, R_SUMH = 3, R_WALL = 4, R_
 
 // One linear solve.
 struct KJob {
-    int32_t n, sx, sxy, ntile;
+    int32_t n, sx, sxy;
+    int32_t rpt;              // rows per tile (multiple of TILE)
+    int32_t ntile;            // tiles of this solve
     int32_t kind;             // KKind
-    int32_t pad;
     const double *A, *b, *minv;
     double *x;
     const double *x0;         // initial guess copied into x on a fresh start (NULL: x = 0)
     double *r, *rh, *p0, *p1, *v0, *v1, *t;
-    double *part;             // [ntile * 4]
+    double *part;             // [2 * NSLOT * ntile]
     KState *st;
     // mixed precision: FP32 operator and work vectors for the inner solve
     const float *A32, *minv32;
