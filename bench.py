@@ -30,7 +30,7 @@ HBM_PEAK_GBS = 8000.0
 def roofline(g, ncell_rows):
     """Dominant kernel class by estimated time per step, from sampled events."""
     best = None
-    for cls in ("cg_a", "cg_b", "bicg_a", "bicg_b", "bicg_c", "asm_mom", "asm_trn", "phase"):
+    for cls in ("cg", "bicg_a", "bicg_b", "bicg_c", "asm_mom", "asm_trn", "phase"):
         t = g.timing(cls)
         if t["launches"] == 0:
             continue
@@ -70,7 +70,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="C2", choices=["C1", "C2", "C3"])
-    ap.add_argument("--precision", default="fp64", choices=["fp64"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
     args = ap.parse_args()
@@ -86,6 +86,8 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     case = W.workload_case(args.workload)
+    if args.precision == "mixed":
+        case["numerics"]["precision"] = W.PRECISION_MIXED
     grid = case["grid"]
     ncell = grid["nx"] * grid["ny"] * (grid["nz"] if grid["dim"] == 3 else 1)
     dev = sol.TorchDevice(0)
@@ -105,7 +107,7 @@ def main():
     if not args.no_roofline:
         g.set_timing(True)
         st2 = g.step(2)
-        per = {k: max(1, st2["iters_total"][3] / 2) for k in ("cg_a", "cg_b")}
+        per = {"cg": max(1, st2["iters_total"][3] / 2)}
         other = sum(st2["iters_total"][s] for s in (0, 1, 2, 4, 5)) / 2
         per.update({k: max(1, other) for k in ("bicg_a", "bicg_b", "bicg_c")})
         best = roofline(g, per)
@@ -123,7 +125,7 @@ def main():
     out = dict(
         metric=METRIC, value=value, unit="cell-updates/s", n_gpus=1, steps=args.steps,
         warmup=args.warmup, ms_per_step=1e3 * secs / args.steps, higher_is_better=True,
-        scaling="weak", vs_baseline=None, dtype="f64", data="synthetic",
+        scaling="weak", vs_baseline=None, dtype="f64" if args.precision == "fp64" else "f32+f64", data="synthetic",
         config=dict(workload=f"{args.workload}: 2D cavity {grid['nx']}x{grid['ny']}" if grid["dim"] == 2
                     else f"{args.workload}: 3D box {grid['nx']}x{grid['ny']}x{grid['nz']}",
                     cells=ncell, dt=case["numerics"]["dt"], tol=case["numerics"]["tol_p"],

@@ -194,17 +194,16 @@ void sol_batch_destroy(sol_batch *b);
    if the solve was still iterating at that launch.  sol_get_timing returns
    the number of timed launches, their summed duration and the algorithmic
    bytes those launches move (matrix values + vectors read and written once,
-   per row of the systems that were iterating).  Enabling or disabling
-   resets the counters. */
-#define SOL_KCLASS_CG_A      0   /* CG: p = Mr + beta p, q = A p, (p,q)        */
-#define SOL_KCLASS_CG_B      1   /* CG: x, r update, (r,Mr), (r,r)             */
-#define SOL_KCLASS_BICG_A    2   /* BiCGSTAB: p, v = A M p, (rh,v)              */
-#define SOL_KCLASS_BICG_B    3   /* BiCGSTAB: t = A M s, (t,s), (t,t)           */
-#define SOL_KCLASS_BICG_C    4   /* BiCGSTAB: x, r update, (rh,r), (r,r)        */
-#define SOL_KCLASS_ASM_MOM   5   /* momentum assembly                           */
-#define SOL_KCLASS_ASM_TRN   6   /* solute + energy assembly                    */
-#define SOL_KCLASS_PHASE     7   /* phase update + commit                       */
-#define SOL_NKCLASS          8
+   per row of the systems that were iterating; FP32 values count 4 bytes).
+   Enabling or disabling resets the counters. */
+#define SOL_KCLASS_CG        0   /* CG iteration (one kernel): p, s, x, r, w = A M r, (r,Mr), (w,Mr) */
+#define SOL_KCLASS_BICG_A    1   /* BiCGSTAB: p, v = A M p, (rh,v)              */
+#define SOL_KCLASS_BICG_B    2   /* BiCGSTAB: t = A M s, (t,s), (t,t)           */
+#define SOL_KCLASS_BICG_C    3   /* BiCGSTAB: x, r update, (rh,r), (r,r)        */
+#define SOL_KCLASS_ASM_MOM   4   /* momentum assembly                           */
+#define SOL_KCLASS_ASM_TRN   5   /* solute + energy assembly                    */
+#define SOL_KCLASS_PHASE     6   /* phase update + commit                       */
+#define SOL_NKCLASS          7
 int sol_set_timing(sol_handle *h, int32_t enable);
 int sol_get_timing(sol_handle *h, int32_t kclass, int64_t *launches, double *total_ms,
                    double *bytes);

@@ -9,8 +9,10 @@ sol_device_ctx alloc/free callbacks) and the stream the library queues on.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
+import weakref
 
 import numpy as np
 
@@ -23,7 +25,7 @@ FIELD_BITS = dict(u=0, v=1, w=2, p=3, T=4, C=5, gl=6, Cl=7, Cs=8,
                   ustar=9, vstar=10, wstar=11, phi=12, Tstar=13)
 STATE_FIELDS = ("u", "v", "w", "p", "T", "C", "gl", "Cl", "Cs")
 NFIELDS = 14
-KCLASS = dict(cg_a=0, cg_b=1, bicg_a=2, bicg_b=3, bicg_c=4, asm_mom=5, asm_trn=6, phase=7)
+KCLASS = dict(cg=0, bicg_a=1, bicg_b=2, bicg_c=3, asm_mom=4, asm_trn=5, phase=6)
 
 
 class SolError(RuntimeError):
@@ -166,17 +168,35 @@ class TorchDevice:
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         dev_index = self.device.index or 0
         st = self.stream
+        c_alloc = torch.cuda.caching_allocator_alloc
+        c_delete = torch.cuda.caching_allocator_delete
+        on_device = torch.cuda.device
 
         def _alloc(nbytes, user):
-            with torch.cuda.device(dev_index):
-                return torch.cuda.caching_allocator_alloc(int(nbytes), dev_index, st)
+            with on_device(dev_index):
+                return c_alloc(int(nbytes), dev_index, st)
 
         def _free(ptr, user):
-            torch.cuda.caching_allocator_delete(ptr)
+            c_delete(ptr)
 
         self._alloc = ALLOC_FN(_alloc)
         self._free = FREE_FN(_free)
         self.ctx = sol_device_ctx(C.c_void_p(self.stream.cuda_stream), self._alloc, self._free, None)
+
+
+_live = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    # release every handle while torch (its allocator) is still alive;
+    # batches before the cases they reference
+    objs = sorted(list(_live), key=lambda o: 0 if isinstance(o, Batch) else 1)
+    for obj in objs:
+        try:
+            obj.close()
+        except Exception:
+            pass
 
 
 class Case:
@@ -192,6 +212,7 @@ class Case:
         check(L.sol_create(C.byref(self.grid), C.byref(self.alloy), C.byref(self.bcs),
                            C.byref(self.num), ctx, C.byref(h)))
         self.h = h
+        _live.add(self)
         self.sizes = {}
         g = case["grid"]
         nx, ny, nz = g["nx"], g["ny"], g["nz"] if g["dim"] == 3 else 1
@@ -284,6 +305,7 @@ class Batch:
         b = C.c_void_p()
         check(load().sol_batch_create(arr, len(self.cases), C.byref(b)))
         self.b = b
+        _live.add(self)
 
     def step(self, nsteps):
         if isinstance(nsteps, int):

@@ -122,7 +122,7 @@ static size_t footprint(const Sizes &z, int precision)
         if (precision) b += al(z.nd * n * F) + al(n * F);
     }
     b += 3 * 7 * al((size_t)z.maxn * D);                        // Krylov work vectors
-    if (precision) b += 3 * 8 * al((size_t)z.maxn * F) + 3 * 2 * al((size_t)z.maxn * D);
+    if (precision) b += 3 * 9 * al((size_t)z.maxn * F);         // FP32 inner work vectors
     b += al((size_t)z.ntile_cell * 4 * D) + 2 * al(256);         // reductions, counters, step
     return b;
 }
@@ -137,19 +137,19 @@ static int rows_per_tile(int n)
 
 // ------------------------------------------------------------------ timing
 
-struct TSample { int cls; int64_t iter; int phase; hipEvent_t a, b; };
+struct JobSet;
+struct TSample { int cls; int64_t iter; const JobSet *set; int tsize; hipEvent_t a, b; };
 struct TAcc { int64_t n = 0; double ms = 0.0, bytes = 0.0; };
 
-// algorithmic bytes per row of one launch (FP64): matrix values and every
-// vector element read or written once
-static double row_bytes(int cls, int nd, int dim)
+// algorithmic bytes per row of one launch: matrix values and every vector
+// element read or written once; tsize = bytes per value (8 FP64, 4 FP32)
+static double row_bytes(int cls, int nd, int dim, int tsize)
 {
     switch (cls) {
-    case SOL_KCLASS_CG_A: return 8.0 * nd + 40.0;   // A, r, p_old, M; p, q
-    case SOL_KCLASS_CG_B: return 56.0;              // x, p, r, q, M; x, r
-    case SOL_KCLASS_BICG_A: return 8.0 * nd + 56.0; // A, r, p, v, M, rh; p, v
-    case SOL_KCLASS_BICG_B: return 8.0 * nd + 32.0; // A, r, v, M; t
-    case SOL_KCLASS_BICG_C: return 72.0;            // x, r, v, p, M, t, rh; x, r
+    case SOL_KCLASS_CG: return (nd + 11.0) * tsize;     // A, r, w, s, M, p, x; p, s, x, r, w
+    case SOL_KCLASS_BICG_A: return (nd + 7.0) * tsize;  // A, r, p, v, M, rh; p, v
+    case SOL_KCLASS_BICG_B: return (nd + 4.0) * tsize;  // A, r, v, M; t
+    case SOL_KCLASS_BICG_C: return 9.0 * tsize;         // x, r, v, p, M, t, rh; x, r
     case SOL_KCLASS_ASM_MOM: return 16.0 * nd + 8.0 * dim + 48.0;
     case SOL_KCLASS_ASM_TRN: return 24.0 * nd + 8.0 * dim + 56.0;
     case SOL_KCLASS_PHASE: return 96.0 + 16.0 * dim;
@@ -171,8 +171,7 @@ struct sol_handle {
     Mem mem;
     CaseDev cd{};
     double *work[3][7] = {};
-    float *work32[3][8] = {};
-    double *work64x[3][2] = {};
+    float *work32[3][9] = {};
     int32_t *csr_cnt = nullptr, *csr_rp[NSYS] = {}, *csr_col[NSYS] = {};
     double *csr_val[NSYS] = {};
     Group *solo = nullptr;
@@ -186,16 +185,23 @@ struct sol_handle {
 
 // ------------------------------------------------------------------ groups
 
-struct Phase {
-    int kind = K_BICGSTAB;
-    int tcls0 = SOL_KCLASS_BICG_A;       // timing class of the first iteration kernel
+// A set of solves launched together (one kernel launch serves all of them).
+struct JobSet {
     std::vector<KJob> jobs;
-    std::vector<int> st_index;          // KState index (case * NSYS + system)
+    std::vector<int> st_index;          // index into the group's KState array
     std::vector<int> case_of, sys_of;
     KJob *jobs_d = nullptr;
     JTile *tiles_d[2] = {nullptr, nullptr};   // [0] 5-point jobs, [1] 7-point jobs
     int nt[2] = {0, 0};
-    int pred = 1;
+};
+
+struct Phase {
+    int kind = K_BICGSTAB;
+    int tcls0 = SOL_KCLASS_BICG_A;       // timing class of the first iteration kernel
+    bool mixed = false;
+    JobSet main;                         // FP64 solves (plain, or the refinements)
+    JobSet inner;                        // mixed precision: FP32 inner solves
+    int pred = 1, pred_inner = 1;
     int64_t launched = 0;
 };
 
@@ -204,16 +210,16 @@ struct Group {
     hipStream_t stream = nullptr;
     std::vector<void *> dmem;            // hipMalloc'd group arrays
     CaseDev *cases_d = nullptr;
-    KState *ks_d = nullptr;
+    KState *ks_d = nullptr;              // [2 * nks]: solves, then inner solves
     double *red_d = nullptr;
     int32_t *cidx_d = nullptr;           // 0..n-1 (per-case one-workgroup kernels)
     Tile *t_mom[2] = {}, *t_cell[2] = {}, *t_const[2] = {};
     int n_mom[2] = {}, n_cell[2] = {}, n_const[2] = {};
     Phase ph[3];                          // momentum, pressure, solute + energy
     KState *ks_h[2] = {nullptr, nullptr};  // pinned poll buffers
-    double *red_h = nullptr;
     hipEvent_t ev[2] = {nullptr, nullptr};
     int nks = 0;
+    int precision = SOL_PRECISION_FP64;
     sol_handle *timer = nullptr;          // handle that collects kernel timing (solo groups)
 };
 
@@ -233,7 +239,6 @@ static void group_free(Group *g)
         if (g->ks_h[i]) (void)hipHostFree(g->ks_h[i]);
         if (g->ev[i]) (void)hipEventDestroy(g->ev[i]);
     }
-    if (g->red_h) (void)hipHostFree(g->red_h);
     delete g;
 }
 
@@ -248,16 +253,45 @@ static int upload(Group &g, T **dst, const std::vector<T> &src)
     return SOL_OK;
 }
 
+// partial-sum buffers, tile lists and device copy of a job set
+static int finish_set(Group &g, JobSet &S)
+{
+    size_t total = 0;
+    for (auto &J : S.jobs) total += (size_t)J.ntile * 2 * NSLOT;
+    double *part = (double *)gmalloc(g, sizeof(double) * std::max<size_t>(total, 1));
+    if (!part) return fail(SOL_ENOMEM, "group allocation failed");
+    size_t off = 0;
+    std::vector<JTile> jt[2];
+    for (size_t j = 0; j < S.jobs.size(); ++j) {
+        KJob &J = S.jobs[j];
+        J.part = part + off;
+        off += (size_t)J.ntile * 2 * NSLOT;
+        const int gi = g.cs[S.case_of[j]]->z.nd == 7 ? 1 : 0;
+        for (int t = 0; t < J.ntile; ++t) jt[gi].push_back({(int)j, t});
+    }
+    RCHK(upload(g, &S.jobs_d, S.jobs));
+    for (int gi = 0; gi < 2; ++gi) {
+        RCHK(upload(g, &S.tiles_d[gi], jt[gi]));
+        S.nt[gi] = (int)jt[gi].size();
+    }
+    return SOL_OK;
+}
+
+// inner relative tolerance of the FP32 solves of the refinement
+static double inner_tol(double tol) { return std::max(tol, 1e-5); }
+
 static int group_build(Group &g)
 {
     const int n = (int)g.cs.size();
     g.nks = n * NSYS;
-    g.ks_d = (KState *)gmalloc(g, sizeof(KState) * g.nks);
+    g.precision = g.cs[0]->num.precision;
+    const bool mixed = g.precision == SOL_PRECISION_MIXED;
+    g.ks_d = (KState *)gmalloc(g, sizeof(KState) * 2 * g.nks);
     g.red_d = (double *)gmalloc(g, sizeof(double) * 16 * n);
     if (!g.ks_d || !g.red_d) return fail(SOL_ENOMEM, "group allocation failed");
     HIPCHK(hipMemset(g.red_d, 0, sizeof(double) * 16 * n));
     std::vector<CaseDev> cdv(n);
-    std::vector<KState> ksv(g.nks);
+    std::vector<KState> ksv(2 * g.nks);
     for (auto &k : ksv) { std::memset(&k, 0, sizeof(k)); k.status = K_IDLE; }
     std::vector<Tile> mom[2], cell[2], cst[2];
     for (int c = 0; c < n; ++c) {
@@ -274,10 +308,15 @@ static int group_build(Group &g)
         for (int s : cs_list)
             for (int t = 0; t < ceil_div(h->z.nsys[s], TILE); ++t) cst[gi].push_back({c, s, t, 0});
         for (int s = 0; s < NSYS; ++s) {
-            KState &k = ksv[c * NSYS + s];
             const double tol = s == SP ? h->num.tol_p : h->num.tol_t;
+            KState &k = ksv[c * NSYS + s];
             k.tol2 = tol * tol;
             k.max_iter = h->num.max_iter;
+            KState &ki = ksv[g.nks + c * NSYS + s];
+            ki.tol2 = inner_tol(tol) * inner_tol(tol);
+            // FP32 Krylov can stagnate near its rounding floor: bound one inner
+            // solve well above the CG count the grid needs (~ a few n per axis)
+            ki.max_iter = std::min(h->num.max_iter, 20 * (h->z.nx + h->z.ny + h->z.nz) + 100);
         }
     }
     RCHK(upload(g, &g.cases_d, cdv));
@@ -286,7 +325,7 @@ static int group_build(Group &g)
         for (int c = 0; c < n; ++c) ci[c] = c;
         RCHK(upload(g, &g.cidx_d, ci));
     }
-    HIPCHK(hipMemcpy(g.ks_d, ksv.data(), sizeof(KState) * g.nks, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(g.ks_d, ksv.data(), sizeof(KState) * 2 * g.nks, hipMemcpyHostToDevice));
     for (int gi = 0; gi < 2; ++gi) {
         RCHK(upload(g, &g.t_mom[gi], mom[gi]));
         RCHK(upload(g, &g.t_cell[gi], cell[gi]));
@@ -300,9 +339,8 @@ static int group_build(Group &g)
     for (int p = 0; p < 3; ++p) {
         Phase &P = g.ph[p];
         P.kind = p == 1 ? K_CG : K_BICGSTAB;
-        P.tcls0 = p == 1 ? SOL_KCLASS_CG_A : SOL_KCLASS_BICG_A;
-        std::vector<JTile> jt[2];
-        size_t part_total = 0;
+        P.tcls0 = p == 1 ? SOL_KCLASS_CG : SOL_KCLASS_BICG_A;
+        P.mixed = mixed;
         for (int c = 0; c < n; ++c) {
             sol_handle *h = g.cs[c];
             for (int k = 0; k < 3; ++k) {
@@ -324,37 +362,53 @@ static int group_build(Group &g)
                 else if (p == 1) { J.x = h->cd.phi; J.x0 = nullptr; }
                 else if (s == SC) { J.x = h->cd.Cnew; J.x0 = h->cd.C; }
                 else { J.x = h->cd.Tstar; J.x0 = h->cd.T; }
-                J.r = h->work[ws][0]; J.rh = h->work[ws][1];
-                J.p0 = h->work[ws][2]; J.p1 = h->work[ws][3];
-                J.v0 = h->work[ws][4]; J.v1 = h->work[ws][5];
-                J.t = h->work[ws][6];
                 J.st = g.ks_d + c * NSYS + s;
-                part_total += (size_t)J.ntile * 2 * NSLOT;
-                const int gi = h->z.nd == 7 ? 1 : 0;
-                const int jidx = (int)P.jobs.size();
-                for (int t = 0; t < J.ntile; ++t) jt[gi].push_back({jidx, t});
-                P.jobs.push_back(J);
-                P.st_index.push_back(c * NSYS + s);
-                P.case_of.push_back(c);
-                P.sys_of.push_back(s);
+                if (!mixed) {
+                    J.role = ROLE_PLAIN;
+                    J.r = h->work[ws][0]; J.rh = h->work[ws][1];
+                    J.p0 = h->work[ws][2]; J.p1 = h->work[ws][3];
+                    J.v0 = h->work[ws][4]; J.v1 = h->work[ws][5];
+                    J.t = h->work[ws][6];
+                } else {
+                    // refinement: FP64 residual sweeps; aux = FP32 residual, t = FP32 correction
+                    KState *ist = g.ks_d + g.nks + c * NSYS + s;
+                    J.role = ROLE_REFINE;
+                    J.aux = h->work32[ws][8];
+                    J.t = h->work32[ws][7];
+                    J.partner = ist;
+                    KJob I = J;
+                    I.role = ROLE_INNER;
+                    I.A = h->cd.A32[s];
+                    I.minv = h->cd.minv32[s];
+                    I.b = h->work32[ws][8];
+                    I.x = h->work32[ws][7];
+                    I.x0 = nullptr;
+                    I.aux = nullptr;
+                    I.r = h->work32[ws][0]; I.rh = h->work32[ws][1];
+                    I.p0 = h->work32[ws][2]; I.p1 = h->work32[ws][3];
+                    I.v0 = h->work32[ws][4]; I.v1 = h->work32[ws][5];
+                    I.t = h->work32[ws][6];
+                    I.st = ist;
+                    I.partner = J.st;
+                    P.inner.jobs.push_back(I);
+                    P.inner.st_index.push_back(g.nks + c * NSYS + s);
+                    P.inner.case_of.push_back(c);
+                    P.inner.sys_of.push_back(s);
+                }
+                P.main.jobs.push_back(J);
+                P.main.st_index.push_back(c * NSYS + s);
+                P.main.case_of.push_back(c);
+                P.main.sys_of.push_back(s);
             }
         }
-        double *part = (double *)gmalloc(g, sizeof(double) * std::max<size_t>(part_total, 1));
-        if (!part) return fail(SOL_ENOMEM, "group allocation failed");
-        size_t off = 0;
-        for (auto &J : P.jobs) { J.part = part + off; off += (size_t)J.ntile * 2 * NSLOT; }
-        RCHK(upload(g, &P.jobs_d, P.jobs));
-        for (int gi = 0; gi < 2; ++gi) {
-            RCHK(upload(g, &P.tiles_d[gi], jt[gi]));
-            P.nt[gi] = (int)jt[gi].size();
-        }
-        P.pred = p == 1 ? 64 : 2;
+        RCHK(finish_set(g, P.main));
+        if (mixed) RCHK(finish_set(g, P.inner));
+        P.pred = P.pred_inner = p == 1 ? 64 : 2;
     }
     for (int i = 0; i < 2; ++i) {
-        HIPCHK(hipHostMalloc((void **)&g.ks_h[i], sizeof(KState) * g.nks, hipHostMallocDefault));
+        HIPCHK(hipHostMalloc((void **)&g.ks_h[i], sizeof(KState) * 2 * g.nks, hipHostMallocDefault));
         HIPCHK(hipEventCreateWithFlags(&g.ev[i], hipEventDisableTiming));
     }
-    HIPCHK(hipHostMalloc((void **)&g.red_h, sizeof(double) * 16 * n, hipHostMallocDefault));
     return SOL_OK;
 }
 
@@ -383,10 +437,10 @@ static hipEvent_t take_event(sol_handle *h)
     return e;
 }
 
-// Turn the samples of a finished solve phase (or of a fixed launch) into
-// durations; a Krylov sample counts only for jobs still iterating at that
-// launch (its iteration index below the job's final count, no restart).
-static void collect_samples(Group &g, Phase *P, const KState *ks)
+// Turn the pending samples into durations (after a synchronising poll whose
+// states are ks); a Krylov sample counts only for solves still iterating at
+// that launch (iteration index below the solve's final count, no restart).
+static void collect_samples(Group &g, const KState *ks)
 {
     sol_handle *h = g.timer;
     if (!h) return;
@@ -395,22 +449,26 @@ static void collect_samples(Group &g, Phase *P, const KState *ks)
         if (hipEventElapsedTime(&ms, s.a, s.b) != hipSuccess) continue;
         double bytes = 0.0;
         bool valid = true;
-        if (s.phase >= 0 && P) {
+        if (s.set) {
             double rows = 0.0;
             int nd = 5, dim = 2;
-            for (size_t j = 0; j < P->jobs.size(); ++j) {
-                const KState &k = ks[P->st_index[j]];
+            for (size_t j = 0; j < s.set->jobs.size(); ++j) {
+                const KState &k = ks[s.set->st_index[j]];
                 if (k.restarts != 0) valid = false;
-                if (s.iter < k.it) { rows += P->jobs[j].n; nd = g.cs[P->case_of[j]]->z.nd; dim = g.cs[P->case_of[j]]->z.dim; }
+                if (s.iter < k.it) {
+                    rows += s.set->jobs[j].n;
+                    nd = g.cs[s.set->case_of[j]]->z.nd;
+                    dim = g.cs[s.set->case_of[j]]->z.dim;
+                }
             }
             if (rows == 0.0) valid = false;
-            bytes = rows * row_bytes(s.cls, nd, dim);
+            bytes = rows * row_bytes(s.cls, nd, dim, s.tsize);
         } else {
             for (auto *c : g.cs) {
                 const double rows = s.cls == SOL_KCLASS_ASM_MOM
                                         ? (double)(c->z.nsys[0] + c->z.nsys[1] + c->z.nsys[2])
                                         : (double)c->z.ncell;
-                bytes += rows * row_bytes(s.cls, c->z.nd, c->z.dim);
+                bytes += rows * row_bytes(s.cls, c->z.nd, c->z.dim, 8);
             }
         }
         if (valid) {
@@ -426,22 +484,22 @@ static void collect_samples(Group &g, Phase *P, const KState *ks)
 
 // ------------------------------------------------------------------ solves
 
-static void enqueue_iters(Group &g, Phase &P, int nits, int &k, int phase_id)
+static void enqueue_iters(Group &g, Phase &P, const JobSet &S, int fp32, int nits, int &k)
 {
     sol_handle *tm = g.timer;
+    const int nk = P.kind == K_CG ? 1 : 3;
     for (int it = 0; it < nits; ++it) {
-        const bool sample = tm && (P.launched % 8 == 0);
-        const int nk = P.kind == K_CG ? 2 : 3;
+        const bool sample = tm && (k % 8 == 0);
         for (int q = 0; q < nk; ++q) {
-            const int which = (P.kind == K_CG ? KI_CG_A : KI_BICG_A) + q;
+            const int which = (P.kind == K_CG ? KI_CG : KI_BICG_A) + q;
             hipEvent_t a = nullptr, b = nullptr;
             if (sample) { a = take_event(tm); b = take_event(tm); }
             if (a && b) (void)hipEventRecord(a, g.stream);
             for (int gi = 0; gi < 2; ++gi)
-                launch_kiter(which, gi ? 7 : 5, P.jobs_d, P.tiles_d[gi], P.nt[gi], k, g.stream);
+                launch_kiter(which, gi ? 7 : 5, fp32, S.jobs_d, S.tiles_d[gi], S.nt[gi], k, g.stream);
             if (a && b) {
                 (void)hipEventRecord(b, g.stream);
-                tm->samples.push_back({P.tcls0 + q, P.launched, phase_id, a, b});
+                tm->samples.push_back({P.tcls0 + q, (int64_t)k, &S, fp32 ? 4 : 8, a, b});
             }
         }
         k += 1;
@@ -451,7 +509,7 @@ static void enqueue_iters(Group &g, Phase &P, int nits, int &k, int phase_id)
 
 static int poll_enqueue(Group &g, int slot)
 {
-    HIPCHK(hipMemcpyAsync(g.ks_h[slot], g.ks_d, sizeof(KState) * g.nks, hipMemcpyDeviceToHost, g.stream));
+    HIPCHK(hipMemcpyAsync(g.ks_h[slot], g.ks_d, sizeof(KState) * 2 * g.nks, hipMemcpyDeviceToHost, g.stream));
     HIPCHK(hipEventRecord(g.ev[slot], g.stream));
     return SOL_OK;
 }
@@ -462,56 +520,136 @@ static int poll_wait(Group &g, int slot)
     return SOL_OK;
 }
 
-static bool any_status(const Group &g, const Phase &P, int slot, int status)
+static bool any_status(const Group &g, const JobSet &S, int slot, int status)
 {
-    for (int idx : P.st_index)
+    for (int idx : S.st_index)
         if (g.ks_h[slot][idx].status == status) return true;
     return false;
 }
 
-static int group_solve(Group &g, Phase &P, int phase_id)
+// does any solve of S still iterate?  gate (inner solves): only those whose
+// refinement was RUNNING at the last synchronising poll (slot gslot)
+static bool any_running(const Group &g, const JobSet &S, int slot, const JobSet *gate, int gslot)
 {
-    if (P.jobs.empty()) return SOL_OK;
+    for (size_t j = 0; j < S.st_index.size(); ++j) {
+        if (gate && g.ks_h[gslot][gate->st_index[j]].status != K_RUNNING) continue;
+        if (g.ks_h[slot][S.st_index[j]].status == K_RUNNING) return true;
+    }
+    return false;
+}
+
+// Queue iteration chunks of the solves in S until none is RUNNING.  While
+// the host inspects chunk i the device runs chunk i+1.  Returns the slot
+// holding the newest states.
+static int iterate(Group &g, Phase &P, const JobSet &S, int fp32, int pred, int &k, const JobSet *gate,
+                   int gslot, int *out_slot)
+{
+    int slot = gslot ^ 1;
+    const int first = std::max(1, pred - pred / 8);
+    const int later = std::max(2, pred / 16);
+    enqueue_iters(g, P, S, fp32, first, k);
+    RCHK(poll_enqueue(g, slot));
+    for (;;) {
+        enqueue_iters(g, P, S, fp32, later, k);
+        RCHK(poll_enqueue(g, slot ^ 1));
+        RCHK(poll_wait(g, slot));
+        if (!any_running(g, S, slot, gate, gslot)) {
+            RCHK(poll_wait(g, slot ^ 1));
+            *out_slot = slot ^ 1;
+            return SOL_OK;
+        }
+        slot ^= 1;
+    }
+}
+
+static void record_iters(Group &g, const JobSet &S, int slot, int *mx)
+{
+    for (size_t j = 0; j < S.jobs.size(); ++j) {
+        const KState &ks = g.ks_h[slot][S.st_index[j]];
+        *mx = std::max(*mx, (int)ks.it);
+        g.cs[S.case_of[j]]->last_iters[S.sys_of[j]] = ks.it;
+    }
+}
+
+// plain FP64 solves
+static int solve_plain(Group &g, Phase &P)
+{
+    JobSet &S = P.main;
     int k = 0;                       // host iteration index of the next launch
     P.launched = 0;
     for (int gi = 0; gi < 2; ++gi)
-        launch_kinit(gi ? 7 : 5, P.jobs_d, P.tiles_d[gi], P.nt[gi], k, 0, g.stream);
+        launch_kinit(P.kind, gi ? 7 : 5, 0, S.jobs_d, S.tiles_d[gi], S.nt[gi], k, 0, g.stream);
     int rc = SOL_OK;
     for (int round = 0; round < 64; ++round) {
-        int slot = 0;
-        const int first = round == 0 ? std::max(1, P.pred - P.pred / 8) : std::max(2, P.pred / 8);
-        const int later = std::max(2, P.pred / 16);
-        enqueue_iters(g, P, first, k, phase_id);
-        RCHK(poll_enqueue(g, slot));
-        for (;;) {
-            enqueue_iters(g, P, later, k, phase_id);
-            RCHK(poll_enqueue(g, slot ^ 1));
-            RCHK(poll_wait(g, slot));
-            if (!any_status(g, P, slot, K_RUNNING)) { RCHK(poll_wait(g, slot ^ 1)); break; }
-            slot ^= 1;
-        }
-        for (int gi = 0; gi < 2; ++gi)
-            launch_kfinish(gi ? 7 : 5, P.jobs_d, P.tiles_d[gi], P.nt[gi], g.stream);
-        launch_kdecide(P.jobs_d, (int)P.jobs.size(), g.stream);
+        int slot;
+        RCHK(iterate(g, P, S, 0, round == 0 ? P.pred : std::max(2, P.pred / 8), k, nullptr, 1, &slot));
+        for (int gi = 0; gi < 2; ++gi) launch_kfinish(gi ? 7 : 5, S.jobs_d, S.tiles_d[gi], S.nt[gi], g.stream);
+        launch_kdecide(S.jobs_d, (int)S.jobs.size(), g.stream);
         RCHK(poll_enqueue(g, 0));
         RCHK(poll_wait(g, 0));
         HIPCHK(hipGetLastError());
-        if (any_status(g, P, 0, K_NONFINITE)) { rc = fail(SOL_ENONFINITE, "non-finite value in a linear solve"); break; }
-        if (any_status(g, P, 0, K_FAILED)) { rc = fail(SOL_ENOCONV, "linear solve did not converge within max_iter"); break; }
-        if (!any_status(g, P, 0, K_RESTART)) break;
+        if (any_status(g, S, 0, K_NONFINITE)) { rc = fail(SOL_ENONFINITE, "non-finite value in a linear solve"); break; }
+        if (any_status(g, S, 0, K_FAILED)) { rc = fail(SOL_ENOCONV, "linear solve did not converge within max_iter"); break; }
+        if (!any_status(g, S, 0, K_RESTART)) break;
         for (int gi = 0; gi < 2; ++gi)
-            launch_kinit(gi ? 7 : 5, P.jobs_d, P.tiles_d[gi], P.nt[gi], k, 1, g.stream);
+            launch_kinit(P.kind, gi ? 7 : 5, 0, S.jobs_d, S.tiles_d[gi], S.nt[gi], k, 1, g.stream);
         if (round == 63) rc = fail(SOL_ENOCONV, "linear solve kept restarting");
     }
     int mx = 1;
-    for (size_t j = 0; j < P.jobs.size(); ++j) {
-        const KState &ks = g.ks_h[0][P.st_index[j]];
-        mx = std::max(mx, (int)ks.it);
-        g.cs[P.case_of[j]]->last_iters[P.sys_of[j]] = ks.it;
-    }
+    record_iters(g, S, 0, &mx);
     P.pred = mx;
-    if (g.timer) collect_samples(g, &P, g.ks_h[0]);
+    if (g.timer) collect_samples(g, g.ks_h[0]);
     return rc;
+}
+
+// mixed precision: FP64 residual sweeps around FP32 inner solves
+static int solve_mixed(Group &g, Phase &P)
+{
+    JobSet &S = P.main, &I = P.inner;
+    const int nj = (int)S.jobs.size();
+    const int max_outer = 60;
+    P.launched = 0;
+    for (int gi = 0; gi < 2; ++gi) launch_ir_resid(gi ? 7 : 5, S.jobs_d, S.tiles_d[gi], S.nt[gi], 0, g.stream);
+    launch_ir_decide(S.jobs_d, nj, 0, max_outer, g.stream);
+    RCHK(poll_enqueue(g, 0));
+    RCHK(poll_wait(g, 0));
+    int mx_inner = 1;
+    for (int outer = 0; outer < max_outer + 1; ++outer) {
+        if (!any_status(g, S, 0, K_RUNNING)) break;
+        int k = 0;
+        for (int gi = 0; gi < 2; ++gi)
+            launch_kinit(P.kind, gi ? 7 : 5, 1, I.jobs_d, I.tiles_d[gi], I.nt[gi], k, 0, g.stream);
+        int slot;
+        RCHK(iterate(g, P, I, 1, P.pred_inner, k, &S, 0, &slot));
+        for (int gi = 0; gi < 2; ++gi) launch_ir_update(gi ? 7 : 5, S.jobs_d, S.tiles_d[gi], S.nt[gi], g.stream);
+        for (int gi = 0; gi < 2; ++gi) launch_ir_resid(gi ? 7 : 5, S.jobs_d, S.tiles_d[gi], S.nt[gi], 1, g.stream);
+        launch_ir_decide(S.jobs_d, nj, 1, max_outer, g.stream);
+        RCHK(poll_enqueue(g, 0));
+        RCHK(poll_wait(g, 0));
+        HIPCHK(hipGetLastError());
+        for (size_t j = 0; j < I.jobs.size(); ++j) mx_inner = std::max(mx_inner, (int)g.ks_h[0][I.st_index[j]].it);
+        if (g.timer) collect_samples(g, g.ks_h[0]);
+    }
+    for (int gi = 0; gi < 2; ++gi) launch_ir_update(gi ? 7 : 5, S.jobs_d, S.tiles_d[gi], S.nt[gi], g.stream);
+    launch_ir_close(S.jobs_d, nj, g.stream);
+    RCHK(poll_enqueue(g, 0));
+    RCHK(poll_wait(g, 0));
+    HIPCHK(hipGetLastError());
+    P.pred_inner = mx_inner;
+    int mx = 1;
+    record_iters(g, S, 0, &mx);
+    P.pred = mx;
+    if (any_status(g, S, 0, K_NONFINITE)) return fail(SOL_ENONFINITE, "non-finite value in a linear solve");
+    if (any_status(g, S, 0, K_FAILED) || any_status(g, S, 0, K_RUNNING))
+        return fail(SOL_ENOCONV, "refinement did not reach the tolerance");
+    if (g.timer) collect_samples(g, g.ks_h[0]);
+    return SOL_OK;
+}
+
+static int group_solve(Group &g, Phase &P)
+{
+    if (P.main.jobs.empty()) return SOL_OK;
+    return P.mixed ? solve_mixed(g, P) : solve_plain(g, P);
 }
 
 template <class F>
@@ -524,7 +662,7 @@ static void timed(Group &g, int cls, F launch)
     launch();
     if (a && b) {
         (void)hipEventRecord(b, g.stream);
-        tm->samples.push_back({cls, 0, -1, a, b});
+        tm->samples.push_back({cls, 0, nullptr, 8, a, b});
     }
 }
 
@@ -536,20 +674,20 @@ static int group_step(Group &g)
     timed(g, SOL_KCLASS_ASM_MOM, [&] {
         for (int gi = 0; gi < 2; ++gi) launch_asm_momentum(gi ? 3 : 2, g.cases_d, g.t_mom[gi], g.n_mom[gi], s);
     });
-    RCHK(group_solve(g, g.ph[0], 0));
+    RCHK(group_solve(g, g.ph[0]));
     // 2: pressure correction
     for (int gi = 0; gi < 2; ++gi) {
         launch_div_rhs(gi ? 3 : 2, g.cases_d, g.t_cell[gi], g.n_cell[gi], 1, s);
         launch_sub_mean(g.cases_d, g.t_cell[gi], g.n_cell[gi], s);
     }
-    RCHK(group_solve(g, g.ph[1], 1));
+    RCHK(group_solve(g, g.ph[1]));
     // 3: projection
     for (int gi = 0; gi < 2; ++gi) launch_project(g.cases_d, g.t_mom[gi], g.n_mom[gi], s);
     // 4-6: solute and energy systems (both only need u^{n+1})
     timed(g, SOL_KCLASS_ASM_TRN, [&] {
         for (int gi = 0; gi < 2; ++gi) launch_asm_transport(gi ? 3 : 2, g.cases_d, g.t_cell[gi], g.n_cell[gi], 1, s);
     });
-    RCHK(group_solve(g, g.ph[2], 2));
+    RCHK(group_solve(g, g.ph[2]));
     // 7-8: phase update, C_l, C_s; commit level n+1
     timed(g, SOL_KCLASS_PHASE, [&] {
         for (int gi = 0; gi < 2; ++gi) launch_phase_commit(gi ? 3 : 2, g.cases_d, g.t_cell[gi], g.n_cell[gi], s);
@@ -607,8 +745,6 @@ static int validate(const sol_grid *g, const sol_alloy *a, const sol_bcs *b, con
     if (n->max_iter < 1) return fail(SOL_EINVAL, "max_iter must be >= 1");
     if (n->precision != SOL_PRECISION_FP64 && n->precision != SOL_PRECISION_MIXED)
         return fail(SOL_EINVAL, "precision must be SOL_PRECISION_FP64 or SOL_PRECISION_MIXED");
-    if (n->precision == SOL_PRECISION_MIXED)
-        return fail(SOL_EINVAL, "mixed precision is not built into this library version");
     return SOL_OK;
 }
 
@@ -698,6 +834,18 @@ static int alloc_case(sol_handle *h)
     for (int w = 0; w < 3; ++w)
         for (int k = 0; k < 7; ++k)
             if (!(h->work[w][k] = dal(z.maxn))) return fail(SOL_ENOMEM, "device allocation failed");
+    if (h->num.precision == SOL_PRECISION_MIXED) {
+        auto fal = [&](size_t n) { return (float *)m.get(std::max<size_t>(n, 1) * sizeof(float)); };
+        for (int s = 0; s < NSYS; ++s) {
+            const size_t n = std::max(z.nsys[s], 1);
+            d.A32[s] = fal(z.nd * n);
+            d.minv32[s] = fal(n);
+            if (!d.A32[s] || !d.minv32[s]) return fail(SOL_ENOMEM, "device allocation failed");
+        }
+        for (int w = 0; w < 3; ++w)
+            for (int k = 0; k < 9; ++k)
+                if (!(h->work32[w][k] = fal(z.maxn))) return fail(SOL_ENOMEM, "device allocation failed");
+    }
     d.red_part = dal((size_t)z.ntile_cell * 4);
     d.red_cnt = (uint32_t *)m.get(256);
     d.step = (int64_t *)m.get(256);
@@ -726,6 +874,9 @@ static int init_state(sol_handle *h)
     launch_fill(d.Tstar, h->al.T_ref, z.ncell, s);
     for (int w = 0; w < 3; ++w)
         for (int k = 0; k < 7; ++k) launch_fill(h->work[w][k], 0.0, z.maxn, s);
+    for (int w = 0; w < 3; ++w)
+        for (int k = 0; k < 9; ++k)
+            if (h->work32[w][k]) HIPCHK(hipMemsetAsync(h->work32[w][k], 0, sizeof(float) * std::max(z.maxn, 1), s));
     HIPCHK(hipMemsetAsync(d.red_cnt, 0, 256, s));
     HIPCHK(hipMemsetAsync(d.step, 0, 256, s));
     HIPCHK(hipGetLastError());
@@ -961,7 +1112,7 @@ int sol_step(sol_handle *h, int32_t nsteps, sol_step_stats *stats)
         for (int s = 0; s < NSYS; ++s) tot[s] += h->last_iters[s];
         if (g.timer) {
             HIPCHK(hipStreamSynchronize(h->stream));
-            collect_samples(g, nullptr, nullptr);
+            collect_samples(g, g.ks_h[0]);
         }
     }
     if (stats) RCHK(fill_stats(g, 0, stats, tot));
@@ -1003,6 +1154,8 @@ int sol_batch_create(sol_handle *const *cases, int32_t n, sol_batch **out)
         if (!cases[i]) return fail(SOL_EINVAL, "NULL handle %d", i);
         if (cases[i]->batch) return fail(SOL_EBUSY, "handle %d already in a batch", i);
         if (cases[i]->stream != cases[0]->stream) return fail(SOL_EINVAL, "handles must share one stream");
+        if (cases[i]->num.precision != cases[0]->num.precision)
+            return fail(SOL_EINVAL, "handles of one batch must share one precision");
         for (int j = 0; j < i; ++j)
             if (cases[j] == cases[i]) return fail(SOL_EINVAL, "handle %d given twice", i);
     }

@@ -101,22 +101,6 @@ __device__ __forceinline__ int slot_off(int s, int sx, int sxy)
     switch (s) { case 0: return -sx; case 1: return -1; case 2: return 0; case 3: return 1; default: return sx; }
 }
 
-// y_i = sum_s A[s][i] * f(i + off_s).  Slots whose neighbour lies outside the
-// domain hold an exact 0 coefficient; their index is clamped into [0, n) so
-// that no access leaves the arrays.
-template <int ND, class TA, class F>
-__device__ __forceinline__ double stencil(const TA *__restrict__ A, int n, int i, int sx, int sxy, F f)
-{
-    double acc = 0.0;
-#pragma unroll
-    for (int s = 0; s < ND; ++s) {
-        int j = i + slot_off<ND>(s, sx, sxy);
-        j = j < 0 ? 0 : (j >= n ? n - 1 : j);
-        acc += (double)A[(size_t)s * n + i] * f(j);
-    }
-    return acc;
-}
-
 __device__ __forceinline__ bool finite(double x) { return __builtin_isfinite(x); }
 
 // ----------------------------------------------------------- grid helpers
@@ -578,25 +562,46 @@ __global__ __launch_bounds__(TILE) void k_case_stats(const CaseDev *__restrict__
 }
 
 // ------------------------------------------------------------- Krylov
-// Jacobi-preconditioned CG (pressure) and BiCGSTAB (transport).  Each
-// iteration is split at its global reductions.  A kernel of iteration k
-// first totals the partial sums the previous kernels left (iteration k-1 in
-// the buffers of parity (k-1)&1, iteration k in parity k&1), derives the
-// scalars (alpha, beta, omega) and the convergence decision, identically in
-// every workgroup, then works on its rows and writes its own partials.
-// The preconditioned vector the matrix product needs at neighbour rows is
-// recomputed there from vectors the previous kernel left unchanged, so no
-// extra pass writes it; vectors overwritten while neighbours still read them
-// are ping-ponged by iteration parity.  Workgroup 0 of a solve records a
-// status change (converged, failed, restart); every other workgroup reaches
-// the same decision from the same totals and stops with it.
-
-typedef __attribute__((address_space(1))) double gdbl;
+// Jacobi-preconditioned CG (pressure) and BiCGSTAB (transport), templated on
+// the vector / matrix type T (double; float for the inner solves of the
+// mixed-precision refinement).  Every kernel of iteration k first totals the
+// partial sums the previous kernels left (iteration k-1 in the buffers of
+// parity (k+1)&1, iteration k in parity k&1), derives the scalars and the
+// convergence decision identically in every workgroup, then works on its
+// rows and writes its own partials.  Vectors a matrix product needs at
+// neighbour rows are recomputed there from vectors the previous kernel left
+// unchanged; vectors overwritten while neighbours still read them are
+// ping-ponged by iteration parity.  Workgroup 0 of a solve records status
+// changes; the other workgroups reach the same decision and stop with it.
+//
+// CG runs one kernel per iteration (the Chronopoulos-Gear arrangement of
+// the same recurrences: both inner products of an iteration are taken
+// together, so one global reduction separates consecutive iterations):
+//   p = u + beta p, s = w + beta s, x += alpha p, r -= alpha s, u = M r,
+//   w = A u, gamma = (r, u), delta = (w, u),
+//   beta = gamma / gamma_old, alpha = gamma / (delta - beta gamma / alpha_old).
 
 template <class T>
-__device__ __forceinline__ gdbl *G(T *p) { return (gdbl *)p; }
+using gptr = __attribute__((address_space(1))) T *;
+
 template <class T>
-__device__ __forceinline__ const gdbl *GC(const T *p) { return (const gdbl *)p; }
+__device__ __forceinline__ gptr<T> G(const void *p) { return (gptr<T>)(p); }
+
+// y_i = sum_s A[s][i] * f(i + off_s) in type T.  Slots whose neighbour lies
+// outside the domain hold an exact 0 coefficient; their index is clamped
+// into [0, n) so that no access leaves the arrays.
+template <int ND, class T, class F>
+__device__ __forceinline__ T kstencil(gptr<T> A, int n, int i, int sx, int sxy, F f)
+{
+    T acc = T(0);
+#pragma unroll
+    for (int s = 0; s < ND; ++s) {
+        int j = i + slot_off<ND>(s, sx, sxy);
+        j = j < 0 ? 0 : (j >= n ? n - 1 : j);
+        acc += A[(size_t)s * n + i] * f(j);
+    }
+    return acc;
+}
 
 __device__ __forceinline__ const KJob &job_of(const KJob *jobs, const JTile *tiles, JTile &tl)
 {
@@ -606,15 +611,21 @@ __device__ __forceinline__ const KJob &job_of(const KJob *jobs, const JTile *til
 
 __device__ __forceinline__ int poff(const KJob &J, int par, int slot) { return (par * NSLOT + slot) * J.ntile; }
 
-// status of a solve as seen by iteration k: RUNNING, or a (re)start whose
-// first iteration is k
-__device__ __forceinline__ bool active(const KState *st, int k)
+// an inner solve whose refinement no longer needs it
+__device__ __forceinline__ bool outer_idle(const KJob &J)
 {
-    const int s = st->status;
-    return s == K_RUNNING || (s == K_RESTART && k == st->k0);
+    return J.role == ROLE_INNER && J.partner->status != K_RUNNING;
 }
 
-// record a terminal (or restart) status: workgroup 0 of the solve only
+// status of a solve as seen by iteration k: RUNNING, or a (re)start whose
+// first iteration is k
+__device__ __forceinline__ bool active(const KJob &J, int k)
+{
+    const int s = J.st->status;
+    return s == K_RUNNING || (s == K_RESTART && k == J.st->k0);
+}
+
+// record a status change: workgroup 0 of the solve only
 __device__ __forceinline__ void set_status(const JTile &tl, KState *st, int status, int it, double rr)
 {
     if (tl.t == 0 && threadIdx.x == 0) {
@@ -624,49 +635,9 @@ __device__ __forceinline__ void set_status(const JTile &tl, KState *st, int stat
     }
 }
 
-// Start of a solve at host iteration index k (mode 0: every solve, x = x0 or
-// 0; mode 1: solves in K_RESTART, keep x).  r = b - A x, rh = r, p = v = 0;
-// partials (r,Mr) or (rh,r), (r,r), (b,b) for iteration k.
-template <int ND>
-__global__ __launch_bounds__(TILE) void k_kinit(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles, int k, int mode)
+// record the start of a solve at iteration index k (workgroup 0)
+__device__ __forceinline__ void mark_start(const JTile &tl, KState *st, int k, int mode)
 {
-    JTile tl;
-    const KJob &J = job_of(jobs, tiles, tl);
-    KState *st = J.st;
-    if (mode == 1 && st->status != K_RESTART) return;
-    const int n = J.n;
-    const int flip = k & 1;
-    const gdbl *A = GC(J.A), *b = GC(J.b), *mi = GC(J.minv);
-    gdbl *x = G(J.x), *r = G(J.r), *rh = G(J.rh);
-    gdbl *po = G(flip ? J.p1 : J.p0), *vo = G(flip ? J.v1 : J.v0);
-    const gdbl *x0 = GC(J.x0);
-    double v[3] = {0.0, 0.0, 0.0};
-    const int i0 = tl.t * J.rpt;
-    const int i1 = min(n, i0 + J.rpt);
-    for (int i = i0 + threadIdx.x; i < i1; i += TILE) {
-        double ri;
-        if (mode == 0) {
-            if (x0) {
-                ri = b[i] - stencil<ND>(A, n, i, J.sx, J.sxy, [&](int j) { return x0[j]; });
-                x[i] = x0[i];
-            } else {
-                ri = b[i];
-                x[i] = 0.0;
-            }
-        } else {
-            ri = b[i] - stencil<ND>(A, n, i, J.sx, J.sxy, [&](int j) { return x[j]; });
-        }
-        r[i] = ri;
-        rh[i] = ri;
-        po[i] = 0.0;
-        vo[i] = 0.0;
-        v[0] += J.kind == K_CG ? ri * mi[i] * ri : ri * ri;
-        v[1] += ri * ri;
-        v[2] += b[i] * b[i];
-    }
-    const int par = (k + 1) & 1;               // = parity of iteration k-1
-    const int off[3] = {poff(J, par, PS_RHO), poff(J, par, PS_RR), poff(J, par, PS_BB)};
-    put_partials<3>(v, J.part, off, tl.t);
     if (tl.t == 0 && threadIdx.x == 0) {
         st->k0 = k;
         if (mode == 0) { st->it_base = 0; st->restarts = 0; st->status = K_RUNNING; }
@@ -674,17 +645,15 @@ __global__ __launch_bounds__(TILE) void k_kinit(const KJob *__restrict__ jobs, c
     }
 }
 
-// convergence test at the start of iteration k (shared by CG and BiCGSTAB);
-// returns false when the solve stops here
-__device__ __forceinline__ bool test_convergence(const KJob &J, const JTile &tl, KState *st, int k,
-                                                 double rr, double &bb)
+// convergence test at the start of iteration k; rr = ||r_k||^2 and bbp =
+// total of the (b,b) partials left by the start kernels (used at k = k0)
+__device__ __forceinline__ bool keep_going(const KJob &J, const JTile &tl, int k, double rr, double bbp)
 {
+    KState *st = J.st;
     const int it = st->it_base + (k - st->k0);
+    double bb;
     if (k == st->k0) {
-        const int off[1] = {poff(J, (k + 1) & 1, PS_BB)};
-        double t[1];
-        sum_partials<1>(J.part, off, J.ntile, t);
-        bb = t[0];
+        bb = bbp;
         if (tl.t == 0 && threadIdx.x == 0) st->bb = bb;
     } else {
         bb = st->bb;
@@ -697,141 +666,109 @@ __device__ __forceinline__ bool test_convergence(const KJob &J, const JTile &tl,
     return true;
 }
 
-// CG, first half of iteration k: beta = rho_k / rho_{k-1}; p = M r + beta p;
-// q = A p; partial (p, q)
-template <int ND>
-__global__ __launch_bounds__(TILE) void k_cg_a(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles, int k)
+// ---- BiCGSTAB start at iteration index k (mode 0: every solve, x = x0 or 0;
+// mode 1: solves in K_RESTART, keep x): r = b - A x, rh = r, p = v = 0;
+// partials (rh, r), (r, r), (b, b) for iteration k.
+template <int ND, class T>
+__global__ __launch_bounds__(TILE) void k_bicg_init(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles, int k, int mode)
 {
     JTile tl;
     const KJob &J = job_of(jobs, tiles, tl);
-    KState *st = J.st;
-    if (!active(st, k)) return;
-    const int pk = k & 1, pm = (k + 1) & 1;
-    double s2[2];
-    {
-        const int off[2] = {poff(J, pm, PS_RHO), poff(J, pm, PS_RR)};
-        sum_partials<2>(J.part, off, J.ntile, s2);
-    }
-    double bb;
-    if (!test_convergence(J, tl, st, k, s2[1], bb)) return;
-    double beta = 0.0;
-    if (k != st->k0) {
-        const int off[1] = {poff(J, pk, PS_RHO)};
-        double t[1];
-        sum_partials<1>(J.part, off, J.ntile, t);
-        beta = s2[0] / t[0];
-    }
+    if (mode == 1 && J.st->status != K_RESTART) return;
+    if (outer_idle(J)) return;
     const int n = J.n;
-    const gdbl *A = GC(J.A), *r = GC(J.r), *mi = GC(J.minv);
-    const gdbl *po = GC(pk ? J.p1 : J.p0);
-    gdbl *pn = G(pk ? J.p0 : J.p1), *q = G(J.t);
-    double v[1] = {0.0};
+    const int flip = k & 1;
+    auto A = G<T>(J.A);
+    auto b = G<T>(J.b);
+    auto x = G<T>(J.x), r = G<T>(J.r), rh = G<T>(J.rh);
+    auto po = G<T>(flip ? J.p1 : J.p0), vo = G<T>(flip ? J.v1 : J.v0);
+    auto x0 = G<T>(J.x0);
+    double v[3] = {0.0, 0.0, 0.0};
     const int i0 = tl.t * J.rpt, i1 = min(n, i0 + J.rpt);
     for (int i = i0 + threadIdx.x; i < i1; i += TILE) {
-        const double pi = mi[i] * r[i] + beta * po[i];
-        const double qi = stencil<ND>(A, n, i, J.sx, J.sxy, [&](int j) { return mi[j] * r[j] + beta * po[j]; });
-        pn[i] = pi;
-        q[i] = qi;
-        v[0] += pi * qi;
-    }
-    const int off[1] = {poff(J, pk, PS_Q)};
-    put_partials<1>(v, J.part, off, tl.t);
-}
-
-// CG, second half: alpha = rho_k / (p, q); x += alpha p; r -= alpha q;
-// partials (r, M r), (r, r) for iteration k+1
-template <int ND>
-__global__ __launch_bounds__(TILE) void k_cg_b(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles, int k)
-{
-    JTile tl;
-    const KJob &J = job_of(jobs, tiles, tl);
-    KState *st = J.st;
-    if (st->status != K_RUNNING) return;
-    const int pk = k & 1, pm = (k + 1) & 1;
-    double s2[2];
-    {
-        const int off[2] = {poff(J, pm, PS_RHO), poff(J, pk, PS_Q)};
-        sum_partials<2>(J.part, off, J.ntile, s2);
-    }
-    if (!(s2[1] > 0.0) || !finite(s2[1])) {
-        set_status(tl, st, finite(s2[1]) ? K_RESTART : K_NONFINITE, st->it_base + (k - st->k0), 0.0);
-        return;
-    }
-    const double alpha = s2[0] / s2[1];
-    const gdbl *pn = GC(pk ? J.p0 : J.p1), *q = GC(J.t), *mi = GC(J.minv);
-    gdbl *x = G(J.x), *r = G(J.r);
-    double v[2] = {0.0, 0.0};
-    const int i0 = tl.t * J.rpt, i1 = min(J.n, i0 + J.rpt);
-    for (int i = i0 + threadIdx.x; i < i1; i += TILE) {
-        x[i] = x[i] + alpha * pn[i];
-        const double ri = r[i] - alpha * q[i];
+        T ri;
+        if (mode == 0) {
+            if (J.x0) {
+                ri = b[i] - kstencil<ND, T>(A, n, i, J.sx, J.sxy, [&](int j) { return x0[j]; });
+                x[i] = x0[i];
+            } else {
+                ri = b[i];
+                x[i] = T(0);
+            }
+        } else {
+            ri = b[i] - kstencil<ND, T>(A, n, i, J.sx, J.sxy, [&](int j) { return x[j]; });
+        }
         r[i] = ri;
-        v[0] += ri * mi[i] * ri;
-        v[1] += ri * ri;
+        rh[i] = ri;
+        po[i] = T(0);
+        vo[i] = T(0);
+        v[0] += (double)ri * ri;
+        v[1] += (double)ri * ri;
+        v[2] += (double)b[i] * b[i];
     }
-    const int off[2] = {poff(J, pk, PS_RHO), poff(J, pk, PS_RR)};
-    put_partials<2>(v, J.part, off, tl.t);
+    const int pm = (k + 1) & 1;
+    const int off[3] = {poff(J, pm, PS_RHO), poff(J, pm, PS_RR), poff(J, pm, PS_BB)};
+    put_partials<3>(v, J.part, off, tl.t);
+    mark_start(tl, J.st, k, mode);
 }
 
-// BiCGSTAB (van der Vorst), right Jacobi preconditioning.
 // a: beta = (rho_k/rho_{k-1})(alpha_{k-1}/omega_{k-1});
 //    p = r + beta (p - omega v); v = A M p; partial (rh, v)
-template <int ND>
+template <int ND, class T>
 __global__ __launch_bounds__(TILE) void k_bicg_a(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles, int k)
 {
     JTile tl;
     const KJob &J = job_of(jobs, tiles, tl);
+    if (!active(J, k) || outer_idle(J)) return;
     KState *st = J.st;
-    if (!active(st, k)) return;
     const int pk = k & 1, pm = (k + 1) & 1;
-    double s2[2];
+    const bool first = k == st->k0;
+    double s7[7];
     {
-        const int off[2] = {poff(J, pm, PS_RHO), poff(J, pm, PS_RR)};
-        sum_partials<2>(J.part, off, J.ntile, s2);
+        const int off[7] = {poff(J, pm, PS_RHO), poff(J, pm, PS_RR), poff(J, pm, PS_BB), poff(J, pk, PS_RHO),
+                            poff(J, pm, PS_Q), poff(J, pm, PS_TS), poff(J, pm, PS_TT)};
+        sum_partials<7>(J.part, off, J.ntile, s7);
     }
-    double bb;
-    if (!test_convergence(J, tl, st, k, s2[1], bb)) return;
-    const double rho = s2[0];
+    if (!keep_going(J, tl, k, s7[1], s7[2])) return;
+    const double rho = s7[0];
     double beta = 0.0, omega = 0.0;
-    if (k != st->k0) {
-        double s4[4];
-        const int off[4] = {poff(J, pk, PS_RHO), poff(J, pm, PS_Q), poff(J, pm, PS_TS), poff(J, pm, PS_TT)};
-        sum_partials<4>(J.part, off, J.ntile, s4);
-        const double rho_prev = s4[0];
-        const double alpha_prev = rho_prev / s4[1];
-        omega = s4[3] > 0.0 ? s4[2] / s4[3] : 0.0;
-        if (omega == 0.0 || rho == 0.0 || rho_prev == 0.0) {
-            set_status(tl, st, K_RESTART, st->it_base + (k - st->k0), s2[1]);
+    if (!first) {
+        const double rho_prev = s7[3];
+        const double alpha_prev = rho_prev / s7[4];
+        omega = s7[6] > 0.0 ? s7[5] / s7[6] : 0.0;
+        if (omega == 0.0 || rho == 0.0 || rho_prev == 0.0 || !finite(alpha_prev)) {
+            set_status(tl, st, K_RESTART, st->it_base + (k - st->k0), s7[1]);
             return;
         }
         beta = (rho / rho_prev) * (alpha_prev / omega);
     }
+    const T tb = (T)beta, tw = (T)omega;
     const int n = J.n;
-    const gdbl *A = GC(J.A), *r = GC(J.r), *mi = GC(J.minv), *rh = GC(J.rh);
-    const gdbl *po = GC(pk ? J.p1 : J.p0), *vo = GC(pk ? J.v1 : J.v0);
-    gdbl *pn = G(pk ? J.p0 : J.p1), *vn = G(pk ? J.v0 : J.v1);
+    auto A = G<T>(J.A);
+    auto r = G<T>(J.r), mi = G<T>(J.minv), rh = G<T>(J.rh);
+    auto po = G<T>(pk ? J.p1 : J.p0), vo = G<T>(pk ? J.v1 : J.v0);
+    auto pn = G<T>(pk ? J.p0 : J.p1), vn = G<T>(pk ? J.v0 : J.v1);
     double v[1] = {0.0};
     const int i0 = tl.t * J.rpt, i1 = min(n, i0 + J.rpt);
     for (int i = i0 + threadIdx.x; i < i1; i += TILE) {
-        const double pi = r[i] + beta * (po[i] - omega * vo[i]);
-        const double vi = stencil<ND>(A, n, i, J.sx, J.sxy,
-                                      [&](int j) { return mi[j] * (r[j] + beta * (po[j] - omega * vo[j])); });
+        const T pi = r[i] + tb * (po[i] - tw * vo[i]);
+        const T vi = kstencil<ND, T>(A, n, i, J.sx, J.sxy,
+                                     [&](int j) { return mi[j] * (r[j] + tb * (po[j] - tw * vo[j])); });
         pn[i] = pi;
         vn[i] = vi;
-        v[0] += rh[i] * vi;
+        v[0] += (double)rh[i] * vi;
     }
     const int off[1] = {poff(J, pk, PS_Q)};
     put_partials<1>(v, J.part, off, tl.t);
 }
 
 // b: alpha = rho_k / (rh, v); s = r - alpha v; t = A M s; partials (t,s), (t,t)
-template <int ND>
+template <int ND, class T>
 __global__ __launch_bounds__(TILE) void k_bicg_b(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles, int k)
 {
     JTile tl;
     const KJob &J = job_of(jobs, tiles, tl);
-    KState *st = J.st;
-    if (st->status != K_RUNNING) return;
+    if (J.st->status != K_RUNNING || outer_idle(J)) return;
     const int pk = k & 1, pm = (k + 1) & 1;
     double s2[2];
     {
@@ -839,22 +776,23 @@ __global__ __launch_bounds__(TILE) void k_bicg_b(const KJob *__restrict__ jobs, 
         sum_partials<2>(J.part, off, J.ntile, s2);
     }
     if (s2[1] == 0.0 || !finite(s2[1])) {
-        set_status(tl, st, finite(s2[1]) ? K_RESTART : K_NONFINITE, st->it_base + (k - st->k0), 0.0);
+        set_status(tl, J.st, finite(s2[1]) ? K_RESTART : K_NONFINITE, J.st->it_base + (k - J.st->k0), 0.0);
         return;
     }
-    const double alpha = s2[0] / s2[1];
+    const T alpha = (T)(s2[0] / s2[1]);
     const int n = J.n;
-    const gdbl *A = GC(J.A), *r = GC(J.r), *mi = GC(J.minv);
-    const gdbl *vn = GC(pk ? J.v0 : J.v1);
-    gdbl *t = G(J.t);
+    auto A = G<T>(J.A);
+    auto r = G<T>(J.r), mi = G<T>(J.minv);
+    auto vn = G<T>(pk ? J.v0 : J.v1);
+    auto t = G<T>(J.t);
     double v[2] = {0.0, 0.0};
     const int i0 = tl.t * J.rpt, i1 = min(n, i0 + J.rpt);
     for (int i = i0 + threadIdx.x; i < i1; i += TILE) {
-        const double si = r[i] - alpha * vn[i];
-        const double ti = stencil<ND>(A, n, i, J.sx, J.sxy, [&](int j) { return mi[j] * (r[j] - alpha * vn[j]); });
+        const T si = r[i] - alpha * vn[i];
+        const T ti = kstencil<ND, T>(A, n, i, J.sx, J.sxy, [&](int j) { return mi[j] * (r[j] - alpha * vn[j]); });
         t[i] = ti;
-        v[0] += ti * si;
-        v[1] += ti * ti;
+        v[0] += (double)ti * si;
+        v[1] += (double)ti * ti;
     }
     const int off[2] = {poff(J, pk, PS_TS), poff(J, pk, PS_TT)};
     put_partials<2>(v, J.part, off, tl.t);
@@ -862,40 +800,169 @@ __global__ __launch_bounds__(TILE) void k_bicg_b(const KJob *__restrict__ jobs, 
 
 // c: omega = (t,s)/(t,t); x += M (alpha p + omega s); r = s - omega t;
 // partials (rh, r), (r, r) for iteration k+1
-template <int ND>
+template <int ND, class T>
 __global__ __launch_bounds__(TILE) void k_bicg_c(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles, int k)
 {
     JTile tl;
     const KJob &J = job_of(jobs, tiles, tl);
-    KState *st = J.st;
-    if (st->status != K_RUNNING) return;
+    if (J.st->status != K_RUNNING || outer_idle(J)) return;
     const int pk = k & 1, pm = (k + 1) & 1;
     double s4[4];
     {
         const int off[4] = {poff(J, pm, PS_RHO), poff(J, pk, PS_Q), poff(J, pk, PS_TS), poff(J, pk, PS_TT)};
         sum_partials<4>(J.part, off, J.ntile, s4);
     }
-    const double alpha = s4[0] / s4[1];
-    const double omega = s4[3] > 0.0 ? s4[2] / s4[3] : 0.0;
-    const gdbl *pn = GC(pk ? J.p0 : J.p1), *vn = GC(pk ? J.v0 : J.v1), *t = GC(J.t);
-    const gdbl *mi = GC(J.minv), *rh = GC(J.rh);
-    gdbl *x = G(J.x), *r = G(J.r);
+    const T alpha = (T)(s4[0] / s4[1]);
+    const T omega = (T)(s4[3] > 0.0 ? s4[2] / s4[3] : 0.0);
+    auto pn = G<T>(pk ? J.p0 : J.p1), vn = G<T>(pk ? J.v0 : J.v1), t = G<T>(J.t);
+    auto mi = G<T>(J.minv), rh = G<T>(J.rh);
+    auto x = G<T>(J.x), r = G<T>(J.r);
     double v[2] = {0.0, 0.0};
     const int i0 = tl.t * J.rpt, i1 = min(J.n, i0 + J.rpt);
     for (int i = i0 + threadIdx.x; i < i1; i += TILE) {
-        const double si = r[i] - alpha * vn[i];
+        const T si = r[i] - alpha * vn[i];
         x[i] = x[i] + mi[i] * (alpha * pn[i] + omega * si);
-        const double ri = si - omega * t[i];
+        const T ri = si - omega * t[i];
         r[i] = ri;
-        v[0] += rh[i] * ri;
-        v[1] += ri * ri;
+        v[0] += (double)rh[i] * ri;
+        v[1] += (double)ri * ri;
     }
     const int off[2] = {poff(J, pk, PS_RHO), poff(J, pk, PS_RR)};
     put_partials<2>(v, J.part, off, tl.t);
 }
 
-// True residual b - A x of a solve that stopped as converged (or x = 0 when
-// ||b|| = 0); partials of ||b - A x||^2, sum(b - A x), sum(x) into parity 0.
+// ---- CG start, first kernel (mode as for BiCGSTAB): r = b - A x into r_(k&1),
+// s_(k&1) = 0, p = 0; partials (r, r), (b, b)
+template <int ND, class T>
+__global__ __launch_bounds__(TILE) void k_cg_init_a(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles, int k, int mode)
+{
+    JTile tl;
+    const KJob &J = job_of(jobs, tiles, tl);
+    if (mode == 1 && J.st->status != K_RESTART) return;
+    if (outer_idle(J)) return;
+    const int n = J.n;
+    const int pk = k & 1;
+    auto A = G<T>(J.A);
+    auto b = G<T>(J.b);
+    auto x = G<T>(J.x), x0 = G<T>(J.x0);
+    auto r = G<T>(pk ? J.rh : J.r), so = G<T>(pk ? J.p1 : J.p0), p = G<T>(J.t);
+    double v[2] = {0.0, 0.0};
+    const int i0 = tl.t * J.rpt, i1 = min(n, i0 + J.rpt);
+    for (int i = i0 + threadIdx.x; i < i1; i += TILE) {
+        T ri;
+        if (mode == 0) {
+            if (J.x0) {
+                ri = b[i] - kstencil<ND, T>(A, n, i, J.sx, J.sxy, [&](int j) { return x0[j]; });
+                x[i] = x0[i];
+            } else {
+                ri = b[i];
+                x[i] = T(0);
+            }
+        } else {
+            ri = b[i] - kstencil<ND, T>(A, n, i, J.sx, J.sxy, [&](int j) { return x[j]; });
+        }
+        r[i] = ri;
+        so[i] = T(0);
+        p[i] = T(0);
+        v[0] += (double)ri * ri;
+        v[1] += (double)b[i] * b[i];
+    }
+    const int pm = (k + 1) & 1;
+    const int off[2] = {poff(J, pm, PS_RR), poff(J, pm, PS_BB)};
+    put_partials<2>(v, J.part, off, tl.t);
+    mark_start(tl, J.st, k, mode);
+}
+
+// CG start, second kernel: w = A M r into w_(k&1); partials (r, M r), (w, M r)
+template <int ND, class T>
+__global__ __launch_bounds__(TILE) void k_cg_init_b(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles, int k, int mode)
+{
+    JTile tl;
+    const KJob &J = job_of(jobs, tiles, tl);
+    if (mode == 1 && !(J.st->status == K_RESTART && J.st->k0 == k)) return;
+    if (outer_idle(J)) return;
+    const int n = J.n;
+    const int pk = k & 1;
+    auto A = G<T>(J.A);
+    auto mi = G<T>(J.minv);
+    auto r = G<T>(pk ? J.rh : J.r), w = G<T>(pk ? J.v1 : J.v0);
+    double v[2] = {0.0, 0.0};
+    const int i0 = tl.t * J.rpt, i1 = min(n, i0 + J.rpt);
+    for (int i = i0 + threadIdx.x; i < i1; i += TILE) {
+        const T wi = kstencil<ND, T>(A, n, i, J.sx, J.sxy, [&](int j) { return mi[j] * r[j]; });
+        w[i] = wi;
+        const T ui = mi[i] * r[i];
+        v[0] += (double)r[i] * ui;
+        v[1] += (double)wi * ui;
+    }
+    const int pm = (k + 1) & 1;
+    const int off[2] = {poff(J, pm, PS_RHO), poff(J, pm, PS_TS)};
+    put_partials<2>(v, J.part, off, tl.t);
+}
+
+// CG iteration k (one kernel)
+template <int ND, class T>
+__global__ __launch_bounds__(TILE) void k_cg(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles, int k)
+{
+    JTile tl;
+    const KJob &J = job_of(jobs, tiles, tl);
+    if (!active(J, k) || outer_idle(J)) return;
+    KState *st = J.st;
+    const int pk = k & 1, pm = (k + 1) & 1;
+    const bool first = k == st->k0;
+    double s5[5];
+    {
+        const int off[5] = {poff(J, pm, PS_RHO), poff(J, pm, PS_TS), poff(J, pm, PS_RR), poff(J, pm, PS_BB),
+                            poff(J, pk, PS_RHO)};
+        sum_partials<5>(J.part, off, J.ntile, s5);
+    }
+    if (!keep_going(J, tl, k, s5[2], s5[3])) return;
+    const double gam = s5[0], del = s5[1];
+    double alpha, beta = 0.0;
+    if (first) {
+        alpha = gam / del;
+    } else {
+        beta = gam / s5[4];
+        alpha = gam / (del - beta * gam / st->alpha[pm]);
+    }
+    if (!(alpha > 0.0) || !finite(alpha) || !finite(beta)) {
+        set_status(tl, st, finite(alpha) ? K_RESTART : K_NONFINITE, st->it_base + (k - st->k0), s5[2]);
+        return;
+    }
+    if (tl.t == 0 && threadIdx.x == 0) st->alpha[pk] = alpha;
+    const T ta = (T)alpha, tb = (T)beta;
+    const int n = J.n;
+    auto A = G<T>(J.A);
+    auto mi = G<T>(J.minv);
+    auto rc = G<T>(pk ? J.rh : J.r), rn = G<T>(pk ? J.r : J.rh);
+    auto wc = G<T>(pk ? J.v1 : J.v0), wn = G<T>(pk ? J.v0 : J.v1);
+    auto so = G<T>(pk ? J.p1 : J.p0), sn = G<T>(pk ? J.p0 : J.p1);
+    auto p = G<T>(J.t), x = G<T>(J.x);
+    double v[3] = {0.0, 0.0, 0.0};
+    const int i0 = tl.t * J.rpt, i1 = min(n, i0 + J.rpt);
+    for (int i = i0 + threadIdx.x; i < i1; i += TILE) {
+        const T mii = mi[i], ri = rc[i];
+        const T pi = mii * ri + tb * p[i];
+        p[i] = pi;
+        const T si = wc[i] + tb * so[i];
+        sn[i] = si;
+        x[i] = x[i] + ta * pi;
+        const T rni = ri - ta * si;
+        rn[i] = rni;
+        const T wi = kstencil<ND, T>(A, n, i, J.sx, J.sxy,
+                                     [&](int j) { return mi[j] * (rc[j] - ta * (wc[j] + tb * so[j])); });
+        wn[i] = wi;
+        const T un = mii * rni;
+        v[0] += (double)rni * un;
+        v[1] += (double)wi * un;
+        v[2] += (double)rni * rni;
+    }
+    const int off[3] = {poff(J, pk, PS_RHO), poff(J, pk, PS_TS), poff(J, pk, PS_RR)};
+    put_partials<3>(v, J.part, off, tl.t);
+}
+
+// ---- verification of a plain FP64 solve on the true residual b - A x (or
+// x = 0 when ||b|| = 0); partials of ||b - A x||^2, sum(b - A x), sum(x)
 template <int ND>
 __global__ __launch_bounds__(TILE) void k_kfinish(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles)
 {
@@ -904,15 +971,16 @@ __global__ __launch_bounds__(TILE) void k_kfinish(const KJob *__restrict__ jobs,
     const int status = J.st->status;
     if (status != K_CONVERGED && status != K_ZERO) return;
     const int n = J.n;
-    const gdbl *A = GC(J.A), *b = GC(J.b);
-    gdbl *x = G(J.x);
+    auto A = G<double>(J.A);
+    auto b = G<double>(J.b);
+    auto x = G<double>(J.x);
     double v[3] = {0.0, 0.0, 0.0};
     const int i0 = tl.t * J.rpt, i1 = min(n, i0 + J.rpt);
     for (int i = i0 + threadIdx.x; i < i1; i += TILE) {
         if (status == K_ZERO) {
             x[i] = 0.0;
         } else {
-            const double rt = b[i] - stencil<ND>(A, n, i, J.sx, J.sxy, [&](int j) { return x[j]; });
+            const double rt = b[i] - kstencil<ND, double>(A, n, i, J.sx, J.sxy, [&](int j) { return x[j]; });
             v[0] += rt * rt;
             v[1] += rt;
             v[2] += x[i];
@@ -939,6 +1007,102 @@ __global__ __launch_bounds__(TILE) void k_kdecide(const KJob *__restrict__ jobs,
         if (status == K_ZERO || tot[0] <= st->tol2 * st->bb) st->status = K_DONE;
         else st->status = st->restarts >= 20 ? K_FAILED : K_RESTART;
     }
+}
+
+// ---- mixed precision: FP64 iterative refinement around an FP32 solve.
+// Residual sweep (mode 0: fresh start, x = x0 or 0; mode 1: keep x):
+// r = b - A x in FP64, its FP32 copy into aux (the inner rhs); partials
+// ||r||^2, ||b||^2, sum(r), sum(x).
+template <int ND>
+__global__ __launch_bounds__(TILE) void k_ir_resid(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles, int mode)
+{
+    JTile tl;
+    const KJob &J = job_of(jobs, tiles, tl);
+    if (mode == 1 && J.st->status != K_RUNNING) return;
+    const int n = J.n;
+    auto A = G<double>(J.A);
+    auto b = G<double>(J.b);
+    auto x = G<double>(J.x), x0 = G<double>(J.x0);
+    auto r32 = G<float>(J.aux);
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    const int i0 = tl.t * J.rpt, i1 = min(n, i0 + J.rpt);
+    for (int i = i0 + threadIdx.x; i < i1; i += TILE) {
+        double ri, xi;
+        if (mode == 0 && !J.x0) {
+            ri = b[i];
+            xi = 0.0;
+            x[i] = 0.0;
+        } else if (mode == 0) {
+            ri = b[i] - kstencil<ND, double>(A, n, i, J.sx, J.sxy, [&](int j) { return x0[j]; });
+            xi = x0[i];
+            x[i] = xi;
+        } else {
+            ri = b[i] - kstencil<ND, double>(A, n, i, J.sx, J.sxy, [&](int j) { return x[j]; });
+            xi = x[i];
+        }
+        r32[i] = (float)ri;
+        v[0] += ri * ri;
+        v[1] += b[i] * b[i];
+        v[2] += ri;
+        v[3] += xi;
+    }
+    const int off[4] = {poff(J, 0, PS_RR), poff(J, 0, PS_BB), poff(J, 0, PS_TS), poff(J, 0, PS_TT)};
+    put_partials<4>(v, J.part, off, tl.t);
+}
+
+// one workgroup per refinement: verdict on the FP64 residual of the sweep;
+// the inner solve's iterations are added to the count
+__global__ __launch_bounds__(TILE) void k_ir_decide(const KJob *__restrict__ jobs, int njobs, int mode, int max_outer)
+{
+    const KJob &J = jobs[blockIdx.x];
+    KState *st = J.st;
+    if (mode == 1 && st->status != K_RUNNING) return;
+    const int off[4] = {poff(J, 0, PS_RR), poff(J, 0, PS_BB), poff(J, 0, PS_TS), poff(J, 0, PS_TT)};
+    double tot[4];
+    sum_partials<4>(J.part, off, J.ntile, tot);
+    if (threadIdx.x == 0) {
+        if (mode == 0) {
+            st->bb = tot[1];
+            st->outer = 0;
+            st->inner_total = 0;
+            st->restarts = 0;
+        } else {
+            st->outer += 1;
+            st->inner_total += J.partner->it;
+        }
+        st->rr = tot[0];
+        st->tr2 = tot[0];
+        st->tsum = tot[2];
+        st->xsum = tot[3];
+        st->it = st->inner_total;
+        if (!finite(tot[0]) || !finite(st->bb)) st->status = K_NONFINITE;
+        else if (st->bb == 0.0) st->status = K_ZERO;
+        else if (tot[0] <= st->tol2 * st->bb) st->status = K_DONE;
+        else if (st->outer >= max_outer || st->inner_total >= st->max_iter) st->status = K_FAILED;
+        else st->status = K_RUNNING;
+    }
+}
+
+// x += d (FP64 += FP32 correction) for refinements still running; x = 0 for
+// a zero right-hand side
+template <int ND>
+__global__ __launch_bounds__(TILE) void k_ir_update(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles)
+{
+    JTile tl;
+    const KJob &J = job_of(jobs, tiles, tl);
+    const int status = J.st->status;
+    if (status != K_RUNNING && status != K_ZERO) return;
+    auto x = G<double>(J.x);
+    auto d = G<float>(J.t);
+    const int i0 = tl.t * J.rpt, i1 = min(J.n, i0 + J.rpt);
+    for (int i = i0 + threadIdx.x; i < i1; i += TILE) x[i] = status == K_ZERO ? 0.0 : x[i] + (double)d[i];
+}
+
+// the zero-rhs verdict of a refinement becomes final after k_ir_update
+__global__ void k_ir_close(const KJob *__restrict__ jobs, int njobs)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < njobs && jobs[j].st->status == K_ZERO) jobs[j].st->status = K_DONE;
 }
 
 // ------------------------------------------------------------ CSR export
@@ -1066,48 +1230,94 @@ void launch_phase_commit(int dim, const CaseDev *c, const Tile *t, int nt, hipSt
     else hipLaunchKernelGGL(k_phase_commit<3>, GRID(nt), 0, s, c, t);
 }
 
-void launch_kinit(int nd, const KJob *j, const JTile *t, int nt, int k, int mode, hipStream_t s)
+template <class T>
+static void launch_iter_t(int which, int nd, const KJob *j, const JTile *t, int nt, int k, hipStream_t s)
+{
+    if (nd == 5) {
+        switch (which) {
+        case KI_CG: hipLaunchKernelGGL((k_cg<5, T>), GRID(nt), 0, s, j, t, k); break;
+        case KI_BICG_A: hipLaunchKernelGGL((k_bicg_a<5, T>), GRID(nt), 0, s, j, t, k); break;
+        case KI_BICG_B: hipLaunchKernelGGL((k_bicg_b<5, T>), GRID(nt), 0, s, j, t, k); break;
+        default: hipLaunchKernelGGL((k_bicg_c<5, T>), GRID(nt), 0, s, j, t, k); break;
+        }
+    } else {
+        switch (which) {
+        case KI_CG: hipLaunchKernelGGL((k_cg<7, T>), GRID(nt), 0, s, j, t, k); break;
+        case KI_BICG_A: hipLaunchKernelGGL((k_bicg_a<7, T>), GRID(nt), 0, s, j, t, k); break;
+        case KI_BICG_B: hipLaunchKernelGGL((k_bicg_b<7, T>), GRID(nt), 0, s, j, t, k); break;
+        default: hipLaunchKernelGGL((k_bicg_c<7, T>), GRID(nt), 0, s, j, t, k); break;
+        }
+    }
+}
+
+void launch_kiter(int which, int nd, int fp32, const KJob *j, const JTile *t, int nt, int k, hipStream_t s)
 {
     if (nt <= 0) return;
-    if (nd == 5) hipLaunchKernelGGL(k_kinit<5>, GRID(nt), 0, s, j, t, k, mode);
-    else hipLaunchKernelGGL(k_kinit<7>, GRID(nt), 0, s, j, t, k, mode);
+    if (fp32) launch_iter_t<float>(which, nd, j, t, nt, k, s);
+    else launch_iter_t<double>(which, nd, j, t, nt, k, s);
 }
-void launch_kdecide(const KJob *j, int njobs, hipStream_t s)
+
+template <class T>
+static void launch_init_t(int kind, int nd, const KJob *j, const JTile *t, int nt, int k, int mode, hipStream_t s)
 {
-    if (njobs <= 0) return;
-    hipLaunchKernelGGL(k_kdecide, dim3(njobs), dim3(TILE), 0, s, j, njobs);
+    if (kind == K_CG) {
+        if (nd == 5) {
+            hipLaunchKernelGGL((k_cg_init_a<5, T>), GRID(nt), 0, s, j, t, k, mode);
+            hipLaunchKernelGGL((k_cg_init_b<5, T>), GRID(nt), 0, s, j, t, k, mode);
+        } else {
+            hipLaunchKernelGGL((k_cg_init_a<7, T>), GRID(nt), 0, s, j, t, k, mode);
+            hipLaunchKernelGGL((k_cg_init_b<7, T>), GRID(nt), 0, s, j, t, k, mode);
+        }
+    } else {
+        if (nd == 5) hipLaunchKernelGGL((k_bicg_init<5, T>), GRID(nt), 0, s, j, t, k, mode);
+        else hipLaunchKernelGGL((k_bicg_init<7, T>), GRID(nt), 0, s, j, t, k, mode);
+    }
 }
-void launch_case_stats(const CaseDev *c, const int32_t *cidx, int ncase, hipStream_t s)
+
+void launch_kinit(int kind, int nd, int fp32, const KJob *j, const JTile *t, int nt, int k, int mode, hipStream_t s)
 {
-    if (ncase <= 0) return;
-    hipLaunchKernelGGL(k_case_stats, dim3(ncase), dim3(TILE), 0, s, c, cidx);
+    if (nt <= 0) return;
+    if (fp32) launch_init_t<float>(kind, nd, j, t, nt, k, mode, s);
+    else launch_init_t<double>(kind, nd, j, t, nt, k, mode, s);
 }
+
 void launch_kfinish(int nd, const KJob *j, const JTile *t, int nt, hipStream_t s)
 {
     if (nt <= 0) return;
     if (nd == 5) hipLaunchKernelGGL(k_kfinish<5>, GRID(nt), 0, s, j, t);
     else hipLaunchKernelGGL(k_kfinish<7>, GRID(nt), 0, s, j, t);
 }
-void launch_kiter(int which, int nd, const KJob *j, const JTile *t, int nt, int k, hipStream_t s)
+void launch_kdecide(const KJob *j, int njobs, hipStream_t s)
+{
+    if (njobs <= 0) return;
+    hipLaunchKernelGGL(k_kdecide, dim3(njobs), dim3(TILE), 0, s, j, njobs);
+}
+void launch_ir_resid(int nd, const KJob *j, const JTile *t, int nt, int mode, hipStream_t s)
 {
     if (nt <= 0) return;
-    if (nd == 5) {
-        switch (which) {
-        case KI_CG_A: hipLaunchKernelGGL(k_cg_a<5>, GRID(nt), 0, s, j, t, k); break;
-        case KI_CG_B: hipLaunchKernelGGL(k_cg_b<5>, GRID(nt), 0, s, j, t, k); break;
-        case KI_BICG_A: hipLaunchKernelGGL(k_bicg_a<5>, GRID(nt), 0, s, j, t, k); break;
-        case KI_BICG_B: hipLaunchKernelGGL(k_bicg_b<5>, GRID(nt), 0, s, j, t, k); break;
-        default: hipLaunchKernelGGL(k_bicg_c<5>, GRID(nt), 0, s, j, t, k); break;
-        }
-    } else {
-        switch (which) {
-        case KI_CG_A: hipLaunchKernelGGL(k_cg_a<7>, GRID(nt), 0, s, j, t, k); break;
-        case KI_CG_B: hipLaunchKernelGGL(k_cg_b<7>, GRID(nt), 0, s, j, t, k); break;
-        case KI_BICG_A: hipLaunchKernelGGL(k_bicg_a<7>, GRID(nt), 0, s, j, t, k); break;
-        case KI_BICG_B: hipLaunchKernelGGL(k_bicg_b<7>, GRID(nt), 0, s, j, t, k); break;
-        default: hipLaunchKernelGGL(k_bicg_c<7>, GRID(nt), 0, s, j, t, k); break;
-        }
-    }
+    if (nd == 5) hipLaunchKernelGGL(k_ir_resid<5>, GRID(nt), 0, s, j, t, mode);
+    else hipLaunchKernelGGL(k_ir_resid<7>, GRID(nt), 0, s, j, t, mode);
+}
+void launch_ir_decide(const KJob *j, int njobs, int mode, int max_outer, hipStream_t s)
+{
+    if (njobs <= 0) return;
+    hipLaunchKernelGGL(k_ir_decide, dim3(njobs), dim3(TILE), 0, s, j, njobs, mode, max_outer);
+}
+void launch_ir_update(int nd, const KJob *j, const JTile *t, int nt, hipStream_t s)
+{
+    if (nt <= 0) return;
+    if (nd == 5) hipLaunchKernelGGL(k_ir_update<5>, GRID(nt), 0, s, j, t);
+    else hipLaunchKernelGGL(k_ir_update<7>, GRID(nt), 0, s, j, t);
+}
+void launch_ir_close(const KJob *j, int njobs, hipStream_t s)
+{
+    if (njobs <= 0) return;
+    hipLaunchKernelGGL(k_ir_close, dim3(ceil_div(njobs, 64)), dim3(64), 0, s, j, njobs);
+}
+void launch_case_stats(const CaseDev *c, const int32_t *cidx, int ncase, hipStream_t s)
+{
+    if (ncase <= 0) return;
+    hipLaunchKernelGGL(k_case_stats, dim3(ncase), dim3(TILE), 0, s, c, cidx);
 }
 void launch_csr(int dim, const CaseDev *cd, int s, int n, int32_t *cnt, int32_t *row_ptr, int32_t *col,
                 double *val, int build_pattern, hipStream_t st)

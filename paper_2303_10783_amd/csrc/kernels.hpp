@@ -12,12 +12,16 @@ void launch_sub_mean(const CaseDev *c, const Tile *t, int nt, hipStream_t s);
 void launch_project(const CaseDev *c, const Tile *t, int nt, hipStream_t s);
 void launch_phase_commit(int dim, const CaseDev *c, const Tile *t, int nt, hipStream_t s);
 
-void launch_kinit(int nd, const KJob *j, const JTile *t, int nt, int k, int mode, hipStream_t s);
-void launch_kdecide(const KJob *j, int njobs, hipStream_t s);
-void launch_case_stats(const CaseDev *c, const int32_t *cidx, int ncase, hipStream_t s);
+void launch_kinit(int kind, int nd, int fp32, const KJob *j, const JTile *t, int nt, int k, int mode, hipStream_t s);
 void launch_kfinish(int nd, const KJob *j, const JTile *t, int nt, hipStream_t s);
-enum KIter { KI_CG_A = 0, KI_CG_B = 1, KI_BICG_A = 2, KI_BICG_B = 3, KI_BICG_C = 4 };
-void launch_kiter(int which, int nd, const KJob *j, const JTile *t, int nt, int k, hipStream_t s);
+void launch_kdecide(const KJob *j, int njobs, hipStream_t s);
+enum KIter { KI_CG = 0, KI_BICG_A = 1, KI_BICG_B = 2, KI_BICG_C = 3 };
+void launch_kiter(int which, int nd, int fp32, const KJob *j, const JTile *t, int nt, int k, hipStream_t s);
+void launch_ir_resid(int nd, const KJob *j, const JTile *t, int nt, int mode, hipStream_t s);
+void launch_ir_decide(const KJob *j, int njobs, int mode, int max_outer, hipStream_t s);
+void launch_ir_update(int nd, const KJob *j, const JTile *t, int nt, hipStream_t s);
+void launch_ir_close(const KJob *j, int njobs, hipStream_t s);
+void launch_case_stats(const CaseDev *c, const int32_t *cidx, int ncase, hipStream_t s);
 
 void launch_csr(int dim, const CaseDev *cd, int s, int n, int32_t *cnt, int32_t *row_ptr, int32_t *col,
                 double *val, int build_pattern, hipStream_t st);

@@ -22,20 +22,24 @@ enum KStatus {
 enum KKind { K_CG = 0, K_BICGSTAB = 1 };
 
 // Per-solve device state.  Iteration kernels read it at their start; only
-// workgroup 0 of a solve writes it, and only the fields no other workgroup
-// of the same kernel reads (status changes are taken by every workgroup from
-// the same reduced partials, so all of them stop together).
+// workgroup 0 of a solve writes it, and only fields no other workgroup of
+// the same kernel reads (alpha is double-buffered by iteration parity;
+// status changes are taken by every workgroup from the same reduced
+// partials, so all of them stop together).
 struct KState {
     double bb;                 // ||b||^2 of the current solve
     double rr;                 // ||r||^2 at the last convergence test
     double tr2, tsum, xsum;    // true residual ||b - A x||^2, sum(b - A x), sum(x)
     double bmean;              // mean of the pressure rhs (removed before the solve)
     double tol2;               // tol^2
+    double alpha[2];           // CG step length of iterations of parity 0 / 1
     int32_t status;            // KStatus
     int32_t it;                // iterations done (valid once not RUNNING)
     int32_t it_base;           // iterations done before the current (re)start
     int32_t k0;                // host iteration index of the current (re)start
     int32_t max_iter, restarts;
+    int32_t outer;             // mixed precision: refinement sweeps done
+    int32_t inner_total;       // mixed precision: inner iterations summed
 };
 
 // Partial-sum slots of a solve: part[(par * NSLOT + slot) * ntile + tile],
@@ -80,22 +84,29 @@ struct CaseDev {
 // Reduction result slots in CaseDev::red
 enum RedSlot { R_SUMB = 0, R_DIVSTAR = 1, R_SUMC = 2, R_SUMH = 3, R_WALL = 4, R_DIVNEW = 5 };
 
-// One linear solve.
+// One linear solve.  Vector and matrix pointers are FP64 for the plain
+// solves and the refinement (outer) solves, FP32 for the inner solves of the
+// mixed-precision form; partial sums and scalars are always FP64.
+// Work-vector roles: BiCGSTAB r, rh, p0/p1, v0/v1, t; CG (one kernel per
+// iteration) r0/r1 = r/rh, s0/s1 = p0/p1, w0/w1 = v0/v1, p = t.
 struct KJob {
     int32_t n, sx, sxy;
     int32_t rpt;              // rows per tile (multiple of TILE)
     int32_t ntile;            // tiles of this solve
     int32_t kind;             // KKind
-    const double *A, *b, *minv;
-    double *x;
-    const double *x0;         // initial guess copied into x on a fresh start (NULL: x = 0)
-    double *r, *rh, *p0, *p1, *v0, *v1, *t;
+    const void *A, *b, *minv;
+    void *x;
+    const void *x0;           // initial guess copied into x on a fresh start (NULL: x = 0)
+    void *r, *rh, *p0, *p1, *v0, *v1, *t;
+    void *aux;                // refinement: FP32 residual (the inner rhs)
     double *part;             // [2 * NSLOT * ntile]
     KState *st;
-    // mixed precision: FP32 operator and work vectors for the inner solve
-    const float *A32, *minv32;
-    float *r32, *rh32, *p032, *p132, *v032, *v132, *t32, *x32;
+    KState *partner;          // refinement: its inner solve; inner solve: its refinement
+    int32_t role;             // KRole
+    int32_t pad;
 };
+
+enum KRole { ROLE_PLAIN = 0, ROLE_REFINE = 1, ROLE_INNER = 2 };
 
 // Tile of a per-row kernel: case, system (or component), tile within it.
 struct Tile { int32_t c, s, t, pad; };
