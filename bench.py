@@ -15,6 +15,7 @@ Also printed in the same JSON line:
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -44,6 +45,22 @@ def roofline(g, ncell_rows):
         if best is None or t["est_ms_per_step"] > best["est_ms_per_step"]:
             best = t
     return best
+
+
+def counter_traffic(workload, kernel_cls):
+    """HBM bytes per launch of the CG kernel from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary (scaled by the copy reference), or None
+    when that summary does not cover this workload or the kernel source has
+    changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "k_cg_hbm_traffic.txt")
+    src = os.path.join(ROOT, "paper_2303_10783_amd", "csrc", "kernels.hip")
+    if kernel_cls != "cg" or not os.path.exists(path):
+        return None
+    doc = json.load(open(path))
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if doc.get("kernels_hip_sha256") != sha or workload not in doc:
+        return None
+    return doc[workload]["traffic_bytes_per_launch"]
 
 
 def cpu_baseline(case, budget_s=12.0, max_steps=20):
@@ -113,8 +130,9 @@ def main():
         best = roofline(g, per)
         g.set_timing(False)
         if best:
+            tr = counter_traffic(args.workload, best["cls"]) if args.precision == "fp64" else None
             roof = dict(bound="hbm", achieved=round(best["gbs"], 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                        frac=round(best["gbs"] / HBM_PEAK_GBS, 4), traffic=None,
+                        frac=round(best["gbs"] / HBM_PEAK_GBS, 4), traffic=tr,
                         kernel=best["cls"], avg_us=round(best["avg_ms"] * 1e3, 2),
                         bytes_per_launch=int(best["bytes_per_launch"]),
                         timed_launches=int(best["launches"]))

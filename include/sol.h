@@ -189,9 +189,11 @@ int sol_batch_step(sol_batch *b, const int32_t *nsteps_per_case, sol_step_stats 
 void sol_batch_destroy(sol_batch *b);
 
 /* Kernel timing for roofline reports.  When enabled, HIP events on the
-   handle's stream bracket sampled launches of the kernel classes below (every
-   8th Krylov iteration, every assembly / phase launch); a sample counts only
-   if the solve was still iterating at that launch.  sol_get_timing returns
+   handle's stream bracket windows of 16 consecutive CG launches (one event
+   pair per window, starting every 32nd iteration), single launches of the
+   BiCGSTAB kernels (every 8th iteration) and every assembly / phase launch;
+   a sample counts only if the solve was still iterating at all its
+   launches.  sol_get_timing returns
    the number of timed launches, their summed duration and the algorithmic
    bytes those launches move (matrix values + vectors read and written once,
    per row of the systems that were iterating; FP32 values count 4 bytes).

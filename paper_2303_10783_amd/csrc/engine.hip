@@ -138,7 +138,7 @@ static int rows_per_tile(int n)
 // ------------------------------------------------------------------ timing
 
 struct JobSet;
-struct TSample { int cls; int64_t iter; const JobSet *set; int tsize; hipEvent_t a, b; };
+struct TSample { int cls; int64_t iter; const JobSet *set; int tsize; hipEvent_t a, b; int count = 1; };
 struct TAcc { int64_t n = 0; double ms = 0.0, bytes = 0.0; };
 
 // algorithmic bytes per row of one launch: matrix values and every vector
@@ -462,7 +462,7 @@ static void collect_samples(Group &g, const KState *ks)
                 }
             }
             if (rows == 0.0) valid = false;
-            bytes = rows * row_bytes(s.cls, nd, dim, s.tsize);
+            bytes = rows * row_bytes(s.cls, nd, dim, s.tsize) * s.count;
         } else {
             for (auto *c : g.cs) {
                 const double rows = s.cls == SOL_KCLASS_ASM_MOM
@@ -472,7 +472,7 @@ static void collect_samples(Group &g, const KState *ks)
             }
         }
         if (valid) {
-            h->tacc[s.cls].n += 1;
+            h->tacc[s.cls].n += s.count;
             h->tacc[s.cls].ms += ms;
             h->tacc[s.cls].bytes += bytes;
         }
@@ -484,12 +484,27 @@ static void collect_samples(Group &g, const KState *ks)
 
 // ------------------------------------------------------------------ solves
 
+// Timing: CG iterations are timed in windows of TWIN consecutive launches
+// (one event pair per window; per-launch events would add their own
+// latency), BiCGSTAB kernels one launch at a time, every 8th iteration.
+constexpr int TWIN = 16;
+
 static void enqueue_iters(Group &g, Phase &P, const JobSet &S, int fp32, int nits, int &k)
 {
     sol_handle *tm = g.timer;
     const int nk = P.kind == K_CG ? 1 : 3;
+    hipEvent_t wa = nullptr, wb = nullptr;
+    int wend = -1;
     for (int it = 0; it < nits; ++it) {
-        const bool sample = tm && (k % 8 == 0);
+        if (tm && P.kind == K_CG && wend < 0 && k % (2 * TWIN) == 0 && nits - it >= TWIN) {
+            wa = take_event(tm);
+            wb = take_event(tm);
+            if (wa && wb) {
+                (void)hipEventRecord(wa, g.stream);
+                wend = k + TWIN - 1;
+            }
+        }
+        const bool sample = tm && P.kind != K_CG && (k % 8 == 0);
         for (int q = 0; q < nk; ++q) {
             const int which = (P.kind == K_CG ? KI_CG : KI_BICG_A) + q;
             hipEvent_t a = nullptr, b = nullptr;
@@ -499,8 +514,13 @@ static void enqueue_iters(Group &g, Phase &P, const JobSet &S, int fp32, int nit
                 launch_kiter(which, gi ? 7 : 5, fp32, S.jobs_d, S.tiles_d[gi], S.nt[gi], k, g.stream);
             if (a && b) {
                 (void)hipEventRecord(b, g.stream);
-                tm->samples.push_back({P.tcls0 + q, (int64_t)k, &S, fp32 ? 4 : 8, a, b});
+                tm->samples.push_back({P.tcls0 + q, (int64_t)k, &S, fp32 ? 4 : 8, a, b, 1});
             }
+        }
+        if (k == wend) {
+            (void)hipEventRecord(wb, g.stream);
+            tm->samples.push_back({P.tcls0, (int64_t)k, &S, fp32 ? 4 : 8, wa, wb, TWIN});
+            wend = -1;
         }
         k += 1;
         P.launched += 1;
@@ -662,7 +682,7 @@ static void timed(Group &g, int cls, F launch)
     launch();
     if (a && b) {
         (void)hipEventRecord(b, g.stream);
-        tm->samples.push_back({cls, 0, nullptr, 8, a, b});
+        tm->samples.push_back({cls, 0, nullptr, 8, a, b, 1});
     }
 }
 
