@@ -9,8 +9,13 @@ state resident on the device.
 
 Also printed in the same JSON line:
   roofline      achieved algorithmic GB/s of the dominant kernel (HIP events
-                on the library's stream, sampled launches) against 8 TB/s;
-  cpu_baseline  the FP64 oracle on the host for a bounded number of steps.
+                on the library's stream, windows of 16 launches) against
+                8 TB/s, and the counter-measured HBM bytes per launch;
+  cpu_baseline  the FP64 oracle on the host for a bounded number of steps;
+  variants      the same step in mixed precision, the 128x128x64 box (FP64
+                and mixed), 64 uneven cavities in one batch (mixed and FP64,
+                graph-replayed chunks, tuned tiles) and the served request
+                stream (continuous batching, p50/p99 latency).
 """
 from __future__ import annotations
 
@@ -63,6 +68,78 @@ def counter_traffic(workload, kernel_cls):
     return doc[workload]["traffic_bytes_per_launch"]
 
 
+def run_single(sol, W, key, precision, steps, warmup, dev, graph=False):
+    import torch
+    case = W.workload_case(key)
+    if precision == "mixed":
+        case["numerics"]["precision"] = W.PRECISION_MIXED
+    g = case["grid"]
+    ncell = g["nx"] * g["ny"] * (g["nz"] if g["dim"] == 3 else 1)
+    h = sol.Case(case, device=dev)
+    if graph:
+        h.set_graph(True)
+    if warmup:
+        h.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = h.step(steps)
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    h.close()
+    return dict(value=ncell * steps / secs, ms_per_step=1e3 * secs / steps, steps=steps,
+                krylov_iters_per_step={n: round(st["iters_total"][i] / steps, 1) for i, n in enumerate("uvwpCT")})
+
+
+def run_batched(sol, W, precision, steps, warmup, dev, n_cases=64, graph=True, tune=True):
+    """64 cavities of uneven size (aspect 0.5-4, 6e3-9.6e4 cells, h and C0
+    drawn per case), every kernel launched once for all of them."""
+    import torch
+    cases = W.batch_cases(n_cases, seed=0, precision=W.PRECISION_MIXED if precision == "mixed" else W.PRECISION_FP64)
+    cells = [c["grid"]["nx"] * c["grid"]["ny"] for c in cases]
+    tuned = {}
+    if tune:
+        # one tuning run per size class, on the largest case of the class
+        by_cls = {}
+        for c, n in zip(cases, cells):
+            k = int(n).bit_length()
+            if k not in by_cls or n > by_cls[k][1]:
+                by_cls[k] = (c, n)
+        for k, (c, n) in sorted(by_cls.items()):
+            h = sol.Case(c, device=dev)
+            tuned[n] = h.autotune()
+            h.close()
+    hs = [sol.Case(c, device=dev) for c in cases]
+    if graph:
+        hs[0].set_graph(True)
+    b = sol.Batch(hs)
+    if warmup:
+        b.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(steps)
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    b.close()
+    for h in hs:
+        h.close()
+    return dict(value=sum(cells) * steps / secs, ms_per_step=1e3 * secs / steps, steps=steps,
+                cases=n_cases, cells=sum(cells), min_cells=min(cells), max_cells=max(cells),
+                graph=graph, tuned_rows_per_tile={str(k): v for k, v in sorted(tuned.items())})
+
+
+def run_served(sol, W, dev, n_requests=40, scale=0.1, steps=200, rate=20.0):
+    """Poisson arrivals at `rate`/s of 2D and 3D cases (sizes log-uniform in
+    the served ranges times `scale`), 200 steps each, mixed precision."""
+    from paper_2303_10783_amd.serve import Request, Server
+    reqs = W.served_arrivals(n_requests, seed=0, rate=rate, scale=scale)
+    requests = [Request(case=c, steps=steps, arrival=c["arrival_s"], rid=i) for i, c in enumerate(reqs)]
+    srv = Server(device=dev, max_active=64, graph=True, keep_results=False)
+    out = srv.run(requests)
+    out.pop("done")
+    out.update(n_requests=n_requests, size_scale=scale, steps_per_request=steps, arrival_rate_per_s=rate)
+    return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in out.items()}
+
+
 def cpu_baseline(case, budget_s=12.0, max_steps=20):
     import oracle
     threads = min(16, os.cpu_count() or 1)
@@ -90,6 +167,8 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--graph", action="store_true", help="replay Krylov chunks as HIP graphs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -109,6 +188,8 @@ def main():
     ncell = grid["nx"] * grid["ny"] * (grid["nz"] if grid["dim"] == 3 else 1)
     dev = sol.TorchDevice(0)
     g = sol.Case(case, device=dev)
+    if args.graph:
+        g.set_graph(True)
     if args.warmup:
         g.step(args.warmup)
     torch.cuda.synchronize()
@@ -136,10 +217,21 @@ def main():
                         kernel=best["cls"], avg_us=round(best["avg_ms"] * 1e3, 2),
                         bytes_per_launch=int(best["bytes_per_launch"]),
                         timed_launches=int(best["launches"]))
+    g.close()
+    variants = None
+    if not args.no_variants:
+        variants = {}
+        if args.workload == "C2" and args.precision == "fp64":
+            variants["C2_mixed"] = run_single(sol, W, "C2", "mixed", args.steps, args.warmup, dev)
+            variants["C2_fp64_graph"] = run_single(sol, W, "C2", "fp64", args.steps, args.warmup, dev, graph=True)
+        variants["C3_fp64"] = run_single(sol, W, "C3", "fp64", 5, 1, dev)
+        variants["C3_mixed"] = run_single(sol, W, "C3", "mixed", 5, 1, dev)
+        variants["C4_batched_mixed"] = run_batched(sol, W, "mixed", 5, 1, dev)
+        variants["C4_batched_fp64"] = run_batched(sol, W, "fp64", 5, 1, dev, tune=False)
+        variants["C5_served_mixed"] = run_served(sol, W, dev)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(case)
-    g.close()
     out = dict(
         metric=METRIC, value=value, unit="cell-updates/s", n_gpus=1, steps=args.steps,
         warmup=args.warmup, ms_per_step=1e3 * secs / args.steps, higher_is_better=True,
@@ -149,7 +241,7 @@ def main():
                     cells=ncell, dt=case["numerics"]["dt"], tol=case["numerics"]["tol_p"],
                     precision=args.precision, krylov_iters_per_step={
                         n: round(iters[i] / args.steps, 1) for i, n in enumerate("uvwpCT")}),
-        roofline=roof, cpu_baseline=cpu,
+        roofline=roof, cpu_baseline=cpu, variants=variants,
     )
     print(json.dumps(out))
 

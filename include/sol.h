@@ -210,6 +210,23 @@ int sol_set_timing(sol_handle *h, int32_t enable);
 int sol_get_timing(sol_handle *h, int32_t kclass, int64_t *launches, double *total_ms,
                    double *bytes);
 
+/* Options.  SOL_OPT_GRAPH (0/1): replay chunks of 16 Krylov iterations as
+   instantiated HIP graphs (the iteration index comes from a device counter
+   the graph advances) instead of launching each kernel; batches follow the
+   option of their first handle.  Results are bit-identical either way. */
+#define SOL_OPT_GRAPH 1
+int sol_set_option(sol_handle *h, int32_t option, int64_t value);
+
+/* Tile-size autotuner: times CG iterations of this case's pressure system
+   (FP32 inner solve under mixed precision) for candidate tile sizes of 256,
+   512, 1024, 2048, 4096 rows per workgroup and keeps the fastest for the
+   case's size class (stencil width, floor(log2 rows)).  The choice is
+   process-wide and applies to every later solve of that class, alone or in
+   a batch (tile size changes the summation order, so tune before creating
+   the cases to be compared).  The state of the case is not changed.
+   *rows_per_tile (nullable) receives the choice. */
+int sol_autotune(sol_handle *h, int32_t *rows_per_tile);
+
 const char *sol_last_error(void);
 const char *sol_version(void);
 

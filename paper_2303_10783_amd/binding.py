@@ -110,6 +110,8 @@ def load():
         "sol_batch_destroy": ([P], None),
         "sol_set_timing": ([P, I32], I32),
         "sol_get_timing": ([P, I32, C.POINTER(C.c_int64), dp, dp], I32),
+        "sol_set_option": ([P, I32, C.c_int64], I32),
+        "sol_autotune": ([P, ip], I32),
         "sol_last_error": ([], C.c_char_p),
         "sol_version": ([], C.c_char_p),
     }
@@ -125,7 +127,7 @@ def exported_symbols():
     return ["sol_create", "sol_destroy", "sol_write_fields", "sol_read_fields", "sol_system_size",
             "sol_assemble", "sol_read_matrix", "sol_step", "sol_footprint_bytes",
             "sol_batch_create", "sol_batch_step", "sol_batch_destroy", "sol_set_timing",
-            "sol_get_timing", "sol_last_error", "sol_version"]
+            "sol_get_timing", "sol_set_option", "sol_autotune", "sol_last_error", "sol_version"]
 
 
 def check(rc):
@@ -286,6 +288,14 @@ class Case:
                                      va.ctypes.data_as(C.POINTER(C.c_double)),
                                      rhs.ctypes.data_as(C.POINTER(C.c_double))))
         return rp, ci[:nnz], va[:nnz], rhs[:n]
+
+    def set_graph(self, on: bool):
+        check(load().sol_set_option(self.h, 1, 1 if on else 0))
+
+    def autotune(self) -> int:
+        r = C.c_int32(0)
+        check(load().sol_autotune(self.h, C.byref(r)))
+        return r.value
 
     def set_timing(self, on: bool):
         check(load().sol_set_timing(self.h, 1 if on else 0))

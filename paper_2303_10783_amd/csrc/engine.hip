@@ -17,7 +17,10 @@
 #include "kernels.hpp"
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <map>
+#include <mutex>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -127,10 +130,23 @@ static size_t footprint(const Sizes &z, int precision)
     return b;
 }
 
-// rows per tile of a solve: 1..8 rows per thread, aiming at <= ~384 tiles so
-// that the per-kernel totals of the partial sums stay cheap
-static int rows_per_tile(int n)
+// Rows per tile of a solve.  Default: 1..8 rows per thread, aiming at
+// <= ~384 tiles so that the per-kernel totals of the partial sums stay
+// cheap.  sol_autotune replaces the default for a size class (stencil
+// width, floor(log2 n)) by the fastest measured choice; the table is
+// process-wide so a case gets the same tiles alone and in a batch.
+static std::mutex g_tune_mu;
+static std::map<int, int> g_tuned_rpt;
+
+static int size_class(int n, int nd) { return nd * 64 + (n > 0 ? 31 - __builtin_clz((unsigned)n) : 0); }
+
+static int rows_per_tile(int n, int nd)
 {
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tuned_rpt.find(size_class(n, nd));
+        if (it != g_tuned_rpt.end()) return it->second;
+    }
     const int m = std::max(1, std::min(8, ceil_div(n, TILE * 384)));
     return TILE * m;
 }
@@ -177,6 +193,7 @@ struct sol_handle {
     Group *solo = nullptr;
     sol_batch *batch = nullptr;
     bool timing = false;
+    bool opt_graph = false;
     TAcc tacc[SOL_NKCLASS];
     std::vector<TSample> samples;
     std::vector<hipEvent_t> event_pool;
@@ -193,6 +210,8 @@ struct JobSet {
     KJob *jobs_d = nullptr;
     JTile *tiles_d[2] = {nullptr, nullptr};   // [0] 5-point jobs, [1] 7-point jobs
     int nt[2] = {0, 0};
+    hipGraph_t graph = nullptr;          // GCH iterations + advance of the index base
+    hipGraphExec_t exec = nullptr;
 };
 
 struct Phase {
@@ -221,6 +240,8 @@ struct Group {
     int nks = 0;
     int precision = SOL_PRECISION_FP64;
     sol_handle *timer = nullptr;          // handle that collects kernel timing (solo groups)
+    int *kbase_d = nullptr;               // iteration index base of graph-replayed chunks
+    bool use_graph = false;
 };
 
 static void *gmalloc(Group &g, size_t bytes)
@@ -234,6 +255,11 @@ static void *gmalloc(Group &g, size_t bytes)
 static void group_free(Group *g)
 {
     if (!g) return;
+    for (auto &P : g->ph)
+        for (JobSet *S : {&P.main, &P.inner}) {
+            if (S->exec) (void)hipGraphExecDestroy(S->exec);
+            if (S->graph) (void)hipGraphDestroy(S->graph);
+        }
     for (void *p : g->dmem) (void)hipFree(p);
     for (int i = 0; i < 2; ++i) {
         if (g->ks_h[i]) (void)hipHostFree(g->ks_h[i]);
@@ -288,7 +314,9 @@ static int group_build(Group &g)
     const bool mixed = g.precision == SOL_PRECISION_MIXED;
     g.ks_d = (KState *)gmalloc(g, sizeof(KState) * 2 * g.nks);
     g.red_d = (double *)gmalloc(g, sizeof(double) * 16 * n);
-    if (!g.ks_d || !g.red_d) return fail(SOL_ENOMEM, "group allocation failed");
+    g.kbase_d = (int *)gmalloc(g, 256);
+    if (!g.ks_d || !g.red_d || !g.kbase_d) return fail(SOL_ENOMEM, "group allocation failed");
+    HIPCHK(hipMemset(g.kbase_d, 0, 256));
     HIPCHK(hipMemset(g.red_d, 0, sizeof(double) * 16 * n));
     std::vector<CaseDev> cdv(n);
     std::vector<KState> ksv(2 * g.nks);
@@ -351,7 +379,7 @@ static int group_build(Group &g)
                 J.n = h->z.nsys[s];
                 J.sx = h->z.sdim[s][0];
                 J.sxy = h->z.sdim[s][0] * h->z.sdim[s][1];
-                J.rpt = rows_per_tile(J.n);
+                J.rpt = rows_per_tile(J.n, h->z.nd);
                 J.ntile = ceil_div(J.n, J.rpt);
                 J.kind = P.kind;
                 J.A = h->cd.A[s];
@@ -484,14 +512,74 @@ static void collect_samples(Group &g, const KState *ks)
 
 // ------------------------------------------------------------------ solves
 
+// Graph replay of iteration chunks: a graph holds GCH iterations of a job set
+// (kernel nodes reading the iteration index from the device base plus a
+// fixed offset) followed by a node that advances the base by GCH.  Built
+// node by node (no stream capture: the library may run on the legacy
+// default stream) on first use and replayed for every chunk.
+constexpr int GCH = 16;
+
+static int build_chunk_graph(Group &g, Phase &P, JobSet &S, int fp32)
+{
+    HIPCHK(hipGraphCreate(&S.graph, 0));
+    hipGraphNode_t prev = nullptr;
+    const int nk = P.kind == K_CG ? 1 : 3;
+    for (int i = 0; i < GCH; ++i)
+        for (int q = 0; q < nk; ++q)
+            for (int gi = 0; gi < 2; ++gi) {
+                if (S.nt[gi] <= 0) continue;
+                const int which = (P.kind == K_CG ? KI_CG : KI_BICG_A) + q;
+                const KJob *jobs = S.jobs_d;
+                const JTile *tiles = S.tiles_d[gi];
+                const int *kb = g.kbase_d;
+                int koff = i;
+                void *args[] = {(void *)&jobs, (void *)&tiles, (void *)&kb, (void *)&koff};
+                hipKernelNodeParams kp;
+                std::memset(&kp, 0, sizeof(kp));
+                kp.func = (void *)kiter_fn(which, gi ? 7 : 5, fp32);
+                kp.gridDim = dim3((unsigned)S.nt[gi]);
+                kp.blockDim = dim3(TILE);
+                kp.sharedMemBytes = 0;
+                kp.kernelParams = args;
+                kp.extra = nullptr;
+                hipGraphNode_t node;
+                HIPCHK(hipGraphAddKernelNode(&node, S.graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp));
+                prev = node;
+            }
+    {
+        int *kb = g.kbase_d;
+        int m = GCH;
+        void *args[] = {(void *)&kb, (void *)&m};
+        hipKernelNodeParams kp;
+        std::memset(&kp, 0, sizeof(kp));
+        kp.func = (void *)kbase_add_fn();
+        kp.gridDim = dim3(1);
+        kp.blockDim = dim3(64);
+        kp.kernelParams = args;
+        hipGraphNode_t node;
+        HIPCHK(hipGraphAddKernelNode(&node, S.graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp));
+    }
+    HIPCHK(hipGraphInstantiate(&S.exec, S.graph, nullptr, nullptr, 0));
+    return SOL_OK;
+}
+
 // Timing: CG iterations are timed in windows of TWIN consecutive launches
 // (one event pair per window; per-launch events would add their own
 // latency), BiCGSTAB kernels one launch at a time, every 8th iteration.
 constexpr int TWIN = 16;
 
-static void enqueue_iters(Group &g, Phase &P, const JobSet &S, int fp32, int nits, int &k)
+static int enqueue_iters(Group &g, Phase &P, JobSet &S, int fp32, int nits, int &k)
 {
     sol_handle *tm = g.timer;
+    if (g.use_graph && !tm && nits >= GCH) {
+        if (!S.exec) RCHK(build_chunk_graph(g, P, S, fp32));
+        launch_kbase_set(g.kbase_d, k, g.stream);
+        const int chunks = ceil_div(nits, GCH);
+        for (int c = 0; c < chunks; ++c) HIPCHK(hipGraphLaunch(S.exec, g.stream));
+        k += chunks * GCH;
+        P.launched += chunks * GCH;
+        return SOL_OK;
+    }
     const int nk = P.kind == K_CG ? 1 : 3;
     hipEvent_t wa = nullptr, wb = nullptr;
     int wend = -1;
@@ -525,6 +613,7 @@ static void enqueue_iters(Group &g, Phase &P, const JobSet &S, int fp32, int nit
         k += 1;
         P.launched += 1;
     }
+    return SOL_OK;
 }
 
 static int poll_enqueue(Group &g, int slot)
@@ -561,16 +650,16 @@ static bool any_running(const Group &g, const JobSet &S, int slot, const JobSet 
 // Queue iteration chunks of the solves in S until none is RUNNING.  While
 // the host inspects chunk i the device runs chunk i+1.  Returns the slot
 // holding the newest states.
-static int iterate(Group &g, Phase &P, const JobSet &S, int fp32, int pred, int &k, const JobSet *gate,
+static int iterate(Group &g, Phase &P, JobSet &S, int fp32, int pred, int &k, const JobSet *gate,
                    int gslot, int *out_slot)
 {
     int slot = gslot ^ 1;
     const int first = std::max(1, pred - pred / 8);
     const int later = std::max(2, pred / 16);
-    enqueue_iters(g, P, S, fp32, first, k);
+    RCHK(enqueue_iters(g, P, S, fp32, first, k));
     RCHK(poll_enqueue(g, slot));
     for (;;) {
-        enqueue_iters(g, P, S, fp32, later, k);
+        RCHK(enqueue_iters(g, P, S, fp32, later, k));
         RCHK(poll_enqueue(g, slot ^ 1));
         RCHK(poll_wait(g, slot));
         if (!any_running(g, S, slot, gate, gslot)) {
@@ -609,7 +698,19 @@ static int solve_plain(Group &g, Phase &P)
         RCHK(poll_wait(g, 0));
         HIPCHK(hipGetLastError());
         if (any_status(g, S, 0, K_NONFINITE)) { rc = fail(SOL_ENONFINITE, "non-finite value in a linear solve"); break; }
-        if (any_status(g, S, 0, K_FAILED)) { rc = fail(SOL_ENOCONV, "linear solve did not converge within max_iter"); break; }
+        if (any_status(g, S, 0, K_FAILED)) {
+            for (size_t j = 0; j < S.jobs.size(); ++j) {
+                const KState &ks = g.ks_h[0][S.st_index[j]];
+                if (ks.status == K_FAILED) {
+                    rc = fail(SOL_ENOCONV, "linear solve did not converge (case %d, system %d, %d iterations, "
+                                           "%d restarts, ||r||/||b|| = %.3e)",
+                              S.case_of[j], S.sys_of[j], ks.it, ks.restarts,
+                              ks.bb > 0 ? std::sqrt(ks.rr / ks.bb) : 0.0);
+                    break;
+                }
+            }
+            break;
+        }
         if (!any_status(g, S, 0, K_RESTART)) break;
         for (int gi = 0; gi < 2; ++gi)
             launch_kinit(P.kind, gi ? 7 : 5, 0, S.jobs_d, S.tiles_d[gi], S.nt[gi], k, 1, g.stream);
@@ -660,8 +761,17 @@ static int solve_mixed(Group &g, Phase &P)
     record_iters(g, S, 0, &mx);
     P.pred = mx;
     if (any_status(g, S, 0, K_NONFINITE)) return fail(SOL_ENONFINITE, "non-finite value in a linear solve");
-    if (any_status(g, S, 0, K_FAILED) || any_status(g, S, 0, K_RUNNING))
-        return fail(SOL_ENOCONV, "refinement did not reach the tolerance");
+    for (size_t j = 0; j < S.jobs.size(); ++j) {
+        const KState &ks = g.ks_h[0][S.st_index[j]];
+        if (ks.status == K_FAILED || ks.status == K_RUNNING) {
+            const KState &ki = g.ks_h[0][I.st_index[j]];
+            return fail(SOL_ENOCONV,
+                        "refinement did not reach the tolerance (case %d, system %d, %d sweeps, %d inner "
+                        "iterations, ||r||/||b|| = %.3e, last inner solve: status %d after %d iterations)",
+                        S.case_of[j], S.sys_of[j], ks.outer, ks.inner_total,
+                        ks.bb > 0 ? std::sqrt(ks.rr / ks.bb) : 0.0, ki.status, ki.it);
+        }
+    }
     if (g.timer) collect_samples(g, g.ks_h[0]);
     return SOL_OK;
 }
@@ -1122,6 +1232,7 @@ int sol_step(sol_handle *h, int32_t nsteps, sol_step_stats *stats)
     if (h->batch) return fail(SOL_EBUSY, "handle is part of a batch");
     Group &g = *h->solo;
     g.timer = h->timing ? h : nullptr;
+    g.use_graph = h->opt_graph;
     int64_t tot[NSYS] = {};
     for (int k = 0; k < nsteps; ++k) {
         int rc = group_step(g);
@@ -1155,6 +1266,93 @@ int sol_get_timing(sol_handle *h, int32_t kclass, int64_t *launches, double *tot
     *launches = h->tacc[kclass].n;
     *total_ms = h->tacc[kclass].ms;
     *bytes = h->tacc[kclass].bytes;
+    return SOL_OK;
+}
+
+int sol_set_option(sol_handle *h, int32_t option, int64_t value)
+{
+    if (!h) return fail(SOL_EINVAL, "NULL handle");
+    switch (option) {
+    case SOL_OPT_GRAPH: h->opt_graph = value != 0; return SOL_OK;
+    }
+    return fail(SOL_EINVAL, "unknown option %d", option);
+}
+
+// time CG iterations of the pressure system (FP32 inner solve for mixed
+// precision) with the current tiles; never converges (tol 0)
+static int time_cg(sol_handle *h, double *ms_per_iter)
+{
+    Group &g = *h->solo;
+    Phase &P = g.ph[1];
+    const bool fp32 = g.precision == SOL_PRECISION_MIXED;
+    JobSet &S = fp32 ? P.inner : P.main;
+    if (S.jobs.empty()) return fail(SOL_EINVAL, "no pressure system to tune");
+    const KJob &J = S.jobs[0];
+    launch_tune_rhs((void *)J.b, fp32 ? 1 : 0, J.n, g.stream);
+    const double zero = 0.0;
+    const int running = K_RUNNING;
+    HIPCHK(hipMemcpy((char *)J.st + offsetof(KState, tol2), &zero, sizeof(zero), hipMemcpyHostToDevice));
+    if (fp32)
+        HIPCHK(hipMemcpy((char *)J.partner + offsetof(KState, status), &running, sizeof(running), hipMemcpyHostToDevice));
+    const int nd = h->z.nd, gi = nd == 7 ? 1 : 0;
+    launch_kinit(K_CG, nd, fp32 ? 1 : 0, S.jobs_d, S.tiles_d[gi], S.nt[gi], 0, 0, g.stream);
+    const int warm = 8, timed_its = 48;
+    for (int k = 0; k < warm; ++k) launch_kiter(KI_CG, nd, fp32 ? 1 : 0, S.jobs_d, S.tiles_d[gi], S.nt[gi], k, g.stream);
+    hipEvent_t a, b;
+    HIPCHK(hipEventCreate(&a));
+    HIPCHK(hipEventCreate(&b));
+    HIPCHK(hipEventRecord(a, g.stream));
+    for (int k = warm; k < warm + timed_its; ++k)
+        launch_kiter(KI_CG, nd, fp32 ? 1 : 0, S.jobs_d, S.tiles_d[gi], S.nt[gi], k, g.stream);
+    HIPCHK(hipEventRecord(b, g.stream));
+    HIPCHK(hipEventSynchronize(b));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, a, b));
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    HIPCHK(hipGetLastError());
+    *ms_per_iter = ms / timed_its;
+    return SOL_OK;
+}
+
+int sol_autotune(sol_handle *h, int32_t *rows_per_tile_out)
+{
+    if (!h) return fail(SOL_EINVAL, "NULL handle");
+    if (h->batch) return fail(SOL_EBUSY, "handle is part of a batch");
+    const int n = h->z.nsys[SP], nd = h->z.nd;
+    const int cls = size_class(n, nd);
+    const int cand[] = {256, 512, 1024, 2048, 4096};
+    int best = -1;
+    double best_ms = 1e300;
+    int rc = SOL_OK;
+    for (int rpt : cand) {
+        const int nt = ceil_div(n, rpt);
+        if (nt > 8192 || (rpt > 256 && nt < 8)) continue;
+        {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            g_tuned_rpt[cls] = rpt;
+        }
+        group_free(h->solo);
+        h->solo = nullptr;
+        rc = group_create({h}, &h->solo);
+        if (rc != SOL_OK) break;
+        double ms = 0.0;
+        rc = time_cg(h, &ms);
+        if (rc != SOL_OK) break;
+        if (ms < best_ms) { best_ms = ms; best = rpt; }
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        if (best > 0) g_tuned_rpt[cls] = best;
+        else g_tuned_rpt.erase(cls);
+    }
+    (void)hipStreamSynchronize(h->stream);
+    group_free(h->solo);
+    h->solo = nullptr;
+    const int rc2 = group_create({h}, &h->solo);
+    if (rc != SOL_OK) return rc;
+    if (rc2 != SOL_OK) return rc2;
+    if (rows_per_tile_out) *rows_per_tile_out = best;
     return SOL_OK;
 }
 
@@ -1216,6 +1414,7 @@ int sol_batch_step(sol_batch *b, const int32_t *nsteps, sol_step_stats *stats)
             b->active = act;
         }
         b->g->timer = nullptr;
+        b->g->use_graph = b->cs[0]->opt_graph;
         int rc = group_step(*b->g);
         if (rc != SOL_OK) { (void)hipStreamSynchronize(b->cs[0]->stream); return rc; }
         for (size_t a = 0; a < act.size(); ++a)

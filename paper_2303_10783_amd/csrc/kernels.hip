@@ -715,8 +715,9 @@ __global__ __launch_bounds__(TILE) void k_bicg_init(const KJob *__restrict__ job
 // a: beta = (rho_k/rho_{k-1})(alpha_{k-1}/omega_{k-1});
 //    p = r + beta (p - omega v); v = A M p; partial (rh, v)
 template <int ND, class T>
-__global__ __launch_bounds__(TILE) void k_bicg_a(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles, int k)
+__global__ __launch_bounds__(TILE) void k_bicg_a(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles, const int *kbase, int koff)
 {
+    const int k = (kbase ? *kbase : 0) + koff;
     JTile tl;
     const KJob &J = job_of(jobs, tiles, tl);
     if (!active(J, k) || outer_idle(J)) return;
@@ -764,8 +765,9 @@ __global__ __launch_bounds__(TILE) void k_bicg_a(const KJob *__restrict__ jobs, 
 
 // b: alpha = rho_k / (rh, v); s = r - alpha v; t = A M s; partials (t,s), (t,t)
 template <int ND, class T>
-__global__ __launch_bounds__(TILE) void k_bicg_b(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles, int k)
+__global__ __launch_bounds__(TILE) void k_bicg_b(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles, const int *kbase, int koff)
 {
+    const int k = (kbase ? *kbase : 0) + koff;
     JTile tl;
     const KJob &J = job_of(jobs, tiles, tl);
     if (J.st->status != K_RUNNING || outer_idle(J)) return;
@@ -801,8 +803,9 @@ __global__ __launch_bounds__(TILE) void k_bicg_b(const KJob *__restrict__ jobs, 
 // c: omega = (t,s)/(t,t); x += M (alpha p + omega s); r = s - omega t;
 // partials (rh, r), (r, r) for iteration k+1
 template <int ND, class T>
-__global__ __launch_bounds__(TILE) void k_bicg_c(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles, int k)
+__global__ __launch_bounds__(TILE) void k_bicg_c(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles, const int *kbase, int koff)
 {
+    const int k = (kbase ? *kbase : 0) + koff;
     JTile tl;
     const KJob &J = job_of(jobs, tiles, tl);
     if (J.st->status != K_RUNNING || outer_idle(J)) return;
@@ -902,34 +905,40 @@ __global__ __launch_bounds__(TILE) void k_cg_init_b(const KJob *__restrict__ job
 
 // CG iteration k (one kernel)
 template <int ND, class T>
-__global__ __launch_bounds__(TILE) void k_cg(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles, int k)
+__global__ __launch_bounds__(TILE) void k_cg(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles, const int *kbase, int koff)
 {
+    const int k = (kbase ? *kbase : 0) + koff;
     JTile tl;
     const KJob &J = job_of(jobs, tiles, tl);
     if (!active(J, k) || outer_idle(J)) return;
     KState *st = J.st;
     const int pk = k & 1, pm = (k + 1) & 1;
     const bool first = k == st->k0;
-    double s5[5];
+    // this kernel writes its partials into the parity-k slots while other
+    // workgroups may still be reading; so it reads only parity k-1 slots and
+    // takes gamma_{k-1}, alpha_{k-1} from the scalars workgroup 0 recorded
+    double s4[4];
     {
-        const int off[5] = {poff(J, pm, PS_RHO), poff(J, pm, PS_TS), poff(J, pm, PS_RR), poff(J, pm, PS_BB),
-                            poff(J, pk, PS_RHO)};
-        sum_partials<5>(J.part, off, J.ntile, s5);
+        const int off[4] = {poff(J, pm, PS_RHO), poff(J, pm, PS_TS), poff(J, pm, PS_RR), poff(J, pm, PS_BB)};
+        sum_partials<4>(J.part, off, J.ntile, s4);
     }
-    if (!keep_going(J, tl, k, s5[2], s5[3])) return;
-    const double gam = s5[0], del = s5[1];
+    if (!keep_going(J, tl, k, s4[2], s4[3])) return;
+    const double gam = s4[0], del = s4[1];
     double alpha, beta = 0.0;
     if (first) {
         alpha = gam / del;
     } else {
-        beta = gam / s5[4];
+        beta = gam / st->gamma[pm];
         alpha = gam / (del - beta * gam / st->alpha[pm]);
     }
     if (!(alpha > 0.0) || !finite(alpha) || !finite(beta)) {
-        set_status(tl, st, finite(alpha) ? K_RESTART : K_NONFINITE, st->it_base + (k - st->k0), s5[2]);
+        set_status(tl, st, finite(alpha) ? K_RESTART : K_NONFINITE, st->it_base + (k - st->k0), s4[2]);
         return;
     }
-    if (tl.t == 0 && threadIdx.x == 0) st->alpha[pk] = alpha;
+    if (tl.t == 0 && threadIdx.x == 0) {
+        st->alpha[pk] = alpha;
+        st->gamma[pk] = gam;
+    }
     const T ta = (T)alpha, tb = (T)beta;
     const int n = J.n;
     auto A = G<T>(J.A);
@@ -1235,19 +1244,69 @@ static void launch_iter_t(int which, int nd, const KJob *j, const JTile *t, int 
 {
     if (nd == 5) {
         switch (which) {
-        case KI_CG: hipLaunchKernelGGL((k_cg<5, T>), GRID(nt), 0, s, j, t, k); break;
-        case KI_BICG_A: hipLaunchKernelGGL((k_bicg_a<5, T>), GRID(nt), 0, s, j, t, k); break;
-        case KI_BICG_B: hipLaunchKernelGGL((k_bicg_b<5, T>), GRID(nt), 0, s, j, t, k); break;
-        default: hipLaunchKernelGGL((k_bicg_c<5, T>), GRID(nt), 0, s, j, t, k); break;
+        case KI_CG: hipLaunchKernelGGL((k_cg<5, T>), GRID(nt), 0, s, j, t, (const int *)nullptr, k); break;
+        case KI_BICG_A: hipLaunchKernelGGL((k_bicg_a<5, T>), GRID(nt), 0, s, j, t, (const int *)nullptr, k); break;
+        case KI_BICG_B: hipLaunchKernelGGL((k_bicg_b<5, T>), GRID(nt), 0, s, j, t, (const int *)nullptr, k); break;
+        default: hipLaunchKernelGGL((k_bicg_c<5, T>), GRID(nt), 0, s, j, t, (const int *)nullptr, k); break;
         }
     } else {
         switch (which) {
-        case KI_CG: hipLaunchKernelGGL((k_cg<7, T>), GRID(nt), 0, s, j, t, k); break;
-        case KI_BICG_A: hipLaunchKernelGGL((k_bicg_a<7, T>), GRID(nt), 0, s, j, t, k); break;
-        case KI_BICG_B: hipLaunchKernelGGL((k_bicg_b<7, T>), GRID(nt), 0, s, j, t, k); break;
-        default: hipLaunchKernelGGL((k_bicg_c<7, T>), GRID(nt), 0, s, j, t, k); break;
+        case KI_CG: hipLaunchKernelGGL((k_cg<7, T>), GRID(nt), 0, s, j, t, (const int *)nullptr, k); break;
+        case KI_BICG_A: hipLaunchKernelGGL((k_bicg_a<7, T>), GRID(nt), 0, s, j, t, (const int *)nullptr, k); break;
+        case KI_BICG_B: hipLaunchKernelGGL((k_bicg_b<7, T>), GRID(nt), 0, s, j, t, (const int *)nullptr, k); break;
+        default: hipLaunchKernelGGL((k_bicg_c<7, T>), GRID(nt), 0, s, j, t, (const int *)nullptr, k); break;
         }
     }
+}
+
+template <class T>
+static const void *iter_fn_t(int which, int nd)
+{
+    if (nd == 5) {
+        switch (which) {
+        case KI_CG: return (const void *)&k_cg<5, T>;
+        case KI_BICG_A: return (const void *)&k_bicg_a<5, T>;
+        case KI_BICG_B: return (const void *)&k_bicg_b<5, T>;
+        default: return (const void *)&k_bicg_c<5, T>;
+        }
+    }
+    switch (which) {
+    case KI_CG: return (const void *)&k_cg<7, T>;
+    case KI_BICG_A: return (const void *)&k_bicg_a<7, T>;
+    case KI_BICG_B: return (const void *)&k_bicg_b<7, T>;
+    default: return (const void *)&k_bicg_c<7, T>;
+    }
+}
+
+const void *kiter_fn(int which, int nd, int fp32)
+{
+    return fp32 ? iter_fn_t<float>(which, nd) : iter_fn_t<double>(which, nd);
+}
+
+// iteration index base of graph-replayed chunks
+__global__ void k_kbase_add(int *kbase, int m) { if (threadIdx.x == 0 && blockIdx.x == 0) *kbase += m; }
+__global__ void k_kbase_set(int *kbase, int v) { if (threadIdx.x == 0 && blockIdx.x == 0) *kbase = v; }
+
+const void *kbase_add_fn() { return (const void *)&k_kbase_add; }
+
+void launch_kbase_set(int *kbase, int v, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_kbase_set, dim3(1), dim3(64), 0, s, kbase, v);
+}
+
+// deterministic right-hand side for the tile-size tuner, b_i = (i mod 7) - 3
+// (any finite, nonzero values do: the tuner never lets the solve converge)
+template <class T>
+__global__ void k_tune_rhs(T *b, int n)
+{
+    const int i = blockIdx.x * TILE + threadIdx.x;
+    if (i < n) b[i] = (T)(i % 7) - (T)3;
+}
+void launch_tune_rhs(void *b, int fp32, int n, hipStream_t s)
+{
+    if (n <= 0) return;
+    if (fp32) hipLaunchKernelGGL(k_tune_rhs<float>, dim3(ceil_div(n, TILE)), dim3(TILE), 0, s, (float *)b, n);
+    else hipLaunchKernelGGL(k_tune_rhs<double>, dim3(ceil_div(n, TILE)), dim3(TILE), 0, s, (double *)b, n);
 }
 
 void launch_kiter(int which, int nd, int fp32, const KJob *j, const JTile *t, int nt, int k, hipStream_t s)

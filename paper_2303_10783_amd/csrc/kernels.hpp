@@ -17,6 +17,11 @@ void launch_kfinish(int nd, const KJob *j, const JTile *t, int nt, hipStream_t s
 void launch_kdecide(const KJob *j, int njobs, hipStream_t s);
 enum KIter { KI_CG = 0, KI_BICG_A = 1, KI_BICG_B = 2, KI_BICG_C = 3 };
 void launch_kiter(int which, int nd, int fp32, const KJob *j, const JTile *t, int nt, int k, hipStream_t s);
+// graph building: kernel addresses (signature jobs, tiles, const int *kbase, int koff)
+const void *kiter_fn(int which, int nd, int fp32);
+const void *kbase_add_fn();   // (int *kbase, int m)
+void launch_kbase_set(int *kbase, int v, hipStream_t s);
+void launch_tune_rhs(void *b, int fp32, int n, hipStream_t s);
 void launch_ir_resid(int nd, const KJob *j, const JTile *t, int nt, int mode, hipStream_t s);
 void launch_ir_decide(const KJob *j, int njobs, int mode, int max_outer, hipStream_t s);
 void launch_ir_update(int nd, const KJob *j, const JTile *t, int nt, hipStream_t s);

@@ -33,6 +33,7 @@ struct KState {
     double bmean;              // mean of the pressure rhs (removed before the solve)
     double tol2;               // tol^2
     double alpha[2];           // CG step length of iterations of parity 0 / 1
+    double gamma[2];           // CG (r, M r) of iterations of parity 0 / 1
     int32_t status;            // KStatus
     int32_t it;                // iterations done (valid once not RUNNING)
     int32_t it_base;           // iterations done before the current (re)start

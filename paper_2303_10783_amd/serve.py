@@ -1,0 +1,123 @@
+"""Continuous-batching request loop over the batched step of libsol.
+
+Requests (cases with an arrival time and a step count) are admitted in
+arrival order while their device footprint (sol_footprint_bytes) fits the
+memory budget and the batch has a free slot.  Admitted cases stay on the
+device; every tick advances all admitted cases by one time step in one
+batched launch sequence (sol_batch_step).  A case that has done its steps
+leaves the batch, its fields are read back, its memory is released and the
+next waiting request can take the slot, while the others keep running.
+Latency = time from arrival until the fields are on the host.
+
+Every step runs in the library's kernels; this module only schedules.
+"""
+from __future__ import annotations
+
+import time
+from collections import deque
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from .binding import Batch, Case, sol_footprint_bytes
+
+
+@dataclass
+class Request:
+    case: dict
+    steps: int
+    arrival: float                    # seconds after the start of the run
+    rid: int = 0
+    cells: int = 0
+    footprint: int = 0
+    admitted: float = -1.0
+    finished: float = -1.0
+    result: dict | None = None
+    steps_done: int = 0
+    handle: Case | None = field(default=None, repr=False)
+
+    @property
+    def latency(self) -> float:
+        return self.finished - self.arrival
+
+
+class Server:
+    def __init__(self, device=None, hbm_budget_bytes: int = 270 * 2 ** 30, max_active: int = 64,
+                 graph: bool = False, keep_results: bool = True):
+        self.device = device
+        self.budget = int(hbm_budget_bytes)
+        self.max_active = int(max_active)
+        self.graph = graph
+        self.keep_results = keep_results
+        self.log = []                 # (time, event, request id)
+
+    def run(self, requests, clock=time.perf_counter, sleep=time.sleep):
+        pending = deque(sorted(requests, key=lambda r: r.arrival))
+        for i, r in enumerate(pending):
+            g = r.case["grid"]
+            r.cells = g["nx"] * g["ny"] * (g["nz"] if g["dim"] == 3 else 1)
+            r.footprint = sol_footprint_bytes(r.case)
+            if r.footprint > self.budget:
+                raise ValueError(f"request {r.rid} needs {r.footprint} B, over the budget")
+        waiting, active, done = deque(), [], []
+        used = 0
+        batch = None
+        members = None
+        t0 = clock()
+        cell_steps = 0
+        while pending or waiting or active:
+            now = clock() - t0
+            while pending and pending[0].arrival <= now:
+                waiting.append(pending.popleft())
+            # admission in arrival order, by footprint and free slots
+            while waiting and len(active) < self.max_active and used + waiting[0].footprint <= self.budget:
+                r = waiting.popleft()
+                r.handle = Case(r.case, device=self.device)
+                if self.graph:
+                    r.handle.set_graph(True)
+                r.admitted = clock() - t0
+                used += r.footprint
+                active.append(r)
+                self.log.append((r.admitted, "admit", r.rid))
+            if not active:
+                if pending:
+                    sleep(max(0.0, min(0.01, pending[0].arrival - (clock() - t0))))
+                continue
+            ids = [r.rid for r in active]
+            if batch is None or members != ids:
+                if batch is not None:
+                    batch.close()
+                batch = Batch([r.handle for r in active])
+                members = ids
+            batch.step([1] * len(active))
+            for r in active:
+                r.steps_done += 1
+                cell_steps += r.cells
+            finished = [r for r in active if r.steps_done >= r.steps]
+            if finished:
+                batch.close()
+                batch = None
+                members = None
+                for r in finished:
+                    fields = r.handle.read_fields()
+                    r.finished = clock() - t0
+                    r.result = fields if self.keep_results else None
+                    r.handle.close()
+                    r.handle = None
+                    used -= r.footprint
+                    active.remove(r)
+                    done.append(r)
+                    self.log.append((r.finished, "finish", r.rid))
+        if batch is not None:
+            batch.close()
+        wall = clock() - t0
+        lat = np.array([r.latency for r in done])
+        span = max(r.arrival for r in done) - min(r.arrival for r in done) if len(done) > 1 else 0.0
+        offered = sum(r.cells * r.steps for r in done) / span if span > 0 else float("inf")
+        return dict(
+            requests=len(done), wall_s=wall,
+            cell_updates_per_s=cell_steps / wall if wall > 0 else 0.0,
+            p50_latency_s=float(np.percentile(lat, 50)), p99_latency_s=float(np.percentile(lat, 99)),
+            mean_latency_s=float(lat.mean()), offered_cell_updates_per_s=offered,
+            done=done,
+        )
