@@ -1,7 +1,9 @@
 """Throughput of the full time step on one MI355X.
 
 Default workload: the 500x300 2D cavity (Sn-10%Pb-type alloy, west wall
-cooled by h = 400 W/m^2K to 298 K, PCG / BiCGSTAB tolerance 1e-10), FP64.
+cooled by h = 400 W/m^2K to 298 K, PCG / BiCGSTAB tolerance 1e-10), FP64,
+pressure CG preconditioned by a multigrid V-cycle (--precond jacobi for the
+inverse diagonal).
 A step is one pass of Algorithm 1 (momentum predictor, pressure
 correction, projection, solute, energy, phase update) through the HIP
 library; value = cells x steps / wall time of the timed steps, with the
@@ -9,11 +11,13 @@ state resident on the device.
 
 Also printed in the same JSON line:
   roofline      achieved algorithmic GB/s of the dominant kernel (HIP events
-                on the library's stream, windows of 16 launches) against
-                8 TB/s, and the counter-measured HBM bytes per launch;
+                on the library's stream: windows of 16 launches for the
+                single-kernel CG, single launches otherwise) against 8 TB/s,
+                and the counter-measured HBM bytes per launch;
   cpu_baseline  the FP64 oracle on the host for a bounded number of steps;
-  variants      the same step in mixed precision, the 128x128x64 box (FP64
-                and mixed), 64 uneven cavities in one batch (mixed and FP64,
+  variants      the same step in mixed precision, with graphs and with
+                Jacobi-PCG, the 128x128x64 box (FP64, mixed, Jacobi-PCG), 64
+                uneven cavities in one batch (mixed and FP64,
                 graph-replayed chunks, tuned tiles) and the served request
                 stream (continuous batching, p50/p99 latency).
 """
@@ -33,42 +37,51 @@ METRIC = "cell-updates/s per full time step (1 GPU), mixed vs FP64; p50/p99 case
 HBM_PEAK_GBS = 8000.0
 
 
-def roofline(g, ncell_rows):
-    """Dominant kernel class by estimated time per step, from sampled events."""
+def roofline(g, launches_per_step):
+    """Dominant kernel class by estimated time per step (average sampled
+    launch duration x launches per step).  The multigrid coarse-level class
+    spans several kernels and carries no byte count; it is not a candidate."""
     best = None
-    for cls in ("cg", "bicg_a", "bicg_b", "bicg_c", "asm_mom", "asm_trn", "phase"):
+    for cls in ("cg", "bicg_a", "bicg_b", "bicg_c", "asm_mom", "asm_trn", "phase", "mg_pq", "mg_down0", "mg_up0"):
         t = g.timing(cls)
-        if t["launches"] == 0:
+        if t["launches"] == 0 or t["bytes"] == 0:
             continue
         t["avg_ms"] = t["ms"] / t["launches"]
         t["bytes_per_launch"] = t["bytes"] / t["launches"]
         t["gbs"] = t["bytes"] / (t["ms"] * 1e-3) / 1e9
         t["cls"] = cls
         # estimated share of the step: avg duration x launches per step
-        per_step = ncell_rows.get(cls, 1.0)
+        per_step = launches_per_step.get(cls, 1.0)
         t["est_ms_per_step"] = t["avg_ms"] * per_step
         if best is None or t["est_ms_per_step"] > best["est_ms_per_step"]:
             best = t
     return best
 
 
-def counter_traffic(workload, kernel_cls):
-    """HBM bytes per launch of the CG kernel from the committed rocprofv3
-    FETCH_SIZE / WRITE_SIZE summary (scaled by the copy reference), or None
-    when that summary does not cover this workload or the kernel source has
-    changed since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", "k_cg_hbm_traffic.txt")
-    src = os.path.join(ROOT, "paper_2303_10783_amd", "csrc", "kernels.hip")
-    if kernel_cls != "cg" or not os.path.exists(path):
+def kernel_sources_sha():
+    """sha256 over the kernel sources (the counters are void once they change)."""
+    h = hashlib.sha256()
+    for f in ("kcommon.hpp", "sol_dev.hpp", "kernels.hip", "mg.hip"):
+        h.update(open(os.path.join(ROOT, "paper_2303_10783_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
+
+
+def counter_traffic(workload, kernel_cls, precond):
+    """HBM bytes per launch of the dominant kernel from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE summary (scaled by the copy reference),
+    or None when that summary does not cover this workload and kernel or the
+    kernel sources have changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    if not os.path.exists(path):
         return None
     doc = json.load(open(path))
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    if doc.get("kernels_hip_sha256") != sha or workload not in doc:
+    key = f"{workload}:{precond}:{kernel_cls}"
+    if doc.get("kernel_sources_sha256") != kernel_sources_sha() or key not in doc:
         return None
-    return doc[workload]["traffic_bytes_per_launch"]
+    return doc[key]["traffic_bytes_per_launch"]
 
 
-def run_single(sol, W, key, precision, steps, warmup, dev, graph=False):
+def run_single(sol, W, key, precision, steps, warmup, dev, graph=False, precond="mg"):
     import torch
     case = W.workload_case(key)
     if precision == "mixed":
@@ -76,6 +89,8 @@ def run_single(sol, W, key, precision, steps, warmup, dev, graph=False):
     g = case["grid"]
     ncell = g["nx"] * g["ny"] * (g["nz"] if g["dim"] == 3 else 1)
     h = sol.Case(case, device=dev)
+    if precond != "mg":
+        h.set_precond(precond)
     if graph:
         h.set_graph(True)
     if warmup:
@@ -169,6 +184,8 @@ def main():
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--graph", action="store_true", help="replay Krylov chunks as HIP graphs")
+    ap.add_argument("--precond", default="mg", choices=["mg", "jacobi"],
+                    help="pressure-CG preconditioner (multigrid V-cycle or Jacobi)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -188,6 +205,8 @@ def main():
     ncell = grid["nx"] * grid["ny"] * (grid["nz"] if grid["dim"] == 3 else 1)
     dev = sol.TorchDevice(0)
     g = sol.Case(case, device=dev)
+    if args.precond != "mg":
+        g.set_precond(args.precond)
     if args.graph:
         g.set_graph(True)
     if args.warmup:
@@ -205,13 +224,14 @@ def main():
     if not args.no_roofline:
         g.set_timing(True)
         st2 = g.step(2)
-        per = {"cg": max(1, st2["iters_total"][3] / 2)}
+        p_its = max(1, st2["iters_total"][3] / 2)
+        per = {"cg": p_its, "mg_pq": p_its, "mg_down0": p_its + 1, "mg_up0": p_its + 1}
         other = sum(st2["iters_total"][s] for s in (0, 1, 2, 4, 5)) / 2
         per.update({k: max(1, other) for k in ("bicg_a", "bicg_b", "bicg_c")})
         best = roofline(g, per)
         g.set_timing(False)
         if best:
-            tr = counter_traffic(args.workload, best["cls"]) if args.precision == "fp64" else None
+            tr = counter_traffic(args.workload, best["cls"], args.precond) if args.precision == "fp64" else None
             roof = dict(bound="hbm", achieved=round(best["gbs"], 1), peak=HBM_PEAK_GBS, unit="GB/s",
                         frac=round(best["gbs"] / HBM_PEAK_GBS, 4), traffic=tr,
                         kernel=best["cls"], avg_us=round(best["avg_ms"] * 1e3, 2),
@@ -224,8 +244,11 @@ def main():
         if args.workload == "C2" and args.precision == "fp64":
             variants["C2_mixed"] = run_single(sol, W, "C2", "mixed", args.steps, args.warmup, dev)
             variants["C2_fp64_graph"] = run_single(sol, W, "C2", "fp64", args.steps, args.warmup, dev, graph=True)
+            variants["C2_fp64_jacobi"] = run_single(sol, W, "C2", "fp64", args.steps, args.warmup, dev,
+                                                    precond="jacobi")
         variants["C3_fp64"] = run_single(sol, W, "C3", "fp64", 5, 1, dev)
         variants["C3_mixed"] = run_single(sol, W, "C3", "mixed", 5, 1, dev)
+        variants["C3_fp64_jacobi"] = run_single(sol, W, "C3", "fp64", 5, 1, dev, precond="jacobi")
         variants["C4_batched_mixed"] = run_batched(sol, W, "mixed", 5, 1, dev)
         variants["C4_batched_fp64"] = run_batched(sol, W, "fp64", 5, 1, dev, tune=False)
         variants["C5_served_mixed"] = run_served(sol, W, dev)
@@ -239,7 +262,7 @@ def main():
         config=dict(workload=f"{args.workload}: 2D cavity {grid['nx']}x{grid['ny']}" if grid["dim"] == 2
                     else f"{args.workload}: 3D box {grid['nx']}x{grid['ny']}x{grid['nz']}",
                     cells=ncell, dt=case["numerics"]["dt"], tol=case["numerics"]["tol_p"],
-                    precision=args.precision, krylov_iters_per_step={
+                    precision=args.precision, pressure_precond=args.precond, krylov_iters_per_step={
                         n: round(iters[i] / args.steps, 1) for i, n in enumerate("uvwpCT")}),
         roofline=roof, cpu_baseline=cpu, variants=variants,
     )

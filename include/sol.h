@@ -191,7 +191,8 @@ void sol_batch_destroy(sol_batch *b);
 /* Kernel timing for roofline reports.  When enabled, HIP events on the
    handle's stream bracket windows of 16 consecutive CG launches (one event
    pair per window, starting every 32nd iteration), single launches of the
-   BiCGSTAB kernels (every 8th iteration) and every assembly / phase launch;
+   BiCGSTAB and multigrid kernels (every 8th iteration) and every assembly /
+   phase launch;
    a sample counts only if the solve was still iterating at all its
    launches.  sol_get_timing returns
    the number of timed launches, their summed duration and the algorithmic
@@ -205,7 +206,11 @@ void sol_batch_destroy(sol_batch *b);
 #define SOL_KCLASS_ASM_MOM   4   /* momentum assembly                           */
 #define SOL_KCLASS_ASM_TRN   5   /* solute + energy assembly                    */
 #define SOL_KCLASS_PHASE     6   /* phase update + commit                       */
-#define SOL_NKCLASS          7
+#define SOL_KCLASS_MG_PQ     7   /* multigrid CG: p = z + beta p, q = A p, (p,q) */
+#define SOL_KCLASS_MG_DOWN0  8   /* multigrid CG: x, r update, (r,r), level-0 pre-smoothing + restriction */
+#define SOL_KCLASS_MG_UP0    9   /* multigrid CG: level-0 prolongation + post-smoothing -> z, (r,z) */
+#define SOL_KCLASS_MG_COARSE 10  /* multigrid CG: levels >= 1 (time only, bytes 0) */
+#define SOL_NKCLASS          11
 int sol_set_timing(sol_handle *h, int32_t enable);
 int sol_get_timing(sol_handle *h, int32_t kclass, int64_t *launches, double *total_ms,
                    double *bytes);
@@ -215,12 +220,24 @@ int sol_get_timing(sol_handle *h, int32_t kclass, int64_t *launches, double *tot
    the graph advances) instead of launching each kernel; batches follow the
    option of their first handle.  Results are bit-identical either way. */
 #define SOL_OPT_GRAPH 1
+/* SOL_OPT_PRECOND: preconditioner of the pressure-correction CG (eq. 3.4).
+   SOL_PRECOND_MG (default): one V-cycle of an aggregation multigrid
+   hierarchy of the constant Neumann Laplacian (Galerkin coarse operators,
+   damped-Jacobi smoothing, built once at sol_create); SOL_PRECOND_JACOBI:
+   the inverse diagonal.  Both stop at the same relative residual.  Not
+   allowed while the handle is part of a batch (SOL_EBUSY); the handles of
+   one batch must share it (SOL_EINVAL at sol_batch_create). */
+#define SOL_OPT_PRECOND 2
+#define SOL_PRECOND_JACOBI 0
+#define SOL_PRECOND_MG     1
 int sol_set_option(sol_handle *h, int32_t option, int64_t value);
 
-/* Tile-size autotuner: times CG iterations of this case's pressure system
-   (FP32 inner solve under mixed precision) for candidate tile sizes of 256,
-   512, 1024, 2048, 4096 rows per workgroup and keeps the fastest for the
-   case's size class (stencil width, floor(log2 rows)).  The choice is
+/* Tile-size autotuner: times iterations of this case's pressure solve
+   (FP32 inner solve under mixed precision) for candidate tile sizes and
+   keeps the fastest for the case's size class (stencil width, floor(log2
+   rows), preconditioner).  Jacobi: 256, 512, 1024, 2048, 4096 rows per
+   workgroup; multigrid: 256, 512, 1024, 2048 level-1 cells per workgroup of
+   the level-0 kernels (each cell covers 4 rows in 2D, 8 in 3D).  The choice is
    process-wide and applies to every later solve of that class, alone or in
    a batch (tile size changes the summation order, so tune before creating
    the cases to be compared).  The state of the case is not changed.

@@ -25,7 +25,10 @@ FIELD_BITS = dict(u=0, v=1, w=2, p=3, T=4, C=5, gl=6, Cl=7, Cs=8,
                   ustar=9, vstar=10, wstar=11, phi=12, Tstar=13)
 STATE_FIELDS = ("u", "v", "w", "p", "T", "C", "gl", "Cl", "Cs")
 NFIELDS = 14
-KCLASS = dict(cg=0, bicg_a=1, bicg_b=2, bicg_c=3, asm_mom=4, asm_trn=5, phase=6)
+KCLASS = dict(cg=0, bicg_a=1, bicg_b=2, bicg_c=3, asm_mom=4, asm_trn=5, phase=6,
+              mg_pq=7, mg_down0=8, mg_up0=9, mg_coarse=10)
+OPT_GRAPH, OPT_PRECOND = 1, 2
+PRECOND = dict(jacobi=0, mg=1)
 
 
 class SolError(RuntimeError):
@@ -290,7 +293,11 @@ class Case:
         return rp, ci[:nnz], va[:nnz], rhs[:n]
 
     def set_graph(self, on: bool):
-        check(load().sol_set_option(self.h, 1, 1 if on else 0))
+        check(load().sol_set_option(self.h, OPT_GRAPH, 1 if on else 0))
+
+    def set_precond(self, name: str):
+        """Pressure-CG preconditioner: 'mg' (default) or 'jacobi'."""
+        check(load().sol_set_option(self.h, OPT_PRECOND, PRECOND[name]))
 
     def autotune(self) -> int:
         r = C.c_int32(0)

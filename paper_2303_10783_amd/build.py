@@ -6,7 +6,7 @@ import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = ["csrc/kernels.hip", "csrc/engine.hip"]
+SOURCES = ["csrc/kernels.hip", "csrc/mg.hip", "csrc/engine.hip"]
 OUT = os.path.join(HERE, "libsol.so")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          # packed FP32 instructions stay off

@@ -108,6 +108,34 @@ static void compute_sizes(const sol_grid &g, Sizes &z)
     z.ntile_cell = ceil_div(z.ncell, TILE);
 }
 
+// multigrid levels of the pressure grid: every count above 1 halves
+// (rounding up) from one level to the next, down to a single cell; nglob =
+// first level >= 1 with at most MG_LDS_MAX cells (it and the coarser levels
+// run in one workgroup)
+struct MGDims {
+    int nlev = 0, nglob = 0;
+    int d[MG_MAXLEV][3];
+    int n[MG_MAXLEV];
+};
+
+static void mg_dims(const Sizes &z, MGDims &m)
+{
+    int d0 = z.nx, d1 = z.ny, d2 = z.nz;
+    for (;;) {
+        const int l = m.nlev++;
+        m.d[l][0] = d0;
+        m.d[l][1] = d1;
+        m.d[l][2] = d2;
+        m.n[l] = d0 * d1 * d2;
+        if (l >= 1 && m.nglob == 0 && m.n[l] <= MG_LDS_MAX) m.nglob = l;
+        if (m.n[l] <= 1 || m.nlev == MG_MAXLEV) break;
+        d0 = (d0 + 1) / 2;
+        d1 = (d1 + 1) / 2;
+        d2 = (d2 + 1) / 2;
+    }
+    if (m.nglob == 0) m.nglob = m.nlev - 1;
+}
+
 // total device bytes of one case (matches the allocations in sol_create)
 static size_t footprint(const Sizes &z, int precision)
 {
@@ -127,6 +155,15 @@ static size_t footprint(const Sizes &z, int precision)
     b += 3 * 7 * al((size_t)z.maxn * D);                        // Krylov work vectors
     if (precision) b += 3 * 9 * al((size_t)z.maxn * F);         // FP32 inner work vectors
     b += al((size_t)z.ntile_cell * 4 * D) + 2 * al(256);         // reductions, counters, step
+    {
+        MGDims m;                                                // pressure multigrid hierarchy
+        mg_dims(z, m);
+        for (int l = 1; l < m.nlev; ++l) {
+            b += al((size_t)z.nd * m.n[l] * D) + 3 * al((size_t)m.n[l] * D);
+            if (precision) b += al((size_t)z.nd * m.n[l] * F) + 3 * al((size_t)m.n[l] * F);
+        }
+        b += al(sizeof(MLevel) * MG_MAXLEV) * (precision ? 2 : 1);
+    }
     return b;
 }
 
@@ -139,6 +176,20 @@ static std::mutex g_tune_mu;
 static std::map<int, int> g_tuned_rpt;
 
 static int size_class(int n, int nd) { return nd * 64 + (n > 0 ? 31 - __builtin_clz((unsigned)n) : 0); }
+
+// multigrid: level-1 cells per tile of the level-0 kernels (1..8 per
+// thread, aiming at <= ~1024 tiles); tuned per size class like the above
+static std::map<int, int> g_tuned_cpt;
+
+static int mg_cells_per_tile(int n, int nd, int cn)
+{
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tuned_cpt.find(size_class(n, nd));
+        if (it != g_tuned_cpt.end()) return it->second;
+    }
+    return TILE * std::max(1, std::min(8, ceil_div(cn, TILE * 1024)));
+}
 
 static int rows_per_tile(int n, int nd)
 {
@@ -166,6 +217,12 @@ static double row_bytes(int cls, int nd, int dim, int tsize)
     case SOL_KCLASS_BICG_A: return (nd + 7.0) * tsize;  // A, r, p, v, M, rh; p, v
     case SOL_KCLASS_BICG_B: return (nd + 4.0) * tsize;  // A, r, v, M; t
     case SOL_KCLASS_BICG_C: return 9.0 * tsize;         // x, r, v, p, M, t, rh; x, r
+    case SOL_KCLASS_MG_PQ: return (nd + 4.0) * tsize;    // A, z, p_old; p, q
+    case SOL_KCLASS_MG_DOWN0:                            // A, M, r, q, x, p; x, r; level-1 rhs
+        return (nd + 7.0 + 1.0 / (1 << dim)) * tsize;
+    case SOL_KCLASS_MG_UP0:                              // A, M, r, level-1 correction; z
+        return (nd + 3.0 + 1.0 / (1 << dim)) * tsize;
+    case SOL_KCLASS_MG_COARSE: return 0.0;
     case SOL_KCLASS_ASM_MOM: return 16.0 * nd + 8.0 * dim + 48.0;
     case SOL_KCLASS_ASM_TRN: return 24.0 * nd + 8.0 * dim + 56.0;
     case SOL_KCLASS_PHASE: return 96.0 + 16.0 * dim;
@@ -194,6 +251,13 @@ struct sol_handle {
     sol_batch *batch = nullptr;
     bool timing = false;
     bool opt_graph = false;
+    int precond = SOL_PRECOND_MG;
+    // pressure multigrid hierarchy (FP64 arrays; FP32 copies for mixed precision)
+    int mg_nlev = 0, mg_nglob = 0;
+    MLevel mg_h[MG_MAXLEV] = {};
+    MLevel mg32_h[MG_MAXLEV] = {};
+    MLevel *mg_d = nullptr, *mg32_d = nullptr;
+    size_t mg_smem = 0, mg_smem32 = 0;     // local memory of the LDS-level kernel
     TAcc tacc[SOL_NKCLASS];
     std::vector<TSample> samples;
     std::vector<hipEvent_t> event_pool;
@@ -201,6 +265,14 @@ struct sol_handle {
 };
 
 // ------------------------------------------------------------------ groups
+
+// One launch of an iteration: kernel, tiles per stencil width, local memory.
+struct Stage {
+    int which = 0, cls = 0;
+    JTile *tiles_d[2] = {nullptr, nullptr};
+    int nt[2] = {0, 0};
+    size_t smem[2] = {0, 0};
+};
 
 // A set of solves launched together (one kernel launch serves all of them).
 struct JobSet {
@@ -212,6 +284,8 @@ struct JobSet {
     int nt[2] = {0, 0};
     hipGraph_t graph = nullptr;          // GCH iterations + advance of the index base
     hipGraphExec_t exec = nullptr;
+    std::vector<Stage> iter;             // launches of one iteration
+    std::vector<Stage> start;            // multigrid: the V-cycle of the start (after its init kernel)
 };
 
 struct Phase {
@@ -303,6 +377,97 @@ static int finish_set(Group &g, JobSet &S)
     return SOL_OK;
 }
 
+// launches of one iteration (and of the multigrid start cycle) of a job set
+static int build_stages(Group &g, JobSet &S, int kind, int fp32)
+{
+    S.iter.clear();
+    S.start.clear();
+    auto row_stage = [&](int which, int cls) {
+        Stage st;
+        st.which = which;
+        st.cls = cls;
+        for (int gi = 0; gi < 2; ++gi) {
+            st.tiles_d[gi] = S.tiles_d[gi];
+            st.nt[gi] = S.nt[gi];
+        }
+        return st;
+    };
+    if (kind == K_CG) {
+        S.iter.push_back(row_stage(KI_CG, SOL_KCLASS_CG));
+        return SOL_OK;
+    }
+    if (kind == K_BICGSTAB) {
+        for (int q = 0; q < 3; ++q) S.iter.push_back(row_stage(KI_BICG_A + q, SOL_KCLASS_BICG_A + q));
+        return SOL_OK;
+    }
+    // multigrid CG: pq, down0, down(1..G-1), lds, up(G-1..1), up0; the start
+    // cycle is the same without pq, with the start variant of down0
+    int gmax = 1;
+    for (size_t j = 0; j < S.jobs.size(); ++j) gmax = std::max(gmax, g.cs[S.case_of[j]]->mg_nglob);
+    std::vector<Stage> down(gmax), up(gmax);
+    for (int l = 1; l < gmax; ++l) {
+        std::vector<JTile> jt[2];
+        for (size_t j = 0; j < S.jobs.size(); ++j) {
+            const sol_handle *h = g.cs[S.case_of[j]];
+            if (h->mg_nglob <= l) continue;
+            const int gi = h->z.nd == 7 ? 1 : 0;
+            for (int t = 0; t < h->mg_h[l].ntile; ++t) jt[gi].push_back({(int)j, t, l, 0});
+        }
+        Stage st;
+        st.which = KI_MG_DOWN;
+        st.cls = SOL_KCLASS_MG_COARSE;
+        for (int gi = 0; gi < 2; ++gi) {
+            RCHK(upload(g, &st.tiles_d[gi], jt[gi]));
+            st.nt[gi] = (int)jt[gi].size();
+        }
+        down[l] = st;
+        up[l] = st;
+        up[l].which = KI_MG_UP;
+    }
+    Stage lds;
+    lds.which = KI_MG_LDS;
+    lds.cls = SOL_KCLASS_MG_COARSE;
+    {
+        std::vector<JTile> jt[2];
+        for (size_t j = 0; j < S.jobs.size(); ++j) {
+            const sol_handle *h = g.cs[S.case_of[j]];
+            const int gi = h->z.nd == 7 ? 1 : 0;
+            jt[gi].push_back({(int)j, 0, h->mg_nglob, 0});
+            lds.smem[gi] = std::max(lds.smem[gi], fp32 ? h->mg_smem32 : h->mg_smem);
+        }
+        for (int gi = 0; gi < 2; ++gi) {
+            RCHK(upload(g, &lds.tiles_d[gi], jt[gi]));
+            lds.nt[gi] = (int)jt[gi].size();
+        }
+    }
+    auto cycle = [&](std::vector<Stage> &out, int down0) {
+        out.push_back(row_stage(down0, SOL_KCLASS_MG_DOWN0));
+        for (int l = 1; l < gmax; ++l) out.push_back(down[l]);
+        out.push_back(lds);
+        for (int l = gmax - 1; l >= 1; --l) out.push_back(up[l]);
+        out.push_back(row_stage(KI_MG_UP0, SOL_KCLASS_MG_UP0));
+    };
+    S.iter.push_back(row_stage(KI_MG_PQ, SOL_KCLASS_MG_PQ));
+    cycle(S.iter, KI_MG_DOWN0);
+    cycle(S.start, KI_MG_DOWN0_INIT);
+    return SOL_OK;
+}
+
+// level tables of the pressure multigrid with the current tiles of the
+// level-0 kernels (tile size is process-wide per size class)
+static int mg_upload(sol_handle *h)
+{
+    const int cpt0 = mg_cells_per_tile(h->z.nsys[SP], h->z.nd, h->mg_h[0].cn);
+    for (MLevel *t : {h->mg_h, h->mg32_h}) {
+        t[0].cpt = cpt0;
+        t[0].ntile = t[0].cn ? ceil_div(t[0].cn, cpt0) : 0;
+    }
+    HIPCHK(hipStreamSynchronize(h->stream));
+    HIPCHK(hipMemcpy(h->mg_d, h->mg_h, sizeof(MLevel) * MG_MAXLEV, hipMemcpyHostToDevice));
+    if (h->mg32_d) HIPCHK(hipMemcpy(h->mg32_d, h->mg32_h, sizeof(MLevel) * MG_MAXLEV, hipMemcpyHostToDevice));
+    return SOL_OK;
+}
+
 // inner relative tolerance of the FP32 solves of the refinement
 static double inner_tol(double tol) { return std::max(tol, 1e-5); }
 
@@ -322,6 +487,8 @@ static int group_build(Group &g)
     std::vector<KState> ksv(2 * g.nks);
     for (auto &k : ksv) { std::memset(&k, 0, sizeof(k)); k.status = K_IDLE; }
     std::vector<Tile> mom[2], cell[2], cst[2];
+    const bool mg = g.cs[0]->precond == SOL_PRECOND_MG;
+    for (int c = 0; c < n; ++c) RCHK(mg_upload(g.cs[c]));
     for (int c = 0; c < n; ++c) {
         sol_handle *h = g.cs[c];
         CaseDev d = h->cd;
@@ -366,8 +533,8 @@ static int group_build(Group &g)
     const int phase_sys[3][3] = {{SU, SV, SW}, {SP, -1, -1}, {SC, ST, -1}};
     for (int p = 0; p < 3; ++p) {
         Phase &P = g.ph[p];
-        P.kind = p == 1 ? K_CG : K_BICGSTAB;
-        P.tcls0 = p == 1 ? SOL_KCLASS_CG : SOL_KCLASS_BICG_A;
+        P.kind = p == 1 ? (mg ? K_MGCG : K_CG) : K_BICGSTAB;
+        P.tcls0 = p == 1 ? (mg ? SOL_KCLASS_MG_PQ : SOL_KCLASS_CG) : SOL_KCLASS_BICG_A;
         P.mixed = mixed;
         for (int c = 0; c < n; ++c) {
             sol_handle *h = g.cs[c];
@@ -382,6 +549,13 @@ static int group_build(Group &g)
                 J.rpt = rows_per_tile(J.n, h->z.nd);
                 J.ntile = ceil_div(J.n, J.rpt);
                 J.kind = P.kind;
+                if (P.kind == K_MGCG) {
+                    J.nlev = h->mg_nlev;
+                    J.nglob = h->mg_nglob;
+                    J.lev = h->mg_d;
+                    J.ntile = h->mg_h[0].ntile;
+                    J.rpt = ceil_div(J.n, J.ntile);
+                }
                 J.A = h->cd.A[s];
                 J.b = h->cd.b[s];
                 J.minv = h->cd.minv[s];
@@ -418,6 +592,7 @@ static int group_build(Group &g)
                     I.t = h->work32[ws][6];
                     I.st = ist;
                     I.partner = J.st;
+                    I.lev = h->mg32_d;
                     P.inner.jobs.push_back(I);
                     P.inner.st_index.push_back(g.nks + c * NSYS + s);
                     P.inner.case_of.push_back(c);
@@ -430,8 +605,12 @@ static int group_build(Group &g)
             }
         }
         RCHK(finish_set(g, P.main));
-        if (mixed) RCHK(finish_set(g, P.inner));
-        P.pred = P.pred_inner = p == 1 ? 64 : 2;
+        RCHK(build_stages(g, P.main, P.kind, 0));
+        if (mixed) {
+            RCHK(finish_set(g, P.inner));
+            RCHK(build_stages(g, P.inner, P.kind, 1));
+        }
+        P.pred = P.pred_inner = p == 1 ? (mg ? 24 : 64) : 2;
     }
     for (int i = 0; i < 2; ++i) {
         HIPCHK(hipHostMalloc((void **)&g.ks_h[i], sizeof(KState) * 2 * g.nks, hipHostMallocDefault));
@@ -521,25 +700,24 @@ constexpr int GCH = 16;
 
 static int build_chunk_graph(Group &g, Phase &P, JobSet &S, int fp32)
 {
+    (void)P;
     HIPCHK(hipGraphCreate(&S.graph, 0));
     hipGraphNode_t prev = nullptr;
-    const int nk = P.kind == K_CG ? 1 : 3;
     for (int i = 0; i < GCH; ++i)
-        for (int q = 0; q < nk; ++q)
+        for (const Stage &st : S.iter)
             for (int gi = 0; gi < 2; ++gi) {
-                if (S.nt[gi] <= 0) continue;
-                const int which = (P.kind == K_CG ? KI_CG : KI_BICG_A) + q;
+                if (st.nt[gi] <= 0) continue;
                 const KJob *jobs = S.jobs_d;
-                const JTile *tiles = S.tiles_d[gi];
+                const JTile *tiles = st.tiles_d[gi];
                 const int *kb = g.kbase_d;
                 int koff = i;
                 void *args[] = {(void *)&jobs, (void *)&tiles, (void *)&kb, (void *)&koff};
                 hipKernelNodeParams kp;
                 std::memset(&kp, 0, sizeof(kp));
-                kp.func = (void *)kiter_fn(which, gi ? 7 : 5, fp32);
-                kp.gridDim = dim3((unsigned)S.nt[gi]);
+                kp.func = (void *)kiter_fn(st.which, gi ? 7 : 5, fp32);
+                kp.gridDim = dim3((unsigned)st.nt[gi]);
                 kp.blockDim = dim3(TILE);
-                kp.sharedMemBytes = 0;
+                kp.sharedMemBytes = (unsigned)st.smem[gi];
                 kp.kernelParams = args;
                 kp.extra = nullptr;
                 hipGraphNode_t node;
@@ -563,6 +741,35 @@ static int build_chunk_graph(Group &g, Phase &P, JobSet &S, int fp32)
     return SOL_OK;
 }
 
+// one launch per stencil width of a stage at iteration index koff (kb NULL)
+static int launch_stage(Group &g, const JobSet &S, const Stage &st, int fp32, int koff)
+{
+    for (int gi = 0; gi < 2; ++gi) {
+        if (st.nt[gi] <= 0) continue;
+        const KJob *jobs = S.jobs_d;
+        const JTile *tiles = st.tiles_d[gi];
+        const int *kb = nullptr;
+        void *args[] = {(void *)&jobs, (void *)&tiles, (void *)&kb, (void *)&koff};
+        HIPCHK(hipLaunchKernel(kiter_fn(st.which, gi ? 7 : 5, fp32), dim3((unsigned)st.nt[gi]), dim3(TILE), args,
+                               st.smem[gi], g.stream));
+    }
+    return SOL_OK;
+}
+
+// (re)start the solves of S at iteration index k (mode 0: all, mode 1: those
+// in K_RESTART); multigrid: init kernel, then the start V-cycle at k - 1
+static int start_solves(Group &g, Phase &P, JobSet &S, int fp32, int k, int mode)
+{
+    if (P.kind != K_MGCG) {
+        for (int gi = 0; gi < 2; ++gi)
+            launch_kinit(P.kind, gi ? 7 : 5, fp32, S.jobs_d, S.tiles_d[gi], S.nt[gi], k, mode, g.stream);
+        return SOL_OK;
+    }
+    for (int gi = 0; gi < 2; ++gi) launch_mg_init(gi ? 7 : 5, fp32, S.jobs_d, S.tiles_d[gi], S.nt[gi], k, mode, g.stream);
+    for (const Stage &st : S.start) RCHK(launch_stage(g, S, st, fp32, k - 1));
+    return SOL_OK;
+}
+
 // Timing: CG iterations are timed in windows of TWIN consecutive launches
 // (one event pair per window; per-launch events would add their own
 // latency), BiCGSTAB kernels one launch at a time, every 8th iteration.
@@ -580,7 +787,6 @@ static int enqueue_iters(Group &g, Phase &P, JobSet &S, int fp32, int nits, int 
         P.launched += chunks * GCH;
         return SOL_OK;
     }
-    const int nk = P.kind == K_CG ? 1 : 3;
     hipEvent_t wa = nullptr, wb = nullptr;
     int wend = -1;
     for (int it = 0; it < nits; ++it) {
@@ -593,16 +799,14 @@ static int enqueue_iters(Group &g, Phase &P, JobSet &S, int fp32, int nits, int 
             }
         }
         const bool sample = tm && P.kind != K_CG && (k % 8 == 0);
-        for (int q = 0; q < nk; ++q) {
-            const int which = (P.kind == K_CG ? KI_CG : KI_BICG_A) + q;
+        for (const Stage &st : S.iter) {
             hipEvent_t a = nullptr, b = nullptr;
             if (sample) { a = take_event(tm); b = take_event(tm); }
             if (a && b) (void)hipEventRecord(a, g.stream);
-            for (int gi = 0; gi < 2; ++gi)
-                launch_kiter(which, gi ? 7 : 5, fp32, S.jobs_d, S.tiles_d[gi], S.nt[gi], k, g.stream);
+            RCHK(launch_stage(g, S, st, fp32, k));
             if (a && b) {
                 (void)hipEventRecord(b, g.stream);
-                tm->samples.push_back({P.tcls0 + q, (int64_t)k, &S, fp32 ? 4 : 8, a, b, 1});
+                tm->samples.push_back({st.cls, (int64_t)k, &S, fp32 ? 4 : 8, a, b, 1});
             }
         }
         if (k == wend) {
@@ -686,8 +890,7 @@ static int solve_plain(Group &g, Phase &P)
     JobSet &S = P.main;
     int k = 0;                       // host iteration index of the next launch
     P.launched = 0;
-    for (int gi = 0; gi < 2; ++gi)
-        launch_kinit(P.kind, gi ? 7 : 5, 0, S.jobs_d, S.tiles_d[gi], S.nt[gi], k, 0, g.stream);
+    RCHK(start_solves(g, P, S, 0, k, 0));
     int rc = SOL_OK;
     for (int round = 0; round < 64; ++round) {
         int slot;
@@ -712,8 +915,7 @@ static int solve_plain(Group &g, Phase &P)
             break;
         }
         if (!any_status(g, S, 0, K_RESTART)) break;
-        for (int gi = 0; gi < 2; ++gi)
-            launch_kinit(P.kind, gi ? 7 : 5, 0, S.jobs_d, S.tiles_d[gi], S.nt[gi], k, 1, g.stream);
+        RCHK(start_solves(g, P, S, 0, k, 1));
         if (round == 63) rc = fail(SOL_ENOCONV, "linear solve kept restarting");
     }
     int mx = 1;
@@ -738,10 +940,15 @@ static int solve_mixed(Group &g, Phase &P)
     for (int outer = 0; outer < max_outer + 1; ++outer) {
         if (!any_status(g, S, 0, K_RUNNING)) break;
         int k = 0;
-        for (int gi = 0; gi < 2; ++gi)
-            launch_kinit(P.kind, gi ? 7 : 5, 1, I.jobs_d, I.tiles_d[gi], I.nt[gi], k, 0, g.stream);
+        RCHK(start_solves(g, P, I, 1, k, 0));
         int slot;
         RCHK(iterate(g, P, I, 1, P.pred_inner, k, &S, 0, &slot));
+        // an inner solve that broke down (K_RESTART) continues from its x
+        // with a fresh residual before its correction is applied
+        for (int rs = 0; rs < 8 && any_status(g, I, slot, K_RESTART); ++rs) {
+            RCHK(start_solves(g, P, I, 1, k, 1));
+            RCHK(iterate(g, P, I, 1, std::max(2, P.pred_inner / 4), k, &S, 0, &slot));
+        }
         for (int gi = 0; gi < 2; ++gi) launch_ir_update(gi ? 7 : 5, S.jobs_d, S.tiles_d[gi], S.nt[gi], g.stream);
         for (int gi = 0; gi < 2; ++gi) launch_ir_resid(gi ? 7 : 5, S.jobs_d, S.tiles_d[gi], S.nt[gi], 1, g.stream);
         launch_ir_decide(S.jobs_d, nj, 1, max_outer, g.stream);
@@ -976,6 +1183,63 @@ static int alloc_case(sol_handle *h)
             for (int k = 0; k < 9; ++k)
                 if (!(h->work32[w][k] = fal(z.maxn))) return fail(SOL_ENOMEM, "device allocation failed");
     }
+    {
+        // pressure multigrid hierarchy: level 0 is the pressure system itself
+        MGDims md;
+        mg_dims(z, md);
+        const bool mixed = h->num.precision == SOL_PRECISION_MIXED;
+        auto fal = [&](size_t n) { return (float *)m.get(std::max<size_t>(n, 1) * sizeof(float)); };
+        h->mg_nlev = md.nlev;
+        h->mg_nglob = md.nglob;
+        size_t lds_vals = 0;
+        for (int l = 0; l < md.nlev; ++l) {
+            MLevel L;
+            std::memset(&L, 0, sizeof(L));
+            L.n = md.n[l];
+            L.nx = md.d[l][0];
+            L.ny = md.d[l][1];
+            L.nz = md.d[l][2];
+            if (l + 1 < md.nlev) {
+                L.cn = md.n[l + 1];
+                L.cnx = md.d[l + 1][0];
+                L.cny = md.d[l + 1][1];
+                L.cnz = md.d[l + 1][2];
+            } else {
+                L.cn = 0;
+                L.cnx = L.cny = L.cnz = 1;
+            }
+            L.cpt = TILE;
+            L.ntile = L.cn ? ceil_div(L.cn, TILE) : 0;
+            MLevel L32 = L;
+            if (l == 0) {
+                L.A = d.A[SP];
+                L.minv = d.minv[SP];
+                L32.A = d.A32[SP];
+                L32.minv = d.minv32[SP];
+            } else {
+                const size_t n = L.n;
+                double *A = dal(z.nd * n), *mi = dal(n), *bl = dal(n), *el = dal(n);
+                if (!A || !mi || !bl || !el) return fail(SOL_ENOMEM, "device allocation failed");
+                L.A = A; L.minv = mi; L.b = bl; L.e = el;
+                if (mixed) {
+                    float *A32 = fal(z.nd * n), *mi32 = fal(n), *b32 = fal(n), *e32 = fal(n);
+                    if (!A32 || !mi32 || !b32 || !e32) return fail(SOL_ENOMEM, "device allocation failed");
+                    L32.A = A32; L32.minv = mi32; L32.b = b32; L32.e = e32;
+                }
+            }
+            if (l >= md.nglob) lds_vals += 2 * (size_t)L.n;
+            h->mg_h[l] = L;
+            h->mg32_h[l] = L32;
+        }
+        h->mg_smem = lds_vals * sizeof(double);
+        h->mg_smem32 = lds_vals * sizeof(float);
+        h->mg_d = (MLevel *)m.get(sizeof(MLevel) * MG_MAXLEV);
+        if (!h->mg_d) return fail(SOL_ENOMEM, "device allocation failed");
+        if (mixed) {
+            h->mg32_d = (MLevel *)m.get(sizeof(MLevel) * MG_MAXLEV);
+            if (!h->mg32_d) return fail(SOL_ENOMEM, "device allocation failed");
+        }
+    }
     d.red_part = dal((size_t)z.ntile_cell * 4);
     d.red_cnt = (uint32_t *)m.get(256);
     d.step = (int64_t *)m.get(256);
@@ -1038,6 +1302,12 @@ int sol_create(const sol_grid *grid, const sol_alloy *alloy, const sol_bcs *bcs,
     if (rc == SOL_OK) {
         Group &g = *h->solo;
         for (int gi = 0; gi < 2; ++gi) launch_asm_const(gi ? 3 : 2, g.cases_d, g.t_const[gi], g.n_const[gi], h->stream);
+        // multigrid operators of the (constant) pressure system, level by level
+        const bool mixed = h->num.precision == SOL_PRECISION_MIXED;
+        for (int l = 0; l + 1 < h->mg_nlev; ++l)
+            launch_mg_coarsen(h->z.dim, h->mg_d, l, h->mg_h[l].cn, (double *)h->mg_h[l + 1].A,
+                              (double *)h->mg_h[l + 1].minv, mixed ? (float *)h->mg32_h[l + 1].A : nullptr,
+                              mixed ? (float *)h->mg32_h[l + 1].minv : nullptr, h->stream);
         if (hipGetLastError() != hipSuccess || hipStreamSynchronize(h->stream) != hipSuccess)
             rc = fail(SOL_EDEVICE, "offline assembly failed");
     }
@@ -1274,13 +1544,25 @@ int sol_set_option(sol_handle *h, int32_t option, int64_t value)
     if (!h) return fail(SOL_EINVAL, "NULL handle");
     switch (option) {
     case SOL_OPT_GRAPH: h->opt_graph = value != 0; return SOL_OK;
+    case SOL_OPT_PRECOND: {
+        if (value != SOL_PRECOND_JACOBI && value != SOL_PRECOND_MG)
+            return fail(SOL_EINVAL, "unknown preconditioner %lld", (long long)value);
+        if (h->batch) return fail(SOL_EBUSY, "handle is part of a batch");
+        if (h->precond == (int)value) return SOL_OK;
+        (void)hipStreamSynchronize(h->stream);
+        h->precond = (int)value;
+        group_free(h->solo);
+        h->solo = nullptr;
+        return group_create({h}, &h->solo);
+    }
     }
     return fail(SOL_EINVAL, "unknown option %d", option);
 }
 
-// time CG iterations of the pressure system (FP32 inner solve for mixed
-// precision) with the current tiles; never converges (tol 0)
-static int time_cg(sol_handle *h, double *ms_per_iter)
+// time iterations of the pressure solve (FP32 inner solve for mixed
+// precision) with the current tiles; never converges (tol 0).  The rhs is
+// mean-free so that the singular Neumann system stays consistent.
+static int time_pressure(sol_handle *h, double *ms_per_iter)
 {
     Group &g = *h->solo;
     Phase &P = g.ph[1];
@@ -1294,16 +1576,19 @@ static int time_cg(sol_handle *h, double *ms_per_iter)
     HIPCHK(hipMemcpy((char *)J.st + offsetof(KState, tol2), &zero, sizeof(zero), hipMemcpyHostToDevice));
     if (fp32)
         HIPCHK(hipMemcpy((char *)J.partner + offsetof(KState, status), &running, sizeof(running), hipMemcpyHostToDevice));
-    const int nd = h->z.nd, gi = nd == 7 ? 1 : 0;
-    launch_kinit(K_CG, nd, fp32 ? 1 : 0, S.jobs_d, S.tiles_d[gi], S.nt[gi], 0, 0, g.stream);
-    const int warm = 8, timed_its = 48;
-    for (int k = 0; k < warm; ++k) launch_kiter(KI_CG, nd, fp32 ? 1 : 0, S.jobs_d, S.tiles_d[gi], S.nt[gi], k, g.stream);
+    // multigrid converges in a few tens of iterations: time few enough that
+    // the residual stays far above rounding (no breakdown, no early stop)
+    const bool mg = P.kind == K_MGCG;
+    const int warm = mg ? 2 : 8, timed_its = mg ? 12 : 48;
+    RCHK(start_solves(g, P, S, fp32 ? 1 : 0, 0, 0));
+    for (int k = 0; k < warm; ++k)
+        for (const Stage &st : S.iter) RCHK(launch_stage(g, S, st, fp32 ? 1 : 0, k));
     hipEvent_t a, b;
     HIPCHK(hipEventCreate(&a));
     HIPCHK(hipEventCreate(&b));
     HIPCHK(hipEventRecord(a, g.stream));
     for (int k = warm; k < warm + timed_its; ++k)
-        launch_kiter(KI_CG, nd, fp32 ? 1 : 0, S.jobs_d, S.tiles_d[gi], S.nt[gi], k, g.stream);
+        for (const Stage &st : S.iter) RCHK(launch_stage(g, S, st, fp32 ? 1 : 0, k));
     HIPCHK(hipEventRecord(b, g.stream));
     HIPCHK(hipEventSynchronize(b));
     float ms = 0.f;
@@ -1321,30 +1606,33 @@ int sol_autotune(sol_handle *h, int32_t *rows_per_tile_out)
     if (h->batch) return fail(SOL_EBUSY, "handle is part of a batch");
     const int n = h->z.nsys[SP], nd = h->z.nd;
     const int cls = size_class(n, nd);
-    const int cand[] = {256, 512, 1024, 2048, 4096};
+    const bool mg = h->precond == SOL_PRECOND_MG;
+    std::map<int, int> &table = mg ? g_tuned_cpt : g_tuned_rpt;
+    const int units = mg ? h->mg_h[0].cn : n;      // what one tile covers a part of
+    std::vector<int> cand = mg ? std::vector<int>{256, 512, 1024, 2048} : std::vector<int>{256, 512, 1024, 2048, 4096};
     int best = -1;
     double best_ms = 1e300;
     int rc = SOL_OK;
-    for (int rpt : cand) {
-        const int nt = ceil_div(n, rpt);
-        if (nt > 8192 || (rpt > 256 && nt < 8)) continue;
+    for (int c : cand) {
+        const int nt = ceil_div(units, c);
+        if (nt > 8192 || (c > 256 && nt < 8)) continue;
         {
             std::lock_guard<std::mutex> lk(g_tune_mu);
-            g_tuned_rpt[cls] = rpt;
+            table[cls] = c;
         }
         group_free(h->solo);
         h->solo = nullptr;
         rc = group_create({h}, &h->solo);
         if (rc != SOL_OK) break;
         double ms = 0.0;
-        rc = time_cg(h, &ms);
+        rc = time_pressure(h, &ms);
         if (rc != SOL_OK) break;
-        if (ms < best_ms) { best_ms = ms; best = rpt; }
+        if (ms < best_ms) { best_ms = ms; best = c; }
     }
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        if (best > 0) g_tuned_rpt[cls] = best;
-        else g_tuned_rpt.erase(cls);
+        if (best > 0) table[cls] = best;
+        else table.erase(cls);
     }
     (void)hipStreamSynchronize(h->stream);
     group_free(h->solo);
@@ -1374,6 +1662,8 @@ int sol_batch_create(sol_handle *const *cases, int32_t n, sol_batch **out)
         if (cases[i]->stream != cases[0]->stream) return fail(SOL_EINVAL, "handles must share one stream");
         if (cases[i]->num.precision != cases[0]->num.precision)
             return fail(SOL_EINVAL, "handles of one batch must share one precision");
+        if (cases[i]->precond != cases[0]->precond)
+            return fail(SOL_EINVAL, "handles of one batch must share one pressure preconditioner");
         for (int j = 0; j < i; ++j)
             if (cases[j] == cases[i]) return fail(SOL_EINVAL, "handle %d given twice", i);
     }

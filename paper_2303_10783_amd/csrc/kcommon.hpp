@@ -1,0 +1,185 @@
+// Device helpers shared by the step kernels and the multigrid kernels:
+// XCD-aware tile order, workgroup sums, the fence-free partial-sum
+// protocol, DIA stencils and the Krylov status bookkeeping.
+#pragma once
+#include "sol_dev.hpp"
+
+namespace sol {
+
+// ------------------------------------------------------------------ helpers
+
+__device__ __forceinline__ int xcd_tile(int b, int nb)
+{
+    const int q = nb / NXCD, r = nb % NXCD;
+    const int x = b % NXCD, k = b / NXCD;
+    return x * q + min(x, r) + k;
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    return v;
+}
+
+// sum of K values over the 256 threads; result valid in thread 0
+template <int K>
+__device__ __forceinline__ void block_sum(double (&v)[K], double *sh)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) sh[w * K + k] = v[k];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[k] = (sh[k] + sh[K + k]) + (sh[2 * K + k] + sh[3 * K + k]);
+    }
+    __syncthreads();
+}
+
+// Reductions.  A kernel writes one partial sum per workgroup (plain stores);
+// the next kernel on the stream (kernel boundaries make them visible) sums
+// the partials of the tiles it needs in tile order, every workgroup in the
+// same order, so all workgroups obtain bit-identical totals and no
+// device-scope fence or atomic is needed.
+
+// block totals of K values -> part[off[k] + t] (written by thread 0)
+template <int K>
+__device__ __forceinline__ void put_partials(double (&v)[K], double *part, const int (&off)[K], int t)
+{
+    __shared__ double sh[4 * K];
+    block_sum<K>(v, sh);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) part[off[k] + t] = v[k];
+    }
+}
+
+// out[k] = sum_{q < ntile} part[off[k] + q], identical in every thread and
+// every workgroup
+template <int K>
+__device__ __forceinline__ void sum_partials(const double *part, const int (&off)[K], int ntile, double (&out)[K])
+{
+    __shared__ double sh[4 * K];
+    double acc[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[k] = 0.0;
+    for (int q = threadIdx.x; q < ntile; q += TILE) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) acc[k] += part[off[k] + q];
+    }
+    block_sum<K>(acc, sh);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) sh[k] = acc[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) out[k] = sh[k];
+    __syncthreads();
+}
+
+// neighbour offset of DIA slot s (slot order -sxy, -sx, -1, 0, +1, +sx, +sxy)
+template <int ND>
+__device__ __forceinline__ int slot_off(int s, int sx, int sxy)
+{
+    if (ND == 7) {
+        switch (s) { case 0: return -sxy; case 1: return -sx; case 2: return -1; case 3: return 0;
+                     case 4: return 1; case 5: return sx; default: return sxy; }
+    }
+    switch (s) { case 0: return -sx; case 1: return -1; case 2: return 0; case 3: return 1; default: return sx; }
+}
+
+__device__ __forceinline__ bool finite(double x) { return __builtin_isfinite(x); }
+
+template <class T>
+using gptr = __attribute__((address_space(1))) T *;
+
+template <class T>
+__device__ __forceinline__ gptr<T> G(const void *p) { return (gptr<T>)(p); }
+
+// y_i = sum_s A[s][i] * f(i + off_s) in type T.  Slots whose neighbour lies
+// outside the domain hold an exact 0 coefficient; their index is clamped
+// into [0, n) so that no access leaves the arrays.
+template <int ND, class T, class F>
+__device__ __forceinline__ T kstencil(gptr<T> A, int n, int i, int sx, int sxy, F f)
+{
+    T acc = T(0);
+#pragma unroll
+    for (int s = 0; s < ND; ++s) {
+        int j = i + slot_off<ND>(s, sx, sxy);
+        j = j < 0 ? 0 : (j >= n ? n - 1 : j);
+        acc += A[(size_t)s * n + i] * f(j);
+    }
+    return acc;
+}
+
+__device__ __forceinline__ const KJob &job_of(const KJob *jobs, const JTile *tiles, JTile &tl)
+{
+    tl = tiles[xcd_tile(blockIdx.x, gridDim.x)];
+    return jobs[tl.j];
+}
+
+__device__ __forceinline__ int poff(const KJob &J, int par, int slot) { return (par * NSLOT + slot) * J.ntile; }
+
+// an inner solve whose refinement no longer needs it
+__device__ __forceinline__ bool outer_idle(const KJob &J)
+{
+    return J.role == ROLE_INNER && J.partner->status != K_RUNNING;
+}
+
+// status of a solve as seen by iteration k: RUNNING, or a (re)start whose
+// first iteration is k
+__device__ __forceinline__ bool active(const KJob &J, int k)
+{
+    const int s = J.st->status;
+    return s == K_RUNNING || (s == K_RESTART && k == J.st->k0);
+}
+
+// record a status change: workgroup 0 of the solve only
+__device__ __forceinline__ void set_status(const JTile &tl, KState *st, int status, int it, double rr)
+{
+    if (tl.t == 0 && threadIdx.x == 0) {
+        st->status = status;
+        st->it = it;
+        st->rr = rr;
+    }
+}
+
+// record the start of a solve at iteration index k (workgroup 0)
+__device__ __forceinline__ void mark_start(const JTile &tl, KState *st, int k, int mode)
+{
+    if (tl.t == 0 && threadIdx.x == 0) {
+        st->k0 = k;
+        if (mode == 0) { st->it_base = 0; st->restarts = 0; st->status = K_RUNNING; }
+        else { st->it_base = st->it; st->restarts += 1; }
+    }
+}
+
+// convergence test at the start of iteration k; rr = ||r_k||^2 and bbp =
+// total of the (b,b) partials left by the start kernels (used at k = k0)
+__device__ __forceinline__ bool keep_going(const KJob &J, const JTile &tl, int k, double rr, double bbp)
+{
+    KState *st = J.st;
+    const int it = st->it_base + (k - st->k0);
+    double bb;
+    if (k == st->k0) {
+        bb = bbp;
+        if (tl.t == 0 && threadIdx.x == 0) st->bb = bb;
+    } else {
+        bb = st->bb;
+    }
+    if (!finite(rr) || !finite(bb)) { set_status(tl, st, K_NONFINITE, it, rr); return false; }
+    if (bb == 0.0) { set_status(tl, st, K_ZERO, it, rr); return false; }
+    if (rr <= st->tol2 * bb) { set_status(tl, st, K_CONVERGED, it, rr); return false; }
+    if (it >= st->max_iter) { set_status(tl, st, K_FAILED, it, rr); return false; }
+    if (k == st->k0 && tl.t == 0 && threadIdx.x == 0) st->status = K_RUNNING;
+    return true;
+}
+
+
+}  // namespace sol

@@ -15,10 +15,22 @@ void launch_phase_commit(int dim, const CaseDev *c, const Tile *t, int nt, hipSt
 void launch_kinit(int kind, int nd, int fp32, const KJob *j, const JTile *t, int nt, int k, int mode, hipStream_t s);
 void launch_kfinish(int nd, const KJob *j, const JTile *t, int nt, hipStream_t s);
 void launch_kdecide(const KJob *j, int njobs, hipStream_t s);
-enum KIter { KI_CG = 0, KI_BICG_A = 1, KI_BICG_B = 2, KI_BICG_C = 3 };
+// iteration kernels, all with the signature (jobs, tiles, const int *kbase,
+// int koff): iteration index = (kbase ? *kbase : 0) + koff
+enum KIter {
+    KI_CG = 0, KI_BICG_A = 1, KI_BICG_B = 2, KI_BICG_C = 3,
+    KI_MG_PQ = 4, KI_MG_DOWN0 = 5, KI_MG_DOWN = 6, KI_MG_LDS = 7, KI_MG_UP = 8, KI_MG_UP0 = 9,
+    KI_MG_DOWN0_INIT = 10
+};
 void launch_kiter(int which, int nd, int fp32, const KJob *j, const JTile *t, int nt, int k, hipStream_t s);
-// graph building: kernel addresses (signature jobs, tiles, const int *kbase, int koff)
+// kernel address of an iteration kernel (direct launches and graph nodes)
 const void *kiter_fn(int which, int nd, int fp32);
+const void *mg_fn(int which, int nd, int fp32);
+// multigrid: start of the solves (r = b - A x, p = 0, partial (b, b)) and
+// the Galerkin operator of level l+1 from level l
+void launch_mg_init(int nd, int fp32, const KJob *j, const JTile *t, int nt, int k, int mode, hipStream_t s);
+void launch_mg_coarsen(int dim, const MLevel *lev, int l, int cn, double *Ac, double *mic, float *Ac32, float *mic32,
+                       hipStream_t s);
 const void *kbase_add_fn();   // (int *kbase, int m)
 void launch_kbase_set(int *kbase, int v, hipStream_t s);
 void launch_tune_rhs(void *b, int fp32, int n, hipStream_t s);

@@ -19,7 +19,23 @@ enum KStatus {
     K_NONFINITE = 7
 };
 
-enum KKind { K_CG = 0, K_BICGSTAB = 1 };
+enum KKind { K_CG = 0, K_BICGSTAB = 1, K_MGCG = 2 };
+
+// Multigrid hierarchy of the pressure system (levels 0 = the system itself,
+// 1, 2, ... down to a single cell).  Level l+1 aggregates 2 x 2 (x 2) cells
+// of level l (1 along a direction whose level-l count is odd at its upper
+// end, or is 1); its operator is the Galerkin product P^T A_l P with the
+// aggregation P, again a 5- / 7-point DIA matrix in the same slot order.
+constexpr int MG_LDS_MAX = 2048;   // first level at or below this size runs in LDS
+constexpr int MG_MAXLEV = 32;
+struct MLevel {
+    int32_t n, nx, ny, nz;        // cells of this level and their counts per axis
+    int32_t cn, cnx, cny, cnz;    // the next coarser level (cn = 0 at the coarsest)
+    int32_t cpt;                  // coarse cells per tile of the kernels that work on this level
+    int32_t ntile;                // tiles of those kernels: ceil(cn / cpt)
+    const void *A, *minv;         // operator and Jacobi inverse (0 where the diagonal is 0)
+    void *b, *e;                  // right-hand side and correction (levels >= 1)
+};
 
 // Per-solve device state.  Iteration kernels read it at their start; only
 // workgroup 0 of a solve writes it, and only fields no other workgroup of
@@ -89,7 +105,8 @@ enum RedSlot { R_SUMB = 0, R_DIVSTAR = 1, R_SUMC = 2, R_SUMH = 3, R_WALL = 4, R_
 // solves and the refinement (outer) solves, FP32 for the inner solves of the
 // mixed-precision form; partial sums and scalars are always FP64.
 // Work-vector roles: BiCGSTAB r, rh, p0/p1, v0/v1, t; CG (one kernel per
-// iteration) r0/r1 = r/rh, s0/s1 = p0/p1, w0/w1 = v0/v1, p = t.
+// iteration) r0/r1 = r/rh, s0/s1 = p0/p1, w0/w1 = v0/v1, p = t; multigrid
+// CG r0/r1 = r/rh, p0/p1, z = v0, q = v1.
 struct KJob {
     int32_t n, sx, sxy;
     int32_t rpt;              // rows per tile (multiple of TILE)
@@ -104,6 +121,9 @@ struct KJob {
     KState *st;
     KState *partner;          // refinement: its inner solve; inner solve: its refinement
     int32_t role;             // KRole
+    int32_t nlev;             // multigrid: levels (0 for the other solves)
+    const MLevel *lev;        // multigrid: level table (device), vectors of type T
+    int32_t nglob;            // multigrid: first level handled in LDS (levels 0..nglob-1 by launches)
     int32_t pad;
 };
 
@@ -111,7 +131,8 @@ enum KRole { ROLE_PLAIN = 0, ROLE_REFINE = 1, ROLE_INNER = 2 };
 
 // Tile of a per-row kernel: case, system (or component), tile within it.
 struct Tile { int32_t c, s, t, pad; };
-struct JTile { int32_t j, t; };
+// Tile of a Krylov kernel: job, tile within it, multigrid level it works on.
+struct JTile { int32_t j, t, lv, pad; };
 
 __host__ __device__ inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
