@@ -109,9 +109,8 @@ static void compute_sizes(const sol_grid &g, Sizes &z)
 }
 
 // multigrid levels of the pressure grid: every count above 1 halves
-// (rounding up) from one level to the next, down to a single cell; nglob =
-// first level >= 1 with at most MG_LDS_MAX cells (it and the coarser levels
-// run in one workgroup)
+// (rounding up) from one level to the next, down to nglob, the first level
+// >= 1 with at most MG_EXACT_MAX cells (solved exactly)
 struct MGDims {
     int nlev = 0, nglob = 0;
     int d[MG_MAXLEV][3];
@@ -127,8 +126,11 @@ static void mg_dims(const Sizes &z, MGDims &m)
         m.d[l][1] = d1;
         m.d[l][2] = d2;
         m.n[l] = d0 * d1 * d2;
-        if (l >= 1 && m.nglob == 0 && m.n[l] <= MG_LDS_MAX) m.nglob = l;
-        if (m.n[l] <= 1 || m.nlev == MG_MAXLEV) break;
+        if (l >= 1 && m.n[l] <= MG_EXACT_MAX) {
+            m.nglob = l;
+            break;
+        }
+        if (m.nlev == MG_MAXLEV) break;
         d0 = (d0 + 1) / 2;
         d1 = (d1 + 1) / 2;
         d2 = (d2 + 1) / 2;
@@ -159,9 +161,11 @@ static size_t footprint(const Sizes &z, int precision)
         MGDims m;                                                // pressure multigrid hierarchy
         mg_dims(z, m);
         for (int l = 1; l < m.nlev; ++l) {
-            b += al((size_t)z.nd * m.n[l] * D) + 3 * al((size_t)m.n[l] * D);
-            if (precision) b += al((size_t)z.nd * m.n[l] * F) + 3 * al((size_t)m.n[l] * F);
+            b += 3 * al((size_t)m.n[l] * D);                     // inverse diagonal, rhs, correction
+            if (precision) b += 3 * al((size_t)m.n[l] * F);
         }
+        const size_t nx2 = (size_t)m.n[m.nglob] * m.n[m.nglob];  // dense inverse of the exact level
+        b += al(nx2 * D) + (precision ? al(nx2 * F) : 0);
         b += al(sizeof(MLevel) * MG_MAXLEV) * (precision ? 2 : 1);
     }
     return b;
@@ -217,11 +221,13 @@ static double row_bytes(int cls, int nd, int dim, int tsize)
     case SOL_KCLASS_BICG_A: return (nd + 7.0) * tsize;  // A, r, p, v, M, rh; p, v
     case SOL_KCLASS_BICG_B: return (nd + 4.0) * tsize;  // A, r, v, M; t
     case SOL_KCLASS_BICG_C: return 9.0 * tsize;         // x, r, v, p, M, t, rh; x, r
-    case SOL_KCLASS_MG_PQ: return (nd + 4.0) * tsize;    // A, z, p_old; p, q
-    case SOL_KCLASS_MG_DOWN0:                            // A, M, r, q, x, p; x, r; level-1 rhs
-        return (nd + 7.0 + 1.0 / (1 << dim)) * tsize;
-    case SOL_KCLASS_MG_UP0:                              // A, M, r, level-1 correction; z
-        return (nd + 3.0 + 1.0 / (1 << dim)) * tsize;
+    // multigrid (the pressure operator is applied from its closed form, no
+    // matrix values are read)
+    case SOL_KCLASS_MG_PQ: return 4.0 * tsize;           // z, p_old; p, q
+    case SOL_KCLASS_MG_DOWN0:                            // M, r, q, x, p; x, r; level-1 rhs
+        return (7.0 + 1.0 / (1 << dim)) * tsize;
+    case SOL_KCLASS_MG_UP0:                              // M, r, level-1 correction; z
+        return (3.0 + 1.0 / (1 << dim)) * tsize;
     case SOL_KCLASS_MG_COARSE: return 0.0;
     case SOL_KCLASS_ASM_MOM: return 16.0 * nd + 8.0 * dim + 48.0;
     case SOL_KCLASS_ASM_TRN: return 24.0 * nd + 8.0 * dim + 56.0;
@@ -257,7 +263,6 @@ struct sol_handle {
     MLevel mg_h[MG_MAXLEV] = {};
     MLevel mg32_h[MG_MAXLEV] = {};
     MLevel *mg_d = nullptr, *mg32_d = nullptr;
-    size_t mg_smem = 0, mg_smem32 = 0;     // local memory of the LDS-level kernel
     TAcc tacc[SOL_NKCLASS];
     std::vector<TSample> samples;
     std::vector<hipEvent_t> event_pool;
@@ -400,7 +405,7 @@ static int build_stages(Group &g, JobSet &S, int kind, int fp32)
         for (int q = 0; q < 3; ++q) S.iter.push_back(row_stage(KI_BICG_A + q, SOL_KCLASS_BICG_A + q));
         return SOL_OK;
     }
-    // multigrid CG: pq, down0, down(1..G-1), lds, up(G-1..1), up0; the start
+    // multigrid CG: pq, down0, down(1..G-1), exact, up(G-1..1), up0; the start
     // cycle is the same without pq, with the start variant of down0
     int gmax = 1;
     for (size_t j = 0; j < S.jobs.size(); ++j) gmax = std::max(gmax, g.cs[S.case_of[j]]->mg_nglob);
@@ -424,26 +429,26 @@ static int build_stages(Group &g, JobSet &S, int kind, int fp32)
         up[l] = st;
         up[l].which = KI_MG_UP;
     }
-    Stage lds;
-    lds.which = KI_MG_LDS;
-    lds.cls = SOL_KCLASS_MG_COARSE;
+    Stage exact;
+    exact.which = KI_MG_EXACT;
+    exact.cls = SOL_KCLASS_MG_COARSE;
     {
         std::vector<JTile> jt[2];
         for (size_t j = 0; j < S.jobs.size(); ++j) {
             const sol_handle *h = g.cs[S.case_of[j]];
             const int gi = h->z.nd == 7 ? 1 : 0;
-            jt[gi].push_back({(int)j, 0, h->mg_nglob, 0});
-            lds.smem[gi] = std::max(lds.smem[gi], fp32 ? h->mg_smem32 : h->mg_smem);
+            const int L = h->mg_nglob;
+            for (int t = 0; t < ceil_div(h->mg_h[L].n, 64); ++t) jt[gi].push_back({(int)j, t, L, 0});
         }
         for (int gi = 0; gi < 2; ++gi) {
-            RCHK(upload(g, &lds.tiles_d[gi], jt[gi]));
-            lds.nt[gi] = (int)jt[gi].size();
+            RCHK(upload(g, &exact.tiles_d[gi], jt[gi]));
+            exact.nt[gi] = (int)jt[gi].size();
         }
     }
     auto cycle = [&](std::vector<Stage> &out, int down0) {
         out.push_back(row_stage(down0, SOL_KCLASS_MG_DOWN0));
         for (int l = 1; l < gmax; ++l) out.push_back(down[l]);
-        out.push_back(lds);
+        out.push_back(exact);
         for (int l = gmax - 1; l >= 1; --l) out.push_back(up[l]);
         out.push_back(row_stage(KI_MG_UP0, SOL_KCLASS_MG_UP0));
     };
@@ -1191,7 +1196,6 @@ static int alloc_case(sol_handle *h)
         auto fal = [&](size_t n) { return (float *)m.get(std::max<size_t>(n, 1) * sizeof(float)); };
         h->mg_nlev = md.nlev;
         h->mg_nglob = md.nglob;
-        size_t lds_vals = 0;
         for (int l = 0; l < md.nlev; ++l) {
             MLevel L;
             std::memset(&L, 0, sizeof(L));
@@ -1210,29 +1214,40 @@ static int alloc_case(sol_handle *h)
             }
             L.cpt = TILE;
             L.ntile = L.cn ? ceil_div(L.cn, TILE) : 0;
+            L.sc = 1 << l;
+            L.n0[0] = z.nx;
+            L.n0[1] = z.ny;
+            L.n0[2] = z.nz;
+            for (int a = 0; a < 3; ++a) L.ih2[a] = d.ph.ih2[a];
             MLevel L32 = L;
             if (l == 0) {
-                L.A = d.A[SP];
                 L.minv = d.minv[SP];
-                L32.A = d.A32[SP];
                 L32.minv = d.minv32[SP];
             } else {
                 const size_t n = L.n;
-                double *A = dal(z.nd * n), *mi = dal(n), *bl = dal(n), *el = dal(n);
-                if (!A || !mi || !bl || !el) return fail(SOL_ENOMEM, "device allocation failed");
-                L.A = A; L.minv = mi; L.b = bl; L.e = el;
+                double *mi = dal(n), *bl = dal(n), *el = dal(n);
+                if (!mi || !bl || !el) return fail(SOL_ENOMEM, "device allocation failed");
+                L.minv = mi; L.b = bl; L.e = el;
                 if (mixed) {
-                    float *A32 = fal(z.nd * n), *mi32 = fal(n), *b32 = fal(n), *e32 = fal(n);
-                    if (!A32 || !mi32 || !b32 || !e32) return fail(SOL_ENOMEM, "device allocation failed");
-                    L32.A = A32; L32.minv = mi32; L32.b = b32; L32.e = e32;
+                    float *mi32 = fal(n), *b32 = fal(n), *e32 = fal(n);
+                    if (!mi32 || !b32 || !e32) return fail(SOL_ENOMEM, "device allocation failed");
+                    L32.minv = mi32; L32.b = b32; L32.e = e32;
                 }
             }
-            if (l >= md.nglob) lds_vals += 2 * (size_t)L.n;
+            if (l == md.nglob) {
+                const size_t n2 = (size_t)L.n * L.n;
+                double *P = dal(n2);
+                if (!P) return fail(SOL_ENOMEM, "device allocation failed");
+                L.pinv = P;
+                if (mixed) {
+                    float *P32 = fal(n2);
+                    if (!P32) return fail(SOL_ENOMEM, "device allocation failed");
+                    L32.pinv = P32;
+                }
+            }
             h->mg_h[l] = L;
             h->mg32_h[l] = L32;
         }
-        h->mg_smem = lds_vals * sizeof(double);
-        h->mg_smem32 = lds_vals * sizeof(float);
         h->mg_d = (MLevel *)m.get(sizeof(MLevel) * MG_MAXLEV);
         if (!h->mg_d) return fail(SOL_ENOMEM, "device allocation failed");
         if (mixed) {
@@ -1302,12 +1317,15 @@ int sol_create(const sol_grid *grid, const sol_alloy *alloy, const sol_bcs *bcs,
     if (rc == SOL_OK) {
         Group &g = *h->solo;
         for (int gi = 0; gi < 2; ++gi) launch_asm_const(gi ? 3 : 2, g.cases_d, g.t_const[gi], g.n_const[gi], h->stream);
-        // multigrid operators of the (constant) pressure system, level by level
+        // inverse diagonals of the coarse multigrid levels of the (constant)
+        // pressure operator
         const bool mixed = h->num.precision == SOL_PRECISION_MIXED;
-        for (int l = 0; l + 1 < h->mg_nlev; ++l)
-            launch_mg_coarsen(h->z.dim, h->mg_d, l, h->mg_h[l].cn, (double *)h->mg_h[l + 1].A,
-                              (double *)h->mg_h[l + 1].minv, mixed ? (float *)h->mg32_h[l + 1].A : nullptr,
-                              mixed ? (float *)h->mg32_h[l + 1].minv : nullptr, h->stream);
+        for (int l = 1; l < h->mg_nlev; ++l)
+            launch_mg_minv(h->z.dim, h->mg_d, l, h->mg_h[l].n, (double *)h->mg_h[l].minv,
+                           mixed ? (float *)h->mg32_h[l].minv : nullptr, h->stream);
+        const int L = h->mg_nglob;
+        launch_mg_pinv(h->z.dim, h->mg_d, L, (double *)h->mg_h[L].pinv, mixed ? (float *)h->mg32_h[L].pinv : nullptr,
+                       h->stream);
         if (hipGetLastError() != hipSuccess || hipStreamSynchronize(h->stream) != hipSuccess)
             rc = fail(SOL_EDEVICE, "offline assembly failed");
     }

@@ -19,7 +19,7 @@ void launch_kdecide(const KJob *j, int njobs, hipStream_t s);
 // int koff): iteration index = (kbase ? *kbase : 0) + koff
 enum KIter {
     KI_CG = 0, KI_BICG_A = 1, KI_BICG_B = 2, KI_BICG_C = 3,
-    KI_MG_PQ = 4, KI_MG_DOWN0 = 5, KI_MG_DOWN = 6, KI_MG_LDS = 7, KI_MG_UP = 8, KI_MG_UP0 = 9,
+    KI_MG_PQ = 4, KI_MG_DOWN0 = 5, KI_MG_DOWN = 6, KI_MG_EXACT = 7, KI_MG_UP = 8, KI_MG_UP0 = 9,
     KI_MG_DOWN0_INIT = 10
 };
 void launch_kiter(int which, int nd, int fp32, const KJob *j, const JTile *t, int nt, int k, hipStream_t s);
@@ -27,10 +27,11 @@ void launch_kiter(int which, int nd, int fp32, const KJob *j, const JTile *t, in
 const void *kiter_fn(int which, int nd, int fp32);
 const void *mg_fn(int which, int nd, int fp32);
 // multigrid: start of the solves (r = b - A x, p = 0, partial (b, b)) and
-// the Galerkin operator of level l+1 from level l
+// the inverse diagonal of level l >= 1 (FP32 copy when mi32 is given)
 void launch_mg_init(int nd, int fp32, const KJob *j, const JTile *t, int nt, int k, int mode, hipStream_t s);
-void launch_mg_coarsen(int dim, const MLevel *lev, int l, int cn, double *Ac, double *mic, float *Ac32, float *mic32,
-                       hipStream_t s);
+void launch_mg_minv(int dim, const MLevel *lev, int l, int n, double *mi, float *mi32, hipStream_t s);
+// multigrid: dense inverse of the exactly solved level l (one workgroup)
+void launch_mg_pinv(int dim, const MLevel *lev, int l, double *P, float *P32, hipStream_t s);
 const void *kbase_add_fn();   // (int *kbase, int m)
 void launch_kbase_set(int *kbase, int v, hipStream_t s);
 void launch_tune_rhs(void *b, int fp32, int n, hipStream_t s);

@@ -3,20 +3,22 @@
 // symmetric Neumann Laplacian open; Jacobi-PCG needs O(n^(1/d)) iterations
 // per solve, a V-cycle preconditioner a few tens at any size.
 //
-// Hierarchy (built once per case, the operator never changes): level l+1
-// aggregates 2 x 2 (x 2) cells of level l; its operator is the Galerkin
-// product P^T A_l P with the piecewise-constant aggregation P.  For a
-// 5- / 7-point operator that is again 5- / 7-point: coarse couplings are sums
-// of the fine couplings across the aggregate faces, the diagonal collects the
-// rest, and row sums stay zero (the constant null space is kept).
+// Hierarchy: level l+1 aggregates 2 x 2 (x 2) cells of level l; its operator
+// is the Galerkin product P^T A_l P with the piecewise-constant aggregation
+// P.  For the pressure Laplacian that product has a closed form (coupling =
+// 1/h_a^2 x level-0 faces between two blocks, diagonal = sum of couplings,
+// rows sum to zero: the constant null space is kept), so every level is
+// applied matrix-free: no kernel of the cycle loads matrix coefficients.
+// Only the inverse diagonals of the coarse levels are stored (built once).
 //
 // Preconditioner z = M r: one V-cycle from a zero initial guess.
-//   launch levels (0 .. nglob-1): one damped-Jacobi sweep before and after
-//     the coarse correction, the correction scaled by MG_OG (aggregation
+//   levels 0 .. nglob-1: one damped-Jacobi sweep before and after the
+//     coarse correction, the correction scaled by MG_OG (aggregation
 //     under-estimates smooth error; the scaling restores most of the rate);
-//   LDS levels (nglob .. coarsest): one workgroup per solve runs a V(2,2)
-//     cycle with correction scaling MG_OL in local memory; the single-cell
-//     coarsest level has a zero operator and returns 0.
+//   level nglob (the first with at most MG_EXACT_MAX cells): solved exactly
+//     with a dense inverse of A + c 1 1^T (c = mean diagonal / n), built once
+//     per case; for a mean-free right-hand side that is the minimum-norm
+//     solution, and a constant part is removed with the mean of z anyway.
 // Every piece is linear and the pre- and post-smoothers are the same
 // symmetric operator, so M is symmetric; the scalings are chosen so that it
 // stays positive definite on the grids of the workloads (checked by the
@@ -35,7 +37,7 @@
 //              r_(k+1) = r_k - alpha q; partial ||r_(k+1)||^2; pre-smooth
 //              on level 0 and restrict the residual to level 1
 //   down(l):   pre-smooth level l, restrict to level l+1     (l = 1 .. nglob-1)
-//   lds:       levels nglob .. coarsest in one workgroup
+//   exact:     e = P^-1 b on level nglob (dense product, 64 rows per workgroup)
 //   up(l):     prolong, post-smooth level l                  (l = nglob-1 .. 1)
 //   up0(k):    prolong, post-smooth level 0 -> z_(k+1); partials (r, z),
 //              sum(z), sum(r)
@@ -51,9 +53,8 @@
 namespace sol {
 
 constexpr double MG_W = 0.8;       // damped-Jacobi weight
-constexpr double MG_OG = 1.8;      // coarse-correction scaling, launch levels
-constexpr double MG_OL = 1.4;      // coarse-correction scaling, LDS levels
-constexpr int MG_LPT = MG_LDS_MAX / TILE;   // LDS-level cells per thread
+constexpr double MG_OG = 1.8;      // coarse-correction scaling
+constexpr int MG_XROWS = 64;       // rows of the exact solve per workgroup
 
 // floor(i / d) for 0 <= i < 2^31, 1 <= d, from the double reciprocal inv = 1/d
 __device__ __forceinline__ int fdiv(int i, int d, double inv)
@@ -63,10 +64,6 @@ __device__ __forceinline__ int fdiv(int i, int d, double inv)
     else if ((long long)(q + 1) * d <= i) ++q;
     return q;
 }
-
-// (axis, direction) of DIA slot s; the centre slot is DIM
-template <int DIM>
-__device__ __forceinline__ int slot_axis(int s) { return s < DIM ? DIM - 1 - s : s - DIM - 1; }
 
 // A coarse cell and its children on the finer level of an MLevel
 template <int DIM>
@@ -98,21 +95,20 @@ __device__ __forceinline__ Agg<DIM> agg_of(const MLevel &L, int I, double icnx, 
     return a;
 }
 
-// coarse cell holding the level-l neighbour of child (cx) in slot s: the
-// neighbour aggregate when the step leaves the aggregate inside the domain,
-// else the cell's own (an out-of-domain neighbour has a zero coefficient)
+// coarse cell holding the in-domain neighbour of child cx along axis ax in
+// direction dir (0: the child itself): the neighbour aggregate when the step
+// leaves the aggregate, else the child's own
 template <int DIM>
-__device__ __forceinline__ int agg_nb(const MLevel &L, const Agg<DIM> &a, const int *cx, int s)
+__device__ __forceinline__ int agg_nb(const MLevel &L, const Agg<DIM> &a, const int *cx, int ax, int dir)
 {
-    if (s == DIM) return a.I;
-    const int ax = slot_axis<DIM>(s);
+    if (dir == 0) return a.I;
     const int cs = ax == 0 ? 1 : (ax == 1 ? L.cnx : L.cnx * L.cny);
-    const int cn = ax == 0 ? L.cnx : (ax == 1 ? L.cny : L.cnz);
-    if (s < DIM) return (cx[ax] == 0 && a.c[ax] > 0) ? a.I - cs : a.I;
-    return (cx[ax] == 1 && a.c[ax] + 1 < cn) ? a.I + cs : a.I;
+    if (dir < 0) return cx[ax] == 0 ? a.I - cs : a.I;
+    return cx[ax] == 1 ? a.I + cs : a.I;
 }
 
-// visit the children of aggregate a: f(i, cx) with cx the child position
+// visit the children of aggregate a: f(i, cx, q) with cx the position in
+// the aggregate and q the fine coordinates
 template <int DIM, class F>
 __device__ __forceinline__ void for_children(const MLevel &L, const Agg<DIM> &a, F f)
 {
@@ -127,17 +123,11 @@ __device__ __forceinline__ void for_children(const MLevel &L, const Agg<DIM> &a,
             for (int cx = 0; cx < 2; ++cx) {
                 if (cx >= a.w[0]) continue;
                 const int c3[3] = {cx, cy, cz};
-                f(a.i0 + cx + L.nx * cy + sxy * cz, c3);
+                const int q[3] = {2 * a.c[0] + cx, 2 * a.c[1] + cy, 2 * a.c[2] + cz};
+                f(a.i0 + cx + L.nx * cy + sxy * cz, c3, q);
             }
         }
     }
-}
-
-template <int ND>
-__device__ __forceinline__ int nb_index(int i, int s, int n, int sx, int sxy)
-{
-    int j = i + slot_off<ND>(s, sx, sxy);
-    return j < 0 ? 0 : (j >= n ? n - 1 : j);
 }
 
 // a solve whose multigrid stages run at iteration index k: RUNNING, or its
@@ -150,59 +140,97 @@ __device__ __forceinline__ bool mg_live(const KJob &J, int k)
 
 __device__ __forceinline__ int kidx(const int *kbase, int koff) { return (kbase ? *kbase : 0) + koff; }
 
-// ------------------------------------------------------------- hierarchy
+// ------------------------------------------------------------- operator
 
-// level l+1 operator from level l (Galerkin with aggregation), inverse
-// diagonal (0 where the diagonal is 0: the single-cell coarsest level), and
-// FP32 copies when requested; deterministic (fixed summation order)
-template <int DIM>
-__global__ __launch_bounds__(TILE) void k_mg_coarsen(const MLevel *__restrict__ lev, int l, double *Ac, double *mic,
-                                                     float *Ac32, float *mic32)
+// couplings of the level-l cell with coordinates q to its neighbours along
+// each axis: 1/h_a^2 times the product of its block extents (in level-0
+// cells) along the other axes
+template <int DIM, class T>
+__device__ __forceinline__ void couplings(const MLevel &L, const int *q, T *co)
 {
-    constexpr int ND = 2 * DIM + 1;
-    const MLevel &L = lev[l];
-    const int I = blockIdx.x * TILE + threadIdx.x;
-    if (I >= L.cn) return;
-    const Agg<DIM> a = agg_of<DIM>(L, I, 1.0 / L.cnx, 1.0 / ((double)L.cnx * L.cny));
-    auto A = G<double>(L.A);
-    double acc[ND];
+    int e[3];
 #pragma unroll
-    for (int s = 0; s < ND; ++s) acc[s] = 0.0;
-    for_children<DIM>(L, a, [&](int i, const int *cx) {
-#pragma unroll
-        for (int s = 0; s < ND; ++s) {
-            const double v = A[(size_t)s * L.n + i];
-            const int J = agg_nb<DIM>(L, a, cx, s);
-            if (J == I) acc[DIM] += v;
-            else acc[s] += v;
-        }
-    });
-    const int cn = L.cn;
-    // a single coarse cell takes every coupling inside itself: its operator
-    // is exactly 0 (zero row sums), while the summed terms above cancel
-    // only to rounding, and 1 / rounding would inject a huge constant
-    if (cn == 1) {
-#pragma unroll
-        for (int s = 0; s < ND; ++s) acc[s] = 0.0;
-    }
-#pragma unroll
-    for (int s = 0; s < ND; ++s) Ac[(size_t)s * cn + I] = acc[s];
-    const double mi = acc[DIM] > 0.0 ? 1.0 / acc[DIM] : 0.0;
-    mic[I] = mi;
-    if (Ac32) {
-#pragma unroll
-        for (int s = 0; s < ND; ++s) Ac32[(size_t)s * cn + I] = (float)acc[s];
-        mic32[I] = (float)mi;
+    for (int b = 0; b < 3; ++b) e[b] = min(L.sc, L.n0[b] - q[b] * L.sc);
+    if (DIM == 2) {
+        co[0] = (T)L.ih2[0] * (T)e[1];
+        co[1] = (T)L.ih2[1] * (T)e[0];
+    } else {
+        co[0] = (T)L.ih2[0] * (T)(e[1] * e[2]);
+        co[1] = (T)L.ih2[1] * (T)(e[0] * e[2]);
+        co[2] = (T)L.ih2[2] * (T)(e[0] * e[1]);
     }
 }
 
-void launch_mg_coarsen(int dim, const MLevel *lev, int l, int cn, double *Ac, double *mic, float *Ac32, float *mic32,
-                       hipStream_t s)
+// diagonal of the level operator at q (0 for a cell without neighbours)
+template <int DIM, class T>
+__device__ __forceinline__ T op_diag(const MLevel &L, const int *q)
 {
-    if (cn <= 0) return;
-    const dim3 g(ceil_div(cn, TILE)), b(TILE);
-    if (dim == 2) hipLaunchKernelGGL(k_mg_coarsen<2>, g, b, 0, s, lev, l, Ac, mic, Ac32, mic32);
-    else hipLaunchKernelGGL(k_mg_coarsen<3>, g, b, 0, s, lev, l, Ac, mic, Ac32, mic32);
+    T co[3];
+    couplings<DIM, T>(L, q, co);
+    const int nn[3] = {L.nx, L.ny, L.nz};
+    T d = T(0);
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        if (q[a] > 0) d += co[a];
+        if (q[a] + 1 < nn[a]) d += co[a];
+    }
+    return d;
+}
+
+// (A f)_i = sum over in-domain neighbours j of c_a (f_i - f_j), with
+// f(j, axis, direction) (direction 0: the cell itself)
+template <int DIM, class T, class F>
+__device__ __forceinline__ T apply_op(const MLevel &L, int i, const int *q, F f)
+{
+    T co[3];
+    couplings<DIM, T>(L, q, co);
+    const int st[3] = {1, L.nx, L.nx * L.ny};
+    const int nn[3] = {L.nx, L.ny, L.nz};
+    const T fi = f(i, 0, 0);
+    T acc = T(0);
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        if (q[a] > 0) acc += co[a] * (fi - f(i - st[a], a, -1));
+        if (q[a] + 1 < nn[a]) acc += co[a] * (fi - f(i + st[a], a, 1));
+    }
+    return acc;
+}
+
+// coordinates of cell i on a level with counts (nx, ny)
+template <int DIM>
+__device__ __forceinline__ void cell_coords(int i, int nx, int ny, double inx, double inxy, int *q)
+{
+    int rem = i;
+    q[2] = 0;
+    if (DIM == 3) {
+        q[2] = fdiv(i, nx * ny, inxy);
+        rem = i - q[2] * nx * ny;
+    }
+    q[1] = fdiv(rem, nx, inx);
+    q[0] = rem - q[1] * nx;
+}
+
+// inverse diagonal of level l >= 1 (FP64, and FP32 when requested)
+template <int DIM>
+__global__ __launch_bounds__(TILE) void k_mg_minv(const MLevel *__restrict__ lev, int l, double *mi, float *mi32)
+{
+    const MLevel &L = lev[l];
+    const int i = blockIdx.x * TILE + threadIdx.x;
+    if (i >= L.n) return;
+    int q[3];
+    cell_coords<DIM>(i, L.nx, L.ny, 1.0 / L.nx, 1.0 / ((double)L.nx * L.ny), q);
+    const double d = op_diag<DIM, double>(L, q);
+    const double m = d > 0.0 ? 1.0 / d : 0.0;
+    mi[i] = m;
+    if (mi32) mi32[i] = (float)m;
+}
+
+void launch_mg_minv(int dim, const MLevel *lev, int l, int n, double *mi, float *mi32, hipStream_t s)
+{
+    if (n <= 0) return;
+    const dim3 g(ceil_div(n, TILE)), b(TILE);
+    if (dim == 2) hipLaunchKernelGGL(k_mg_minv<2>, g, b, 0, s, lev, l, mi, mi32);
+    else hipLaunchKernelGGL(k_mg_minv<3>, g, b, 0, s, lev, l, mi, mi32);
 }
 
 // ------------------------------------------------------------- start
@@ -213,7 +241,6 @@ template <int DIM, class T>
 __global__ __launch_bounds__(TILE) void k_mg_init(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles, int k,
                                                   int mode)
 {
-    constexpr int ND = 2 * DIM + 1;
     JTile tl;
     const KJob &J = job_of(jobs, tiles, tl);
     if (mode == 1 && J.st->status != K_RESTART) return;
@@ -221,8 +248,6 @@ __global__ __launch_bounds__(TILE) void k_mg_init(const KJob *__restrict__ jobs,
     const int pk = k & 1;
     const MLevel &L = J.lev[0];
     const double icx = 1.0 / L.cnx, icxy = 1.0 / ((double)L.cnx * L.cny);
-    const int n = J.n, sx = J.sx, sxy = J.sxy;
-    auto A = G<T>(J.A);
     auto b = G<T>(J.b);
     auto x = G<T>(J.x), x0 = G<T>(J.x0);
     auto r = G<T>(pk ? J.rh : J.r), pz = G<T>(pk ? J.p0 : J.p1);
@@ -232,15 +257,12 @@ __global__ __launch_bounds__(TILE) void k_mg_init(const KJob *__restrict__ jobs,
     const int I0 = tl.t * L.cpt, I1 = min(L.cn, I0 + L.cpt);
     for (int I = I0 + threadIdx.x; I < I1; I += TILE) {
         const Agg<DIM> a = agg_of<DIM>(L, I, icx, icxy);
-        for_children<DIM>(L, a, [&](int i, const int *) {
+        for_children<DIM>(L, a, [&](int i, const int *, const int *q) {
             const T bi = b[i];
             T ri = bi;
             if (from_x0 || keep_x) {
                 auto src = from_x0 ? x0 : x;
-                T ax = T(0);
-#pragma unroll
-                for (int s = 0; s < ND; ++s) ax += A[(size_t)s * n + i] * src[nb_index<ND>(i, s, n, sx, sxy)];
-                ri = bi - ax;
+                ri = bi - apply_op<DIM, T>(L, i, q, [&](int j, int, int) { return src[j]; });
             }
             if (from_x0) x[i] = x0[i];
             else if (!keep_x) x[i] = T(0);
@@ -261,7 +283,6 @@ template <int DIM, class T>
 __global__ __launch_bounds__(TILE) void k_mg_pq(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles,
                                                 const int *kbase, int koff)
 {
-    constexpr int ND = 2 * DIM + 1;
     const int k = kidx(kbase, koff);
     JTile tl;
     const KJob &J = job_of(jobs, tiles, tl);
@@ -287,8 +308,6 @@ __global__ __launch_bounds__(TILE) void k_mg_pq(const KJob *__restrict__ jobs, c
     const T tb = (T)beta, tz = (T)zbar;
     const MLevel &L = J.lev[0];
     const double icx = 1.0 / L.cnx, icxy = 1.0 / ((double)L.cnx * L.cny);
-    const int n = J.n, sx = J.sx, sxy = J.sxy;
-    auto A = G<T>(J.A);
     auto z = G<T>(J.v0);
     auto q = G<T>(J.v1);
     auto po = G<T>(pm ? J.p1 : J.p0), pn = G<T>(pk ? J.p1 : J.p0);
@@ -296,13 +315,8 @@ __global__ __launch_bounds__(TILE) void k_mg_pq(const KJob *__restrict__ jobs, c
     const int I0 = tl.t * L.cpt, I1 = min(L.cn, I0 + L.cpt);
     for (int I = I0 + threadIdx.x; I < I1; I += TILE) {
         const Agg<DIM> a = agg_of<DIM>(L, I, icx, icxy);
-        for_children<DIM>(L, a, [&](int i, const int *) {
-            T qi = T(0);
-#pragma unroll
-            for (int s = 0; s < ND; ++s) {
-                const int j = nb_index<ND>(i, s, n, sx, sxy);
-                qi += A[(size_t)s * n + i] * ((z[j] - tz) + tb * po[j]);
-            }
+        for_children<DIM>(L, a, [&](int i, const int *, const int *qc) {
+            const T qi = apply_op<DIM, T>(L, i, qc, [&](int j, int, int) { return (z[j] - tz) + tb * po[j]; });
             const T pi = (z[i] - tz) + tb * po[i];
             pn[i] = pi;
             q[i] = qi;
@@ -320,7 +334,6 @@ template <int DIM, class T, bool INIT>
 __global__ __launch_bounds__(TILE) void k_mg_down0(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles,
                                                    const int *kbase, int koff)
 {
-    constexpr int ND = 2 * DIM + 1;
     const int k = kidx(kbase, koff);
     JTile tl;
     const KJob &J = job_of(jobs, tiles, tl);
@@ -343,8 +356,6 @@ __global__ __launch_bounds__(TILE) void k_mg_down0(const KJob *__restrict__ jobs
     const T ta = (T)alpha, w = (T)MG_W;
     const MLevel &L = J.lev[0];
     const double icx = 1.0 / L.cnx, icxy = 1.0 / ((double)L.cnx * L.cny);
-    const int n = J.n, sx = J.sx, sxy = J.sxy;
-    auto A = G<T>(J.A);
     auto mi = G<T>(J.minv);
     auto x = G<T>(J.x);
     auto p = G<T>(pk ? J.p1 : J.p0);
@@ -356,14 +367,11 @@ __global__ __launch_bounds__(TILE) void k_mg_down0(const KJob *__restrict__ jobs
     for (int I = I0 + threadIdx.x; I < I1; I += TILE) {
         const Agg<DIM> a = agg_of<DIM>(L, I, icx, icxy);
         T bsum = T(0);
-        for_children<DIM>(L, a, [&](int i, const int *) {
-            T ax = T(0);
-#pragma unroll
-            for (int s = 0; s < ND; ++s) {
-                const int j = nb_index<ND>(i, s, n, sx, sxy);
+        for_children<DIM>(L, a, [&](int i, const int *, const int *qc) {
+            const T ax = apply_op<DIM, T>(L, i, qc, [&](int j, int, int) {
                 const T rj = INIT ? rn[j] : rc[j] - ta * q[j];
-                ax += A[(size_t)s * n + i] * (w * mi[j] * rj);
-            }
+                return w * mi[j] * rj;
+            });
             T ri;
             if (INIT) {
                 ri = rn[i];
@@ -387,16 +395,13 @@ template <int DIM, class T>
 __global__ __launch_bounds__(TILE) void k_mg_down(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles,
                                                   const int *kbase, int koff)
 {
-    constexpr int ND = 2 * DIM + 1;
     const int k = kidx(kbase, koff);
     JTile tl;
     const KJob &J = job_of(jobs, tiles, tl);
     if (outer_idle(J) || !mg_live(J, k)) return;
     const MLevel &L = J.lev[tl.lv];
     const double icx = 1.0 / L.cnx, icxy = 1.0 / ((double)L.cnx * L.cny);
-    const int n = L.n, sx = L.nx, sxy = L.nx * L.ny;
     const T w = (T)MG_W;
-    auto A = G<T>(L.A);
     auto mi = G<T>(L.minv);
     auto b = G<T>(L.b);
     auto bc = G<T>(J.lev[tl.lv + 1].b);
@@ -404,13 +409,8 @@ __global__ __launch_bounds__(TILE) void k_mg_down(const KJob *__restrict__ jobs,
     for (int I = I0 + threadIdx.x; I < I1; I += TILE) {
         const Agg<DIM> a = agg_of<DIM>(L, I, icx, icxy);
         T bsum = T(0);
-        for_children<DIM>(L, a, [&](int i, const int *) {
-            T ax = T(0);
-#pragma unroll
-            for (int s = 0; s < ND; ++s) {
-                const int j = nb_index<ND>(i, s, n, sx, sxy);
-                ax += A[(size_t)s * n + i] * (w * mi[j] * b[j]);
-            }
+        for_children<DIM>(L, a, [&](int i, const int *, const int *qc) {
+            const T ax = apply_op<DIM, T>(L, i, qc, [&](int j, int, int) { return w * mi[j] * b[j]; });
             bsum += b[i] - ax;
         });
         bc[I] = bsum;
@@ -423,16 +423,13 @@ template <int DIM, class T>
 __global__ __launch_bounds__(TILE) void k_mg_up(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles,
                                                 const int *kbase, int koff)
 {
-    constexpr int ND = 2 * DIM + 1;
     const int k = kidx(kbase, koff);
     JTile tl;
     const KJob &J = job_of(jobs, tiles, tl);
     if (outer_idle(J) || !mg_live(J, k)) return;
     const MLevel &L = J.lev[tl.lv];
     const double icx = 1.0 / L.cnx, icxy = 1.0 / ((double)L.cnx * L.cny);
-    const int n = L.n, sx = L.nx, sxy = L.nx * L.ny;
     const T w = (T)MG_W, og = (T)MG_OG;
-    auto A = G<T>(L.A);
     auto mi = G<T>(L.minv);
     auto b = G<T>(L.b);
     auto e = G<T>(L.e);
@@ -440,13 +437,10 @@ __global__ __launch_bounds__(TILE) void k_mg_up(const KJob *__restrict__ jobs, c
     const int I0 = tl.t * L.cpt, I1 = min(L.cn, I0 + L.cpt);
     for (int I = I0 + threadIdx.x; I < I1; I += TILE) {
         const Agg<DIM> a = agg_of<DIM>(L, I, icx, icxy);
-        for_children<DIM>(L, a, [&](int i, const int *cx) {
-            T ax = T(0);
-#pragma unroll
-            for (int s = 0; s < ND; ++s) {
-                const int j = nb_index<ND>(i, s, n, sx, sxy);
-                ax += A[(size_t)s * n + i] * (w * mi[j] * b[j] + og * ec[agg_nb<DIM>(L, a, cx, s)]);
-            }
+        for_children<DIM>(L, a, [&](int i, const int *cx, const int *qc) {
+            const T ax = apply_op<DIM, T>(L, i, qc, [&](int j, int ax_, int dir) {
+                return w * mi[j] * b[j] + og * ec[agg_nb<DIM>(L, a, cx, ax_, dir)];
+            });
             const T xi = w * mi[i] * b[i] + og * ec[I];
             e[i] = xi + w * mi[i] * (b[i] - ax);
         });
@@ -459,7 +453,6 @@ template <int DIM, class T>
 __global__ __launch_bounds__(TILE) void k_mg_up0(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles,
                                                  const int *kbase, int koff)
 {
-    constexpr int ND = 2 * DIM + 1;
     const int k = kidx(kbase, koff);
     JTile tl;
     const KJob &J = job_of(jobs, tiles, tl);
@@ -467,9 +460,7 @@ __global__ __launch_bounds__(TILE) void k_mg_up0(const KJob *__restrict__ jobs, 
     const int pn1 = (k + 1) & 1;
     const MLevel &L = J.lev[0];
     const double icx = 1.0 / L.cnx, icxy = 1.0 / ((double)L.cnx * L.cny);
-    const int n = J.n, sx = J.sx, sxy = J.sxy;
     const T w = (T)MG_W, og = (T)MG_OG;
-    auto A = G<T>(J.A);
     auto mi = G<T>(J.minv);
     auto r = G<T>(pn1 ? J.rh : J.r);
     auto z = G<T>(J.v0);
@@ -478,13 +469,10 @@ __global__ __launch_bounds__(TILE) void k_mg_up0(const KJob *__restrict__ jobs, 
     const int I0 = tl.t * L.cpt, I1 = min(L.cn, I0 + L.cpt);
     for (int I = I0 + threadIdx.x; I < I1; I += TILE) {
         const Agg<DIM> a = agg_of<DIM>(L, I, icx, icxy);
-        for_children<DIM>(L, a, [&](int i, const int *cx) {
-            T ax = T(0);
-#pragma unroll
-            for (int s = 0; s < ND; ++s) {
-                const int j = nb_index<ND>(i, s, n, sx, sxy);
-                ax += A[(size_t)s * n + i] * (w * mi[j] * r[j] + og * ec[agg_nb<DIM>(L, a, cx, s)]);
-            }
+        for_children<DIM>(L, a, [&](int i, const int *cx, const int *qc) {
+            const T ax = apply_op<DIM, T>(L, i, qc, [&](int j, int ax_, int dir) {
+                return w * mi[j] * r[j] + og * ec[agg_nb<DIM>(L, a, cx, ax_, dir)];
+            });
             const T ri = r[i];
             const T xi = w * mi[i] * ri + og * ec[I];
             const T zi = xi + w * mi[i] * (ri - ax);
@@ -498,124 +486,112 @@ __global__ __launch_bounds__(TILE) void k_mg_up0(const KJob *__restrict__ jobs, 
     put_partials<3>(vv, J.part, off, tl.t);
 }
 
-// ------------------------------------------------------------- LDS levels
-// Levels nglob .. coarsest of one solve in one workgroup: b and x of every
-// level in local memory (level l at an offset, b then x), operators read
-// from global memory.  V(2,2) with damped Jacobi, correction scaled by MG_OL.
-
-template <int DIM, class T>
-__device__ __forceinline__ int lds_parent(const MLevel &L, int i, double inx, double inxy)
+// ------------------------------------------------------------- exact level
+// e = P^-1 b on level nglob: workgroup (job, t) takes rows t*64 .. t*64+63;
+// wave w sums columns j = w, w+4, ... of those rows (P^-1 is symmetric and
+// stored row-major, so the 64 lanes read one contiguous row segment per j),
+// and the four wave sums are added in a fixed order.
+template <class T>
+__global__ __launch_bounds__(TILE) void k_mg_exact(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles,
+                                                   const int *kbase, int koff)
 {
-    int fz = 0, rem = i;
-    if (DIM == 3) {
-        fz = fdiv(i, L.nx * L.ny, inxy);
-        rem = i - fz * L.nx * L.ny;
-    }
-    const int fy = fdiv(rem, L.nx, inx);
-    const int fx = rem - fy * L.nx;
-    return (fx >> 1) + L.cnx * ((fy >> 1) + L.cny * (fz >> 1));
-}
-
-// x = x + w M (b - A x) on one level in local memory (two barriers)
-template <int ND, class T>
-__device__ __forceinline__ void lds_sweep(const MLevel &L, const T *b, T *x)
-{
-    const int n = L.n, sx = L.nx, sxy = L.nx * L.ny;
-    auto A = G<T>(L.A);
-    auto mi = G<T>(L.minv);
-    const T w = (T)MG_W;
-    T nv[MG_LPT];
-#pragma unroll
-    for (int c = 0; c < MG_LPT; ++c) {
-        const int i = threadIdx.x + c * TILE;
-        if (i < n) {
-            T ax = T(0);
-#pragma unroll
-            for (int s = 0; s < ND; ++s) ax += A[(size_t)s * n + i] * x[nb_index<ND>(i, s, n, sx, sxy)];
-            nv[c] = x[i] + w * mi[i] * (b[i] - ax);
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int c = 0; c < MG_LPT; ++c) {
-        const int i = threadIdx.x + c * TILE;
-        if (i < n) x[i] = nv[c];
-    }
-    __syncthreads();
-}
-
-template <int DIM, class T>
-__global__ __launch_bounds__(TILE) void k_mg_lds(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles,
-                                                 const int *kbase, int koff)
-{
-    constexpr int ND = 2 * DIM + 1;
     const int k = kidx(kbase, koff);
     const JTile tl = tiles[blockIdx.x];
     const KJob &J = jobs[tl.j];
     if (outer_idle(J) || !mg_live(J, k)) return;
-    extern __shared__ __align__(16) unsigned char mg_smem[];
-    T *sh = reinterpret_cast<T *>(mg_smem);
-    const MLevel *Lv = J.lev;
-    const int L0 = J.nglob, M = J.nlev - 1;
-    const T w = (T)MG_W, ol = (T)MG_OL;
-    {
-        auto bg = G<T>(Lv[L0].b);
-        for (int i = threadIdx.x; i < Lv[L0].n; i += TILE) sh[i] = bg[i];
-    }
+    const MLevel &L = J.lev[tl.lv];
+    const int n = L.n;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int row = tl.t * MG_XROWS + lane;
+    auto P = G<T>(L.pinv);
+    auto b = G<T>(L.b);
+    T acc = T(0);
+    if (row < n)
+        for (int j = wv; j < n; j += TILE / 64) acc += P[(size_t)j * n + row] * b[j];
+    __shared__ T part[TILE];
+    part[threadIdx.x] = acc;
     __syncthreads();
-    // down: levels L0 .. M-1
-    int o = 0;
-    for (int l = L0; l < M; ++l) {
-        const MLevel &L = Lv[l];
-        const int n = L.n, sx = L.nx, sxy = L.nx * L.ny;
-        T *b = sh + o, *x = sh + o + n, *bc = sh + o + 2 * n;
-        auto A = G<T>(L.A);
-        auto mi = G<T>(L.minv);
-        for (int i = threadIdx.x; i < n; i += TILE) x[i] = w * mi[i] * b[i];
+    if (wv == 0 && row < n) {
+        auto e = G<T>(L.e);
+        e[row] = (part[lane] + part[64 + lane]) + (part[128 + lane] + part[192 + lane]);
+    }
+}
+
+// setup: P^-1 of level l (n <= MG_EXACT_MAX) by Gauss-Jordan elimination of
+// the symmetric positive definite A + c 1 1^T in place (no pivoting needed),
+// one workgroup; FP32 copy when requested
+template <int DIM>
+__global__ __launch_bounds__(TILE) void k_mg_pinv(const MLevel *__restrict__ lev, int l, double *P, float *P32)
+{
+    const MLevel &L = lev[l];
+    const int n = L.n;
+    __shared__ double rk[MG_EXACT_MAX], ck[MG_EXACT_MAX];
+    __shared__ double csh;
+    const double inx = 1.0 / L.nx, inxy = 1.0 / ((double)L.nx * L.ny);
+    // dense operator, row by row (thread = column)
+    double dsum = 0.0;
+    for (int i = 0; i < n; ++i) {
+        int q[3];
+        cell_coords<DIM>(i, L.nx, L.ny, inx, inxy, q);
+        const int j = threadIdx.x;
+        if (j < n) {
+            // A_ij from the closed form: -coupling for a neighbour, diagonal for j = i
+            double co[3];
+            couplings<DIM, double>(L, q, co);
+            const int st[3] = {1, L.nx, L.nx * L.ny};
+            const int nn[3] = {L.nx, L.ny, L.nz};
+            double v = 0.0;
+            if (j == i) v = op_diag<DIM, double>(L, q);
+            for (int a = 0; a < DIM; ++a) {
+                if (q[a] > 0 && j == i - st[a]) v = -co[a];
+                if (q[a] + 1 < nn[a] && j == i + st[a]) v = -co[a];
+            }
+            P[(size_t)i * n + j] = v;
+            if (j == i) dsum += v;
+        }
+    }
+    // c = (sum of diagonals) / n^2 (1 for a zero operator)
+    {
+        __shared__ double red[TILE];
+        red[threadIdx.x] = dsum;
         __syncthreads();
-        lds_sweep<ND, T>(L, b, x);
-        const double icx = 1.0 / L.cnx, icxy = 1.0 / ((double)L.cnx * L.cny);
-        for (int I = threadIdx.x; I < L.cn; I += TILE) {
-            const Agg<DIM> a = agg_of<DIM>(L, I, icx, icxy);
-            T bsum = T(0);
-            for_children<DIM>(L, a, [&](int i, const int *) {
-                T ax = T(0);
-#pragma unroll
-                for (int s = 0; s < ND; ++s) ax += A[(size_t)s * n + i] * x[nb_index<ND>(i, s, n, sx, sxy)];
-                bsum += b[i] - ax;
-            });
-            bc[I] = bsum;
+        if (threadIdx.x == 0) {
+            double t = 0.0;
+            for (int q = 0; q < TILE; ++q) t += red[q];
+            csh = t > 0.0 ? t / ((double)n * n) : 1.0;
         }
         __syncthreads();
-        o += 2 * n;
     }
-    // coarsest level: one damped-Jacobi application (the single cell has a
-    // zero operator and a zero inverse diagonal: x = 0)
-    {
-        const MLevel &L = Lv[M];
-        auto mi = G<T>(L.minv);
-        T *b = sh + o, *x = sh + o + L.n;
-        for (int i = threadIdx.x; i < L.n; i += TILE) x[i] = w * mi[i] * b[i];
+    const double c = csh;
+    for (int i = 0; i < n; ++i)
+        if ((int)threadIdx.x < n) P[(size_t)i * n + threadIdx.x] += c;
+    __syncthreads();
+    for (int kk = 0; kk < n; ++kk) {
+        const int j = threadIdx.x;
+        const double piv = P[(size_t)kk * n + kk];
+        if (j < n) {
+            rk[j] = (j == kk ? 1.0 : P[(size_t)kk * n + j]) / piv;
+            ck[j] = j == kk ? 0.0 : P[(size_t)j * n + kk];
+        }
+        __syncthreads();
+        if (j < n) {
+            for (int i = 0; i < n; ++i) {
+                double v;
+                if (i == kk) v = rk[j];
+                else v = (j == kk ? 0.0 : P[(size_t)i * n + j]) - ck[i] * rk[j];
+                P[(size_t)i * n + j] = v;
+            }
+        }
         __syncthreads();
     }
-    // up: levels M-1 .. L0
-    for (int l = M - 1; l >= L0; --l) {
-        const MLevel &L = Lv[l];
-        const int n = L.n;
-        o -= 2 * n;
-        T *b = sh + o, *x = sh + o + n;
-        const T *xc = sh + o + 2 * n + L.cn;
-        const double inx = 1.0 / L.nx, inxy = 1.0 / ((double)L.nx * L.ny);
-        for (int i = threadIdx.x; i < n; i += TILE) x[i] += ol * xc[lds_parent<DIM, T>(L, i, inx, inxy)];
-        __syncthreads();
-        lds_sweep<ND, T>(L, b, x);
-        lds_sweep<ND, T>(L, b, x);
-    }
-    {
-        auto eg = G<T>(Lv[L0].e);
-        const T *x = sh + Lv[L0].n;
-        for (int i = threadIdx.x; i < Lv[L0].n; i += TILE) eg[i] = x[i];
-    }
+    if (P32 && (int)threadIdx.x < n)
+        for (int i = 0; i < n; ++i) P32[(size_t)i * n + threadIdx.x] = (float)P[(size_t)i * n + threadIdx.x];
+}
+
+void launch_mg_pinv(int dim, const MLevel *lev, int l, double *P, float *P32, hipStream_t s)
+{
+    if (dim == 2) hipLaunchKernelGGL(k_mg_pinv<2>, dim3(1), dim3(TILE), 0, s, lev, l, P, P32);
+    else hipLaunchKernelGGL(k_mg_pinv<3>, dim3(1), dim3(TILE), 0, s, lev, l, P, P32);
 }
 
 // ------------------------------------------------------------- launchers
@@ -628,7 +604,7 @@ static const void *mg_fn_t(int which)
     case KI_MG_DOWN0: return (const void *)&k_mg_down0<DIM, T, false>;
     case KI_MG_DOWN0_INIT: return (const void *)&k_mg_down0<DIM, T, true>;
     case KI_MG_DOWN: return (const void *)&k_mg_down<DIM, T>;
-    case KI_MG_LDS: return (const void *)&k_mg_lds<DIM, T>;
+    case KI_MG_EXACT: return (const void *)&k_mg_exact<T>;
     case KI_MG_UP: return (const void *)&k_mg_up<DIM, T>;
     case KI_MG_UP0: return (const void *)&k_mg_up0<DIM, T>;
     }

@@ -24,17 +24,26 @@ enum KKind { K_CG = 0, K_BICGSTAB = 1, K_MGCG = 2 };
 // Multigrid hierarchy of the pressure system (levels 0 = the system itself,
 // 1, 2, ... down to a single cell).  Level l+1 aggregates 2 x 2 (x 2) cells
 // of level l (1 along a direction whose level-l count is odd at its upper
-// end, or is 1); its operator is the Galerkin product P^T A_l P with the
-// aggregation P, again a 5- / 7-point DIA matrix in the same slot order.
-constexpr int MG_LDS_MAX = 2048;   // first level at or below this size runs in LDS
+// end, or is 1); a level-l cell is then an aligned block of up to 2^l
+// level-0 cells per axis.  Its operator is the Galerkin product P^T A_l P
+// with the aggregation P: for the Neumann Laplacian (constant 1/h_a^2 per
+// axis) the coupling of two neighbouring level-l cells across an a-face is
+// 1/h_a^2 times the number of level-0 faces in it, the product of the block
+// extents along the other axes, and the diagonal is the sum of the
+// couplings (rows sum to zero).  The kernels apply it in this closed form.
+constexpr int MG_EXACT_MAX = 256;  // first level at or below this size is solved exactly
 constexpr int MG_MAXLEV = 32;
 struct MLevel {
     int32_t n, nx, ny, nz;        // cells of this level and their counts per axis
     int32_t cn, cnx, cny, cnz;    // the next coarser level (cn = 0 at the coarsest)
     int32_t cpt;                  // coarse cells per tile of the kernels that work on this level
     int32_t ntile;                // tiles of those kernels: ceil(cn / cpt)
-    const void *A, *minv;         // operator and Jacobi inverse (0 where the diagonal is 0)
+    int32_t sc;                   // 2^l: block extent of a level-l cell in level-0 cells
+    int32_t n0[3];                // level-0 cell counts per axis
+    double ih2[3];                // 1 / h_a^2 of level 0
+    const void *minv;             // Jacobi inverse of the diagonal (levels above the exact one)
     void *b, *e;                  // right-hand side and correction (levels >= 1)
+    const void *pinv;             // exact level: dense n x n inverse of A + c 1 1^T (symmetric)
 };
 
 // Per-solve device state.  Iteration kernels read it at their start; only
@@ -123,7 +132,7 @@ struct KJob {
     int32_t role;             // KRole
     int32_t nlev;             // multigrid: levels (0 for the other solves)
     const MLevel *lev;        // multigrid: level table (device), vectors of type T
-    int32_t nglob;            // multigrid: first level handled in LDS (levels 0..nglob-1 by launches)
+    int32_t nglob;            // multigrid: the exactly solved level (levels 0..nglob-1 are smoothed)
     int32_t pad;
 };
 
