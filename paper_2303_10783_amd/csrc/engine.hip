@@ -438,7 +438,7 @@ static int build_stages(Group &g, JobSet &S, int kind, int fp32)
             const sol_handle *h = g.cs[S.case_of[j]];
             const int gi = h->z.nd == 7 ? 1 : 0;
             const int L = h->mg_nglob;
-            for (int t = 0; t < ceil_div(h->mg_h[L].n, 64); ++t) jt[gi].push_back({(int)j, t, L, 0});
+            for (int t = 0; t < ceil_div(h->mg_h[L].n, MG_XROWS); ++t) jt[gi].push_back({(int)j, t, L, 0});
         }
         for (int gi = 0; gi < 2; ++gi) {
             RCHK(upload(g, &exact.tiles_d[gi], jt[gi]));
@@ -1212,8 +1212,10 @@ static int alloc_case(sol_handle *h)
                 L.cn = 0;
                 L.cnx = L.cny = L.cnz = 1;
             }
-            L.cpt = TILE;
-            L.ntile = L.cn ? ceil_div(L.cn, TILE) : 0;
+            // level 0: tiles of the kernels with partial sums (set with the
+            // tuned size by mg_upload); levels >= 1: one thread per child
+            L.cpt = l == 0 ? TILE : TILE >> z.dim;
+            L.ntile = L.cn ? ceil_div(L.cn, L.cpt) : 0;
             L.sc = 1 << l;
             L.n0[0] = z.nx;
             L.n0[1] = z.ny;

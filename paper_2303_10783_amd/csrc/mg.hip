@@ -37,7 +37,7 @@
 //              r_(k+1) = r_k - alpha q; partial ||r_(k+1)||^2; pre-smooth
 //              on level 0 and restrict the residual to level 1
 //   down(l):   pre-smooth level l, restrict to level l+1     (l = 1 .. nglob-1)
-//   exact:     e = P^-1 b on level nglob (dense product, 64 rows per workgroup)
+//   exact:     e = P^-1 b on level nglob (dense product, 16 rows per workgroup)
 //   up(l):     prolong, post-smooth level l                  (l = nglob-1 .. 1)
 //   up0(k):    prolong, post-smooth level 0 -> z_(k+1); partials (r, z),
 //              sum(z), sum(r)
@@ -54,7 +54,6 @@ namespace sol {
 
 constexpr double MG_W = 0.8;       // damped-Jacobi weight
 constexpr double MG_OG = 1.8;      // coarse-correction scaling
-constexpr int MG_XROWS = 64;       // rows of the exact solve per workgroup
 
 // floor(i / d) for 0 <= i < 2^31, 1 <= d, from the double reciprocal inv = 1/d
 __device__ __forceinline__ int fdiv(int i, int d, double inv)
@@ -390,6 +389,29 @@ __global__ __launch_bounds__(TILE) void k_mg_down0(const KJob *__restrict__ jobs
     put_partials<1>(vv, J.part, off, tl.t);
 }
 
+// Levels l >= 1 carry no partial sums, so their kernels take one thread per
+// child: tile t covers the coarse cells t*cpt .. t*cpt+cpt-1 with cpt =
+// TILE / 2^d, thread = (coarse cell, child); a child beyond an odd upper end
+// does nothing.
+template <int DIM>
+__device__ __forceinline__ bool child_of(const MLevel &L, int t, double icx, double icxy, Agg<DIM> &a, int *cx, int *q,
+                                         int &i, int &I)
+{
+    constexpr int NC = 1 << DIM;
+    const int c = threadIdx.x & (NC - 1);
+    I = t * L.cpt + (int)(threadIdx.x >> DIM);
+    if (I >= L.cn) return false;
+    a = agg_of<DIM>(L, I, icx, icxy);
+    cx[0] = c & 1;
+    cx[1] = (c >> 1) & 1;
+    cx[2] = DIM == 3 ? (c >> 2) & 1 : 0;
+    if (cx[0] >= a.w[0] || cx[1] >= a.w[1] || cx[2] >= a.w[2]) return false;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) q[d] = 2 * a.c[d] + cx[d];
+    i = a.i0 + cx[0] + L.nx * cx[1] + L.nx * L.ny * cx[2];
+    return true;
+}
+
 // level l >= 1 (launch level): pre-smooth from zero and restrict
 template <int DIM, class T>
 __global__ __launch_bounds__(TILE) void k_mg_down(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles,
@@ -404,16 +426,19 @@ __global__ __launch_bounds__(TILE) void k_mg_down(const KJob *__restrict__ jobs,
     const T w = (T)MG_W;
     auto mi = G<T>(L.minv);
     auto b = G<T>(L.b);
-    auto bc = G<T>(J.lev[tl.lv + 1].b);
-    const int I0 = tl.t * L.cpt, I1 = min(L.cn, I0 + L.cpt);
-    for (int I = I0 + threadIdx.x; I < I1; I += TILE) {
-        const Agg<DIM> a = agg_of<DIM>(L, I, icx, icxy);
-        T bsum = T(0);
-        for_children<DIM>(L, a, [&](int i, const int *, const int *qc) {
-            const T ax = apply_op<DIM, T>(L, i, qc, [&](int j, int, int) { return w * mi[j] * b[j]; });
-            bsum += b[i] - ax;
-        });
-        bc[I] = bsum;
+    Agg<DIM> a;
+    int cx[3], q[3], i, I;
+    T v = T(0);
+    if (child_of<DIM>(L, tl.t, icx, icxy, a, cx, q, i, I)) {
+        const T ax = apply_op<DIM, T>(L, i, q, [&](int j, int, int) { return w * mi[j] * b[j]; });
+        v = b[i] - ax;
+    }
+    // sum over the 2^d children (consecutive lanes), fixed order
+#pragma unroll
+    for (int o = 1; o < (1 << DIM); o <<= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & ((1 << DIM) - 1)) == 0) {
+        const int Iw = tl.t * L.cpt + (int)(threadIdx.x >> DIM);
+        if (Iw < L.cn) G<T>(J.lev[tl.lv + 1].b)[Iw] = v;
     }
 }
 
@@ -434,17 +459,14 @@ __global__ __launch_bounds__(TILE) void k_mg_up(const KJob *__restrict__ jobs, c
     auto b = G<T>(L.b);
     auto e = G<T>(L.e);
     auto ec = G<T>(J.lev[tl.lv + 1].e);
-    const int I0 = tl.t * L.cpt, I1 = min(L.cn, I0 + L.cpt);
-    for (int I = I0 + threadIdx.x; I < I1; I += TILE) {
-        const Agg<DIM> a = agg_of<DIM>(L, I, icx, icxy);
-        for_children<DIM>(L, a, [&](int i, const int *cx, const int *qc) {
-            const T ax = apply_op<DIM, T>(L, i, qc, [&](int j, int ax_, int dir) {
-                return w * mi[j] * b[j] + og * ec[agg_nb<DIM>(L, a, cx, ax_, dir)];
-            });
-            const T xi = w * mi[i] * b[i] + og * ec[I];
-            e[i] = xi + w * mi[i] * (b[i] - ax);
-        });
-    }
+    Agg<DIM> a;
+    int cx[3], q[3], i, I;
+    if (!child_of<DIM>(L, tl.t, icx, icxy, a, cx, q, i, I)) return;
+    const T ax = apply_op<DIM, T>(L, i, q, [&](int j, int ax_, int dir) {
+        return w * mi[j] * b[j] + og * ec[agg_nb<DIM>(L, a, cx, ax_, dir)];
+    });
+    const T xi = w * mi[i] * b[i] + og * ec[I];
+    e[i] = xi + w * mi[i] * (b[i] - ax);
 }
 
 // level 0: prolong, post-smooth -> z_(k+1); partials (r_(k+1), z_(k+1)),
@@ -487,10 +509,11 @@ __global__ __launch_bounds__(TILE) void k_mg_up0(const KJob *__restrict__ jobs, 
 }
 
 // ------------------------------------------------------------- exact level
-// e = P^-1 b on level nglob: workgroup (job, t) takes rows t*64 .. t*64+63;
-// wave w sums columns j = w, w+4, ... of those rows (P^-1 is symmetric and
-// stored row-major, so the 64 lanes read one contiguous row segment per j),
-// and the four wave sums are added in a fixed order.
+// e = P^-1 b on level nglob: workgroup (job, t) takes rows t*16 .. t*16+15;
+// thread (r, g) = (tid & 15, tid >> 4) sums columns j = g, g+16, ... of row
+// t*16+r with four independent accumulators (P^-1 is symmetric, stored
+// row-major: 16 lanes read 16 consecutive entries of one stored row per j);
+// the 16 group sums of a row are added in a fixed order.
 template <class T>
 __global__ __launch_bounds__(TILE) void k_mg_exact(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles,
                                                    const int *kbase, int koff)
@@ -501,19 +524,29 @@ __global__ __launch_bounds__(TILE) void k_mg_exact(const KJob *__restrict__ jobs
     if (outer_idle(J) || !mg_live(J, k)) return;
     const MLevel &L = J.lev[tl.lv];
     const int n = L.n;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int row = tl.t * MG_XROWS + lane;
+    const int r = threadIdx.x & (MG_XROWS - 1), grp = threadIdx.x / MG_XROWS;
+    constexpr int NG = TILE / MG_XROWS;
+    const int row = tl.t * MG_XROWS + r;
     auto P = G<T>(L.pinv);
     auto b = G<T>(L.b);
-    T acc = T(0);
-    if (row < n)
-        for (int j = wv; j < n; j += TILE / 64) acc += P[(size_t)j * n + row] * b[j];
+    T acc[4] = {T(0), T(0), T(0), T(0)};
+    if (row < n) {
+        int j = grp;
+        for (; j + 3 * NG < n; j += 4 * NG) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc[u] += P[(size_t)(j + u * NG) * n + row] * b[j + u * NG];
+        }
+        for (; j < n; j += NG) acc[0] += P[(size_t)j * n + row] * b[j];
+    }
     __shared__ T part[TILE];
-    part[threadIdx.x] = acc;
+    part[threadIdx.x] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
     __syncthreads();
-    if (wv == 0 && row < n) {
+    if (threadIdx.x < MG_XROWS && row < n) {
+        T s = T(0);
+#pragma unroll
+        for (int g2 = 0; g2 < NG; ++g2) s += part[g2 * MG_XROWS + r];
         auto e = G<T>(L.e);
-        e[row] = (part[lane] + part[64 + lane]) + (part[128 + lane] + part[192 + lane]);
+        e[row] = s;
     }
 }
 

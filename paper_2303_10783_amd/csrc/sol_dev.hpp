@@ -32,6 +32,7 @@ enum KKind { K_CG = 0, K_BICGSTAB = 1, K_MGCG = 2 };
 // extents along the other axes, and the diagonal is the sum of the
 // couplings (rows sum to zero).  The kernels apply it in this closed form.
 constexpr int MG_EXACT_MAX = 256;  // first level at or below this size is solved exactly
+constexpr int MG_XROWS = 16;       // rows of the exact solve per workgroup
 constexpr int MG_MAXLEV = 32;
 struct MLevel {
     int32_t n, nx, ny, nz;        // cells of this level and their counts per axis
