@@ -224,10 +224,14 @@ def main():
     if not args.no_roofline:
         g.set_timing(True)
         st2 = g.step(2)
-        p_its = max(1, st2["iters_total"][3] / 2)
-        per = {"cg": p_its, "mg_pq": p_its, "mg_down0": p_its + 1, "mg_up0": p_its + 1}
-        other = sum(st2["iters_total"][s] for s in (0, 1, 2, 4, 5)) / 2
-        per.update({k: max(1, other) for k in ("bicg_a", "bicg_b", "bicg_c")})
+        it = [x / 2 for x in st2["iters_total"]]
+        # launches per step: one per iteration of a phase (the momentum
+        # systems share launches, and so do solute and energy); the
+        # multigrid start cycle adds one down0 / up0 launch per solve
+        per = {"cg": it[3], "mg_pq": it[3], "mg_down0": it[3] + 1, "mg_up0": it[3] + 1,
+               "asm_mom": 1, "asm_trn": 1, "phase": 1}
+        bicg = max(it[0], it[1], it[2]) + max(it[4], it[5])
+        per.update({k: bicg for k in ("bicg_a", "bicg_b", "bicg_c")})
         best = roofline(g, per)
         g.set_timing(False)
         if best:

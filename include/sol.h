@@ -190,9 +190,9 @@ void sol_batch_destroy(sol_batch *b);
 
 /* Kernel timing for roofline reports.  When enabled, HIP events on the
    handle's stream bracket windows of 16 consecutive CG launches (one event
-   pair per window, starting every 32nd iteration), single launches of the
-   BiCGSTAB and multigrid kernels (every 8th iteration) and every assembly /
-   phase launch;
+   pair per window, starting every 32nd iteration), every single launch of
+   the BiCGSTAB and multigrid kernels (events stamped by the dispatch itself)
+   and every assembly / phase launch;
    a sample counts only if the solve was still iterating at all its
    launches.  sol_get_timing returns
    the number of timed launches, their summed duration and the algorithmic

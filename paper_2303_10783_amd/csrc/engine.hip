@@ -16,6 +16,8 @@
 #include "sol_dev.hpp"
 #include "kernels.hpp"
 
+#include <hip/hip_ext.h>
+
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -746,8 +748,11 @@ static int build_chunk_graph(Group &g, Phase &P, JobSet &S, int fp32)
     return SOL_OK;
 }
 
-// one launch per stencil width of a stage at iteration index koff (kb NULL)
-static int launch_stage(Group &g, const JobSet &S, const Stage &st, int fp32, int koff)
+// one launch per stencil width of a stage at iteration index koff (kb NULL);
+// with events ta / tb (a stage of one stencil width only) the dispatch
+// itself is time-stamped, as a profiler sees it
+static int launch_stage(Group &g, const JobSet &S, const Stage &st, int fp32, int koff, hipEvent_t ta = nullptr,
+                        hipEvent_t tb = nullptr)
 {
     for (int gi = 0; gi < 2; ++gi) {
         if (st.nt[gi] <= 0) continue;
@@ -755,8 +760,11 @@ static int launch_stage(Group &g, const JobSet &S, const Stage &st, int fp32, in
         const JTile *tiles = st.tiles_d[gi];
         const int *kb = nullptr;
         void *args[] = {(void *)&jobs, (void *)&tiles, (void *)&kb, (void *)&koff};
-        HIPCHK(hipLaunchKernel(kiter_fn(st.which, gi ? 7 : 5, fp32), dim3((unsigned)st.nt[gi]), dim3(TILE), args,
-                               st.smem[gi], g.stream));
+        const void *fn = kiter_fn(st.which, gi ? 7 : 5, fp32);
+        if (ta && tb)
+            HIPCHK(hipExtLaunchKernel(fn, dim3((unsigned)st.nt[gi]), dim3(TILE), args, st.smem[gi], g.stream, ta, tb, 0));
+        else
+            HIPCHK(hipLaunchKernel(fn, dim3((unsigned)st.nt[gi]), dim3(TILE), args, st.smem[gi], g.stream));
     }
     return SOL_OK;
 }
@@ -777,7 +785,9 @@ static int start_solves(Group &g, Phase &P, JobSet &S, int fp32, int k, int mode
 
 // Timing: CG iterations are timed in windows of TWIN consecutive launches
 // (one event pair per window; per-launch events would add their own
-// latency), BiCGSTAB kernels one launch at a time, every 8th iteration.
+// latency), BiCGSTAB and multigrid kernels one launch at a time with the
+// events stamped by the dispatch itself (hipExtLaunchKernel), every launch
+// (so the average covers the same launches as a profiler's).
 constexpr int TWIN = 16;
 
 static int enqueue_iters(Group &g, Phase &P, JobSet &S, int fp32, int nits, int &k)
@@ -803,16 +813,12 @@ static int enqueue_iters(Group &g, Phase &P, JobSet &S, int fp32, int nits, int 
                 wend = k + TWIN - 1;
             }
         }
-        const bool sample = tm && P.kind != K_CG && (k % 8 == 0);
+        const bool sample = tm && P.kind != K_CG;
         for (const Stage &st : S.iter) {
             hipEvent_t a = nullptr, b = nullptr;
-            if (sample) { a = take_event(tm); b = take_event(tm); }
-            if (a && b) (void)hipEventRecord(a, g.stream);
-            RCHK(launch_stage(g, S, st, fp32, k));
-            if (a && b) {
-                (void)hipEventRecord(b, g.stream);
-                tm->samples.push_back({st.cls, (int64_t)k, &S, fp32 ? 4 : 8, a, b, 1});
-            }
+            if (sample && (st.nt[0] <= 0 || st.nt[1] <= 0)) { a = take_event(tm); b = take_event(tm); }
+            RCHK(launch_stage(g, S, st, fp32, k, a, b));
+            if (a && b) tm->samples.push_back({st.cls, (int64_t)k, &S, fp32 ? 4 : 8, a, b, 1});
         }
         if (k == wend) {
             (void)hipEventRecord(wb, g.stream);
