@@ -149,7 +149,7 @@ static size_t footprint(const Sizes &z, int precision)
     size_t nf = 0;
     for (int s = 0; s < 3; ++s) nf += std::max(z.nsys[s], 1);
     b += 3 * (al(nf * D));                                       // u,v,w / us / un (per component)
-    b += 9 * al((size_t)z.ncell * D);                           // p T C gl Cl Cs phi Cnew Tstar
+    b += 11 * al((size_t)z.ncell * D);                          // p T C gl Cl Cs phi Cnew Tstar Tprev phiprev
     for (int s = 0; s < NSYS; ++s) {
         const size_t n = std::max(z.nsys[s], 1);
         b += al(z.nd * n * D) + 2 * al(n * D);                   // A, b, minv
@@ -568,9 +568,11 @@ static int group_build(Group &g)
                 J.minv = h->cd.minv[s];
                 const int ws = p == 0 ? s : (p == 1 ? 0 : (s == SC ? 0 : 1));
                 if (p == 0) { J.x = h->cd.us[s]; J.x0 = s == SU ? h->cd.u : (s == SV ? h->cd.v : h->cd.w); }
-                else if (p == 1) { J.x = h->cd.phi; J.x0 = nullptr; }
+                // phi and T*: the initial guess is written into the solution
+                // buffer itself by k_guess before the pressure solve
+                else if (p == 1) { J.x = h->cd.phi; J.x0 = h->cd.phi; }
                 else if (s == SC) { J.x = h->cd.Cnew; J.x0 = h->cd.C; }
-                else { J.x = h->cd.Tstar; J.x0 = h->cd.T; }
+                else { J.x = h->cd.Tstar; J.x0 = h->cd.Tstar; }
                 J.st = g.ks_d + c * NSYS + s;
                 if (!mixed) {
                     J.role = ROLE_PLAIN;
@@ -1023,10 +1025,11 @@ static int group_step(Group &g)
         for (int gi = 0; gi < 2; ++gi) launch_asm_momentum(gi ? 3 : 2, g.cases_d, g.t_mom[gi], g.n_mom[gi], s);
     });
     RCHK(group_solve(g, g.ph[0]));
-    // 2: pressure correction
+    // 2: pressure correction (and the initial guesses of phi and T*)
     for (int gi = 0; gi < 2; ++gi) {
         launch_div_rhs(gi ? 3 : 2, g.cases_d, g.t_cell[gi], g.n_cell[gi], 1, s);
         launch_sub_mean(g.cases_d, g.t_cell[gi], g.n_cell[gi], s);
+        launch_guess(g.cases_d, g.t_cell[gi], g.n_cell[gi], s);
     }
     RCHK(group_solve(g, g.ph[1]));
     // 3: projection
@@ -1166,7 +1169,7 @@ static int alloc_case(sol_handle *h)
     d.u = fu; d.v = fu + nf[0]; d.w = fu + nf[0] + nf[1];
     d.us[0] = fs; d.us[1] = fs + nf[0]; d.us[2] = fs + nf[0] + nf[1];
     d.un[0] = fn; d.un[1] = fn + nf[0]; d.un[2] = fn + nf[0] + nf[1];
-    double **cellf[] = {&d.p, &d.T, &d.C, &d.gl, &d.Cl, &d.Cs, &d.phi, &d.Cnew, &d.Tstar};
+    double **cellf[] = {&d.p, &d.T, &d.C, &d.gl, &d.Cl, &d.Cs, &d.phi, &d.Cnew, &d.Tstar, &d.Tprev, &d.phiprev};
     for (double **pp : cellf) if (!(*pp = dal(z.ncell))) return fail(SOL_ENOMEM, "device allocation failed");
     for (int s = 0; s < NSYS; ++s) {
         const size_t n = std::max(z.nsys[s], 1);
@@ -1267,6 +1270,7 @@ static int alloc_case(sol_handle *h)
     d.red_cnt = (uint32_t *)m.get(256);
     d.step = (int64_t *)m.get(256);
     if (!d.red_part || !d.red_cnt || !d.step) return fail(SOL_ENOMEM, "device allocation failed");
+    d.hist = d.step + 1;                 // same 256-byte block, zeroed with it
     d.ntile_cell = z.ntile_cell;
     return SOL_OK;
 }
@@ -1289,6 +1293,8 @@ static int init_state(sol_handle *h)
     launch_fill(d.phi, 0.0, z.ncell, s);
     launch_fill(d.Cnew, h->al.C_ref, z.ncell, s);
     launch_fill(d.Tstar, h->al.T_ref, z.ncell, s);
+    launch_fill(d.Tprev, 0.0, z.ncell, s);
+    launch_fill(d.phiprev, 0.0, z.ncell, s);
     for (int w = 0; w < 3; ++w)
         for (int k = 0; k < 7; ++k) launch_fill(h->work[w][k], 0.0, z.maxn, s);
     for (int w = 0; w < 3; ++w)
@@ -1407,6 +1413,8 @@ int sol_write_fields(sol_handle *h, uint32_t mask, const double *const *src)
         double *d = field_ptr(h, bit, &n);
         if (n) HIPCHK(hipMemcpyAsync(d, src[bit], n * sizeof(double), hipMemcpyHostToDevice, h->stream));
     }
+    // the solution history no longer belongs to these fields
+    HIPCHK(hipMemcpyAsync(h->cd.hist, h->cd.step, sizeof(int64_t), hipMemcpyDeviceToDevice, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
     return SOL_OK;
 }
@@ -1533,6 +1541,8 @@ int sol_step(sol_handle *h, int32_t nsteps, sol_step_stats *stats)
     for (int k = 0; k < nsteps; ++k) {
         int rc = group_step(g);
         if (rc != SOL_OK) {
+            // a failed step leaves partial solutions in the step buffers
+            launch_hist_reset(g.cases_d, (int)g.cs.size(), g.stream);
             (void)hipStreamSynchronize(h->stream);
             return rc;
         }
@@ -1732,7 +1742,11 @@ int sol_batch_step(sol_batch *b, const int32_t *nsteps, sol_step_stats *stats)
         b->g->timer = nullptr;
         b->g->use_graph = b->cs[0]->opt_graph;
         int rc = group_step(*b->g);
-        if (rc != SOL_OK) { (void)hipStreamSynchronize(b->cs[0]->stream); return rc; }
+        if (rc != SOL_OK) {
+            launch_hist_reset(b->g->cases_d, (int)b->g->cs.size(), b->g->stream);
+            (void)hipStreamSynchronize(b->cs[0]->stream);
+            return rc;
+        }
         for (size_t a = 0; a < act.size(); ++a)
             for (int s = 0; s < NSYS; ++s) tot[(size_t)act[a] * NSYS + s] += b->cs[act[a]]->last_iters[s];
     }

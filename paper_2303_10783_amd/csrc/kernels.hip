@@ -454,6 +454,34 @@ __global__ __launch_bounds__(TILE) void k_phase_commit(const CaseDev *__restrict
     put_partials<4>(v, c.red_part, off, tl.t);
 }
 
+// Initial guesses of the pressure-correction and energy solves (the paper
+// fixes none; the converged solution does not depend on it): linear
+// extrapolation in time from the previous two solutions of the same case,
+// 2 x^n - x^(n-1), once two steps have been solved since the history was
+// last reset (creation, written fields, a failed step); before that phi = 0
+// and T* = T^n.  The guess is written into the solution buffer, which the
+// solve then takes as its initial guess; the history shifts by one.
+__global__ __launch_bounds__(TILE) void k_guess(const CaseDev *__restrict__ cases, const Tile *__restrict__ tiles)
+{
+    const Tile tl = tiles[xcd_tile(blockIdx.x, gridDim.x)];
+    const CaseDev &c = cases[tl.c];
+    const int i = tl.t * TILE + threadIdx.x;
+    if (i >= c.ph.ncell) return;
+    const bool ext = *c.step - *c.hist >= 2;
+    const double ts = c.Tstar[i], ph = c.phi[i];
+    c.Tstar[i] = ext ? 2.0 * ts - c.Tprev[i] : c.T[i];
+    c.phi[i] = ext ? 2.0 * ph - c.phiprev[i] : 0.0;
+    c.Tprev[i] = ts;
+    c.phiprev[i] = ph;
+}
+
+// history reset of every case of a group (hist = step)
+__global__ void k_hist_reset(const CaseDev *__restrict__ cases, int ncase)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < ncase) *cases[c].hist = *cases[c].step;
+}
+
 // per-case totals of the committed step (one workgroup per case); advances
 // the step counter after every workgroup of k_phase_commit has read it
 __global__ __launch_bounds__(TILE) void k_case_stats(const CaseDev *__restrict__ cases, const int32_t *__restrict__ cidx)
@@ -1200,6 +1228,16 @@ void launch_ir_close(const KJob *j, int njobs, hipStream_t s)
 {
     if (njobs <= 0) return;
     hipLaunchKernelGGL(k_ir_close, dim3(ceil_div(njobs, 64)), dim3(64), 0, s, j, njobs);
+}
+void launch_guess(const CaseDev *c, const Tile *t, int nt, hipStream_t s)
+{
+    if (nt <= 0) return;
+    hipLaunchKernelGGL(k_guess, GRID(nt), 0, s, c, t);
+}
+void launch_hist_reset(const CaseDev *c, int ncase, hipStream_t s)
+{
+    if (ncase <= 0) return;
+    hipLaunchKernelGGL(k_hist_reset, dim3(ceil_div(ncase, 64)), dim3(64), 0, s, c, ncase);
 }
 void launch_case_stats(const CaseDev *c, const int32_t *cidx, int ncase, hipStream_t s)
 {

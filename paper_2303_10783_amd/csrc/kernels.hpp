@@ -40,6 +40,9 @@ void launch_ir_decide(const KJob *j, int njobs, int mode, int max_outer, hipStre
 void launch_ir_update(int nd, const KJob *j, const JTile *t, int nt, hipStream_t s);
 void launch_ir_close(const KJob *j, int njobs, hipStream_t s);
 void launch_case_stats(const CaseDev *c, const int32_t *cidx, int ncase, hipStream_t s);
+// initial guesses of the pressure-correction and energy solves; history reset
+void launch_guess(const CaseDev *c, const Tile *t, int nt, hipStream_t s);
+void launch_hist_reset(const CaseDev *c, int ncase, hipStream_t s);
 
 void launch_csr(int dim, const CaseDev *cd, int s, int n, int32_t *cnt, int32_t *row_ptr, int32_t *col,
                 double *val, int build_pattern, hipStream_t st);

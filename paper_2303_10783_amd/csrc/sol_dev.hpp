@@ -101,6 +101,10 @@ struct CaseDev {
     // mixed precision copies (FP32) of matrices and inverse diagonals
     float *A32[NSYS], *minv32[NSYS];
     int64_t *step;            // completed steps (device counter)
+    int64_t *hist;            // step at which the solution history below was last reset
+    // previous solutions of the energy (T*) and pressure-correction (phi)
+    // solves: the initial guess of a solve is 2 x^n - x^(n-1) once two exist
+    double *Tprev, *phiprev;
     KState *ks;               // [NSYS] solver states of this case
     double *red;              // [16] per-case reduction results
     double *red_part;         // [ntile_cell * 4] reduction partials
