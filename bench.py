@@ -37,10 +37,13 @@ METRIC = "cell-updates/s per full time step (1 GPU), mixed vs FP64; p50/p99 case
 HBM_PEAK_GBS = 8000.0
 
 
-def roofline(g, launches_per_step):
-    """Dominant kernel class by estimated time per step (average sampled
-    launch duration x launches per step).  The multigrid coarse-level class
-    spans several kernels and carries no byte count; it is not a candidate."""
+def roofline(g, nsteps, cg_launches_per_step):
+    """Dominant kernel class by GPU time per step.  Every launch of a class is
+    timed (dispatch-stamped events), so its time per step is the timed total
+    over the timing steps; the single-kernel Jacobi CG is timed in windows of
+    16 launches, its time per step is the window average x iterations.  The
+    multigrid coarse-level class spans several kernels and carries no byte
+    count; it is not a candidate."""
     best = None
     for cls in ("cg", "bicg_a", "bicg_b", "bicg_c", "asm_mom", "asm_trn", "phase", "mg_pq", "mg_down0", "mg_up0"):
         t = g.timing(cls)
@@ -50,9 +53,7 @@ def roofline(g, launches_per_step):
         t["bytes_per_launch"] = t["bytes"] / t["launches"]
         t["gbs"] = t["bytes"] / (t["ms"] * 1e-3) / 1e9
         t["cls"] = cls
-        # estimated share of the step: avg duration x launches per step
-        per_step = launches_per_step.get(cls, 1.0)
-        t["est_ms_per_step"] = t["avg_ms"] * per_step
+        t["est_ms_per_step"] = t["avg_ms"] * cg_launches_per_step if cls == "cg" else t["ms"] / nsteps
         if best is None or t["est_ms_per_step"] > best["est_ms_per_step"]:
             best = t
     return best
@@ -224,15 +225,7 @@ def main():
     if not args.no_roofline:
         g.set_timing(True)
         st2 = g.step(2)
-        it = [x / 2 for x in st2["iters_total"]]
-        # launches per step: one per iteration of a phase (the momentum
-        # systems share launches, and so do solute and energy); the
-        # multigrid start cycle adds one down0 / up0 launch per solve
-        per = {"cg": it[3], "mg_pq": it[3], "mg_down0": it[3] + 1, "mg_up0": it[3] + 1,
-               "asm_mom": 1, "asm_trn": 1, "phase": 1}
-        bicg = max(it[0], it[1], it[2]) + max(it[4], it[5])
-        per.update({k: bicg for k in ("bicg_a", "bicg_b", "bicg_c")})
-        best = roofline(g, per)
+        best = roofline(g, 2, st2["iters_total"][3] / 2)
         g.set_timing(False)
         if best:
             tr = counter_traffic(args.workload, best["cls"], args.precond) if args.precision == "fp64" else None

@@ -192,13 +192,13 @@ void sol_batch_destroy(sol_batch *b);
    handle's stream bracket windows of 16 consecutive CG launches (one event
    pair per window, starting every 32nd iteration), every single launch of
    the BiCGSTAB and multigrid kernels (events stamped by the dispatch itself)
-   and every assembly / phase launch;
-   a sample counts only if the solve was still iterating at all its
-   launches.  sol_get_timing returns
-   the number of timed launches, their summed duration and the algorithmic
-   bytes those launches move (matrix values + vectors read and written once,
-   per row of the systems that were iterating; FP32 values count 4 bytes).
-   Enabling or disabling resets the counters. */
+   and every assembly / phase launch.  Every launch counts, also one queued
+   after its solves converged (it exits at once: time, no bytes); samples of
+   a solve that restarted are dropped.  sol_get_timing returns the number of
+   timed launches, their summed duration and the algorithmic bytes those
+   launches move (matrix values + vectors read and written once, per row of
+   the systems that were iterating; FP32 values count 4 bytes).  Enabling or
+   disabling resets the counters. */
 #define SOL_KCLASS_CG        0   /* CG iteration (one kernel): p, s, x, r, w = A M r, (r,Mr), (w,Mr) */
 #define SOL_KCLASS_BICG_A    1   /* BiCGSTAB: p, v = A M p, (rh,v)              */
 #define SOL_KCLASS_BICG_B    2   /* BiCGSTAB: t = A M s, (t,s), (t,t)           */

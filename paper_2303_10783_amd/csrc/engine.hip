@@ -654,8 +654,11 @@ static hipEvent_t take_event(sol_handle *h)
 }
 
 // Turn the pending samples into durations (after a synchronising poll whose
-// states are ks); a Krylov sample counts only for solves still iterating at
-// that launch (iteration index below the solve's final count, no restart).
+// states are ks).  Every launch counts; the bytes of a Krylov launch are
+// those of the solves still iterating at it (iteration index below the
+// solve's final count), so a launch queued after convergence, which exits at
+// once, adds its time and no bytes, as a profiler would see it.  Samples
+// of solves that restarted are dropped (their iteration indices are shifted).
 static void collect_samples(Group &g, const KState *ks)
 {
     sol_handle *h = g.timer;
@@ -677,7 +680,6 @@ static void collect_samples(Group &g, const KState *ks)
                     dim = g.cs[s.set->case_of[j]]->z.dim;
                 }
             }
-            if (rows == 0.0) valid = false;
             bytes = rows * row_bytes(s.cls, nd, dim, s.tsize) * s.count;
         } else {
             for (auto *c : g.cs) {

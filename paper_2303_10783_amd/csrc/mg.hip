@@ -129,6 +129,26 @@ __device__ __forceinline__ void for_children(const MLevel &L, const Agg<DIM> &a,
     }
 }
 
+// visit the four child slots of layer cz of aggregate a (2D: the only
+// layer): f(c, valid, i, cx, q) with c = cx + 2 cy; a slot beyond an odd
+// upper end is mapped onto the layer's first child of the aggregate (valid =
+// false) so that every access stays inside the level.  The kernels load and
+// compute a whole layer before storing it: the loads of four children are
+// then issued together, with registers for four children only.
+template <int DIM, class F>
+__device__ __forceinline__ void for_layer(const MLevel &L, const Agg<DIM> &a, int cz, F f)
+{
+    const int sxy = L.nx * L.ny;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        int cx[3] = {c & 1, (c >> 1) & 1, cz};
+        const bool valid = cx[0] < a.w[0] && cx[1] < a.w[1] && cx[2] < a.w[2];
+        if (!valid) cx[0] = cx[1] = cx[2] = 0;
+        const int q[3] = {2 * a.c[0] + cx[0], 2 * a.c[1] + cx[1], 2 * a.c[2] + cx[2]};
+        f(c, valid, a.i0 + cx[0] + L.nx * cx[1] + sxy * cx[2], cx, q);
+    }
+}
+
 // a solve whose multigrid stages run at iteration index k: RUNNING, or its
 // (re)start whose first iteration is k + 1 (the start cycle runs at k0 - 1)
 __device__ __forceinline__ bool mg_live(const KJob &J, int k)
@@ -177,7 +197,9 @@ __device__ __forceinline__ T op_diag(const MLevel &L, const int *q)
 }
 
 // (A f)_i = sum over in-domain neighbours j of c_a (f_i - f_j), with
-// f(j, axis, direction) (direction 0: the cell itself)
+// f(j, axis, direction) (direction 0: the cell itself).  Branch-free: a
+// missing neighbour is replaced by the cell itself with a zero coupling, so
+// every value is loaded unconditionally and the loads can be issued together.
 template <int DIM, class T, class F>
 __device__ __forceinline__ T apply_op(const MLevel &L, int i, const int *q, F f)
 {
@@ -189,8 +211,10 @@ __device__ __forceinline__ T apply_op(const MLevel &L, int i, const int *q, F f)
     T acc = T(0);
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
-        if (q[a] > 0) acc += co[a] * (fi - f(i - st[a], a, -1));
-        if (q[a] + 1 < nn[a]) acc += co[a] * (fi - f(i + st[a], a, 1));
+        const bool lo = q[a] > 0, hi = q[a] + 1 < nn[a];
+        const T vlo = f(lo ? i - st[a] : i, a, lo ? -1 : 0);
+        const T vhi = f(hi ? i + st[a] : i, a, hi ? 1 : 0);
+        acc += (lo ? co[a] : T(0)) * (fi - vlo) + (hi ? co[a] : T(0)) * (fi - vhi);
     }
     return acc;
 }
@@ -314,13 +338,25 @@ __global__ __launch_bounds__(TILE) void k_mg_pq(const KJob *__restrict__ jobs, c
     const int I0 = tl.t * L.cpt, I1 = min(L.cn, I0 + L.cpt);
     for (int I = I0 + threadIdx.x; I < I1; I += TILE) {
         const Agg<DIM> a = agg_of<DIM>(L, I, icx, icxy);
-        for_children<DIM>(L, a, [&](int i, const int *, const int *qc) {
-            const T qi = apply_op<DIM, T>(L, i, qc, [&](int j, int, int) { return (z[j] - tz) + tb * po[j]; });
-            const T pi = (z[i] - tz) + tb * po[i];
-            pn[i] = pi;
-            q[i] = qi;
-            v += (double)pi * qi;
-        });
+#pragma unroll
+        for (int cz = 0; cz < (DIM == 3 ? 2 : 1); ++cz) {
+            T pv[4], qv[4];
+            int iv[4];
+            bool ok[4];
+            for_layer<DIM>(L, a, cz, [&](int c, bool valid, int i, const int *, const int *qc) {
+                qv[c] = apply_op<DIM, T>(L, i, qc, [&](int j, int, int) { return (z[j] - tz) + tb * po[j]; });
+                pv[c] = (z[i] - tz) + tb * po[i];
+                iv[c] = i;
+                ok[c] = valid;
+            });
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                if (ok[c]) {
+                    pn[iv[c]] = pv[c];
+                    q[iv[c]] = qv[c];
+                    v += (double)pv[c] * qv[c];
+                }
+        }
     }
     double vv[1] = {v};
     const int off[1] = {poff(J, pk, PS_TS)};
@@ -366,22 +402,34 @@ __global__ __launch_bounds__(TILE) void k_mg_down0(const KJob *__restrict__ jobs
     for (int I = I0 + threadIdx.x; I < I1; I += TILE) {
         const Agg<DIM> a = agg_of<DIM>(L, I, icx, icxy);
         T bsum = T(0);
-        for_children<DIM>(L, a, [&](int i, const int *, const int *qc) {
-            const T ax = apply_op<DIM, T>(L, i, qc, [&](int j, int, int) {
-                const T rj = INIT ? rn[j] : rc[j] - ta * q[j];
-                return w * mi[j] * rj;
+#pragma unroll
+        for (int cz = 0; cz < (DIM == 3 ? 2 : 1); ++cz) {
+            T rv[4], xv[4], sv[4];
+            int iv[4];
+            bool ok[4];
+            for_layer<DIM>(L, a, cz, [&](int c, bool valid, int i, const int *, const int *qc) {
+                const T ax = apply_op<DIM, T>(L, i, qc, [&](int j, int, int) {
+                    const T rj = INIT ? rn[j] : rc[j] - ta * q[j];
+                    return w * mi[j] * rj;
+                });
+                const T ri = INIT ? rn[i] : rc[i] - ta * q[i];
+                rv[c] = ri;
+                if (!INIT) xv[c] = x[i] + ta * p[i];
+                sv[c] = ri - ax;
+                iv[c] = i;
+                ok[c] = valid;
             });
-            T ri;
-            if (INIT) {
-                ri = rn[i];
-            } else {
-                ri = rc[i] - ta * q[i];
-                rn[i] = ri;
-                x[i] = x[i] + ta * p[i];
-            }
-            rr += (double)ri * ri;
-            bsum += ri - ax;
-        });
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                if (ok[c]) {
+                    if (!INIT) {
+                        rn[iv[c]] = rv[c];
+                        x[iv[c]] = xv[c];
+                    }
+                    rr += (double)rv[c] * rv[c];
+                    bsum += sv[c];
+                }
+        }
         bc[I] = bsum;
     }
     double vv[1] = {rr};
@@ -491,18 +539,31 @@ __global__ __launch_bounds__(TILE) void k_mg_up0(const KJob *__restrict__ jobs, 
     const int I0 = tl.t * L.cpt, I1 = min(L.cn, I0 + L.cpt);
     for (int I = I0 + threadIdx.x; I < I1; I += TILE) {
         const Agg<DIM> a = agg_of<DIM>(L, I, icx, icxy);
-        for_children<DIM>(L, a, [&](int i, const int *cx, const int *qc) {
-            const T ax = apply_op<DIM, T>(L, i, qc, [&](int j, int ax_, int dir) {
-                return w * mi[j] * r[j] + og * ec[agg_nb<DIM>(L, a, cx, ax_, dir)];
+#pragma unroll
+        for (int cz = 0; cz < (DIM == 3 ? 2 : 1); ++cz) {
+            T zv[4], rv[4];
+            int iv[4];
+            bool ok[4];
+            for_layer<DIM>(L, a, cz, [&](int c, bool valid, int i, const int *cx, const int *qc) {
+                const T ax = apply_op<DIM, T>(L, i, qc, [&](int j, int ax_, int dir) {
+                    return w * mi[j] * r[j] + og * ec[agg_nb<DIM>(L, a, cx, ax_, dir)];
+                });
+                const T ri = r[i];
+                const T xi = w * mi[i] * ri + og * ec[I];
+                zv[c] = xi + w * mi[i] * (ri - ax);
+                rv[c] = ri;
+                iv[c] = i;
+                ok[c] = valid;
             });
-            const T ri = r[i];
-            const T xi = w * mi[i] * ri + og * ec[I];
-            const T zi = xi + w * mi[i] * (ri - ax);
-            z[i] = zi;
-            vv[0] += (double)ri * zi;
-            vv[1] += (double)zi;
-            vv[2] += (double)ri;
-        });
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                if (ok[c]) {
+                    z[iv[c]] = zv[c];
+                    vv[0] += (double)rv[c] * zv[c];
+                    vv[1] += (double)zv[c];
+                    vv[2] += (double)rv[c];
+                }
+        }
     }
     const int off[3] = {poff(J, pn1, PS_RHO), poff(J, pn1, PS_Q), poff(J, pn1, PS_TT)};
     put_partials<3>(vv, J.part, off, tl.t);
