@@ -605,13 +605,29 @@ __global__ __launch_bounds__(TILE) void k_bicg_a(const KJob *__restrict__ jobs, 
     auto pn = G<T>(pk ? J.p0 : J.p1), vn = G<T>(pk ? J.v0 : J.v1);
     double v[1] = {0.0};
     const int i0 = tl.t * J.rpt, i1 = min(n, i0 + J.rpt);
-    for (int i = i0 + threadIdx.x; i < i1; i += TILE) {
-        const T pi = r[i] + tb * (po[i] - tw * vo[i]);
-        const T vi = kstencil<ND, T>(A, n, i, J.sx, J.sxy,
-                                     [&](int j) { return mi[j] * (r[j] + tb * (po[j] - tw * vo[j])); });
-        pn[i] = pi;
-        vn[i] = vi;
-        v[0] += (double)rh[i] * vi;
+    // two rows per pass, both loaded and computed before either is stored
+    // (the compiler cannot move loads above stores it cannot prove disjoint)
+    for (int i = i0 + threadIdx.x; i < i1; i += 2 * TILE) {
+        const bool two = i + TILE < i1;
+        const int i2 = two ? i + TILE : i;
+        T pv[2], vv[2];
+        const int iv[2] = {i, i2};
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int ii = iv[u];
+            pv[u] = r[ii] + tb * (po[ii] - tw * vo[ii]);
+            vv[u] = kstencil<ND, T>(A, n, ii, J.sx, J.sxy,
+                                    [&](int j) { return mi[j] * (r[j] + tb * (po[j] - tw * vo[j])); });
+        }
+        const T rh0 = rh[i], rh1 = rh[i2];
+        pn[i] = pv[0];
+        vn[i] = vv[0];
+        v[0] += (double)rh0 * vv[0];
+        if (two) {
+            pn[i2] = pv[1];
+            vn[i2] = vv[1];
+            v[0] += (double)rh1 * vv[1];
+        }
     }
     const int off[1] = {poff(J, pk, PS_Q)};
     put_partials<1>(v, J.part, off, tl.t);
@@ -643,12 +659,25 @@ __global__ __launch_bounds__(TILE) void k_bicg_b(const KJob *__restrict__ jobs, 
     auto t = G<T>(J.t);
     double v[2] = {0.0, 0.0};
     const int i0 = tl.t * J.rpt, i1 = min(n, i0 + J.rpt);
-    for (int i = i0 + threadIdx.x; i < i1; i += TILE) {
-        const T si = r[i] - alpha * vn[i];
-        const T ti = kstencil<ND, T>(A, n, i, J.sx, J.sxy, [&](int j) { return mi[j] * (r[j] - alpha * vn[j]); });
-        t[i] = ti;
-        v[0] += (double)ti * si;
-        v[1] += (double)ti * ti;
+    for (int i = i0 + threadIdx.x; i < i1; i += 2 * TILE) {
+        const bool two = i + TILE < i1;
+        const int i2 = two ? i + TILE : i;
+        T sv[2], tv[2];
+        const int iv[2] = {i, i2};
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int ii = iv[u];
+            sv[u] = r[ii] - alpha * vn[ii];
+            tv[u] = kstencil<ND, T>(A, n, ii, J.sx, J.sxy, [&](int j) { return mi[j] * (r[j] - alpha * vn[j]); });
+        }
+        t[i] = tv[0];
+        v[0] += (double)tv[0] * sv[0];
+        v[1] += (double)tv[0] * tv[0];
+        if (two) {
+            t[i2] = tv[1];
+            v[0] += (double)tv[1] * sv[1];
+            v[1] += (double)tv[1] * tv[1];
+        }
     }
     const int off[2] = {poff(J, pk, PS_TS), poff(J, pk, PS_TT)};
     put_partials<2>(v, J.part, off, tl.t);
@@ -676,13 +705,29 @@ __global__ __launch_bounds__(TILE) void k_bicg_c(const KJob *__restrict__ jobs, 
     auto x = G<T>(J.x), r = G<T>(J.r);
     double v[2] = {0.0, 0.0};
     const int i0 = tl.t * J.rpt, i1 = min(J.n, i0 + J.rpt);
-    for (int i = i0 + threadIdx.x; i < i1; i += TILE) {
-        const T si = r[i] - alpha * vn[i];
-        x[i] = x[i] + mi[i] * (alpha * pn[i] + omega * si);
-        const T ri = si - omega * t[i];
-        r[i] = ri;
-        v[0] += (double)rh[i] * ri;
-        v[1] += (double)ri * ri;
+    for (int i = i0 + threadIdx.x; i < i1; i += 2 * TILE) {
+        const bool two = i + TILE < i1;
+        const int i2 = two ? i + TILE : i;
+        T xv[2], rv[2], hv[2];
+        const int iv[2] = {i, i2};
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int ii = iv[u];
+            const T si = r[ii] - alpha * vn[ii];
+            xv[u] = x[ii] + mi[ii] * (alpha * pn[ii] + omega * si);
+            rv[u] = si - omega * t[ii];
+            hv[u] = rh[ii];
+        }
+        x[i] = xv[0];
+        r[i] = rv[0];
+        v[0] += (double)hv[0] * rv[0];
+        v[1] += (double)rv[0] * rv[0];
+        if (two) {
+            x[i2] = xv[1];
+            r[i2] = rv[1];
+            v[0] += (double)hv[1] * rv[1];
+            v[1] += (double)rv[1] * rv[1];
+        }
     }
     const int off[2] = {poff(J, pk, PS_RHO), poff(J, pk, PS_RR)};
     put_partials<2>(v, J.part, off, tl.t);
