@@ -15,11 +15,33 @@ __device__ __forceinline__ int xcd_tile(int b, int nb)
     return x * q + min(x, r) + k;
 }
 
+// v from the lane selected by DPP control CTRL (rows in ROWMASK; lanes
+// without a source and rows outside the mask get 0)
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_get(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROWMASK, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWMASK, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// sum over the 64 lanes, returned in every lane.  Within each row of 16
+// lanes, shifts by 1, 2, 4, 8 with zero fill leave the row total in lane 15;
+// row broadcasts then add row 0 into row 1, row 2 into row 3, and lane 31
+// into row 3: lane 63 holds the total.  A fixed tree, so every wave that sums
+// the same values gets the same bits; all on the VALU (DPP), no LDS traffic.
 __device__ __forceinline__ double wave_sum(double v)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
-    return v;
+    v += dpp_get<0x111, 0xf>(v);   // row_shr:1
+    v += dpp_get<0x112, 0xf>(v);   // row_shr:2
+    v += dpp_get<0x114, 0xf>(v);   // row_shr:4
+    v += dpp_get<0x118, 0xf>(v);   // row_shr:8
+    v += dpp_get<0x142, 0xa>(v);   // row_bcast:15 into rows 1, 3
+    v += dpp_get<0x143, 0xc>(v);   // row_bcast:31 into rows 2, 3
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, 63), hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
 // sum of K values over the 256 threads; result valid in thread 0
