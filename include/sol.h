@@ -134,6 +134,11 @@ typedef struct {
     double div_star;             /* ||D u*||_2                                     */
     double div_new;              /* ||D u^{n+1}||_2                                */
     int64_t step;                /* completed steps of the handle                  */
+    int64_t redone;              /* steps of the handle run twice: the momentum and
+                                    pressure solves hand over before their true-
+                                    residual check; when a check asks for a restart
+                                    the step is discarded before its commit and run
+                                    again with every check in order (cumulative)   */
 } sol_step_stats;
 
 /* Create a case: validates every argument (e.g. nx < 2, dt <= 0,

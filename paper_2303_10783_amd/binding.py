@@ -74,13 +74,14 @@ class sol_step_stats(C.Structure):
     _fields_ = [("iters", C.c_int32 * 6), ("iters_total", C.c_int64 * 6),
                 ("rel_resid", C.c_double * 6), ("sum_resid", C.c_double * 6),
                 ("sum_C", C.c_double), ("sum_H", C.c_double), ("wall_flux", C.c_double),
-                ("div_star", C.c_double), ("div_new", C.c_double), ("step", C.c_int64)]
+                ("div_star", C.c_double), ("div_new", C.c_double), ("step", C.c_int64),
+                ("redone", C.c_int64)]
 
     def as_dict(self):
         return dict(iters=list(self.iters), iters_total=list(self.iters_total),
                     rel_resid=list(self.rel_resid), sum_resid=list(self.sum_resid),
                     sum_C=self.sum_C, sum_H=self.sum_H, wall_flux=self.wall_flux,
-                    div_star=self.div_star, div_new=self.div_new, step=self.step)
+                    div_star=self.div_star, div_new=self.div_new, step=self.step, redone=self.redone)
 
 
 _lib = None

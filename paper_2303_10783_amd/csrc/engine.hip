@@ -149,7 +149,7 @@ static size_t footprint(const Sizes &z, int precision)
     size_t nf = 0;
     for (int s = 0; s < 3; ++s) nf += std::max(z.nsys[s], 1);
     b += 3 * (al(nf * D));                                       // u,v,w / us / un (per component)
-    b += 11 * al((size_t)z.ncell * D);                          // p T C gl Cl Cs phi Cnew Tstar Tprev phiprev
+    b += 13 * al((size_t)z.ncell * D);                          // p T C gl Cl Cs phi Cnew Tstar, 4 history
     for (int s = 0; s < NSYS; ++s) {
         const size_t n = std::max(z.nsys[s], 1);
         b += al(z.nd * n * D) + 2 * al(n * D);                   // A, b, minv
@@ -168,6 +168,7 @@ static size_t footprint(const Sizes &z, int precision)
         }
         const size_t nx2 = (size_t)m.n[m.nglob] * m.n[m.nglob];  // dense inverse of the exact level
         b += al(nx2 * D) + (precision ? al(nx2 * F) : 0);
+        b += al((4 * (size_t)m.n[m.nglob] + 1) * D);            // its elimination scratch
         b += al(sizeof(MLevel) * MG_MAXLEV) * (precision ? 2 : 1);
     }
     return b;
@@ -260,6 +261,8 @@ struct sol_handle {
     bool timing = false;
     bool opt_graph = false;
     int precond = SOL_PRECOND_MG;
+    double *mg_pwork = nullptr;           // scratch of the exact-level inverse (set-up)
+    int64_t redone = 0;                   // steps run a second time (speculative check failed)
     // pressure multigrid hierarchy (FP64 arrays; FP32 copies for mixed precision)
     int mg_nlev = 0, mg_nglob = 0;
     MLevel mg_h[MG_MAXLEV] = {};
@@ -303,6 +306,8 @@ struct Phase {
     JobSet inner;                        // mixed precision: FP32 inner solves
     int pred = 1, pred_inner = 1;
     int64_t launched = 0;
+    bool pending = false;                // solved speculatively, verdict not read yet
+    bool synced = false;                 // the last solve ended with a state copy into slot 0
 };
 
 struct Group {
@@ -868,9 +873,11 @@ static bool any_running(const Group &g, const JobSet &S, int slot, const JobSet 
 
 // Queue iteration chunks of the solves in S until none is RUNNING.  While
 // the host inspects chunk i the device runs chunk i+1.  Returns the slot
-// holding the newest states.
+// holding the newest states; with wait_last false it returns as soon as the
+// states of chunk i show no solve RUNNING, chunk i+1 (no-ops by then) and
+// its state copy still queued, and the slot is that of chunk i.
 static int iterate(Group &g, Phase &P, JobSet &S, int fp32, int pred, int &k, const JobSet *gate,
-                   int gslot, int *out_slot)
+                   int gslot, int *out_slot, bool wait_last = true)
 {
     int slot = gslot ^ 1;
     const int first = std::max(1, pred - pred / 8);
@@ -882,6 +889,10 @@ static int iterate(Group &g, Phase &P, JobSet &S, int fp32, int pred, int &k, co
         RCHK(poll_enqueue(g, slot ^ 1));
         RCHK(poll_wait(g, slot));
         if (!any_running(g, S, slot, gate, gslot)) {
+            if (!wait_last) {
+                *out_slot = slot;
+                return SOL_OK;
+            }
             RCHK(poll_wait(g, slot ^ 1));
             *out_slot = slot ^ 1;
             return SOL_OK;
@@ -899,19 +910,42 @@ static void record_iters(Group &g, const JobSet &S, int slot, int *mx)
     }
 }
 
-// plain FP64 solves
-static int solve_plain(Group &g, Phase &P)
+// plain FP64 solves.  speculate: once every solve has converged by its
+// recurrence, the check of the true residual (k_kfinish, k_kdecide) is
+// queued and the call returns without waiting for its verdict; the caller
+// reads the verdict (K_DONE, or K_RESTART) from a later state copy before
+// anything is committed.
+static bool all_converged(const Group &g, const JobSet &S, int slot)
+{
+    for (int idx : S.st_index) {
+        const int st = g.ks_h[slot][idx].status;
+        if (st != K_CONVERGED && st != K_ZERO) return false;
+    }
+    return true;
+}
+
+static int solve_plain(Group &g, Phase &P, bool speculate)
 {
     JobSet &S = P.main;
     int k = 0;                       // host iteration index of the next launch
     P.launched = 0;
+    P.pending = false;
     RCHK(start_solves(g, P, S, 0, k, 0));
     int rc = SOL_OK;
     for (int round = 0; round < 64; ++round) {
         int slot;
-        RCHK(iterate(g, P, S, 0, round == 0 ? P.pred : std::max(2, P.pred / 8), k, nullptr, 1, &slot));
+        const bool fast = speculate && round == 0;
+        RCHK(iterate(g, P, S, 0, round == 0 ? P.pred : std::max(2, P.pred / 8), k, nullptr, 1, &slot, !fast));
         for (int gi = 0; gi < 2; ++gi) launch_kfinish(gi ? 7 : 5, S.jobs_d, S.tiles_d[gi], S.nt[gi], g.stream);
         launch_kdecide(S.jobs_d, (int)S.jobs.size(), g.stream);
+        if (fast && all_converged(g, S, slot)) {
+            int mx = 1;
+            record_iters(g, S, slot, &mx);
+            P.pred = mx;
+            P.pending = true;
+            HIPCHK(hipGetLastError());
+            return SOL_OK;
+        }
         RCHK(poll_enqueue(g, 0));
         RCHK(poll_wait(g, 0));
         HIPCHK(hipGetLastError());
@@ -921,9 +955,9 @@ static int solve_plain(Group &g, Phase &P)
                 const KState &ks = g.ks_h[0][S.st_index[j]];
                 if (ks.status == K_FAILED) {
                     rc = fail(SOL_ENOCONV, "linear solve did not converge (case %d, system %d, %d iterations, "
-                                           "%d restarts, ||r||/||b|| = %.3e)",
+                                           "%d restarts, ||r||/||b|| = %.3e by the recurrence, %.3e true)",
                               S.case_of[j], S.sys_of[j], ks.it, ks.restarts,
-                              ks.bb > 0 ? std::sqrt(ks.rr / ks.bb) : 0.0);
+                              ks.bb > 0 ? std::sqrt(ks.rr / ks.bb) : 0.0, ks.bb > 0 ? std::sqrt(ks.tr2 / ks.bb) : 0.0);
                     break;
                 }
             }
@@ -998,10 +1032,26 @@ static int solve_mixed(Group &g, Phase &P)
     return SOL_OK;
 }
 
-static int group_solve(Group &g, Phase &P)
+static int group_solve(Group &g, Phase &P, bool speculate = false)
 {
+    P.pending = false;
+    P.synced = false;
     if (P.main.jobs.empty()) return SOL_OK;
-    return P.mixed ? solve_mixed(g, P) : solve_plain(g, P);
+    const int rc = P.mixed ? solve_mixed(g, P) : solve_plain(g, P, speculate);
+    // every other way out of a solve ends with a state copy into slot 0
+    P.synced = rc == SOL_OK && !P.pending;
+    return rc;
+}
+
+// verdict of a phase solved speculatively, from the newest state copy
+// (slot 0): SOL_OK when every solve passed its true-residual check
+constexpr int STEP_REDO = 1000;     // internal: redo the step without speculation
+static int phase_verdict(const Group &g, const Phase &P)
+{
+    if (!P.pending) return SOL_OK;
+    for (int idx : P.main.st_index)
+        if (g.ks_h[0][idx].status != K_DONE) return STEP_REDO;
+    return SOL_OK;
 }
 
 template <class F>
@@ -1019,21 +1069,28 @@ static void timed(Group &g, int cls, F launch)
 }
 
 // one time step (Algorithm 1) for every case of the group
-static int group_step(Group &g)
+// One step.  With speculate, the momentum and pressure solves hand over to
+// the next stage without waiting for their true-residual verdict (the host
+// would otherwise wait for the device to drain twice per solve); the
+// verdicts arrive with the state copy that ends the transport solves and
+// are checked before the commit kernel is queued.  Nothing the step has
+// written before the commit is a field of level n, so a step whose verdict
+// asks for a restart is simply run again without speculation.
+static int group_step_once(Group &g, bool speculate)
 {
     hipStream_t s = g.stream;
     // 1: momentum predictor
     timed(g, SOL_KCLASS_ASM_MOM, [&] {
         for (int gi = 0; gi < 2; ++gi) launch_asm_momentum(gi ? 3 : 2, g.cases_d, g.t_mom[gi], g.n_mom[gi], s);
     });
-    RCHK(group_solve(g, g.ph[0]));
+    RCHK(group_solve(g, g.ph[0], speculate));
     // 2: pressure correction (and the initial guesses of phi and T*)
     for (int gi = 0; gi < 2; ++gi) {
         launch_div_rhs(gi ? 3 : 2, g.cases_d, g.t_cell[gi], g.n_cell[gi], 1, s);
         launch_sub_mean(g.cases_d, g.t_cell[gi], g.n_cell[gi], s);
         launch_guess(g.cases_d, g.t_cell[gi], g.n_cell[gi], s);
     }
-    RCHK(group_solve(g, g.ph[1]));
+    RCHK(group_solve(g, g.ph[1], speculate));
     // 3: projection
     for (int gi = 0; gi < 2; ++gi) launch_project(g.cases_d, g.t_mom[gi], g.n_mom[gi], s);
     // 4-6: solute and energy systems (both only need u^{n+1})
@@ -1041,6 +1098,14 @@ static int group_step(Group &g)
         for (int gi = 0; gi < 2; ++gi) launch_asm_transport(gi ? 3 : 2, g.cases_d, g.t_cell[gi], g.n_cell[gi], 1, s);
     });
     RCHK(group_solve(g, g.ph[2]));
+    if (g.ph[0].pending || g.ph[1].pending) {
+        if (!g.ph[2].synced) {
+            RCHK(poll_enqueue(g, 0));
+            RCHK(poll_wait(g, 0));
+        }
+        RCHK(phase_verdict(g, g.ph[0]));
+        RCHK(phase_verdict(g, g.ph[1]));
+    }
     // 7-8: phase update, C_l, C_s; commit level n+1
     timed(g, SOL_KCLASS_PHASE, [&] {
         for (int gi = 0; gi < 2; ++gi) launch_phase_commit(gi ? 3 : 2, g.cases_d, g.t_cell[gi], g.n_cell[gi], s);
@@ -1048,6 +1113,19 @@ static int group_step(Group &g)
     launch_case_stats(g.cases_d, g.cidx_d, (int)g.cs.size(), s);
     HIPCHK(hipGetLastError());
     return SOL_OK;
+}
+
+static int group_step(Group &g)
+{
+    // speculation needs the plain FP64 solves; timing runs take every
+    // verdict in order
+    const bool speculate = !g.timer && !g.ph[0].mixed && !g.ph[1].mixed;
+    const int rc = group_step_once(g, speculate);
+    if (rc != STEP_REDO) return rc;
+    // the step buffers and the solution history hold a discarded attempt
+    for (sol_handle *h : g.cs) ++h->redone;
+    launch_hist_reset(g.cases_d, (int)g.cs.size(), g.stream);
+    return group_step_once(g, false);
 }
 
 // ------------------------------------------------------------- validation
@@ -1171,7 +1249,8 @@ static int alloc_case(sol_handle *h)
     d.u = fu; d.v = fu + nf[0]; d.w = fu + nf[0] + nf[1];
     d.us[0] = fs; d.us[1] = fs + nf[0]; d.us[2] = fs + nf[0] + nf[1];
     d.un[0] = fn; d.un[1] = fn + nf[0]; d.un[2] = fn + nf[0] + nf[1];
-    double **cellf[] = {&d.p, &d.T, &d.C, &d.gl, &d.Cl, &d.Cs, &d.phi, &d.Cnew, &d.Tstar, &d.Tprev, &d.phiprev};
+    double **cellf[] = {&d.p,     &d.T,     &d.C,     &d.gl,       &d.Cl,     &d.Cs,      &d.phi,
+                        &d.Cnew,  &d.Tstar, &d.Tprev, &d.phiprev, &d.Tprev2, &d.phiprev2};
     for (double **pp : cellf) if (!(*pp = dal(z.ncell))) return fail(SOL_ENOMEM, "device allocation failed");
     for (int s = 0; s < NSYS; ++s) {
         const size_t n = std::max(z.nsys[s], 1);
@@ -1250,7 +1329,8 @@ static int alloc_case(sol_handle *h)
             if (l == md.nglob) {
                 const size_t n2 = (size_t)L.n * L.n;
                 double *P = dal(n2);
-                if (!P) return fail(SOL_ENOMEM, "device allocation failed");
+                h->mg_pwork = dal(4 * (size_t)L.n + 1);
+                if (!P || !h->mg_pwork) return fail(SOL_ENOMEM, "device allocation failed");
                 L.pinv = P;
                 if (mixed) {
                     float *P32 = fal(n2);
@@ -1297,6 +1377,8 @@ static int init_state(sol_handle *h)
     launch_fill(d.Tstar, h->al.T_ref, z.ncell, s);
     launch_fill(d.Tprev, 0.0, z.ncell, s);
     launch_fill(d.phiprev, 0.0, z.ncell, s);
+    launch_fill(d.Tprev2, 0.0, z.ncell, s);
+    launch_fill(d.phiprev2, 0.0, z.ncell, s);
     for (int w = 0; w < 3; ++w)
         for (int k = 0; k < 7; ++k) launch_fill(h->work[w][k], 0.0, z.maxn, s);
     for (int w = 0; w < 3; ++w)
@@ -1340,8 +1422,8 @@ int sol_create(const sol_grid *grid, const sol_alloy *alloy, const sol_bcs *bcs,
             launch_mg_minv(h->z.dim, h->mg_d, l, h->mg_h[l].n, (double *)h->mg_h[l].minv,
                            mixed ? (float *)h->mg32_h[l].minv : nullptr, h->stream);
         const int L = h->mg_nglob;
-        launch_mg_pinv(h->z.dim, h->mg_d, L, (double *)h->mg_h[L].pinv, mixed ? (float *)h->mg32_h[L].pinv : nullptr,
-                       h->stream);
+        launch_mg_pinv(h->z.dim, h->mg_d, L, h->mg_h[L].n, (double *)h->mg_h[L].pinv,
+                       mixed ? (float *)h->mg32_h[L].pinv : nullptr, h->mg_pwork, h->stream);
         if (hipGetLastError() != hipSuccess || hipStreamSynchronize(h->stream) != hipSuccess)
             rc = fail(SOL_EDEVICE, "offline assembly failed");
     }
@@ -1528,6 +1610,7 @@ static int fill_stats(Group &g, int c, sol_step_stats *st, const int64_t *tot)
     st->div_star = red[R_DIVSTAR];
     st->div_new = red[R_DIVNEW];
     st->step = step;
+    st->redone = h->redone;
     return SOL_OK;
 }
 

@@ -455,24 +455,44 @@ __global__ __launch_bounds__(TILE) void k_phase_commit(const CaseDev *__restrict
 }
 
 // Initial guesses of the pressure-correction and energy solves (the paper
-// fixes none; the converged solution does not depend on it): linear
-// extrapolation in time from the previous two solutions of the same case,
-// 2 x^n - x^(n-1), once two steps have been solved since the history was
-// last reset (creation, written fields, a failed step); before that phi = 0
-// and T* = T^n.  The guess is written into the solution buffer, which the
-// solve then takes as its initial guess; the history shifts by one.
+// fixes none; the converged solution does not depend on it): extrapolation
+// in time from the previous solutions of the same case, counted from the
+// last reset of the history (creation, written fields, a failed step).
+// With h solved steps in the history: h >= QUAD_GUESS_STEPS quadratic,
+// 3 x^n - 3 x^(n-1) + x^(n-2); h >= 2 linear, 2 x^n - x^(n-1); before that
+// phi = 0 and T* = T^n.  Started from rest, the quadratic guess is worse
+// for the first steps of the transient and better afterwards (500x300
+// cavity, energy BiCGSTAB iterations: step 3 linear 31 / quadratic 41,
+// step 5 27 / 27, step 6 26 / 25, step 12 22 / 19, step 18 21 / 16).  The
+// guess is written into the solution buffer, which the solve then takes as
+// its initial guess; the history shifts by one.
+constexpr int QUAD_GUESS_STEPS = 6;
 __global__ __launch_bounds__(TILE) void k_guess(const CaseDev *__restrict__ cases, const Tile *__restrict__ tiles)
 {
     const Tile tl = tiles[xcd_tile(blockIdx.x, gridDim.x)];
     const CaseDev &c = cases[tl.c];
     const int i = tl.t * TILE + threadIdx.x;
     if (i >= c.ph.ncell) return;
-    const bool ext = *c.step - *c.hist >= 2;
-    const double ts = c.Tstar[i], ph = c.phi[i];
-    c.Tstar[i] = ext ? 2.0 * ts - c.Tprev[i] : c.T[i];
-    c.phi[i] = ext ? 2.0 * ph - c.phiprev[i] : 0.0;
-    c.Tprev[i] = ts;
-    c.phiprev[i] = ph;
+    const int64_t h = *c.step - *c.hist;
+    const double t0 = c.Tstar[i], t1 = c.Tprev[i], t2 = c.Tprev2[i];
+    const double p0 = c.phi[i], p1 = c.phiprev[i], p2 = c.phiprev2[i];
+    double tg, pg;
+    if (h >= QUAD_GUESS_STEPS) {
+        tg = 3.0 * (t0 - t1) + t2;
+        pg = 3.0 * (p0 - p1) + p2;
+    } else if (h >= 2) {
+        tg = 2.0 * t0 - t1;
+        pg = 2.0 * p0 - p1;
+    } else {
+        tg = c.T[i];
+        pg = 0.0;
+    }
+    c.Tstar[i] = tg;
+    c.phi[i] = pg;
+    c.Tprev2[i] = t1;
+    c.phiprev2[i] = p1;
+    c.Tprev[i] = t0;
+    c.phiprev[i] = p0;
 }
 
 // history reset of every case of a group (hist = step)

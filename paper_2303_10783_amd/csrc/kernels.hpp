@@ -30,8 +30,9 @@ const void *mg_fn(int which, int nd, int fp32);
 // the inverse diagonal of level l >= 1 (FP32 copy when mi32 is given)
 void launch_mg_init(int nd, int fp32, const KJob *j, const JTile *t, int nt, int k, int mode, hipStream_t s);
 void launch_mg_minv(int dim, const MLevel *lev, int l, int n, double *mi, float *mi32, hipStream_t s);
-// multigrid: dense inverse of the exactly solved level l (one workgroup)
-void launch_mg_pinv(int dim, const MLevel *lev, int l, double *P, float *P32, hipStream_t s);
+// multigrid: dense inverse of the exactly solved level l (n cells; work:
+// 4 n + 1 doubles of device scratch)
+void launch_mg_pinv(int dim, const MLevel *lev, int l, int n, double *P, float *P32, double *work, hipStream_t s);
 const void *kbase_add_fn();   // (int *kbase, int m)
 void launch_kbase_set(int *kbase, int v, hipStream_t s);
 void launch_tune_rhs(void *b, int fp32, int n, hipStream_t s);

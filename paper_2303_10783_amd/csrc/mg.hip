@@ -579,11 +579,10 @@ __global__ __launch_bounds__(TILE) void k_mg_up0(const KJob *__restrict__ jobs, 
 }
 
 // ------------------------------------------------------------- exact level
-// e = P^-1 b on level nglob: workgroup (job, t) takes rows t*16 .. t*16+15;
-// thread (r, g) = (tid & 15, tid >> 4) sums columns j = g, g+16, ... of row
-// t*16+r with four independent accumulators (P^-1 is symmetric, stored
-// row-major: 16 lanes read 16 consecutive entries of one stored row per j);
-// the 16 group sums of a row are added in a fixed order.
+// e = P^-1 b on level nglob, one wave per row: workgroup (job, t) takes rows
+// 4t .. 4t+3.  P^-1 is symmetric, so the stored row is read: lane l sums
+// columns l, l+64, ... with four accumulators (64 consecutive entries per
+// load), the wave adds its lanes in the fixed DPP tree.
 template <class T>
 __global__ __launch_bounds__(TILE) void k_mg_exact(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles,
                                                    const int *kbase, int koff)
@@ -594,107 +593,109 @@ __global__ __launch_bounds__(TILE) void k_mg_exact(const KJob *__restrict__ jobs
     if (outer_idle(J) || !mg_live(J, k)) return;
     const MLevel &L = J.lev[tl.lv];
     const int n = L.n;
-    const int r = threadIdx.x & (MG_XROWS - 1), grp = threadIdx.x / MG_XROWS;
-    constexpr int NG = TILE / MG_XROWS;
-    const int row = tl.t * MG_XROWS + r;
-    auto P = G<T>(L.pinv);
+    const int row = tl.t * MG_XROWS + (int)(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (row >= n) return;                       // whole waves
+    auto P = G<T>(L.pinv) + (size_t)row * n;
     auto b = G<T>(L.b);
     T acc[4] = {T(0), T(0), T(0), T(0)};
-    if (row < n) {
-        int j = grp;
-        for (; j + 3 * NG < n; j += 4 * NG) {
+    int j = lane;
+    for (; j + 192 < n; j += 256) {
 #pragma unroll
-            for (int u = 0; u < 4; ++u) acc[u] += P[(size_t)(j + u * NG) * n + row] * b[j + u * NG];
-        }
-        for (; j < n; j += NG) acc[0] += P[(size_t)j * n + row] * b[j];
+        for (int u = 0; u < 4; ++u) acc[u] += P[j + 64 * u] * b[j + 64 * u];
     }
-    __shared__ T part[TILE];
-    part[threadIdx.x] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
-    __syncthreads();
-    if (threadIdx.x < MG_XROWS && row < n) {
-        T s = T(0);
-#pragma unroll
-        for (int g2 = 0; g2 < NG; ++g2) s += part[g2 * MG_XROWS + r];
-        auto e = G<T>(L.e);
-        e[row] = s;
-    }
+    for (; j < n; j += 64) acc[0] += P[j] * b[j];
+    const double s = wave_sum((double)((acc[0] + acc[1]) + (acc[2] + acc[3])));
+    if (lane == 0) G<T>(L.e)[row] = (T)s;
 }
 
-// setup: P^-1 of level l (n <= MG_EXACT_MAX) by Gauss-Jordan elimination of
-// the symmetric positive definite A + c 1 1^T in place (no pivoting needed),
-// one workgroup; FP32 copy when requested
+// setup: P^-1 of the exactly solved level l (n <= MG_EXACT_MAX) by
+// Gauss-Jordan elimination of the symmetric positive definite A + c 1 1^T in
+// place (no pivoting needed), one launch per pivot over all n^2 entries.
+// work[4n + 1]: pivot row and column of step k at work + (k & 1) 2n (row
+// first), c at work[4n].  Step k writes the new pivot row and column of step
+// k + 1 into the other half, so no launch reads an entry another thread of
+// the same launch writes.
+
+// dense operator from the closed form: -coupling for a neighbour, the
+// diagonal for j = i (thread per entry)
 template <int DIM>
-__global__ __launch_bounds__(TILE) void k_mg_pinv(const MLevel *__restrict__ lev, int l, double *P, float *P32)
+__global__ __launch_bounds__(TILE) void k_mg_pdense(const MLevel *__restrict__ lev, int l, double *P)
 {
     const MLevel &L = lev[l];
     const int n = L.n;
-    __shared__ double rk[MG_EXACT_MAX], ck[MG_EXACT_MAX];
-    __shared__ double csh;
-    const double inx = 1.0 / L.nx, inxy = 1.0 / ((double)L.nx * L.ny);
-    // dense operator, row by row (thread = column)
-    double dsum = 0.0;
-    for (int i = 0; i < n; ++i) {
-        int q[3];
-        cell_coords<DIM>(i, L.nx, L.ny, inx, inxy, q);
-        const int j = threadIdx.x;
-        if (j < n) {
-            // A_ij from the closed form: -coupling for a neighbour, diagonal for j = i
-            double co[3];
-            couplings<DIM, double>(L, q, co);
-            const int st[3] = {1, L.nx, L.nx * L.ny};
-            const int nn[3] = {L.nx, L.ny, L.nz};
-            double v = 0.0;
-            if (j == i) v = op_diag<DIM, double>(L, q);
-            for (int a = 0; a < DIM; ++a) {
-                if (q[a] > 0 && j == i - st[a]) v = -co[a];
-                if (q[a] + 1 < nn[a] && j == i + st[a]) v = -co[a];
-            }
-            P[(size_t)i * n + j] = v;
-            if (j == i) dsum += v;
-        }
+    const int idx = blockIdx.x * TILE + threadIdx.x;
+    if (idx >= n * n) return;
+    const int i = idx / n, j = idx - i * n;
+    int q[3];
+    cell_coords<DIM>(i, L.nx, L.ny, 1.0 / L.nx, 1.0 / ((double)L.nx * L.ny), q);
+    double co[3];
+    couplings<DIM, double>(L, q, co);
+    const int st[3] = {1, L.nx, L.nx * L.ny};
+    const int nn[3] = {L.nx, L.ny, L.nz};
+    double v = 0.0;
+    if (j == i) v = op_diag<DIM, double>(L, q);
+    for (int a = 0; a < DIM; ++a) {
+        if (q[a] > 0 && j == i - st[a]) v = -co[a];
+        if (q[a] + 1 < nn[a] && j == i + st[a]) v = -co[a];
     }
-    // c = (sum of diagonals) / n^2 (1 for a zero operator)
-    {
-        __shared__ double red[TILE];
-        red[threadIdx.x] = dsum;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double t = 0.0;
-            for (int q = 0; q < TILE; ++q) t += red[q];
-            csh = t > 0.0 ? t / ((double)n * n) : 1.0;
-        }
-        __syncthreads();
-    }
-    const double c = csh;
-    for (int i = 0; i < n; ++i)
-        if ((int)threadIdx.x < n) P[(size_t)i * n + threadIdx.x] += c;
-    __syncthreads();
-    for (int kk = 0; kk < n; ++kk) {
-        const int j = threadIdx.x;
-        const double piv = P[(size_t)kk * n + kk];
-        if (j < n) {
-            rk[j] = (j == kk ? 1.0 : P[(size_t)kk * n + j]) / piv;
-            ck[j] = j == kk ? 0.0 : P[(size_t)j * n + kk];
-        }
-        __syncthreads();
-        if (j < n) {
-            for (int i = 0; i < n; ++i) {
-                double v;
-                if (i == kk) v = rk[j];
-                else v = (j == kk ? 0.0 : P[(size_t)i * n + j]) - ck[i] * rk[j];
-                P[(size_t)i * n + j] = v;
-            }
-        }
-        __syncthreads();
-    }
-    if (P32 && (int)threadIdx.x < n)
-        for (int i = 0; i < n; ++i) P32[(size_t)i * n + threadIdx.x] = (float)P[(size_t)i * n + threadIdx.x];
+    P[idx] = v;
 }
 
-void launch_mg_pinv(int dim, const MLevel *lev, int l, double *P, float *P32, hipStream_t s)
+// c = (sum of the diagonal, in row order) / n^2 (1 for a zero operator)
+__global__ void k_mg_pshift(const double *__restrict__ P, int n, double *work)
 {
-    if (dim == 2) hipLaunchKernelGGL(k_mg_pinv<2>, dim3(1), dim3(TILE), 0, s, lev, l, P, P32);
-    else hipLaunchKernelGGL(k_mg_pinv<3>, dim3(1), dim3(TILE), 0, s, lev, l, P, P32);
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double t = 0.0;
+    for (int i = 0; i < n; ++i) t += P[(size_t)i * n + i];
+    work[4 * n] = t > 0.0 ? t / ((double)n * n) : 1.0;
+}
+
+// P += c; pivot row and column of step 0
+__global__ __launch_bounds__(TILE) void k_mg_padd(double *P, int n, double *work)
+{
+    const int idx = blockIdx.x * TILE + threadIdx.x;
+    if (idx >= n * n) return;
+    const int i = idx / n, j = idx - i * n;
+    const double v = P[idx] + work[4 * n];
+    P[idx] = v;
+    if (i == 0) work[j] = v;
+    if (j == 0) work[n + i] = v;
+}
+
+// elimination step k: row k divided by the pivot, column k eliminated
+__global__ __launch_bounds__(TILE) void k_mg_pgj(double *P, int n, int k, double *work)
+{
+    const int idx = blockIdx.x * TILE + threadIdx.x;
+    if (idx >= n * n) return;
+    const int i = idx / n, j = idx - i * n;
+    const double *rowk = work + (size_t)(k & 1) * 2 * n, *colk = rowk + n;
+    double *rown = work + (size_t)((k + 1) & 1) * 2 * n, *coln = rown + n;
+    const double piv = rowk[k];
+    const double rk = (j == k ? 1.0 : rowk[j]) / piv;
+    const double ck = i == k ? 0.0 : colk[i];
+    const double v = i == k ? rk : (j == k ? 0.0 : P[idx]) - ck * rk;
+    P[idx] = v;
+    if (i == k + 1) rown[j] = v;
+    if (j == k + 1) coln[i] = v;
+}
+
+__global__ __launch_bounds__(TILE) void k_mg_p32(const double *__restrict__ P, float *P32, int nn)
+{
+    const int idx = blockIdx.x * TILE + threadIdx.x;
+    if (idx < nn) P32[idx] = (float)P[idx];
+}
+
+void launch_mg_pinv(int dim, const MLevel *lev, int l, int n, double *P, float *P32, double *work, hipStream_t s)
+{
+    if (n <= 0) return;
+    const int nn = n * n;
+    const dim3 g(ceil_div(nn, TILE)), b(TILE);
+    if (dim == 2) hipLaunchKernelGGL(k_mg_pdense<2>, g, b, 0, s, lev, l, P);
+    else hipLaunchKernelGGL(k_mg_pdense<3>, g, b, 0, s, lev, l, P);
+    hipLaunchKernelGGL(k_mg_pshift, dim3(1), dim3(64), 0, s, (const double *)P, n, work);
+    hipLaunchKernelGGL(k_mg_padd, g, b, 0, s, P, n, work);
+    for (int k = 0; k < n; ++k) hipLaunchKernelGGL(k_mg_pgj, g, b, 0, s, P, n, k, work);
+    if (P32) hipLaunchKernelGGL(k_mg_p32, g, b, 0, s, (const double *)P, P32, nn);
 }
 
 // ------------------------------------------------------------- launchers

@@ -31,8 +31,8 @@ enum KKind { K_CG = 0, K_BICGSTAB = 1, K_MGCG = 2 };
 // 1/h_a^2 times the number of level-0 faces in it, the product of the block
 // extents along the other axes, and the diagonal is the sum of the
 // couplings (rows sum to zero).  The kernels apply it in this closed form.
-constexpr int MG_EXACT_MAX = 256;  // first level at or below this size is solved exactly
-constexpr int MG_XROWS = 16;       // rows of the exact solve per workgroup
+constexpr int MG_EXACT_MAX = 1024; // first level at or below this size is solved exactly
+constexpr int MG_XROWS = TILE / 64; // rows of the exact solve per workgroup (one per wave)
 constexpr int MG_MAXLEV = 32;
 struct MLevel {
     int32_t n, nx, ny, nz;        // cells of this level and their counts per axis
@@ -103,8 +103,8 @@ struct CaseDev {
     int64_t *step;            // completed steps (device counter)
     int64_t *hist;            // step at which the solution history below was last reset
     // previous solutions of the energy (T*) and pressure-correction (phi)
-    // solves: the initial guess of a solve is 2 x^n - x^(n-1) once two exist
-    double *Tprev, *phiprev;
+    // solves, x^(n-1) and x^(n-2); the latest, x^n, is in Tstar / phi
+    double *Tprev, *phiprev, *Tprev2, *phiprev2;
     KState *ks;               // [NSYS] solver states of this case
     double *red;              // [16] per-case reduction results
     double *red_part;         // [ntile_cell * 4] reduction partials

@@ -162,14 +162,17 @@ def test_steps_match_oracle(sol, dev, name, case, nsteps, precond):
 def test_cavity_50x30_200_steps(sol, dev):
     """The 50x30 cavity (cooled west wall, Sn-10%Pb-type constants), 200 steps:
     GPU vs oracle with the pressure solved to 1e-13 and the transport systems
-    to 1e-14 (gate 1e-9), and the spread at the workload tolerance 1e-10
+    to 1e-14 (gate 3e-9), and the spread at the workload tolerance 1e-10
     reported.  A T* difference inside the solver tolerance reaches u and p
     amplified ~5e3-fold by the buoyancy (T - T_ref ~ 0.1 K) and accumulates
     over the steps; the two sides start their solves from different initial
     guesses (the oracle from the level-n field, the library by extrapolation
     in time), so they end at different points of the tolerance band: the
-    gated run pins the systems tighter than the gate, and at 1e-10 the
-    spread (measured 1.5e-5 in p) is bounded by 1e-4."""
+    gated run pins the systems tighter than the gate (measured 7e-10 with
+    linear guesses, 1.2e-9 in u once quadratic guesses start the solves
+    nearer the solution and they stop nearer the band edge; T and C stay
+    at ~4e-14), and at 1e-10 the spread (measured 1.5e-5 in p) is bounded
+    by 1e-4."""
     case = W.cavity_2d(50, 30, tol=1e-13, seed=0)
     case["numerics"]["tol_t"] = 1e-14
     print("[gpu] 50x30 cavity, 200 steps, tol_p 1e-13, tol_t 1e-14", flush=True)
@@ -179,7 +182,8 @@ def test_cavity_50x30_200_steps(sol, dev):
     o.step(200)
     errs = field_errors(g.read_fields(), o.fields())
     print("rel L2 (tol 1e-13 / 1e-14):", {k: f"{v:.1e}" for k, v in errs.items()})
-    assert max(errs.values()) < 1e-9, errs
+    assert max(errs.values()) < 3e-9, errs
+    assert max(errs[k] for k in ("T", "C")) < 1e-12, errs
     assert (g.read_fields()["gl"] < 1).any()        # solidification has started
     g.close()
     case = W.cavity_2d(50, 30, tol=1e-10, seed=0)
@@ -547,9 +551,12 @@ def test_multigrid_pressure_solve(sol, dev):
     """The multigrid-preconditioned pressure CG reaches the same tolerance in
     far fewer iterations than Jacobi-PCG (a few tens, against O(n) per axis),
     both paths agree to the solve tolerance, and the preconditioner can be
-    switched between steps of one handle.  Pressure solved to 1e-13 and the
-    transport systems to 1e-14, so the fields are pinned below the gates."""
-    case = W.cavity_2d(250, 150, tol=1e-13, seed=71)
+    switched between steps of one handle.  Pressure solved to 2e-13 and the
+    transport systems to 1e-14, so the fields are pinned below the gates
+    (1e-13 sits on the FP64 floor of this pressure system: the true residual
+    b - A x of a solution rounds to ~1e-13 relative, and a handle switched
+    from Jacobi kept restarting there)."""
+    case = W.cavity_2d(250, 150, tol=2e-13, seed=71)
     case["numerics"]["tol_t"] = 1e-14
     gm = make(sol, dev, case, "mg")
     gj = make(sol, dev, case, "jacobi")
@@ -558,12 +565,14 @@ def test_multigrid_pressure_solve(sol, dev):
     print("pressure iterations over 3 steps: mg", sm["iters_total"][3], "jacobi", sj["iters_total"][3], flush=True)
     assert sm["iters_total"][3] <= 3 * 60
     assert sm["iters_total"][3] * 10 <= sj["iters_total"][3]
-    assert sm["rel_resid"][3] <= 1e-13 * (1 + 1e-6)
+    assert sm["rel_resid"][3] <= 2e-13 * (1 + 1e-6)
     errs = field_errors(gm.read_fields(), gj.read_fields())
+    print("mg vs jacobi", max(errs.values()), flush=True)
     assert max(errs.values()) < 1e-7, errs
     o = oracle.Oracle(case)
     o.step(3)
     errs = field_errors(gm.read_fields(), o.fields())
+    print("mg vs oracle", max(errs.values()), flush=True)
     assert max(errs.values()) < 1e-9, errs
     # switch the Jacobi handle to multigrid and both on: still the oracle
     gj.set_precond("mg")
@@ -573,6 +582,7 @@ def test_multigrid_pressure_solve(sol, dev):
     o.step(2)
     for g in (gm, gj):
         errs = field_errors(g.read_fields(), o.fields())
+        print("after the switch, vs oracle", max(errs.values()), flush=True)
         assert max(errs.values()) < 1e-9, errs
     gm.close()
     gj.close()
@@ -585,5 +595,32 @@ def test_batch_rejects_mixed_preconditioners(sol, dev):
     with pytest.raises(B.SolError) as e:
         sol.Batch([a, b])
     assert e.value.code == B.SOL_EINVAL
+    a.close()
+    b.close()
+
+
+@pytest.mark.parametrize("case", [W.cavity_2d(64, 30, seed=101),
+                                  W.box_3d(12, 10, 8, lx=0.012, ly=0.010, lz=0.008, seed=102)],
+                         ids=["2d-64x30", "3d-12x10x8"])
+def test_speculative_handover_matches_in_order_checks(sol, dev, case):
+    """The momentum and pressure solves hand over to the next stage before
+    their true-residual verdict.  Without a redo the fields are bit-identical
+    to a run that takes every verdict in order (timing mode does); with one
+    they still match the oracle."""
+    a = make(sol, dev, case)
+    b = make(sol, dev, case)
+    b.set_timing(True)
+    sa = a.step(8)
+    sb = b.step(8)
+    fa, fb = a.read_fields(), b.read_fields()
+    assert sb["redone"] == 0
+    if sa["redone"] == 0:
+        for k in FIELDS:
+            assert np.array_equal(fa[k], fb[k]), k
+    else:
+        o = oracle.Oracle(case)
+        o.step(8)
+        errs = field_errors(fa, o.fields())
+        assert max(errs.values()) < 1e-6, errs
     a.close()
     b.close()
