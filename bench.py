@@ -103,7 +103,8 @@ def run_single(sol, W, key, precision, steps, warmup, dev, graph=False, precond=
     secs = time.perf_counter() - t0
     h.close()
     return dict(value=ncell * steps / secs, ms_per_step=1e3 * secs / steps, steps=steps,
-                krylov_iters_per_step={n: round(st["iters_total"][i] / steps, 1) for i, n in enumerate("uvwpCT")})
+                krylov_iters_per_step={n: round(st["iters_total"][i] / steps, 1) for i, n in enumerate("uvwpCT")},
+                steps_redone=st["redone"])
 
 
 def run_batched(sol, W, precision, steps, warmup, dev, n_cases=64, graph=True, tune=True):
@@ -260,7 +261,8 @@ def main():
                     else f"{args.workload}: 3D box {grid['nx']}x{grid['ny']}x{grid['nz']}",
                     cells=ncell, dt=case["numerics"]["dt"], tol=case["numerics"]["tol_p"],
                     precision=args.precision, pressure_precond=args.precond, krylov_iters_per_step={
-                        n: round(iters[i] / args.steps, 1) for i, n in enumerate("uvwpCT")}),
+                        n: round(iters[i] / args.steps, 1) for i, n in enumerate("uvwpCT")},
+                    steps_redone=st["redone"]),
         roofline=roof, cpu_baseline=cpu, variants=variants,
     )
     print(json.dumps(out))
