@@ -167,7 +167,7 @@ static size_t footprint(const Sizes &z, int precision)
             if (precision) b += 3 * al((size_t)m.n[l] * F);
         }
         const size_t nx2 = (size_t)m.n[m.nglob] * m.n[m.nglob];  // dense inverse of the exact level
-        b += al(nx2 * D) + (precision ? al(nx2 * F) : 0);
+        b += al(nx2 * D) + al(nx2 * F);
         b += al((4 * (size_t)m.n[m.nglob] + 1) * D);            // its elimination scratch
         b += al(sizeof(MLevel) * MG_MAXLEV) * (precision ? 2 : 1);
     }
@@ -262,6 +262,7 @@ struct sol_handle {
     bool opt_graph = false;
     int precond = SOL_PRECOND_MG;
     double *mg_pwork = nullptr;           // scratch of the exact-level inverse (set-up)
+    double *mg_p64 = nullptr;             // FP64 exact-level inverse (set-up; solves read its FP32 copy)
     int64_t redone = 0;                   // steps run a second time (speculative check failed)
     // pressure multigrid hierarchy (FP64 arrays; FP32 copies for mixed precision)
     int mg_nlev = 0, mg_nglob = 0;
@@ -1327,16 +1328,15 @@ static int alloc_case(sol_handle *h)
                 }
             }
             if (l == md.nglob) {
+                // the elimination runs in FP64 (set-up only); the product of
+                // every solve reads the FP32 copy
                 const size_t n2 = (size_t)L.n * L.n;
-                double *P = dal(n2);
+                h->mg_p64 = dal(n2);
                 h->mg_pwork = dal(4 * (size_t)L.n + 1);
-                if (!P || !h->mg_pwork) return fail(SOL_ENOMEM, "device allocation failed");
-                L.pinv = P;
-                if (mixed) {
-                    float *P32 = fal(n2);
-                    if (!P32) return fail(SOL_ENOMEM, "device allocation failed");
-                    L32.pinv = P32;
-                }
+                float *P32 = fal(n2);
+                if (!h->mg_p64 || !h->mg_pwork || !P32) return fail(SOL_ENOMEM, "device allocation failed");
+                L.pinv = P32;
+                L32.pinv = P32;
             }
             h->mg_h[l] = L;
             h->mg32_h[l] = L32;
@@ -1422,8 +1422,8 @@ int sol_create(const sol_grid *grid, const sol_alloy *alloy, const sol_bcs *bcs,
             launch_mg_minv(h->z.dim, h->mg_d, l, h->mg_h[l].n, (double *)h->mg_h[l].minv,
                            mixed ? (float *)h->mg32_h[l].minv : nullptr, h->stream);
         const int L = h->mg_nglob;
-        launch_mg_pinv(h->z.dim, h->mg_d, L, h->mg_h[L].n, (double *)h->mg_h[L].pinv,
-                       mixed ? (float *)h->mg32_h[L].pinv : nullptr, h->mg_pwork, h->stream);
+        launch_mg_pinv(h->z.dim, h->mg_d, L, h->mg_h[L].n, h->mg_p64, (float *)h->mg_h[L].pinv, h->mg_pwork,
+                       h->stream);
         if (hipGetLastError() != hipSuccess || hipStreamSynchronize(h->stream) != hipSuccess)
             rc = fail(SOL_EDEVICE, "offline assembly failed");
     }

@@ -582,7 +582,12 @@ __global__ __launch_bounds__(TILE) void k_mg_up0(const KJob *__restrict__ jobs, 
 // e = P^-1 b on level nglob, one wave per row: workgroup (job, t) takes rows
 // 4t .. 4t+3.  P^-1 is symmetric, so the stored row is read: lane l sums
 // columns l, l+64, ... with four accumulators (64 consecutive entries per
-// load), the wave adds its lanes in the fixed DPP tree.
+// load), the wave adds its lanes in the fixed DPP tree.  The entries are
+// the FP32 rounding of the FP64 inverse at either precision (half the bytes
+// of the product that dominates this kernel): still symmetric, and its
+// relative perturbation (6e-8) is far below 1 / cond(A + c 1 1^T), so the
+// preconditioner stays positive definite; the FP64 solve's residuals and
+// updates stay FP64.
 template <class T>
 __global__ __launch_bounds__(TILE) void k_mg_exact(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles,
                                                    const int *kbase, int koff)
@@ -595,15 +600,15 @@ __global__ __launch_bounds__(TILE) void k_mg_exact(const KJob *__restrict__ jobs
     const int n = L.n;
     const int row = tl.t * MG_XROWS + (int)(threadIdx.x >> 6), lane = threadIdx.x & 63;
     if (row >= n) return;                       // whole waves
-    auto P = G<T>(L.pinv) + (size_t)row * n;
+    auto P = G<float>(L.pinv) + (size_t)row * n;
     auto b = G<T>(L.b);
     T acc[4] = {T(0), T(0), T(0), T(0)};
     int j = lane;
     for (; j + 192 < n; j += 256) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) acc[u] += P[j + 64 * u] * b[j + 64 * u];
+        for (int u = 0; u < 4; ++u) acc[u] += (T)P[j + 64 * u] * b[j + 64 * u];
     }
-    for (; j < n; j += 64) acc[0] += P[j] * b[j];
+    for (; j < n; j += 64) acc[0] += (T)P[j] * b[j];
     const double s = wave_sum((double)((acc[0] + acc[1]) + (acc[2] + acc[3])));
     if (lane == 0) G<T>(L.e)[row] = (T)s;
 }

@@ -44,7 +44,7 @@ struct MLevel {
     double ih2[3];                // 1 / h_a^2 of level 0
     const void *minv;             // Jacobi inverse of the diagonal (levels above the exact one)
     void *b, *e;                  // right-hand side and correction (levels >= 1)
-    const void *pinv;             // exact level: dense n x n inverse of A + c 1 1^T (symmetric)
+    const void *pinv;             // exact level: dense n x n inverse of A + c 1 1^T (symmetric), FP32
 };
 
 // Per-solve device state.  Iteration kernels read it at their start; only
