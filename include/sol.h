@@ -205,9 +205,9 @@ void sol_batch_destroy(sol_batch *b);
    the systems that were iterating; FP32 values count 4 bytes).  Enabling or
    disabling resets the counters. */
 #define SOL_KCLASS_CG        0   /* CG iteration (one kernel): p, s, x, r, w = A M r, (r,Mr), (w,Mr) */
-#define SOL_KCLASS_BICG_A    1   /* BiCGSTAB: p, v = A M p, (rh,v)              */
-#define SOL_KCLASS_BICG_B    2   /* BiCGSTAB: t = A M s, (t,s), (t,t)           */
-#define SOL_KCLASS_BICG_C    3   /* BiCGSTAB: x, r update, (rh,r), (r,r)        */
+#define SOL_KCLASS_BICG_A    1   /* BiCGSTAB: x, r update; p, v = A M p; (rh,v), (r,r) */
+#define SOL_KCLASS_BICG_B    2   /* BiCGSTAB: s, t = A M s; (t,s), (t,t), (rh,s), (rh,t) */
+#define SOL_KCLASS_BICG_C    3   /* unused (the x, r update rides in SOL_KCLASS_BICG_A); never launched */
 #define SOL_KCLASS_ASM_MOM   4   /* momentum assembly                           */
 #define SOL_KCLASS_ASM_TRN   5   /* solute + energy assembly                    */
 #define SOL_KCLASS_PHASE     6   /* phase update + commit                       */

@@ -140,6 +140,10 @@ static void mg_dims(const Sizes &z, MGDims &m)
     if (m.nglob == 0) m.nglob = m.nlev - 1;
 }
 
+// Krylov work vectors per set: r, rh, p0, p1, v0, v1, t, r1 (FP64); the FP32
+// sets add the inner solution and right-hand side (7, 8) and r1 (9)
+constexpr int NWORK = 8, NWORK32 = 10;
+
 // total device bytes of one case (matches the allocations in sol_create)
 static size_t footprint(const Sizes &z, int precision)
 {
@@ -156,8 +160,8 @@ static size_t footprint(const Sizes &z, int precision)
         if (s != SP && s != SC) b += al(z.nd * n * D);           // constant parts
         if (precision) b += al(z.nd * n * F) + al(n * F);
     }
-    b += 3 * 7 * al((size_t)z.maxn * D);                        // Krylov work vectors
-    if (precision) b += 3 * 9 * al((size_t)z.maxn * F);         // FP32 inner work vectors
+    b += 3 * NWORK * al((size_t)z.maxn * D);                    // Krylov work vectors
+    if (precision) b += 3 * NWORK32 * al((size_t)z.maxn * F);   // FP32 inner work vectors
     b += al((size_t)z.ntile_cell * 4 * D) + 2 * al(256);         // reductions, counters, step
     {
         MGDims m;                                                // pressure multigrid hierarchy
@@ -221,9 +225,8 @@ static double row_bytes(int cls, int nd, int dim, int tsize)
 {
     switch (cls) {
     case SOL_KCLASS_CG: return (nd + 11.0) * tsize;     // A, r, w, s, M, p, x; p, s, x, r, w
-    case SOL_KCLASS_BICG_A: return (nd + 7.0) * tsize;  // A, r, p, v, M, rh; p, v
-    case SOL_KCLASS_BICG_B: return (nd + 4.0) * tsize;  // A, r, v, M; t
-    case SOL_KCLASS_BICG_C: return 9.0 * tsize;         // x, r, v, p, M, t, rh; x, r
+    case SOL_KCLASS_BICG_A: return (nd + 11.0) * tsize; // A, r, v, t, p, M, rh, x; x, r', p', v'
+    case SOL_KCLASS_BICG_B: return (nd + 5.0) * tsize;  // A, r, v, M, rh; t
     // multigrid (the pressure operator is applied from its closed form, no
     // matrix values are read)
     case SOL_KCLASS_MG_PQ: return 4.0 * tsize;           // z, p_old; p, q
@@ -252,8 +255,8 @@ struct sol_handle {
     hipStream_t stream = nullptr;
     Mem mem;
     CaseDev cd{};
-    double *work[3][7] = {};
-    float *work32[3][9] = {};
+    double *work[3][NWORK] = {};
+    float *work32[3][NWORK32] = {};
     int32_t *csr_cnt = nullptr, *csr_rp[NSYS] = {}, *csr_col[NSYS] = {};
     double *csr_val[NSYS] = {};
     Group *solo = nullptr;
@@ -410,7 +413,8 @@ static int build_stages(Group &g, JobSet &S, int kind, int fp32)
         return SOL_OK;
     }
     if (kind == K_BICGSTAB) {
-        for (int q = 0; q < 3; ++q) S.iter.push_back(row_stage(KI_BICG_A + q, SOL_KCLASS_BICG_A + q));
+        S.iter.push_back(row_stage(KI_BICG_B, SOL_KCLASS_BICG_B));
+        S.iter.push_back(row_stage(KI_BICG_A, SOL_KCLASS_BICG_A));
         return SOL_OK;
     }
     // multigrid CG: pq, down0, down(1..G-1), exact, up(G-1..1), up0; the start
@@ -585,7 +589,7 @@ static int group_build(Group &g)
                     J.r = h->work[ws][0]; J.rh = h->work[ws][1];
                     J.p0 = h->work[ws][2]; J.p1 = h->work[ws][3];
                     J.v0 = h->work[ws][4]; J.v1 = h->work[ws][5];
-                    J.t = h->work[ws][6];
+                    J.t = h->work[ws][6]; J.r1 = h->work[ws][7];
                 } else {
                     // refinement: FP64 residual sweeps; aux = FP32 residual, t = FP32 correction
                     KState *ist = g.ks_d + g.nks + c * NSYS + s;
@@ -604,7 +608,7 @@ static int group_build(Group &g)
                     I.r = h->work32[ws][0]; I.rh = h->work32[ws][1];
                     I.p0 = h->work32[ws][2]; I.p1 = h->work32[ws][3];
                     I.v0 = h->work32[ws][4]; I.v1 = h->work32[ws][5];
-                    I.t = h->work32[ws][6];
+                    I.t = h->work32[ws][6]; I.r1 = h->work32[ws][9];
                     I.st = ist;
                     I.partner = J.st;
                     I.lev = h->mg32_d;
@@ -1265,7 +1269,7 @@ static int alloc_case(sol_handle *h)
         }
     }
     for (int w = 0; w < 3; ++w)
-        for (int k = 0; k < 7; ++k)
+        for (int k = 0; k < NWORK; ++k)
             if (!(h->work[w][k] = dal(z.maxn))) return fail(SOL_ENOMEM, "device allocation failed");
     if (h->num.precision == SOL_PRECISION_MIXED) {
         auto fal = [&](size_t n) { return (float *)m.get(std::max<size_t>(n, 1) * sizeof(float)); };
@@ -1276,7 +1280,7 @@ static int alloc_case(sol_handle *h)
             if (!d.A32[s] || !d.minv32[s]) return fail(SOL_ENOMEM, "device allocation failed");
         }
         for (int w = 0; w < 3; ++w)
-            for (int k = 0; k < 9; ++k)
+            for (int k = 0; k < NWORK32; ++k)
                 if (!(h->work32[w][k] = fal(z.maxn))) return fail(SOL_ENOMEM, "device allocation failed");
     }
     {
@@ -1380,9 +1384,9 @@ static int init_state(sol_handle *h)
     launch_fill(d.Tprev2, 0.0, z.ncell, s);
     launch_fill(d.phiprev2, 0.0, z.ncell, s);
     for (int w = 0; w < 3; ++w)
-        for (int k = 0; k < 7; ++k) launch_fill(h->work[w][k], 0.0, z.maxn, s);
+        for (int k = 0; k < NWORK; ++k) launch_fill(h->work[w][k], 0.0, z.maxn, s);
     for (int w = 0; w < 3; ++w)
-        for (int k = 0; k < 9; ++k)
+        for (int k = 0; k < NWORK32; ++k)
             if (h->work32[w][k]) HIPCHK(hipMemsetAsync(h->work32[w][k], 0, sizeof(float) * std::max(z.maxn, 1), s));
     HIPCHK(hipMemsetAsync(d.red_cnt, 0, 256, s));
     HIPCHK(hipMemsetAsync(d.step, 0, 256, s));

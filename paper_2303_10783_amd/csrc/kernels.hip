@@ -540,9 +540,30 @@ __global__ __launch_bounds__(TILE) void k_case_stats(const CaseDev *__restrict__
 //   w = A u, gamma = (r, u), delta = (w, u),
 //   beta = gamma / gamma_old, alpha = gamma / (delta - beta gamma / alpha_old).
 
-// ---- BiCGSTAB start at iteration index k (mode 0: every solve, x = x0 or 0;
-// mode 1: solves in K_RESTART, keep x): r = b - A x, rh = r, p = v = 0;
-// partials (rh, r), (r, r), (b, b) for iteration k.
+// ---- BiCGSTAB (van der Vorst's recurrences) with two reductions per
+// iteration.  r_k, p_k, v_k of iteration k live in the buffers of parity
+// k & 1 (r / r1, p0 / p1, v0 / v1); rho_k = (rh, r_k) is kept per parity in
+// st->gamma by workgroup 0.  Iteration k is two launches:
+//   B(k): convergence test on ||r_k||^2 (from A(k-1); the start kernels
+//         test r_k0); alpha_k = rho_k / (rh, v_k); s = r_k - alpha_k v_k;
+//         t = A M s; partials (t,s), (t,t), (rh,s), (rh,t)
+//   A(k): omega_k = (t,s) / (t,t); x += M (alpha_k p_k + omega_k s);
+//         r_(k+1) = s - omega_k t; rho_(k+1) = (rh, r_(k+1)) expanded as
+//         (rh,s) - omega_k (rh,t), so beta = (rho_(k+1)/rho_k)(alpha_k/omega_k)
+//         needs no reduction of its own; p_(k+1) = r_(k+1) + beta (p_k -
+//         omega_k v_k), v_(k+1) = A M p_(k+1); partials (rh, v_(k+1)) and
+//         ||r_(k+1)||^2 from the rows themselves.
+// s and p_(k+1) are recomputed at the neighbour rows a stencil needs.  The
+// textbook arrangement takes a third reduction for (rh, r_(k+1)) and
+// ||r_(k+1)||.  Here the norm is summed from r_(k+1) and tested one kernel
+// later (x_(k+1) is written by then); expanding it in (s,s), (t,s), (t,t)
+// instead cancels catastrophically when one step shrinks the residual by
+// orders of magnitude, as the diagonally dominant momentum systems do.  rho
+// has no such cancellation: (rh,s) vanishes in exact arithmetic.
+//
+// Start at iteration index k (mode 0: every solve, x = x0 or 0; mode 1:
+// solves in K_RESTART, keep x): r_k = b - A x, rh = r_k; partials (rh, r_k),
+// (r_k, r_k), (b, b).
 template <int ND, class T>
 __global__ __launch_bounds__(TILE) void k_bicg_init(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles, int k, int mode)
 {
@@ -551,11 +572,9 @@ __global__ __launch_bounds__(TILE) void k_bicg_init(const KJob *__restrict__ job
     if (mode == 1 && J.st->status != K_RESTART) return;
     if (outer_idle(J)) return;
     const int n = J.n;
-    const int flip = k & 1;
     auto A = G<T>(J.A);
     auto b = G<T>(J.b);
-    auto x = G<T>(J.x), r = G<T>(J.r), rh = G<T>(J.rh);
-    auto po = G<T>(flip ? J.p1 : J.p0), vo = G<T>(flip ? J.v1 : J.v0);
+    auto x = G<T>(J.x), r = G<T>((k & 1) ? J.r1 : J.r), rh = G<T>(J.rh);
     auto x0 = G<T>(J.x0);
     double v[3] = {0.0, 0.0, 0.0};
     const int i0 = tl.t * J.rpt, i1 = min(n, i0 + J.rpt);
@@ -574,86 +593,50 @@ __global__ __launch_bounds__(TILE) void k_bicg_init(const KJob *__restrict__ job
         }
         r[i] = ri;
         rh[i] = ri;
-        po[i] = T(0);
-        vo[i] = T(0);
         v[0] += (double)ri * ri;
         v[1] += (double)ri * ri;
         v[2] += (double)b[i] * b[i];
     }
-    const int pm = (k + 1) & 1;
-    const int off[3] = {poff(J, pm, PS_RHO), poff(J, pm, PS_RR), poff(J, pm, PS_BB)};
+    const int pk = k & 1;
+    const int off[3] = {poff(J, pk, PS_RHO), poff(J, pk, PS_RR), poff(J, pk, PS_BB)};
     put_partials<3>(v, J.part, off, tl.t);
     mark_start(tl, J.st, k, mode);
 }
 
-// a: beta = (rho_k/rho_{k-1})(alpha_{k-1}/omega_{k-1});
-//    p = r + beta (p - omega v); v = A M p; partial (rh, v)
+// first iteration of a (re)start at k = k0: convergence test on r_k; p_k =
+// r_k, v_k = A M p_k; partial (rh, v_k)
 template <int ND, class T>
-__global__ __launch_bounds__(TILE) void k_bicg_a(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles, const int *kbase, int koff)
+__global__ __launch_bounds__(TILE) void k_bicg_first(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles, int k)
 {
-    const int k = (kbase ? *kbase : 0) + koff;
     JTile tl;
     const KJob &J = job_of(jobs, tiles, tl);
     if (!active(J, k) || outer_idle(J)) return;
-    KState *st = J.st;
-    const int pk = k & 1, pm = (k + 1) & 1;
-    const bool first = k == st->k0;
-    double s7[7];
+    const int pk = k & 1;
+    double s3[3];
     {
-        const int off[7] = {poff(J, pm, PS_RHO), poff(J, pm, PS_RR), poff(J, pm, PS_BB), poff(J, pk, PS_RHO),
-                            poff(J, pm, PS_Q), poff(J, pm, PS_TS), poff(J, pm, PS_TT)};
-        sum_partials<7>(J.part, off, J.ntile, s7);
+        const int off[3] = {poff(J, pk, PS_RHO), poff(J, pk, PS_RR), poff(J, pk, PS_BB)};
+        sum_partials<3>(J.part, off, J.ntile, s3);
     }
-    if (!keep_going(J, tl, k, s7[1], s7[2])) return;
-    const double rho = s7[0];
-    double beta = 0.0, omega = 0.0;
-    if (!first) {
-        const double rho_prev = s7[3];
-        const double alpha_prev = rho_prev / s7[4];
-        omega = s7[6] > 0.0 ? s7[5] / s7[6] : 0.0;
-        if (omega == 0.0 || rho == 0.0 || rho_prev == 0.0 || !finite(alpha_prev)) {
-            set_status(tl, st, K_RESTART, st->it_base + (k - st->k0), s7[1]);
-            return;
-        }
-        beta = (rho / rho_prev) * (alpha_prev / omega);
-    }
-    const T tb = (T)beta, tw = (T)omega;
+    if (!keep_going(J, tl, k, s3[1], s3[2])) return;
+    if (tl.t == 0 && threadIdx.x == 0) J.st->gamma[pk] = s3[0];
     const int n = J.n;
     auto A = G<T>(J.A);
-    auto r = G<T>(J.r), mi = G<T>(J.minv), rh = G<T>(J.rh);
-    auto po = G<T>(pk ? J.p1 : J.p0), vo = G<T>(pk ? J.v1 : J.v0);
-    auto pn = G<T>(pk ? J.p0 : J.p1), vn = G<T>(pk ? J.v0 : J.v1);
-    double v[1] = {0.0};
+    auto r = G<T>(pk ? J.r1 : J.r), mi = G<T>(J.minv), rh = G<T>(J.rh);
+    auto p = G<T>(pk ? J.p1 : J.p0), vv = G<T>(pk ? J.v1 : J.v0);
+    double q = 0.0;
     const int i0 = tl.t * J.rpt, i1 = min(n, i0 + J.rpt);
-    // two rows per pass, both loaded and computed before either is stored
-    // (the compiler cannot move loads above stores it cannot prove disjoint)
-    for (int i = i0 + threadIdx.x; i < i1; i += 2 * TILE) {
-        const bool two = i + TILE < i1;
-        const int i2 = two ? i + TILE : i;
-        T pv[2], vv[2];
-        const int iv[2] = {i, i2};
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            const int ii = iv[u];
-            pv[u] = r[ii] + tb * (po[ii] - tw * vo[ii]);
-            vv[u] = kstencil<ND, T>(A, n, ii, J.sx, J.sxy,
-                                    [&](int j) { return mi[j] * (r[j] + tb * (po[j] - tw * vo[j])); });
-        }
-        const T rh0 = rh[i], rh1 = rh[i2];
-        pn[i] = pv[0];
-        vn[i] = vv[0];
-        v[0] += (double)rh0 * vv[0];
-        if (two) {
-            pn[i2] = pv[1];
-            vn[i2] = vv[1];
-            v[0] += (double)rh1 * vv[1];
-        }
+    for (int i = i0 + threadIdx.x; i < i1; i += TILE) {
+        const T vi = kstencil<ND, T>(A, n, i, J.sx, J.sxy, [&](int j) { return mi[j] * r[j]; });
+        p[i] = r[i];
+        vv[i] = vi;
+        q += (double)rh[i] * vi;
     }
+    double v1[1] = {q};
     const int off[1] = {poff(J, pk, PS_Q)};
-    put_partials<1>(v, J.part, off, tl.t);
+    put_partials<1>(v1, J.part, off, tl.t);
 }
 
-// b: alpha = rho_k / (rh, v); s = r - alpha v; t = A M s; partials (t,s), (t,t)
+// B(k)
 template <int ND, class T>
 __global__ __launch_bounds__(TILE) void k_bicg_b(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles, const int *kbase, int koff)
 {
@@ -661,96 +644,136 @@ __global__ __launch_bounds__(TILE) void k_bicg_b(const KJob *__restrict__ jobs, 
     JTile tl;
     const KJob &J = job_of(jobs, tiles, tl);
     if (J.st->status != K_RUNNING || outer_idle(J)) return;
-    const int pk = k & 1, pm = (k + 1) & 1;
+    const int pk = k & 1;
     double s2[2];
     {
-        const int off[2] = {poff(J, pm, PS_RHO), poff(J, pk, PS_Q)};
+        const int off[2] = {poff(J, pk, PS_Q), poff(J, pk, PS_RR)};
         sum_partials<2>(J.part, off, J.ntile, s2);
     }
-    if (s2[1] == 0.0 || !finite(s2[1])) {
-        set_status(tl, J.st, finite(s2[1]) ? K_RESTART : K_NONFINITE, J.st->it_base + (k - J.st->k0), 0.0);
+    if (k > J.st->k0 && !keep_going(J, tl, k, s2[1], 0.0)) return;
+    double s1[1] = {s2[0]};
+    if (s1[0] == 0.0 || !finite(s1[0])) {
+        set_status(tl, J.st, finite(s1[0]) ? K_RESTART : K_NONFINITE, J.st->it_base + (k - J.st->k0), 0.0);
         return;
     }
-    const T alpha = (T)(s2[0] / s2[1]);
+    const T alpha = (T)(J.st->gamma[pk] / s1[0]);
     const int n = J.n;
     auto A = G<T>(J.A);
-    auto r = G<T>(J.r), mi = G<T>(J.minv);
-    auto vn = G<T>(pk ? J.v0 : J.v1);
+    auto r = G<T>(pk ? J.r1 : J.r), mi = G<T>(J.minv), rh = G<T>(J.rh);
+    auto vk = G<T>(pk ? J.v1 : J.v0);
     auto t = G<T>(J.t);
-    double v[2] = {0.0, 0.0};
+    double v[4] = {0.0, 0.0, 0.0, 0.0};     // (t,s) (t,t) (rh,s) (rh,t)
     const int i0 = tl.t * J.rpt, i1 = min(n, i0 + J.rpt);
     for (int i = i0 + threadIdx.x; i < i1; i += 2 * TILE) {
         const bool two = i + TILE < i1;
         const int i2 = two ? i + TILE : i;
-        T sv[2], tv[2];
+        T sv[2], tv[2], hv[2];
         const int iv[2] = {i, i2};
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
             const int ii = iv[u];
-            sv[u] = r[ii] - alpha * vn[ii];
-            tv[u] = kstencil<ND, T>(A, n, ii, J.sx, J.sxy, [&](int j) { return mi[j] * (r[j] - alpha * vn[j]); });
+            sv[u] = r[ii] - alpha * vk[ii];
+            tv[u] = kstencil<ND, T>(A, n, ii, J.sx, J.sxy, [&](int j) { return mi[j] * (r[j] - alpha * vk[j]); });
+            hv[u] = rh[ii];
         }
-        t[i] = tv[0];
-        v[0] += (double)tv[0] * sv[0];
-        v[1] += (double)tv[0] * tv[0];
-        if (two) {
-            t[i2] = tv[1];
-            v[0] += (double)tv[1] * sv[1];
-            v[1] += (double)tv[1] * tv[1];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            if (u == 1 && !two) break;
+            t[iv[u]] = tv[u];
+            const double sd = sv[u], td = tv[u], hd = hv[u];
+            v[0] += td * sd;
+            v[1] += td * td;
+            v[2] += hd * sd;
+            v[3] += hd * td;
         }
     }
-    const int off[2] = {poff(J, pk, PS_TS), poff(J, pk, PS_TT)};
-    put_partials<2>(v, J.part, off, tl.t);
+    const int off[4] = {poff(J, pk, PS_TS), poff(J, pk, PS_TT), poff(J, pk, PS_RHS), poff(J, pk, PS_RHT)};
+    put_partials<4>(v, J.part, off, tl.t);
 }
 
-// c: omega = (t,s)/(t,t); x += M (alpha p + omega s); r = s - omega t;
-// partials (rh, r), (r, r) for iteration k+1
+// A(k)
 template <int ND, class T>
-__global__ __launch_bounds__(TILE) void k_bicg_c(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles, const int *kbase, int koff)
+__global__ __launch_bounds__(TILE) void k_bicg_a(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles, const int *kbase, int koff)
 {
     const int k = (kbase ? *kbase : 0) + koff;
     JTile tl;
     const KJob &J = job_of(jobs, tiles, tl);
     if (J.st->status != K_RUNNING || outer_idle(J)) return;
-    const int pk = k & 1, pm = (k + 1) & 1;
-    double s4[4];
+    KState *st = J.st;
+    const int pk = k & 1, pn = (k + 1) & 1;
+    double s5[5];
     {
-        const int off[4] = {poff(J, pm, PS_RHO), poff(J, pk, PS_Q), poff(J, pk, PS_TS), poff(J, pk, PS_TT)};
-        sum_partials<4>(J.part, off, J.ntile, s4);
+        const int off[5] = {poff(J, pk, PS_TS), poff(J, pk, PS_TT), poff(J, pk, PS_RHS), poff(J, pk, PS_RHT),
+                            poff(J, pk, PS_Q)};
+        sum_partials<5>(J.part, off, J.ntile, s5);
     }
-    const T alpha = (T)(s4[0] / s4[1]);
-    const T omega = (T)(s4[3] > 0.0 ? s4[2] / s4[3] : 0.0);
-    auto pn = G<T>(pk ? J.p0 : J.p1), vn = G<T>(pk ? J.v0 : J.v1), t = G<T>(J.t);
-    auto mi = G<T>(J.minv), rh = G<T>(J.rh);
-    auto x = G<T>(J.x), r = G<T>(J.r);
-    double v[2] = {0.0, 0.0};
-    const int i0 = tl.t * J.rpt, i1 = min(J.n, i0 + J.rpt);
+    const double rho = st->gamma[pk];
+    const double alpha = rho / s5[4];
+    const double omega = s5[1] > 0.0 ? s5[0] / s5[1] : 0.0;
+    const double rho_n = s5[2] - omega * s5[3];
+    // x and r_(k+1) are written whatever the decision: a restarted solve
+    // starts from x_(k+1)
+    bool go = true;
+    double beta = 0.0;
+    if (omega == 0.0 || rho_n == 0.0 || rho == 0.0 || !finite(rho_n) || !finite(alpha)) {
+        set_status(tl, st, finite(rho_n) && finite(alpha) ? K_RESTART : K_NONFINITE, st->it_base + (k + 1 - st->k0),
+                   st->rr);
+        go = false;
+    } else {
+        beta = (rho_n / rho) * (alpha / omega);
+        if (tl.t == 0 && threadIdx.x == 0) st->gamma[pn] = rho_n;
+    }
+    const T ta = (T)alpha, tw = (T)omega, tb = (T)beta;
+    const int n = J.n;
+    auto A = G<T>(J.A);
+    auto rk = G<T>(pk ? J.r1 : J.r), rn = G<T>(pn ? J.r1 : J.r);
+    auto pkv = G<T>(pk ? J.p1 : J.p0), pnv = G<T>(pn ? J.p1 : J.p0);
+    auto vk = G<T>(pk ? J.v1 : J.v0), vn = G<T>(pn ? J.v1 : J.v0);
+    auto t = G<T>(J.t), mi = G<T>(J.minv), rh = G<T>(J.rh), x = G<T>(J.x);
+    double q[2] = {0.0, 0.0};       // (rh, v_(k+1)), ||r_(k+1)||^2
+    const int i0 = tl.t * J.rpt, i1 = min(n, i0 + J.rpt);
+    if (!go) {
+        for (int i = i0 + threadIdx.x; i < i1; i += TILE) {
+            const T si = rk[i] - ta * vk[i];
+            x[i] = x[i] + mi[i] * (ta * pkv[i] + tw * si);
+            rn[i] = si - tw * t[i];
+        }
+        return;
+    }
+    // p_(k+1) at row j from vectors no workgroup of this launch writes
+    auto pnext = [&](int j) {
+        const T rj = (rk[j] - ta * vk[j]) - tw * t[j];
+        return rj + tb * (pkv[j] - tw * vk[j]);
+    };
     for (int i = i0 + threadIdx.x; i < i1; i += 2 * TILE) {
         const bool two = i + TILE < i1;
         const int i2 = two ? i + TILE : i;
-        T xv[2], rv[2], hv[2];
+        T xv[2], rv[2], pv[2], vv[2], hv[2];
         const int iv[2] = {i, i2};
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
             const int ii = iv[u];
-            const T si = r[ii] - alpha * vn[ii];
-            xv[u] = x[ii] + mi[ii] * (alpha * pn[ii] + omega * si);
-            rv[u] = si - omega * t[ii];
+            const T si = rk[ii] - ta * vk[ii];
+            xv[u] = x[ii] + mi[ii] * (ta * pkv[ii] + tw * si);
+            rv[u] = si - tw * t[ii];
+            pv[u] = pnext(ii);
+            vv[u] = kstencil<ND, T>(A, n, ii, J.sx, J.sxy, [&](int j) { return mi[j] * pnext(j); });
             hv[u] = rh[ii];
         }
-        x[i] = xv[0];
-        r[i] = rv[0];
-        v[0] += (double)hv[0] * rv[0];
-        v[1] += (double)rv[0] * rv[0];
-        if (two) {
-            x[i2] = xv[1];
-            r[i2] = rv[1];
-            v[0] += (double)hv[1] * rv[1];
-            v[1] += (double)rv[1] * rv[1];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            if (u == 1 && !two) break;
+            const int ii = iv[u];
+            x[ii] = xv[u];
+            rn[ii] = rv[u];
+            pnv[ii] = pv[u];
+            vn[ii] = vv[u];
+            q[0] += (double)hv[u] * vv[u];
+            q[1] += (double)rv[u] * rv[u];
         }
     }
-    const int off[2] = {poff(J, pk, PS_RHO), poff(J, pk, PS_RR)};
-    put_partials<2>(v, J.part, off, tl.t);
+    const int off[2] = {poff(J, pn, PS_Q), poff(J, pn, PS_RR)};
+    put_partials<2>(q, J.part, off, tl.t);
 }
 
 // ---- CG start, first kernel (mode as for BiCGSTAB): r = b - A x into r_(k&1),
@@ -1165,15 +1188,13 @@ static void launch_iter_t(int which, int nd, const KJob *j, const JTile *t, int 
         switch (which) {
         case KI_CG: hipLaunchKernelGGL((k_cg<5, T>), GRID(nt), 0, s, j, t, (const int *)nullptr, k); break;
         case KI_BICG_A: hipLaunchKernelGGL((k_bicg_a<5, T>), GRID(nt), 0, s, j, t, (const int *)nullptr, k); break;
-        case KI_BICG_B: hipLaunchKernelGGL((k_bicg_b<5, T>), GRID(nt), 0, s, j, t, (const int *)nullptr, k); break;
-        default: hipLaunchKernelGGL((k_bicg_c<5, T>), GRID(nt), 0, s, j, t, (const int *)nullptr, k); break;
+        default: hipLaunchKernelGGL((k_bicg_b<5, T>), GRID(nt), 0, s, j, t, (const int *)nullptr, k); break;
         }
     } else {
         switch (which) {
         case KI_CG: hipLaunchKernelGGL((k_cg<7, T>), GRID(nt), 0, s, j, t, (const int *)nullptr, k); break;
         case KI_BICG_A: hipLaunchKernelGGL((k_bicg_a<7, T>), GRID(nt), 0, s, j, t, (const int *)nullptr, k); break;
-        case KI_BICG_B: hipLaunchKernelGGL((k_bicg_b<7, T>), GRID(nt), 0, s, j, t, (const int *)nullptr, k); break;
-        default: hipLaunchKernelGGL((k_bicg_c<7, T>), GRID(nt), 0, s, j, t, (const int *)nullptr, k); break;
+        default: hipLaunchKernelGGL((k_bicg_b<7, T>), GRID(nt), 0, s, j, t, (const int *)nullptr, k); break;
         }
     }
 }
@@ -1185,15 +1206,13 @@ static const void *iter_fn_t(int which, int nd)
         switch (which) {
         case KI_CG: return (const void *)&k_cg<5, T>;
         case KI_BICG_A: return (const void *)&k_bicg_a<5, T>;
-        case KI_BICG_B: return (const void *)&k_bicg_b<5, T>;
-        default: return (const void *)&k_bicg_c<5, T>;
+        default: return (const void *)&k_bicg_b<5, T>;
         }
     }
     switch (which) {
     case KI_CG: return (const void *)&k_cg<7, T>;
     case KI_BICG_A: return (const void *)&k_bicg_a<7, T>;
-    case KI_BICG_B: return (const void *)&k_bicg_b<7, T>;
-    default: return (const void *)&k_bicg_c<7, T>;
+    default: return (const void *)&k_bicg_b<7, T>;
     }
 }
 
@@ -1249,8 +1268,13 @@ static void launch_init_t(int kind, int nd, const KJob *j, const JTile *t, int n
             hipLaunchKernelGGL((k_cg_init_b<7, T>), GRID(nt), 0, s, j, t, k, mode);
         }
     } else {
-        if (nd == 5) hipLaunchKernelGGL((k_bicg_init<5, T>), GRID(nt), 0, s, j, t, k, mode);
-        else hipLaunchKernelGGL((k_bicg_init<7, T>), GRID(nt), 0, s, j, t, k, mode);
+        if (nd == 5) {
+            hipLaunchKernelGGL((k_bicg_init<5, T>), GRID(nt), 0, s, j, t, k, mode);
+            hipLaunchKernelGGL((k_bicg_first<5, T>), GRID(nt), 0, s, j, t, k);
+        } else {
+            hipLaunchKernelGGL((k_bicg_init<7, T>), GRID(nt), 0, s, j, t, k, mode);
+            hipLaunchKernelGGL((k_bicg_first<7, T>), GRID(nt), 0, s, j, t, k);
+        }
     }
 }
 

@@ -18,7 +18,7 @@ void launch_kdecide(const KJob *j, int njobs, hipStream_t s);
 // iteration kernels, all with the signature (jobs, tiles, const int *kbase,
 // int koff): iteration index = (kbase ? *kbase : 0) + koff
 enum KIter {
-    KI_CG = 0, KI_BICG_A = 1, KI_BICG_B = 2, KI_BICG_C = 3,
+    KI_CG = 0, KI_BICG_A = 1, KI_BICG_B = 2,
     KI_MG_PQ = 4, KI_MG_DOWN0 = 5, KI_MG_DOWN = 6, KI_MG_EXACT = 7, KI_MG_UP = 8, KI_MG_UP0 = 9,
     KI_MG_DOWN0_INIT = 10
 };

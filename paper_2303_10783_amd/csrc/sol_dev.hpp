@@ -71,7 +71,7 @@ struct KState {
 
 // Partial-sum slots of a solve: part[(par * NSLOT + slot) * ntile + tile],
 // par = parity of the iteration that produced them.
-enum PSlot { PS_Q = 0, PS_TS = 1, PS_TT = 2, PS_RHO = 3, PS_RR = 4, PS_BB = 5, NSLOT = 6 };
+enum PSlot { PS_Q = 0, PS_TS = 1, PS_TT = 2, PS_RHO = 3, PS_RR = 4, PS_BB = 5, PS_RHS = 6, PS_RHT = 7, NSLOT = 8 };
 
 // Physical / geometric constants of one case (immutable after create).
 struct Phys {
@@ -130,6 +130,7 @@ struct KJob {
     void *x;
     const void *x0;           // initial guess copied into x on a fresh start (NULL: x = 0)
     void *r, *rh, *p0, *p1, *v0, *v1, *t;
+    void *r1;                 // BiCGSTAB: residual of odd iterations (r holds the even ones)
     void *aux;                // refinement: FP32 residual (the inner rhs)
     double *part;             // [2 * NSLOT * ntile]
     KState *st;
