@@ -370,6 +370,34 @@ static int upload(Group &g, T **dst, const std::vector<T> &src)
 }
 
 // partial-sum buffers, tile lists and device copy of a job set
+// Tile list of a launch that serves several solves.  The kernels map
+// workgroup b (dispatched to XCD b mod 8) to list position
+// xcd_tile(b, n): XCD x works through the x-th contiguous eighth of the
+// list.  Listing the solves one after another would give a solve that has
+// converged (its workgroups exit at once) whole XCDs, and the solves still
+// iterating only the others.  Here the x-th eighth of every solve's tiles is
+// placed in XCD x's range (tiles of one solve stay contiguous there, so
+// neighbour rows stay in that XCD's L2), the remainders dealt round-robin
+// so that the range sizes are those xcd_tile expects.
+static std::vector<JTile> xcd_order(const std::vector<std::vector<JTile>> &per_solve)
+{
+    std::vector<std::vector<JTile>> xl(NXCD);
+    int next = 0;
+    for (const auto &tl : per_solve) {
+        const int nt = (int)tl.size(), base = nt / NXCD, extra = nt % NXCD;
+        int cnt[NXCD];
+        for (int x = 0; x < NXCD; ++x) cnt[x] = base;
+        for (int e = 0; e < extra; ++e) cnt[(next + e) % NXCD] += 1;
+        next = (next + extra) % NXCD;
+        int pos = 0;
+        for (int x = 0; x < NXCD; ++x)
+            for (int i = 0; i < cnt[x]; ++i) xl[x].push_back(tl[pos++]);
+    }
+    std::vector<JTile> out;
+    for (const auto &l : xl) out.insert(out.end(), l.begin(), l.end());
+    return out;
+}
+
 static int finish_set(Group &g, JobSet &S)
 {
     size_t total = 0;
@@ -377,18 +405,21 @@ static int finish_set(Group &g, JobSet &S)
     double *part = (double *)gmalloc(g, sizeof(double) * std::max<size_t>(total, 1));
     if (!part) return fail(SOL_ENOMEM, "group allocation failed");
     size_t off = 0;
-    std::vector<JTile> jt[2];
+    std::vector<std::vector<JTile>> per[2];
     for (size_t j = 0; j < S.jobs.size(); ++j) {
         KJob &J = S.jobs[j];
         J.part = part + off;
         off += (size_t)J.ntile * 2 * NSLOT;
         const int gi = g.cs[S.case_of[j]]->z.nd == 7 ? 1 : 0;
-        for (int t = 0; t < J.ntile; ++t) jt[gi].push_back({(int)j, t});
+        std::vector<JTile> tl;
+        for (int t = 0; t < J.ntile; ++t) tl.push_back({(int)j, t, 0, 0});
+        per[gi].push_back(std::move(tl));
     }
     RCHK(upload(g, &S.jobs_d, S.jobs));
     for (int gi = 0; gi < 2; ++gi) {
-        RCHK(upload(g, &S.tiles_d[gi], jt[gi]));
-        S.nt[gi] = (int)jt[gi].size();
+        const std::vector<JTile> jt = xcd_order(per[gi]);
+        RCHK(upload(g, &S.tiles_d[gi], jt));
+        S.nt[gi] = (int)jt.size();
     }
     return SOL_OK;
 }
@@ -423,19 +454,22 @@ static int build_stages(Group &g, JobSet &S, int kind, int fp32)
     for (size_t j = 0; j < S.jobs.size(); ++j) gmax = std::max(gmax, g.cs[S.case_of[j]]->mg_nglob);
     std::vector<Stage> down(gmax), up(gmax);
     for (int l = 1; l < gmax; ++l) {
-        std::vector<JTile> jt[2];
+        std::vector<std::vector<JTile>> per[2];
         for (size_t j = 0; j < S.jobs.size(); ++j) {
             const sol_handle *h = g.cs[S.case_of[j]];
             if (h->mg_nglob <= l) continue;
             const int gi = h->z.nd == 7 ? 1 : 0;
-            for (int t = 0; t < h->mg_h[l].ntile; ++t) jt[gi].push_back({(int)j, t, l, 0});
+            std::vector<JTile> tl;
+            for (int t = 0; t < h->mg_h[l].ntile; ++t) tl.push_back({(int)j, t, l, 0});
+            per[gi].push_back(std::move(tl));
         }
         Stage st;
         st.which = KI_MG_DOWN;
         st.cls = SOL_KCLASS_MG_COARSE;
         for (int gi = 0; gi < 2; ++gi) {
-            RCHK(upload(g, &st.tiles_d[gi], jt[gi]));
-            st.nt[gi] = (int)jt[gi].size();
+            const std::vector<JTile> jt = xcd_order(per[gi]);
+            RCHK(upload(g, &st.tiles_d[gi], jt));
+            st.nt[gi] = (int)jt.size();
         }
         down[l] = st;
         up[l] = st;

@@ -711,18 +711,17 @@ __global__ __launch_bounds__(TILE) void k_bicg_a(const KJob *__restrict__ jobs, 
     const double alpha = rho / s5[4];
     const double omega = s5[1] > 0.0 ? s5[0] / s5[1] : 0.0;
     const double rho_n = s5[2] - omega * s5[3];
-    // x and r_(k+1) are written whatever the decision: a restarted solve
-    // starts from x_(k+1)
-    bool go = true;
-    double beta = 0.0;
+    // On a breakdown nothing is written: workgroup 0 records the restart,
+    // and a workgroup of this launch that starts after it reads the new
+    // status and returns at once, so a partial update by the others would
+    // leave x half-advanced.  The restart starts from x_k.
     if (omega == 0.0 || rho_n == 0.0 || rho == 0.0 || !finite(rho_n) || !finite(alpha)) {
-        set_status(tl, st, finite(rho_n) && finite(alpha) ? K_RESTART : K_NONFINITE, st->it_base + (k + 1 - st->k0),
+        set_status(tl, st, finite(rho_n) && finite(alpha) ? K_RESTART : K_NONFINITE, st->it_base + (k - st->k0),
                    st->rr);
-        go = false;
-    } else {
-        beta = (rho_n / rho) * (alpha / omega);
-        if (tl.t == 0 && threadIdx.x == 0) st->gamma[pn] = rho_n;
+        return;
     }
+    const double beta = (rho_n / rho) * (alpha / omega);
+    if (tl.t == 0 && threadIdx.x == 0) st->gamma[pn] = rho_n;
     const T ta = (T)alpha, tw = (T)omega, tb = (T)beta;
     const int n = J.n;
     auto A = G<T>(J.A);
@@ -732,14 +731,6 @@ __global__ __launch_bounds__(TILE) void k_bicg_a(const KJob *__restrict__ jobs, 
     auto t = G<T>(J.t), mi = G<T>(J.minv), rh = G<T>(J.rh), x = G<T>(J.x);
     double q[2] = {0.0, 0.0};       // (rh, v_(k+1)), ||r_(k+1)||^2
     const int i0 = tl.t * J.rpt, i1 = min(n, i0 + J.rpt);
-    if (!go) {
-        for (int i = i0 + threadIdx.x; i < i1; i += TILE) {
-            const T si = rk[i] - ta * vk[i];
-            x[i] = x[i] + mi[i] * (ta * pkv[i] + tw * si);
-            rn[i] = si - tw * t[i];
-        }
-        return;
-    }
     // p_(k+1) at row j from vectors no workgroup of this launch writes
     auto pnext = [&](int j) {
         const T rj = (rk[j] - ta * vk[j]) - tw * t[j];
