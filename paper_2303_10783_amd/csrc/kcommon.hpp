@@ -124,6 +124,25 @@ using gptr = __attribute__((address_space(1))) T *;
 template <class T>
 __device__ __forceinline__ gptr<T> G(const void *p) { return (gptr<T>)(p); }
 
+// Read-only view of a global vector indexed by a 32-bit element index: the
+// address is a uniform base plus a 32-bit byte offset, which the compiler
+// emits as the scalar-base form of the global loads (one VGPR per address
+// instead of two); kernels that gather many neighbour values hold fewer
+// registers and more waves.  For vectors only: a vector of the largest
+// grid sol_create accepts (2.9e8 rows) stays below 4 GiB, a 7-diagonal
+// matrix would not.
+template <class T>
+struct RO {
+    const __attribute__((address_space(1))) char *b;
+    __device__ __forceinline__ T operator[](int i) const
+    {
+        return *(const __attribute__((address_space(1))) T *)(b + (unsigned)i * (unsigned)sizeof(T));
+    }
+};
+
+template <class T>
+__device__ __forceinline__ RO<T> R(const void *p) { return RO<T>{(const __attribute__((address_space(1))) char *)p}; }
+
 // y_i = sum_s A[s][i] * f(i + off_s) in type T.  Slots whose neighbour lies
 // outside the domain hold an exact 0 coefficient; their index is clamped
 // into [0, n) so that no access leaves the arrays.

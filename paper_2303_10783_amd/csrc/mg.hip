@@ -340,9 +340,10 @@ __global__ __launch_bounds__(TILE) void k_mg_pq(const KJob *__restrict__ jobs, c
     const T tb = (T)beta, tz = (T)zbar;
     const MLevel &L = J.lev[0];
     const double icx = 1.0 / L.cnx, icxy = 1.0 / ((double)L.cnx * L.cny);
-    auto z = G<T>(J.v0);
+    auto z = R<T>(J.v0);
     auto q = G<T>(J.v1);
-    auto po = G<T>(pm ? J.p1 : J.p0), pn = G<T>(pk ? J.p1 : J.p0);
+    auto po = R<T>(pm ? J.p1 : J.p0);
+    auto pn = G<T>(pk ? J.p1 : J.p0);
     double v = 0.0;
     const int I0 = tl.t * L.cpt, I1 = min(L.cn, I0 + L.cpt);
     for (int I = I0 + threadIdx.x; I < I1; I += TILE) {
@@ -400,11 +401,12 @@ __global__ __launch_bounds__(TILE) void k_mg_down0(const KJob *__restrict__ jobs
     const T ta = (T)alpha, w = (T)mg_w<DIM>();
     const MLevel &L = J.lev[0];
     const double icx = 1.0 / L.cnx, icxy = 1.0 / ((double)L.cnx * L.cny);
-    auto mi = G<T>(J.minv);
+    auto mi = R<T>(J.minv);
     auto x = G<T>(J.x);
-    auto p = G<T>(pk ? J.p1 : J.p0);
-    auto q = G<T>(J.v1);
-    auto rc = G<T>(pk ? J.rh : J.r), rn = G<T>(pn1 ? J.rh : J.r);
+    auto p = R<T>(pk ? J.p1 : J.p0);
+    auto q = R<T>(J.v1);
+    auto rc = R<T>(pk ? J.rh : J.r);
+    auto rn = G<T>(pn1 ? J.rh : J.r);
     auto bc = G<T>(J.lev[1].b);
     double rr = 0.0;
     const int I0 = tl.t * L.cpt, I1 = min(L.cn, I0 + L.cpt);
@@ -540,10 +542,10 @@ __global__ __launch_bounds__(TILE) void k_mg_up0(const KJob *__restrict__ jobs, 
     const MLevel &L = J.lev[0];
     const double icx = 1.0 / L.cnx, icxy = 1.0 / ((double)L.cnx * L.cny);
     const T w = (T)mg_w<DIM>(), og = (T)mg_og<DIM>();
-    auto mi = G<T>(J.minv);
-    auto r = G<T>(pn1 ? J.rh : J.r);
+    auto mi = R<T>(J.minv);
+    auto r = R<T>(pn1 ? J.rh : J.r);
     auto z = G<T>(J.v0);
-    auto ec = G<T>(J.lev[1].e);
+    auto ec = R<T>(J.lev[1].e);
     double vv[3] = {0.0, 0.0, 0.0};     // (r, z), sum z, sum r
     const int I0 = tl.t * L.cpt, I1 = min(L.cn, I0 + L.cpt);
     for (int I = I0 + threadIdx.x; I < I1; I += TILE) {
