@@ -1021,7 +1021,15 @@ __global__ __launch_bounds__(TILE) void k_ir_decide(const KJob *__restrict__ job
         else if (st->bb == 0.0) st->status = K_ZERO;
         else if (tot[0] <= st->tol2 * st->bb) st->status = K_DONE;
         else if (st->outer >= max_outer || st->inner_total >= st->max_iter) st->status = K_FAILED;
-        else st->status = K_RUNNING;
+        else {
+            st->status = K_RUNNING;
+            // the next inner solve reduces its right-hand side r only as far
+            // as the FP64 target still needs, (0.3 tol ||b|| / ||r||)^2,
+            // bounded by what FP32 reaches (1e-5, or tol when looser) and by
+            // at least halving r
+            const double need = 0.09 * st->tol2 * st->bb / tot[0];
+            J.partner->tol2 = fmin(0.25, fmax(fmax(st->tol2, 1e-10), need));
+        }
     }
 }
 
