@@ -974,7 +974,9 @@ static int solve_plain(Group &g, Phase &P, bool speculate)
     for (int round = 0; round < 64; ++round) {
         int slot;
         const bool fast = speculate && round == 0;
-        RCHK(iterate(g, P, S, 0, round == 0 ? P.pred : std::max(2, P.pred / 8), k, nullptr, 1, &slot, !fast));
+        // the state copy after k_kdecide below follows the chunk queued
+        // ahead on the stream, so the host need not wait for that chunk
+        RCHK(iterate(g, P, S, 0, round == 0 ? P.pred : std::max(2, P.pred / 8), k, nullptr, 1, &slot, false));
         for (int gi = 0; gi < 2; ++gi) launch_kfinish(gi ? 7 : 5, S.jobs_d, S.tiles_d[gi], S.nt[gi], g.stream);
         launch_kdecide(S.jobs_d, (int)S.jobs.size(), g.stream);
         if (fast && all_converged(g, S, slot)) {

@@ -37,7 +37,7 @@
 //              r_(k+1) = r_k - alpha q; partial ||r_(k+1)||^2; pre-smooth
 //              on level 0 and restrict the residual to level 1
 //   down(l):   pre-smooth level l, restrict to level l+1     (l = 1 .. nglob-1)
-//   exact:     e = P^-1 b on level nglob (dense product, 16 rows per workgroup)
+//   exact:     e = P^-1 b on level nglob (dense product, one wave per row)
 //   up(l):     prolong, post-smooth level l                  (l = nglob-1 .. 1)
 //   up0(k):    prolong, post-smooth level 0 -> z_(k+1); partials (r, z),
 //              sum(z), sum(r)
