@@ -82,7 +82,7 @@ def counter_traffic(workload, kernel_cls, precond):
     return doc[key]["traffic_bytes_per_launch"]
 
 
-def run_single(sol, W, key, precision, steps, warmup, dev, graph=False, precond="mg"):
+def run_single(sol, W, key, precision, steps, warmup, dev, graph=False, precond="mg", tprecond=None):
     import torch
     case = W.workload_case(key)
     if precision == "mixed":
@@ -92,6 +92,8 @@ def run_single(sol, W, key, precision, steps, warmup, dev, graph=False, precond=
     h = sol.Case(case, device=dev)
     if precond != "mg":
         h.set_precond(precond)
+    if tprecond:
+        h.set_tprecond(tprecond)
     if graph:
         h.set_graph(True)
     if warmup:
@@ -188,6 +190,9 @@ def main():
     ap.add_argument("--graph", action="store_true", help="replay Krylov chunks as HIP graphs")
     ap.add_argument("--precond", default="mg", choices=["mg", "jacobi"],
                     help="pressure-CG preconditioner (multigrid V-cycle or Jacobi)")
+    ap.add_argument("--tprecond", default=None, choices=["jacobi", "jacobi2", "auto"],
+                    help="BiCGSTAB preconditioner: one or two Jacobi sweeps, or the library's default "
+                         "(auto: two in 2D, one in 3D)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -209,6 +214,8 @@ def main():
     g = sol.Case(case, device=dev)
     if args.precond != "mg":
         g.set_precond(args.precond)
+    if args.tprecond:
+        g.set_tprecond(args.tprecond)
     if args.graph:
         g.set_graph(True)
     if args.warmup:
@@ -260,7 +267,8 @@ def main():
         config=dict(workload=f"{args.workload}: 2D cavity {grid['nx']}x{grid['ny']}" if grid["dim"] == 2
                     else f"{args.workload}: 3D box {grid['nx']}x{grid['ny']}x{grid['nz']}",
                     cells=ncell, dt=case["numerics"]["dt"], tol=case["numerics"]["tol_p"],
-                    precision=args.precision, pressure_precond=args.precond, krylov_iters_per_step={
+                    precision=args.precision, pressure_precond=args.precond,
+                    transport_precond=args.tprecond or "auto", krylov_iters_per_step={
                         n: round(iters[i] / args.steps, 1) for i, n in enumerate("uvwpCT")},
                     steps_redone=st["redone"]),
         roofline=roof, cpu_baseline=cpu, variants=variants,

@@ -10,8 +10,9 @@
  * assembled term-wise (Section 4): constant-coefficient terms (transient,
  * diffusion, wall terms, the pressure Laplacian) once at creation, upwind
  * convection, Carman-Kozeny drag and the right-hand sides every step.
- * Linear systems: Jacobi-preconditioned CG (pressure) and BiCGSTAB
- * (momentum, solute, energy), stopped on the true residual
+ * Linear systems: CG preconditioned by a multigrid V-cycle (pressure;
+ * Jacobi on request) and BiCGSTAB preconditioned by one or two Jacobi
+ * sweeps (momentum, solute, energy), stopped on the true residual
  * ||b - A x||_2 <= tol ||b||_2.  Every step of the path runs in HIP kernels
  * on one gfx950 device; the library never computes a step on the host.
  *
@@ -235,6 +236,21 @@ int sol_get_timing(sol_handle *h, int32_t kclass, int64_t *launches, double *tot
 #define SOL_OPT_PRECOND 2
 #define SOL_PRECOND_JACOBI 0
 #define SOL_PRECOND_MG     1
+/* SOL_OPT_TPRECOND: preconditioner of the BiCGSTAB solves of the momentum
+   (eq. 3.3), solute (eq. 3.10) and energy (eq. 3.11) systems.
+   SOL_TPRECOND_JACOBI: the inverse diagonal.  SOL_TPRECOND_JACOBI2: two
+   Jacobi sweeps from a zero start, M f = D^-1 (f - (A - D) D^-1 f), D the
+   diagonal of A: about half the iterations of one sweep on these systems,
+   each product A M f reaching two stencil steps.  SOL_TPRECOND_AUTO
+   (default): two sweeps on 2D (5-point) systems, one on 3D (7-point)
+   systems, the faster choice for each on gfx950.  All stop at the same
+   relative residual of the unpreconditioned system.  Not allowed while the
+   handle is part of a batch (SOL_EBUSY); the handles of one batch must
+   share it (SOL_EINVAL at sol_batch_create). */
+#define SOL_OPT_TPRECOND 3
+#define SOL_TPRECOND_JACOBI  0
+#define SOL_TPRECOND_JACOBI2 1
+#define SOL_TPRECOND_AUTO    2
 int sol_set_option(sol_handle *h, int32_t option, int64_t value);
 
 /* Tile-size autotuner: times iterations of this case's pressure solve

@@ -9,7 +9,8 @@ ROOT = os.path.dirname(HERE)
 SOURCES = ["csrc/kernels.hip", "csrc/mg.hip", "csrc/engine.hip"]
 OUT = os.path.join(HERE, "libsol.so")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
-         # packed FP32 instructions stay off
+         # packed FP32 instructions stay off: some of their forms have given
+         # silently wrong results on gfx950
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-function"]
 

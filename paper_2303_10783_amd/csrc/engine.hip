@@ -264,6 +264,7 @@ struct sol_handle {
     bool timing = false;
     bool opt_graph = false;
     int precond = SOL_PRECOND_MG;
+    int tprecond = SOL_TPRECOND_AUTO;
     double *mg_pwork = nullptr;           // scratch of the exact-level inverse (set-up)
     double *mg_p64 = nullptr;             // FP64 exact-level inverse (set-up; solves read its FP32 copy)
     int64_t redone = 0;                   // steps run a second time (speculative check failed)
@@ -286,6 +287,7 @@ struct Stage {
     JTile *tiles_d[2] = {nullptr, nullptr};
     int nt[2] = {0, 0};
     size_t smem[2] = {0, 0};
+    bool two[2] = {false, false};        // BiCGSTAB: two Jacobi sweeps (per stencil width)
 };
 
 // A set of solves launched together (one kernel launch serves all of them).
@@ -304,6 +306,7 @@ struct JobSet {
 
 struct Phase {
     int kind = K_BICGSTAB;
+    bool two[2] = {false, false};        // BiCGSTAB: two Jacobi sweeps, 5- / 7-point systems
     int tcls0 = SOL_KCLASS_BICG_A;       // timing class of the first iteration kernel
     bool mixed = false;
     JobSet main;                         // FP64 solves (plain, or the refinements)
@@ -398,6 +401,15 @@ static std::vector<JTile> xcd_order(const std::vector<std::vector<JTile>> &per_s
     return out;
 }
 
+// BiCGSTAB preconditioner of a system with nd diagonals: two Jacobi sweeps
+// or one.  Automatic: two on 5-point (2D) systems, where halving the
+// iterations outweighs the wider gathers; one on 7-point (3D) systems, where
+// the 25-cell gathers cost more than the iterations they save.
+static bool two_sweeps(int tprecond, int nd)
+{
+    return tprecond == SOL_TPRECOND_JACOBI2 || (tprecond == SOL_TPRECOND_AUTO && nd == 5);
+}
+
 static int finish_set(Group &g, JobSet &S)
 {
     size_t total = 0;
@@ -425,7 +437,7 @@ static int finish_set(Group &g, JobSet &S)
 }
 
 // launches of one iteration (and of the multigrid start cycle) of a job set
-static int build_stages(Group &g, JobSet &S, int kind, int fp32)
+static int build_stages(Group &g, JobSet &S, int kind, const bool (&two)[2], int fp32)
 {
     S.iter.clear();
     S.start.clear();
@@ -436,6 +448,7 @@ static int build_stages(Group &g, JobSet &S, int kind, int fp32)
         for (int gi = 0; gi < 2; ++gi) {
             st.tiles_d[gi] = S.tiles_d[gi];
             st.nt[gi] = S.nt[gi];
+            st.two[gi] = two[gi];
         }
         return st;
     };
@@ -585,6 +598,7 @@ static int group_build(Group &g)
     for (int p = 0; p < 3; ++p) {
         Phase &P = g.ph[p];
         P.kind = p == 1 ? (mg ? K_MGCG : K_CG) : K_BICGSTAB;
+        for (int gi = 0; gi < 2; ++gi) P.two[gi] = P.kind == K_BICGSTAB && two_sweeps(g.cs[0]->tprecond, gi ? 7 : 5);
         P.tcls0 = p == 1 ? (mg ? SOL_KCLASS_MG_PQ : SOL_KCLASS_CG) : SOL_KCLASS_BICG_A;
         P.mixed = mixed;
         for (int c = 0; c < n; ++c) {
@@ -658,10 +672,10 @@ static int group_build(Group &g)
             }
         }
         RCHK(finish_set(g, P.main));
-        RCHK(build_stages(g, P.main, P.kind, 0));
+        RCHK(build_stages(g, P.main, P.kind, P.two, 0));
         if (mixed) {
             RCHK(finish_set(g, P.inner));
-            RCHK(build_stages(g, P.inner, P.kind, 1));
+            RCHK(build_stages(g, P.inner, P.kind, P.two, 1));
         }
         P.pred = P.pred_inner = p == 1 ? (mg ? 24 : 64) : 2;
     }
@@ -769,7 +783,7 @@ static int build_chunk_graph(Group &g, Phase &P, JobSet &S, int fp32)
                 void *args[] = {(void *)&jobs, (void *)&tiles, (void *)&kb, (void *)&koff};
                 hipKernelNodeParams kp;
                 std::memset(&kp, 0, sizeof(kp));
-                kp.func = (void *)kiter_fn(st.which, gi ? 7 : 5, fp32);
+                kp.func = (void *)kiter_fn(st.which, gi ? 7 : 5, fp32, st.two[gi]);
                 kp.gridDim = dim3((unsigned)st.nt[gi]);
                 kp.blockDim = dim3(TILE);
                 kp.sharedMemBytes = (unsigned)st.smem[gi];
@@ -808,7 +822,7 @@ static int launch_stage(Group &g, const JobSet &S, const Stage &st, int fp32, in
         const JTile *tiles = st.tiles_d[gi];
         const int *kb = nullptr;
         void *args[] = {(void *)&jobs, (void *)&tiles, (void *)&kb, (void *)&koff};
-        const void *fn = kiter_fn(st.which, gi ? 7 : 5, fp32);
+        const void *fn = kiter_fn(st.which, gi ? 7 : 5, fp32, st.two[gi]);
         if (ta && tb)
             HIPCHK(hipExtLaunchKernel(fn, dim3((unsigned)st.nt[gi]), dim3(TILE), args, st.smem[gi], g.stream, ta, tb, 0));
         else
@@ -823,7 +837,7 @@ static int start_solves(Group &g, Phase &P, JobSet &S, int fp32, int k, int mode
 {
     if (P.kind != K_MGCG) {
         for (int gi = 0; gi < 2; ++gi)
-            launch_kinit(P.kind, gi ? 7 : 5, fp32, S.jobs_d, S.tiles_d[gi], S.nt[gi], k, mode, g.stream);
+            launch_kinit(P.kind, gi ? 7 : 5, fp32, P.two[gi], S.jobs_d, S.tiles_d[gi], S.nt[gi], k, mode, g.stream);
         return SOL_OK;
     }
     for (int gi = 0; gi < 2; ++gi) launch_mg_init(gi ? 7 : 5, fp32, S.jobs_d, S.tiles_d[gi], S.nt[gi], k, mode, g.stream);
@@ -1716,6 +1730,17 @@ int sol_set_option(sol_handle *h, int32_t option, int64_t value)
         h->solo = nullptr;
         return group_create({h}, &h->solo);
     }
+    case SOL_OPT_TPRECOND: {
+        if (value != SOL_TPRECOND_JACOBI && value != SOL_TPRECOND_JACOBI2 && value != SOL_TPRECOND_AUTO)
+            return fail(SOL_EINVAL, "unknown transport preconditioner %lld", (long long)value);
+        if (h->batch) return fail(SOL_EBUSY, "handle is part of a batch");
+        if (h->tprecond == (int)value) return SOL_OK;
+        (void)hipStreamSynchronize(h->stream);
+        h->tprecond = (int)value;
+        group_free(h->solo);
+        h->solo = nullptr;
+        return group_create({h}, &h->solo);
+    }
     }
     return fail(SOL_EINVAL, "unknown option %d", option);
 }
@@ -1825,6 +1850,8 @@ int sol_batch_create(sol_handle *const *cases, int32_t n, sol_batch **out)
             return fail(SOL_EINVAL, "handles of one batch must share one precision");
         if (cases[i]->precond != cases[0]->precond)
             return fail(SOL_EINVAL, "handles of one batch must share one pressure preconditioner");
+        if (cases[i]->tprecond != cases[0]->tprecond)
+            return fail(SOL_EINVAL, "handles of one batch must share one transport preconditioner");
         for (int j = 0; j < i; ++j)
             if (cases[j] == cases[i]) return fail(SOL_EINVAL, "handle %d given twice", i);
     }

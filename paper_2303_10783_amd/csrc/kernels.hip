@@ -561,6 +561,104 @@ __global__ __launch_bounds__(TILE) void k_case_stats(const CaseDev *__restrict__
 // orders of magnitude, as the diagonally dominant momentum systems do.  rho
 // has no such cancellation: (rh,s) vanishes in exact arithmetic.
 //
+// ---- Transport preconditioner M (template argument PD).  PD 1: the inverse
+// diagonal.  PD 2: two Jacobi sweeps from zero, z1 = D^-1 f, z2 = z1 + D^-1
+// (f - A z1), i.e. M f = D^-1 (f - N D^-1 f) with N = A - D the off-diagonal
+// part; about half the iterations of PD 1 on the momentum and energy
+// systems.  A product A M f at row i then reaches every cell within two
+// stencil steps of i (13 in 2D, 25 in 3D); each is gathered once, with the
+// vectors that define f there recomputed as for PD 1, and combined from
+// registers.  A cell outside the domain is only reached through an exact 0
+// coefficient (of row i, or of the neighbour row in between); its index is
+// clamped into [0, n) like kstencil's.
+
+template <int ND>
+struct Ring2 {
+    static constexpr int NC = ND == 5 ? 13 : 25;
+    int d[NC][3];                 // (dx, dy, dz) of each cell
+    int nb[ND][ND];               // cell reached by DIA slot s, then slot s2
+};
+
+// unit step along axis a of DIA slot s (slot order -z, -y, -x, 0, +x, +y, +z)
+template <int ND>
+constexpr int slot_step(int s, int a)
+{
+    const int u = s - ND / 2;
+    const int m = u < 0 ? -u : u;
+    return (m != 0 && m - 1 == a) ? (u < 0 ? -1 : 1) : 0;
+}
+
+template <int ND>
+constexpr Ring2<ND> make_ring2()
+{
+    Ring2<ND> R{};
+    int c = 0;
+    const int zr = ND == 7 ? 2 : 0;
+    for (int dz = -zr; dz <= zr; ++dz)
+        for (int dy = -2; dy <= 2; ++dy)
+            for (int dx = -2; dx <= 2; ++dx)
+                if ((dx < 0 ? -dx : dx) + (dy < 0 ? -dy : dy) + (dz < 0 ? -dz : dz) <= 2) {
+                    R.d[c][0] = dx;
+                    R.d[c][1] = dy;
+                    R.d[c][2] = dz;
+                    ++c;
+                }
+    for (int s = 0; s < ND; ++s)
+        for (int s2 = 0; s2 < ND; ++s2)
+            for (int q = 0; q < Ring2<ND>::NC; ++q) {
+                bool same = true;
+                for (int a = 0; a < 3; ++a) same = same && R.d[q][a] == slot_step<ND>(s, a) + slot_step<ND>(s2, a);
+                if (same) R.nb[s][s2] = q;
+            }
+    return R;
+}
+
+template <int ND>
+struct Ring2Tab {
+    static constexpr Ring2<ND> R = make_ring2<ND>();
+};
+
+// row of ring cell c of row i, clamped into [0, n)
+template <int ND>
+__device__ __forceinline__ int ring_row(int i, int c, int sx, int sxy, int n)
+{
+    constexpr Ring2<ND> R = Ring2Tab<ND>::R;
+    const int j = i + R.d[c][0] + R.d[c][1] * sx + R.d[c][2] * sxy;
+    return j < 0 ? 0 : (j >= n ? n - 1 : j);
+}
+
+// PD 2: (A M f)_i from y[c] = (D^-1 f) at the ring cells idx[c] of row i.
+// Ad[s] views diagonal s, mi the inverse diagonal: every load is a uniform
+// base plus the 32-bit offset of its cell, one register per ring cell for
+// all vectors and diagonals.
+template <int ND, class T>
+__device__ __forceinline__ T ring_amf(const RO<T> (&Ad)[ND], RO<T> mi, const int (&idx)[Ring2<ND>::NC],
+                                      const T (&y)[Ring2<ND>::NC])
+{
+    constexpr Ring2<ND> RG = Ring2Tab<ND>::R;
+    constexpr int C = ND / 2;
+    const int i = idx[RG.nb[C][C]];
+    T acc = T(0);
+#pragma unroll
+    for (int s = 0; s < ND; ++s) {
+        const int cj = RG.nb[s][C];
+        const int j = idx[cj];
+        T ns = T(0);
+#pragma unroll
+        for (int s2 = 0; s2 < ND; ++s2)
+            if (s2 != C) ns += Ad[s2][j] * y[RG.nb[s][s2]];
+        acc += Ad[s][i] * (y[cj] - mi[j] * ns);
+    }
+    return acc;
+}
+
+template <int ND, class T>
+__device__ __forceinline__ void diag_views(const void *A, int n, RO<T> (&Ad)[ND])
+{
+#pragma unroll
+    for (int s = 0; s < ND; ++s) Ad[s] = R<T>((const T *)A + (size_t)s * n);
+}
+
 // Start at iteration index k (mode 0: every solve, x = x0 or 0; mode 1:
 // solves in K_RESTART, keep x): r_k = b - A x, rh = r_k; partials (rh, r_k),
 // (r_k, r_k), (b, b).
@@ -605,7 +703,7 @@ __global__ __launch_bounds__(TILE) void k_bicg_init(const KJob *__restrict__ job
 
 // first iteration of a (re)start at k = k0: convergence test on r_k; p_k =
 // r_k, v_k = A M p_k; partial (rh, v_k)
-template <int ND, class T>
+template <int ND, int PD, class T>
 __global__ __launch_bounds__(TILE) void k_bicg_first(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles, int k)
 {
     JTile tl;
@@ -626,7 +724,23 @@ __global__ __launch_bounds__(TILE) void k_bicg_first(const KJob *__restrict__ jo
     double q = 0.0;
     const int i0 = tl.t * J.rpt, i1 = min(n, i0 + J.rpt);
     for (int i = i0 + threadIdx.x; i < i1; i += TILE) {
-        const T vi = kstencil<ND, T>(A, n, i, J.sx, J.sxy, [&](int j) { return mi[j] * r[j]; });
+        T vi;
+        if constexpr (PD == 1) {
+            vi = kstencil<ND, T>(A, n, i, J.sx, J.sxy, [&](int j) { return mi[j] * r[j]; });
+        } else {
+            constexpr int NC = Ring2<ND>::NC;
+            RO<T> Ad[ND];
+            diag_views<ND, T>(J.A, n, Ad);
+            const auto Mi = R<T>(J.minv), Rr = R<T>(pk ? J.r1 : J.r);
+            int idx[NC];
+            T y[NC];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                idx[c] = ring_row<ND>(i, c, J.sx, J.sxy, n);
+                y[c] = Mi[idx[c]] * Rr[idx[c]];
+            }
+            vi = ring_amf<ND, T>(Ad, Mi, idx, y);
+        }
         p[i] = r[i];
         vv[i] = vi;
         q += (double)rh[i] * vi;
@@ -636,9 +750,9 @@ __global__ __launch_bounds__(TILE) void k_bicg_first(const KJob *__restrict__ jo
     put_partials<1>(v1, J.part, off, tl.t);
 }
 
-// B(k)
-template <int ND, class T>
-__global__ __launch_bounds__(TILE) void k_bicg_b(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles, const int *kbase, int koff)
+// B(k); kernels below
+template <int ND, int PD, class T>
+__device__ __forceinline__ void bicg_b_body(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles, const int *kbase, int koff)
 {
     const int k = (kbase ? *kbase : 0) + koff;
     JTile tl;
@@ -664,6 +778,30 @@ __global__ __launch_bounds__(TILE) void k_bicg_b(const KJob *__restrict__ jobs, 
     auto t = G<T>(J.t);
     double v[4] = {0.0, 0.0, 0.0, 0.0};     // (t,s) (t,t) (rh,s) (rh,t)
     const int i0 = tl.t * J.rpt, i1 = min(n, i0 + J.rpt);
+    if constexpr (PD == 2) {
+        constexpr int NC = Ring2<ND>::NC;
+        RO<T> Ad[ND];
+        diag_views<ND, T>(J.A, n, Ad);
+        const auto Mi = R<T>(J.minv), Rr = R<T>(pk ? J.r1 : J.r), Vk = R<T>(pk ? J.v1 : J.v0), Rh = R<T>(J.rh);
+        for (int i = i0 + threadIdx.x; i < i1; i += TILE) {
+            int idx[NC];
+            T y[NC];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                idx[c] = ring_row<ND>(i, c, J.sx, J.sxy, n);
+                y[c] = Mi[idx[c]] * (Rr[idx[c]] - alpha * Vk[idx[c]]);
+            }
+            const T ti = ring_amf<ND, T>(Ad, Mi, idx, y);
+            const T si = Rr[i] - alpha * Vk[i];
+            const T hi = Rh[i];
+            t[i] = ti;
+            const double sd = si, td = ti, hd = hi;
+            v[0] += td * sd;
+            v[1] += td * td;
+            v[2] += hd * sd;
+            v[3] += hd * td;
+        }
+    } else
     for (int i = i0 + threadIdx.x; i < i1; i += 2 * TILE) {
         const bool two = i + TILE < i1;
         const int i2 = two ? i + TILE : i;
@@ -691,9 +829,9 @@ __global__ __launch_bounds__(TILE) void k_bicg_b(const KJob *__restrict__ jobs, 
     put_partials<4>(v, J.part, off, tl.t);
 }
 
-// A(k)
-template <int ND, class T>
-__global__ __launch_bounds__(TILE) void k_bicg_a(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles, const int *kbase, int koff)
+// A(k); kernels below
+template <int ND, int PD, class T>
+__device__ __forceinline__ void bicg_a_body(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles, const int *kbase, int koff)
 {
     const int k = (kbase ? *kbase : 0) + koff;
     JTile tl;
@@ -736,6 +874,47 @@ __global__ __launch_bounds__(TILE) void k_bicg_a(const KJob *__restrict__ jobs, 
         const T rj = (rk[j] - ta * vk[j]) - tw * t[j];
         return rj + tb * (pkv[j] - tw * vk[j]);
     };
+    if constexpr (PD == 2) {
+        constexpr int NC = Ring2<ND>::NC, C = ND / 2;
+        constexpr Ring2<ND> RG = Ring2Tab<ND>::R;
+        RO<T> Ad[ND];
+        diag_views<ND, T>(J.A, n, Ad);
+        const auto Mi = R<T>(J.minv), Rk = R<T>(pk ? J.r1 : J.r), Vk = R<T>(pk ? J.v1 : J.v0),
+                   Pk = R<T>(pk ? J.p1 : J.p0), Tt = R<T>(J.t), Rh = R<T>(J.rh), X = R<T>(J.x);
+        for (int i = i0 + threadIdx.x; i < i1; i += TILE) {
+            int idx[NC];
+            T y[NC], g[ND];
+            T pi = T(0);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                const int j = ring_row<ND>(i, c, J.sx, J.sxy, n);
+                idx[c] = j;
+                const T sj = Rk[j] - ta * Vk[j];
+                const T pc = (sj - tw * Tt[j]) + tb * (Pk[j] - tw * Vk[j]);
+                if (c == RG.nb[C][C]) pi = pc;
+                y[c] = Mi[j] * pc;
+#pragma unroll
+                for (int s2 = 0; s2 < ND; ++s2)
+                    if (c == RG.nb[s2][C]) g[s2] = ta * Pk[j] + tw * sj;
+            }
+            const T vi = ring_amf<ND, T>(Ad, Mi, idx, y);
+            // x += M (alpha p_k + omega s), the product at row i only
+            T gs = T(0);
+#pragma unroll
+            for (int s2 = 0; s2 < ND; ++s2)
+                if (s2 != C) gs += Ad[s2][i] * (Mi[idx[RG.nb[s2][C]]] * g[s2]);
+            const T si = Rk[i] - ta * Vk[i];
+            const T xi = X[i] + Mi[i] * (g[C] - gs);
+            const T ri = si - tw * Tt[i];
+            const T hi = Rh[i];
+            x[i] = xi;
+            rn[i] = ri;
+            pnv[i] = pi;
+            vn[i] = vi;
+            q[0] += (double)hi * vi;
+            q[1] += (double)ri * ri;
+        }
+    } else
     for (int i = i0 + threadIdx.x; i < i1; i += 2 * TILE) {
         const bool two = i + TILE < i1;
         const int i2 = two ? i + TILE : i;
@@ -766,6 +945,26 @@ __global__ __launch_bounds__(TILE) void k_bicg_a(const KJob *__restrict__ jobs, 
     const int off[2] = {poff(J, pn, PS_Q), poff(J, pn, PS_RR)};
     put_partials<2>(q, J.part, off, tl.t);
 }
+
+// B(k) and A(k) kernels.  One sweep: k_bicg_b / k_bicg_a.  Two sweeps:
+// k_bicg2_b64 / k_bicg2_a64 (FP64) let the compiler use up to two waves' worth
+// of registers per lane, so that a row's 60-180 gathers are issued together
+// rather than in a chain of round trips (measured faster at 500x300);
+// k_bicg2_b32 / k_bicg2_a32 (FP32 inner solves) were faster without it.
+template <int ND, class T>
+__global__ __launch_bounds__(TILE) void k_bicg_b(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles, const int *kbase, int koff) { bicg_b_body<ND, 1, T>(jobs, tiles, kbase, koff); }
+template <int ND, class T>
+__global__ __launch_bounds__(TILE) void k_bicg_a(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles, const int *kbase, int koff) { bicg_a_body<ND, 1, T>(jobs, tiles, kbase, koff); }
+template <int ND>
+__global__ __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(1, 2)))
+void k_bicg2_b64(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles, const int *kbase, int koff) { bicg_b_body<ND, 2, double>(jobs, tiles, kbase, koff); }
+template <int ND>
+__global__ __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(1, 2)))
+void k_bicg2_a64(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles, const int *kbase, int koff) { bicg_a_body<ND, 2, double>(jobs, tiles, kbase, koff); }
+template <int ND>
+__global__ __launch_bounds__(TILE) void k_bicg2_b32(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles, const int *kbase, int koff) { bicg_b_body<ND, 2, float>(jobs, tiles, kbase, koff); }
+template <int ND>
+__global__ __launch_bounds__(TILE) void k_bicg2_a32(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles, const int *kbase, int koff) { bicg_a_body<ND, 2, float>(jobs, tiles, kbase, koff); }
 
 // ---- CG start, first kernel (mode as for BiCGSTAB): r = b - A x into r_(k&1),
 // s_(k&1) = 0, p = 0; partials (r, r), (b, b)
@@ -1180,45 +1379,27 @@ void launch_phase_commit(int dim, const CaseDev *c, const Tile *t, int nt, hipSt
     else hipLaunchKernelGGL(k_phase_commit<3>, GRID(nt), 0, s, c, t);
 }
 
-template <class T>
-static void launch_iter_t(int which, int nd, const KJob *j, const JTile *t, int nt, int k, hipStream_t s)
+template <int ND, class T>
+static const void *iter_fn_t(int which, bool two)
 {
-    if (nd == 5) {
-        switch (which) {
-        case KI_CG: hipLaunchKernelGGL((k_cg<5, T>), GRID(nt), 0, s, j, t, (const int *)nullptr, k); break;
-        case KI_BICG_A: hipLaunchKernelGGL((k_bicg_a<5, T>), GRID(nt), 0, s, j, t, (const int *)nullptr, k); break;
-        default: hipLaunchKernelGGL((k_bicg_b<5, T>), GRID(nt), 0, s, j, t, (const int *)nullptr, k); break;
-        }
-    } else {
-        switch (which) {
-        case KI_CG: hipLaunchKernelGGL((k_cg<7, T>), GRID(nt), 0, s, j, t, (const int *)nullptr, k); break;
-        case KI_BICG_A: hipLaunchKernelGGL((k_bicg_a<7, T>), GRID(nt), 0, s, j, t, (const int *)nullptr, k); break;
-        default: hipLaunchKernelGGL((k_bicg_b<7, T>), GRID(nt), 0, s, j, t, (const int *)nullptr, k); break;
-        }
-    }
-}
-
-template <class T>
-static const void *iter_fn_t(int which, int nd)
-{
-    if (nd == 5) {
-        switch (which) {
-        case KI_CG: return (const void *)&k_cg<5, T>;
-        case KI_BICG_A: return (const void *)&k_bicg_a<5, T>;
-        default: return (const void *)&k_bicg_b<5, T>;
-        }
-    }
+    constexpr bool f64 = sizeof(T) == 8;
     switch (which) {
-    case KI_CG: return (const void *)&k_cg<7, T>;
-    case KI_BICG_A: return (const void *)&k_bicg_a<7, T>;
-    default: return (const void *)&k_bicg_b<7, T>;
+    case KI_CG: return (const void *)&k_cg<ND, T>;
+    case KI_BICG_A:
+        if (!two) return (const void *)&k_bicg_a<ND, T>;
+        return f64 ? (const void *)&k_bicg2_a64<ND> : (const void *)&k_bicg2_a32<ND>;
+    case KI_BICG_B:
+        if (!two) return (const void *)&k_bicg_b<ND, T>;
+        return f64 ? (const void *)&k_bicg2_b64<ND> : (const void *)&k_bicg2_b32<ND>;
     }
+    return nullptr;
 }
 
-const void *kiter_fn(int which, int nd, int fp32)
+const void *kiter_fn(int which, int nd, int fp32, bool two)
 {
     if (which >= KI_MG_PQ) return mg_fn(which, nd, fp32);
-    return fp32 ? iter_fn_t<float>(which, nd) : iter_fn_t<double>(which, nd);
+    if (nd == 5) return fp32 ? iter_fn_t<5, float>(which, two) : iter_fn_t<5, double>(which, two);
+    return fp32 ? iter_fn_t<7, float>(which, two) : iter_fn_t<7, double>(which, two);
 }
 
 // iteration index base of graph-replayed chunks
@@ -1248,40 +1429,30 @@ void launch_tune_rhs(void *b, int fp32, int n, hipStream_t s)
     else hipLaunchKernelGGL(k_tune_rhs<double>, dim3(ceil_div(n, TILE)), dim3(TILE), 0, s, (double *)b, n);
 }
 
-void launch_kiter(int which, int nd, int fp32, const KJob *j, const JTile *t, int nt, int k, hipStream_t s)
-{
-    if (nt <= 0) return;
-    if (fp32) launch_iter_t<float>(which, nd, j, t, nt, k, s);
-    else launch_iter_t<double>(which, nd, j, t, nt, k, s);
-}
-
-template <class T>
-static void launch_init_t(int kind, int nd, const KJob *j, const JTile *t, int nt, int k, int mode, hipStream_t s)
+template <int ND, class T>
+static void launch_init_nd(int kind, bool two, const KJob *j, const JTile *t, int nt, int k, int mode, hipStream_t s)
 {
     if (kind == K_CG) {
-        if (nd == 5) {
-            hipLaunchKernelGGL((k_cg_init_a<5, T>), GRID(nt), 0, s, j, t, k, mode);
-            hipLaunchKernelGGL((k_cg_init_b<5, T>), GRID(nt), 0, s, j, t, k, mode);
-        } else {
-            hipLaunchKernelGGL((k_cg_init_a<7, T>), GRID(nt), 0, s, j, t, k, mode);
-            hipLaunchKernelGGL((k_cg_init_b<7, T>), GRID(nt), 0, s, j, t, k, mode);
-        }
-    } else {
-        if (nd == 5) {
-            hipLaunchKernelGGL((k_bicg_init<5, T>), GRID(nt), 0, s, j, t, k, mode);
-            hipLaunchKernelGGL((k_bicg_first<5, T>), GRID(nt), 0, s, j, t, k);
-        } else {
-            hipLaunchKernelGGL((k_bicg_init<7, T>), GRID(nt), 0, s, j, t, k, mode);
-            hipLaunchKernelGGL((k_bicg_first<7, T>), GRID(nt), 0, s, j, t, k);
-        }
+        hipLaunchKernelGGL((k_cg_init_a<ND, T>), GRID(nt), 0, s, j, t, k, mode);
+        hipLaunchKernelGGL((k_cg_init_b<ND, T>), GRID(nt), 0, s, j, t, k, mode);
+        return;
     }
+    hipLaunchKernelGGL((k_bicg_init<ND, T>), GRID(nt), 0, s, j, t, k, mode);
+    if (two) hipLaunchKernelGGL((k_bicg_first<ND, 2, T>), GRID(nt), 0, s, j, t, k);
+    else hipLaunchKernelGGL((k_bicg_first<ND, 1, T>), GRID(nt), 0, s, j, t, k);
 }
 
-void launch_kinit(int kind, int nd, int fp32, const KJob *j, const JTile *t, int nt, int k, int mode, hipStream_t s)
+void launch_kinit(int kind, int nd, int fp32, bool two, const KJob *j, const JTile *t, int nt, int k, int mode,
+                  hipStream_t s)
 {
     if (nt <= 0) return;
-    if (fp32) launch_init_t<float>(kind, nd, j, t, nt, k, mode, s);
-    else launch_init_t<double>(kind, nd, j, t, nt, k, mode, s);
+    if (nd == 5) {
+        if (fp32) launch_init_nd<5, float>(kind, two, j, t, nt, k, mode, s);
+        else launch_init_nd<5, double>(kind, two, j, t, nt, k, mode, s);
+    } else {
+        if (fp32) launch_init_nd<7, float>(kind, two, j, t, nt, k, mode, s);
+        else launch_init_nd<7, double>(kind, two, j, t, nt, k, mode, s);
+    }
 }
 
 void launch_kfinish(int nd, const KJob *j, const JTile *t, int nt, hipStream_t s)

@@ -12,7 +12,9 @@ void launch_sub_mean(const CaseDev *c, const Tile *t, int nt, hipStream_t s);
 void launch_project(const CaseDev *c, const Tile *t, int nt, hipStream_t s);
 void launch_phase_commit(int dim, const CaseDev *c, const Tile *t, int nt, hipStream_t s);
 
-void launch_kinit(int kind, int nd, int fp32, const KJob *j, const JTile *t, int nt, int k, int mode, hipStream_t s);
+// two: BiCGSTAB preconditioned by two Jacobi sweeps instead of one
+void launch_kinit(int kind, int nd, int fp32, bool two, const KJob *j, const JTile *t, int nt, int k, int mode,
+                  hipStream_t s);
 void launch_kfinish(int nd, const KJob *j, const JTile *t, int nt, hipStream_t s);
 void launch_kdecide(const KJob *j, int njobs, hipStream_t s);
 // iteration kernels, all with the signature (jobs, tiles, const int *kbase,
@@ -22,9 +24,9 @@ enum KIter {
     KI_MG_PQ = 4, KI_MG_DOWN0 = 5, KI_MG_DOWN = 6, KI_MG_EXACT = 7, KI_MG_UP = 8, KI_MG_UP0 = 9,
     KI_MG_DOWN0_INIT = 10
 };
-void launch_kiter(int which, int nd, int fp32, const KJob *j, const JTile *t, int nt, int k, hipStream_t s);
-// kernel address of an iteration kernel (direct launches and graph nodes)
-const void *kiter_fn(int which, int nd, int fp32);
+// kernel address of an iteration kernel (direct launches and graph nodes);
+// two selects the two-sweep BiCGSTAB kernels
+const void *kiter_fn(int which, int nd, int fp32, bool two);
 const void *mg_fn(int which, int nd, int fp32);
 // multigrid: start of the solves (r = b - A x, p = 0, partial (b, b)) and
 // the inverse diagonal of level l >= 1 (FP32 copy when mi32 is given)
