@@ -410,6 +410,16 @@ static bool two_sweeps(int tprecond, int nd)
     return tprecond == SOL_TPRECOND_JACOBI2 || (tprecond == SOL_TPRECOND_AUTO && nd == 5);
 }
 
+// a two-sweep 5-point FP64 solve goes through LDS when its tile
+// neighbourhood fits the LDS budget and its halo (two rows of the grid on
+// either side) is at most four times the tile, beyond which staging loads
+// more than gathering per row; the choice depends on the case alone, so a
+// case gets the same kernels' arithmetic alone and in a batch
+static int stage2_fits(bool two5, int rpt, int sx, size_t tsize)
+{
+    return two5 && 4 * sx + 4 <= 4 * rpt && (size_t)stage2_values(rpt, sx) * tsize <= (size_t)STAGE2_LDS_MAX ? 1 : 0;
+}
+
 static int finish_set(Group &g, JobSet &S)
 {
     size_t total = 0;
@@ -457,8 +467,14 @@ static int build_stages(Group &g, JobSet &S, int kind, const bool (&two)[2], int
         return SOL_OK;
     }
     if (kind == K_BICGSTAB) {
+        // 5-point two-sweep solves staged in LDS: the launch reserves the
+        // largest tile neighbourhood among them
+        size_t lds = 0;
+        for (const KJob &J : S.jobs)
+            if (J.staged) lds = std::max(lds, (size_t)stage2_values(J.rpt, J.sx) * (fp32 ? sizeof(float) : sizeof(double)));
         S.iter.push_back(row_stage(KI_BICG_B, SOL_KCLASS_BICG_B));
         S.iter.push_back(row_stage(KI_BICG_A, SOL_KCLASS_BICG_A));
+        for (Stage &st : S.iter) st.smem[0] = lds;
         return SOL_OK;
     }
     // multigrid CG: pq, down0, down(1..G-1), exact, up(G-1..1), up0; the start
@@ -660,11 +676,13 @@ static int group_build(Group &g)
                     I.st = ist;
                     I.partner = J.st;
                     I.lev = h->mg32_d;
+                    I.staged = 0;     // FP32: gathering per row measured faster
                     P.inner.jobs.push_back(I);
                     P.inner.st_index.push_back(g.nks + c * NSYS + s);
                     P.inner.case_of.push_back(c);
                     P.inner.sys_of.push_back(s);
                 }
+                J.staged = stage2_fits(P.two[0] && h->z.nd == 5, J.rpt, J.sx, sizeof(double));
                 P.main.jobs.push_back(J);
                 P.main.st_index.push_back(c * NSYS + s);
                 P.main.case_of.push_back(c);

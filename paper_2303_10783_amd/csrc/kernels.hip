@@ -659,6 +659,56 @@ __device__ __forceinline__ void diag_views(const void *A, int n, RO<T> (&Ad)[ND]
     for (int s = 0; s < ND; ++s) Ad[s] = R<T>((const T *)A + (size_t)s * n);
 }
 
+// PD 2 on a 5-point FP64 system, the tile [i0, i1) staged through LDS (KJob::
+// staged; the FP32 inner solves were faster gathering per row).  The rows within two stencil steps of the tile are [i0 - 2 sx - 2,
+// i1 + 2 sx + 2).  Pass 1 writes y = D^-1 f for each of them (0 outside
+// [0, n): only exact-0 coefficients reach those), pass 2 z = M f = y -
+// D^-1 N y for the rows within one step, pass 3 hands (A z)_i of each own
+// row to out(i, .).  Each value is loaded once per workgroup instead of once
+// per row that reaches it; the arithmetic and its order are those of
+// ring_amf.  The dynamic LDS holds stage2_values(rpt, sx) values.
+template <class T, class FY, class FO>
+__device__ __forceinline__ void stage2_amf(const KJob &J, int i0, int i1, const RO<T> (&Ad)[5], RO<T> Mi, FY fy,
+                                           FO out)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    T *Y = reinterpret_cast<T *>(lds_raw);
+    const int n = J.n, sx = J.sx;
+    const int ylo = i0 - 2 * sx - 2, yn = (i1 - i0) + 4 * sx + 4;
+    const int zlo = i0 - sx - 1, zn = (i1 - i0) + 2 * sx + 2;
+    T *Z = Y + yn;
+    for (int q = threadIdx.x; q < yn; q += TILE) {
+        const int j = ylo + q;
+        Y[q] = (j >= 0 && j < n) ? Mi[j] * fy(j) : T(0);
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < zn; q += TILE) {
+        const int j = zlo + q;
+        T z = T(0);
+        if (j >= 0 && j < n) {
+            const int c = j - ylo;
+            T ns = T(0);
+            ns += Ad[0][j] * Y[c - sx];
+            ns += Ad[1][j] * Y[c - 1];
+            ns += Ad[3][j] * Y[c + 1];
+            ns += Ad[4][j] * Y[c + sx];
+            z = Y[c] - Mi[j] * ns;
+        }
+        Z[q] = z;
+    }
+    __syncthreads();
+    for (int i = i0 + threadIdx.x; i < i1; i += TILE) {
+        const int c = i - zlo;
+        T acc = T(0);
+        acc += Ad[0][i] * Z[c - sx];
+        acc += Ad[1][i] * Z[c - 1];
+        acc += Ad[2][i] * Z[c];
+        acc += Ad[3][i] * Z[c + 1];
+        acc += Ad[4][i] * Z[c + sx];
+        out(i, acc);
+    }
+}
+
 // Start at iteration index k (mode 0: every solve, x = x0 or 0; mode 1:
 // solves in K_RESTART, keep x): r_k = b - A x, rh = r_k; partials (rh, r_k),
 // (r_k, r_k), (b, b).
@@ -783,6 +833,23 @@ __device__ __forceinline__ void bicg_b_body(const KJob *__restrict__ jobs, const
         RO<T> Ad[ND];
         diag_views<ND, T>(J.A, n, Ad);
         const auto Mi = R<T>(J.minv), Rr = R<T>(pk ? J.r1 : J.r), Vk = R<T>(pk ? J.v1 : J.v0), Rh = R<T>(J.rh);
+        bool done = false;
+        if constexpr (ND == 5 && sizeof(T) == 8) {
+            if (J.staged) {
+                stage2_amf<T>(J, i0, i1, Ad, Mi, [&](int j) { return Rr[j] - alpha * Vk[j]; }, [&](int i, T ti) {
+                    const T si = Rr[i] - alpha * Vk[i];
+                    const T hi = Rh[i];
+                    t[i] = ti;
+                    const double sd = si, td = ti, hd = hi;
+                    v[0] += td * sd;
+                    v[1] += td * td;
+                    v[2] += hd * sd;
+                    v[3] += hd * td;
+                });
+                done = true;
+            }
+        }
+        if (!done)
         for (int i = i0 + threadIdx.x; i < i1; i += TILE) {
             int idx[NC];
             T y[NC];
@@ -881,6 +948,34 @@ __device__ __forceinline__ void bicg_a_body(const KJob *__restrict__ jobs, const
         diag_views<ND, T>(J.A, n, Ad);
         const auto Mi = R<T>(J.minv), Rk = R<T>(pk ? J.r1 : J.r), Vk = R<T>(pk ? J.v1 : J.v0),
                    Pk = R<T>(pk ? J.p1 : J.p0), Tt = R<T>(J.t), Rh = R<T>(J.rh), X = R<T>(J.x);
+        bool done = false;
+        if constexpr (ND == 5 && sizeof(T) == 8) {
+            if (J.staged) {
+                auto pn = [&](int j) { return ((Rk[j] - ta * Vk[j]) - tw * Tt[j]) + tb * (Pk[j] - tw * Vk[j]); };
+                stage2_amf<T>(J, i0, i1, Ad, Mi, pn, [&](int i, T vi) {
+                    T gs = T(0);
+#pragma unroll
+                    for (int s2 = 0; s2 < ND; ++s2) {
+                        if (s2 == C) continue;
+                        const int j = min(max(i + slot_off<ND>(s2, J.sx, J.sxy), 0), n - 1);
+                        gs += Ad[s2][i] * (Mi[j] * (ta * Pk[j] + tw * (Rk[j] - ta * Vk[j])));
+                    }
+                    const T si = Rk[i] - ta * Vk[i];
+                    const T xi = X[i] + Mi[i] * ((ta * Pk[i] + tw * si) - gs);
+                    const T ri = si - tw * Tt[i];
+                    const T pi = pn(i);
+                    const T hi = Rh[i];
+                    x[i] = xi;
+                    rn[i] = ri;
+                    pnv[i] = pi;
+                    vn[i] = vi;
+                    q[0] += (double)hi * vi;
+                    q[1] += (double)ri * ri;
+                });
+                done = true;
+            }
+        }
+        if (!done)
         for (int i = i0 + threadIdx.x; i < i1; i += TILE) {
             int idx[NC];
             T y[NC], g[ND];

@@ -139,7 +139,7 @@ struct KJob {
     int32_t nlev;             // multigrid: levels (0 for the other solves)
     const MLevel *lev;        // multigrid: level table (device), vectors of type T
     int32_t nglob;            // multigrid: the exactly solved level (levels 0..nglob-1 are smoothed)
-    int32_t pad;
+    int32_t staged;           // BiCGSTAB, two sweeps, 5-point, FP64: the tile's neighbourhood goes through LDS
 };
 
 enum KRole { ROLE_PLAIN = 0, ROLE_REFINE = 1, ROLE_INNER = 2 };
@@ -150,5 +150,12 @@ struct Tile { int32_t c, s, t, pad; };
 struct JTile { int32_t j, t, lv, pad; };
 
 __host__ __device__ inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
+
+// Two-sweep BiCGSTAB on a 5-point system with its tile staged in LDS: values
+// held per tile of rpt rows on a grid of row stride sx (rows within two
+// stencil steps, then within one); a tile is staged when they fit
+// STAGE2_LDS_MAX bytes.
+__host__ __device__ inline int stage2_values(int rpt, int sx) { return 2 * rpt + 6 * sx + 6; }
+constexpr int STAGE2_LDS_MAX = 60 * 1024;
 
 }  // namespace sol
