@@ -45,6 +45,7 @@ def roofline(g, nsteps, cg_launches_per_step):
     multigrid coarse-level class spans several kernels and carries no byte
     count; it is not a candidate."""
     best = None
+    classes = {}
     for cls in ("cg", "bicg_a", "bicg_b", "bicg_c", "asm_mom", "asm_trn", "phase", "mg_pq", "mg_down0", "mg_up0"):
         t = g.timing(cls)
         if t["launches"] == 0 or t["bytes"] == 0:
@@ -54,8 +55,13 @@ def roofline(g, nsteps, cg_launches_per_step):
         t["gbs"] = t["bytes"] / (t["ms"] * 1e-3) / 1e9
         t["cls"] = cls
         t["est_ms_per_step"] = t["avg_ms"] * cg_launches_per_step if cls == "cg" else t["ms"] / nsteps
+        classes[cls] = dict(avg_us=round(t["avg_ms"] * 1e3, 2), mb_per_launch=round(t["bytes_per_launch"] / 1e6, 2),
+                            gbs=round(t["gbs"], 1), frac=round(t["gbs"] / HBM_PEAK_GBS, 4),
+                            ms_per_step=round(t["est_ms_per_step"], 4))
         if best is None or t["est_ms_per_step"] > best["est_ms_per_step"]:
             best = t
+    if best is not None:
+        best["classes"] = classes
     return best
 
 
@@ -241,7 +247,8 @@ def main():
                         frac=round(best["gbs"] / HBM_PEAK_GBS, 4), traffic=tr,
                         kernel=best["cls"], avg_us=round(best["avg_ms"] * 1e3, 2),
                         bytes_per_launch=int(best["bytes_per_launch"]),
-                        timed_launches=int(best["launches"]))
+                        timed_launches=int(best["launches"]),
+                        all_classes=best["classes"])
     g.close()
     variants = None
     if not args.no_variants:

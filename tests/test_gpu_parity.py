@@ -715,3 +715,22 @@ def test_speculative_redo(sol, dev, precond, case):
     assert max(errs.values()) < 1e-9, errs      # measured 1.9e-12 (v)
     a.close()
     b.close()
+
+
+def test_option_errors(sol, dev):
+    """Unknown option values are rejected; preconditioners cannot change while
+    a handle is part of a batch."""
+    import paper_2303_10783_amd.binding as B
+    g = make(sol, dev, W.cavity_2d(20, 12, seed=91))
+    L = B.load()
+    assert L.sol_set_option(g.h, B.OPT_TPRECOND, 7) == B.SOL_EINVAL
+    assert L.sol_set_option(g.h, B.OPT_PRECOND, 5) == B.SOL_EINVAL
+    assert L.sol_set_option(g.h, 99, 0) == B.SOL_EINVAL
+    b = sol.Batch([g])
+    with pytest.raises(B.SolError) as e:
+        g.set_tprecond("jacobi")
+    assert e.value.code == B.SOL_EBUSY
+    b.close()
+    g.set_tprecond("jacobi")
+    g.step(1)
+    g.close()
