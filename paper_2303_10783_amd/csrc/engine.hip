@@ -112,7 +112,8 @@ static void compute_sizes(const sol_grid &g, Sizes &z)
 
 // multigrid levels of the pressure grid: every count above 1 halves
 // (rounding up) from one level to the next, down to nglob, the first level
-// >= 1 with at most MG_EXACT_MAX cells (solved exactly)
+// >= 1 with at most MG_EXACT_MAX cells (MG_EXACT_MAX_LARGE for grids of at
+// least MG_LARGE_CELLS cells), solved exactly
 struct MGDims {
     int nlev = 0, nglob = 0;
     int d[MG_MAXLEV][3];
@@ -122,13 +123,14 @@ struct MGDims {
 static void mg_dims(const Sizes &z, MGDims &m)
 {
     int d0 = z.nx, d1 = z.ny, d2 = z.nz;
+    const int cap = (int64_t)d0 * d1 * d2 >= MG_LARGE_CELLS ? MG_EXACT_MAX_LARGE : MG_EXACT_MAX;
     for (;;) {
         const int l = m.nlev++;
         m.d[l][0] = d0;
         m.d[l][1] = d1;
         m.d[l][2] = d2;
         m.n[l] = d0 * d1 * d2;
-        if (l >= 1 && m.n[l] <= MG_EXACT_MAX) {
+        if (l >= 1 && m.n[l] <= cap) {
             m.nglob = l;
             break;
         }

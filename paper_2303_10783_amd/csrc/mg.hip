@@ -15,7 +15,8 @@
 //   levels 0 .. nglob-1: one damped-Jacobi sweep before and after the
 //     coarse correction, the correction scaled by mg_og (aggregation
 //     under-estimates smooth error; the scaling restores most of the rate);
-//   level nglob (the first with at most MG_EXACT_MAX cells): solved exactly
+//   level nglob (the first with at most MG_EXACT_MAX cells, or
+//     MG_EXACT_MAX_LARGE on large grids): solved exactly
 //     with a dense inverse of A + c 1 1^T (c = mean diagonal / n), built once
 //     per case; for a mean-free right-hand side that is the minimum-norm
 //     solution, and a constant part is removed with the mean of z anyway.
@@ -615,7 +616,7 @@ __global__ __launch_bounds__(TILE) void k_mg_exact(const KJob *__restrict__ jobs
     if (lane == 0) G<T>(L.e)[row] = (T)s;
 }
 
-// setup: P^-1 of the exactly solved level l (n <= MG_EXACT_MAX) by
+// setup: P^-1 of the exactly solved level l (n <= MG_EXACT_MAX_LARGE) by
 // Gauss-Jordan elimination of the symmetric positive definite A + c 1 1^T in
 // place (no pivoting needed), one launch per pivot over all n^2 entries.
 // work[4n + 1]: pivot row and column of step k at work + (k & 1) 2n (row
