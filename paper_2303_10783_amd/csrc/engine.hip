@@ -116,6 +116,7 @@ static void compute_sizes(const sol_grid &g, Sizes &z)
 // least MG_LARGE_CELLS cells), solved exactly
 struct MGDims {
     int nlev = 0, nglob = 0;
+    int nbig = 0;                 // large grids: the first level >= 1 with <= MG_EXACT_MAX_LARGE cells, if above nglob
     int d[MG_MAXLEV][3];
     int n[MG_MAXLEV];
 };
@@ -123,14 +124,15 @@ struct MGDims {
 static void mg_dims(const Sizes &z, MGDims &m)
 {
     int d0 = z.nx, d1 = z.ny, d2 = z.nz;
-    const int cap = (int64_t)d0 * d1 * d2 >= MG_LARGE_CELLS ? MG_EXACT_MAX_LARGE : MG_EXACT_MAX;
+    const bool large = (int64_t)d0 * d1 * d2 >= MG_LARGE_CELLS;
     for (;;) {
         const int l = m.nlev++;
         m.d[l][0] = d0;
         m.d[l][1] = d1;
         m.d[l][2] = d2;
         m.n[l] = d0 * d1 * d2;
-        if (l >= 1 && m.n[l] <= cap) {
+        if (large && l >= 1 && m.nbig == 0 && m.n[l] <= MG_EXACT_MAX_LARGE) m.nbig = l;
+        if (l >= 1 && m.n[l] <= MG_EXACT_MAX) {
             m.nglob = l;
             break;
         }
@@ -140,6 +142,7 @@ static void mg_dims(const Sizes &z, MGDims &m)
         d2 = (d2 + 1) / 2;
     }
     if (m.nglob == 0) m.nglob = m.nlev - 1;
+    if (m.nbig >= m.nglob) m.nbig = 0;
 }
 
 // Krylov work vectors per set: r, rh, p0, p1, v0, v1, t, r1 (FP64); the FP32
@@ -175,6 +178,10 @@ static size_t footprint(const Sizes &z, int precision)
         const size_t nx2 = (size_t)m.n[m.nglob] * m.n[m.nglob];  // dense inverse of the exact level
         b += al(nx2 * D) + al(nx2 * F);
         b += al((4 * (size_t)m.n[m.nglob] + 1) * D);            // its elimination scratch
+        if (m.nbig) {                                            // large grids alone: a larger exact level
+            const size_t nb2 = (size_t)m.n[m.nbig] * m.n[m.nbig];
+            b += al(nb2 * D) + al(nb2 * F) + al((4 * (size_t)m.n[m.nbig] + 1) * D);
+        }
         b += al(sizeof(MLevel) * MG_MAXLEV) * (precision ? 2 : 1);
     }
     return b;
@@ -269,6 +276,11 @@ struct sol_handle {
     int tprecond = SOL_TPRECOND_AUTO;
     double *mg_pwork = nullptr;           // scratch of the exact-level inverse (set-up)
     double *mg_p64 = nullptr;             // FP64 exact-level inverse (set-up; solves read its FP32 copy)
+    // large grids: level mg_nbig (> 0) is solved exactly instead of mg_nglob
+    // when the case runs alone; its inverse is built before the first such step
+    int mg_nbig = 0;
+    bool mg_big_ready = false;
+    double *mg_pbig64 = nullptr, *mg_pbigwork = nullptr;
     int64_t redone = 0;                   // steps run a second time (speculative check failed)
     // pressure multigrid hierarchy (FP64 arrays; FP32 copies for mixed precision)
     int mg_nlev = 0, mg_nglob = 0;
@@ -403,6 +415,15 @@ static std::vector<JTile> xcd_order(const std::vector<std::vector<JTile>> &per_s
     return out;
 }
 
+// multigrid level solved exactly for case h in group g: a large grid
+// stepped alone (its iterations launch bound) uses its larger exact level
+// once that inverse is built; in a batch of several cases every case keeps
+// the standard one, whose product each case reads in every iteration
+static int case_nglob(const Group &g, const sol_handle *h)
+{
+    return (g.cs.size() == 1 && h->mg_nbig > 0 && h->mg_big_ready) ? h->mg_nbig : h->mg_nglob;
+}
+
 // BiCGSTAB preconditioner of a system with nd diagonals: two Jacobi sweeps
 // or one.  Automatic: two on 5-point (2D) systems, where halving the
 // iterations outweighs the wider gathers; one on 7-point (3D) systems, where
@@ -482,13 +503,13 @@ static int build_stages(Group &g, JobSet &S, int kind, const bool (&two)[2], int
     // multigrid CG: pq, down0, down(1..G-1), exact, up(G-1..1), up0; the start
     // cycle is the same without pq, with the start variant of down0
     int gmax = 1;
-    for (size_t j = 0; j < S.jobs.size(); ++j) gmax = std::max(gmax, g.cs[S.case_of[j]]->mg_nglob);
+    for (size_t j = 0; j < S.jobs.size(); ++j) gmax = std::max(gmax, case_nglob(g, g.cs[S.case_of[j]]));
     std::vector<Stage> down(gmax), up(gmax);
     for (int l = 1; l < gmax; ++l) {
         std::vector<std::vector<JTile>> per[2];
         for (size_t j = 0; j < S.jobs.size(); ++j) {
             const sol_handle *h = g.cs[S.case_of[j]];
-            if (h->mg_nglob <= l) continue;
+            if (case_nglob(g, h) <= l) continue;
             const int gi = h->z.nd == 7 ? 1 : 0;
             std::vector<JTile> tl;
             for (int t = 0; t < h->mg_h[l].ntile; ++t) tl.push_back({(int)j, t, l, 0});
@@ -514,7 +535,7 @@ static int build_stages(Group &g, JobSet &S, int kind, const bool (&two)[2], int
         for (size_t j = 0; j < S.jobs.size(); ++j) {
             const sol_handle *h = g.cs[S.case_of[j]];
             const int gi = h->z.nd == 7 ? 1 : 0;
-            const int L = h->mg_nglob;
+            const int L = case_nglob(g, h);
             for (int t = 0; t < ceil_div(h->mg_h[L].n, MG_XROWS); ++t) jt[gi].push_back({(int)j, t, L, 0});
         }
         for (int gi = 0; gi < 2; ++gi) {
@@ -634,7 +655,7 @@ static int group_build(Group &g)
                 J.kind = P.kind;
                 if (P.kind == K_MGCG) {
                     J.nlev = h->mg_nlev;
-                    J.nglob = h->mg_nglob;
+                    J.nglob = case_nglob(g, h);
                     J.lev = h->mg_d;
                     J.ntile = h->mg_h[0].ntile;
                     J.rpt = ceil_div(J.n, J.ntile);
@@ -1361,6 +1382,7 @@ static int alloc_case(sol_handle *h)
         auto fal = [&](size_t n) { return (float *)m.get(std::max<size_t>(n, 1) * sizeof(float)); };
         h->mg_nlev = md.nlev;
         h->mg_nglob = md.nglob;
+        h->mg_nbig = md.nbig;
         for (int l = 0; l < md.nlev; ++l) {
             MLevel L;
             std::memset(&L, 0, sizeof(L));
@@ -1409,6 +1431,15 @@ static int alloc_case(sol_handle *h)
                 h->mg_pwork = dal(4 * (size_t)L.n + 1);
                 float *P32 = fal(n2);
                 if (!h->mg_p64 || !h->mg_pwork || !P32) return fail(SOL_ENOMEM, "device allocation failed");
+                L.pinv = P32;
+                L32.pinv = P32;
+            }
+            if (md.nbig && l == md.nbig) {
+                const size_t n2 = (size_t)L.n * L.n;
+                h->mg_pbig64 = dal(n2);
+                h->mg_pbigwork = dal(4 * (size_t)L.n + 1);
+                float *P32 = fal(n2);
+                if (!h->mg_pbig64 || !h->mg_pbigwork || !P32) return fail(SOL_ENOMEM, "device allocation failed");
                 L.pinv = P32;
                 L32.pinv = P32;
             }
@@ -1688,11 +1719,28 @@ static int fill_stats(Group &g, int c, sol_step_stats *st, const int64_t *tot)
     return SOL_OK;
 }
 
+// build the larger exact level's inverse of a large grid (once, before its
+// first multigrid solve alone) and rebuild the case's own group with it
+static int mg_big_prepare(sol_handle *h)
+{
+    if (h->mg_nbig <= 0 || h->mg_big_ready || h->precond != SOL_PRECOND_MG) return SOL_OK;
+    const int L = h->mg_nbig;
+    launch_mg_pinv(h->z.dim, h->mg_d, L, h->mg_h[L].n, h->mg_pbig64, (float *)h->mg_h[L].pinv, h->mg_pbigwork,
+                   h->stream);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(h->stream) != hipSuccess)
+        return fail(SOL_EDEVICE, "multigrid set-up failed");
+    h->mg_big_ready = true;
+    group_free(h->solo);
+    h->solo = nullptr;
+    return group_create({h}, &h->solo);
+}
+
 int sol_step(sol_handle *h, int32_t nsteps, sol_step_stats *stats)
 {
     if (!h) return fail(SOL_EINVAL, "NULL handle");
     if (nsteps < 0) return fail(SOL_EINVAL, "nsteps must be >= 0");
     if (h->batch) return fail(SOL_EBUSY, "handle is part of a batch");
+    if (nsteps > 0) RCHK(mg_big_prepare(h));
     Group &g = *h->solo;
     g.timer = h->timing ? h : nullptr;
     g.use_graph = h->opt_graph;
@@ -1810,6 +1858,7 @@ int sol_autotune(sol_handle *h, int32_t *rows_per_tile_out)
 {
     if (!h) return fail(SOL_EINVAL, "NULL handle");
     if (h->batch) return fail(SOL_EBUSY, "handle is part of a batch");
+    RCHK(mg_big_prepare(h));
     const int n = h->z.nsys[SP], nd = h->z.nd;
     const int cls = size_class(n, nd);
     const bool mg = h->precond == SOL_PRECOND_MG;

@@ -31,13 +31,13 @@ enum KKind { K_CG = 0, K_BICGSTAB = 1, K_MGCG = 2 };
 // 1/h_a^2 times the number of level-0 faces in it, the product of the block
 // extents along the other axes, and the diagonal is the sum of the
 // couplings (rows sum to zero).  The kernels apply it in this closed form.
-// The first level at or below MG_EXACT_MAX cells is solved exactly; grids
-// of at least MG_LARGE_CELLS cells go on to MG_EXACT_MAX_LARGE.  A larger
-// exact level saves the launches of the levels below it and some iterations
-// (500x300: 18 -> 17, 128x128x64: 26 -> 23), for a dense product of
-// n^2 FP32 values per iteration (23 MB at 2394 cells): a gain for a large
-// case, whose iterations are launch bound, a loss for many small cases in
-// one batch, which would each read their own.
+// The first level at or below MG_EXACT_MAX cells is solved exactly.  A grid
+// of at least MG_LARGE_CELLS cells stepped alone solves the first level at
+// or below MG_EXACT_MAX_LARGE exactly instead: that saves the launches of
+// the levels below it and some iterations (500x300: 18 -> 17, 128x128x64:
+// 26 -> 23), for a dense product of n^2 FP32 values per iteration (23 MB at
+// 2394 cells), a gain for a case whose iterations are launch bound, a loss
+// in a batch, where every case would read its own.
 constexpr int MG_EXACT_MAX = 1024;
 constexpr int MG_EXACT_MAX_LARGE = 2600;
 constexpr int MG_LARGE_CELLS = 131072;

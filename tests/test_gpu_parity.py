@@ -734,3 +734,32 @@ def test_option_errors(sol, dev):
     g.set_tprecond("jacobi")
     g.step(1)
     g.close()
+
+
+def test_large_grid_exact_level_alone_and_batched(sol, dev):
+    """A grid of at least 131072 cells stepped alone solves the larger
+    coarse level (here 50 x 42 cells) exactly, five coarse launches per
+    pressure iteration instead of seven, and needs no more iterations; in a
+    batch it keeps the standard exact level.  Both runs reach the tolerance
+    and agree to the spread it allows."""
+    case = W.cavity_2d(400, 330, lx=0.08, ly=0.066, tol=1e-13, seed=131)
+    case["numerics"]["tol_t"] = 1e-14
+    small = W.cavity_2d(30, 20, seed=132)
+    a = make(sol, dev, case)
+    sa = a.step(3)
+    b1, b2 = make(sol, dev, case), make(sol, dev, small)
+    bt = sol.Batch([b1, b2])
+    sb = bt.step([3, 3])
+    bt.close()
+    print("pressure iterations over 3 steps: alone", sa["iters_total"][3], "batched", sb[0]["iters_total"][3],
+          flush=True)
+    assert sa["iters_total"][3] <= sb[0]["iters_total"][3]
+    for s in range(6):
+        assert sa["rel_resid"][s] <= 1e-13 * (1 + 1e-6)
+        assert sb[0]["rel_resid"][s] <= 1e-13 * (1 + 1e-6)
+    errs = field_errors(a.read_fields(), b1.read_fields())
+    print("alone vs batched", {k: f"{v:.1e}" for k, v in errs.items()}, flush=True)
+    assert max(errs[k] for k in ("T", "C", "gl", "Cl", "Cs")) < 1e-11, errs
+    assert max(errs.values()) < 1e-8, errs
+    for g in (a, b1, b2):
+        g.close()
