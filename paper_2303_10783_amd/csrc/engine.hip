@@ -172,8 +172,8 @@ static size_t footprint(const Sizes &z, int precision)
         MGDims m;                                                // pressure multigrid hierarchy
         mg_dims(z, m);
         for (int l = 1; l < m.nlev; ++l) {
-            b += 3 * al((size_t)m.n[l] * D);                     // inverse diagonal, rhs, correction
-            if (precision) b += 3 * al((size_t)m.n[l] * F);
+            b += 4 * al((size_t)m.n[l] * D);                     // inverse diagonal, rhs, correction, pre-smoothed
+            if (precision) b += 4 * al((size_t)m.n[l] * F);
         }
         const size_t nx2 = (size_t)m.n[m.nglob] * m.n[m.nglob];  // dense inverse of the exact level
         b += al(nx2 * D) + al(nx2 * F);
@@ -1414,13 +1414,13 @@ static int alloc_case(sol_handle *h)
                 L32.minv = d.minv32[SP];
             } else {
                 const size_t n = L.n;
-                double *mi = dal(n), *bl = dal(n), *el = dal(n);
-                if (!mi || !bl || !el) return fail(SOL_ENOMEM, "device allocation failed");
-                L.minv = mi; L.b = bl; L.e = el;
+                double *mi = dal(n), *bl = dal(n), *el = dal(n), *xl = dal(n);
+                if (!mi || !bl || !el || !xl) return fail(SOL_ENOMEM, "device allocation failed");
+                L.minv = mi; L.b = bl; L.e = el; L.xs = xl;
                 if (mixed) {
-                    float *mi32 = fal(n), *b32 = fal(n), *e32 = fal(n);
-                    if (!mi32 || !b32 || !e32) return fail(SOL_ENOMEM, "device allocation failed");
-                    L32.minv = mi32; L32.b = b32; L32.e = e32;
+                    float *mi32 = fal(n), *b32 = fal(n), *e32 = fal(n), *x32 = fal(n);
+                    if (!mi32 || !b32 || !e32 || !x32) return fail(SOL_ENOMEM, "device allocation failed");
+                    L32.minv = mi32; L32.b = b32; L32.e = e32; L32.xs = x32;
                 }
             }
             if (l == md.nglob) {
