@@ -167,6 +167,22 @@ __device__ __forceinline__ const KJob &job_of(const KJob *jobs, const JTile *til
 
 __device__ __forceinline__ int poff(const KJob &J, int par, int slot) { return (par * NSLOT + slot) * J.ntile; }
 
+// The status of a solve, read once for the whole workgroup.  Workgroup 0 of
+// a launch may change it (convergence, breakdown) while the waves of a
+// workgroup that starts later read it one by one.  Had they disagreed, the
+// waves that returned at once would have left their slots of the block-wide
+// sums stale, and the waves that went on would have derived their scalars,
+// and then their row updates, from those slots.  Every kernel whose entry
+// check reads a status that its own workgroup 0 may change takes it from
+// here, once, before any other use of LDS.
+__device__ __forceinline__ int wg_status(const KState *st)
+{
+    __shared__ int s;
+    if (threadIdx.x == 0) s = st->status;
+    __syncthreads();
+    return s;
+}
+
 // an inner solve whose refinement no longer needs it
 __device__ __forceinline__ bool outer_idle(const KJob &J)
 {
@@ -177,7 +193,7 @@ __device__ __forceinline__ bool outer_idle(const KJob &J)
 // first iteration is k
 __device__ __forceinline__ bool active(const KJob &J, int k)
 {
-    const int s = J.st->status;
+    const int s = wg_status(J.st);
     return s == K_RUNNING || (s == K_RESTART && k == J.st->k0);
 }
 

@@ -807,7 +807,7 @@ __device__ __forceinline__ void bicg_b_body(const KJob *__restrict__ jobs, const
     const int k = (kbase ? *kbase : 0) + koff;
     JTile tl;
     const KJob &J = job_of(jobs, tiles, tl);
-    if (J.st->status != K_RUNNING || outer_idle(J)) return;
+    if (wg_status(J.st) != K_RUNNING || outer_idle(J)) return;
     const int pk = k & 1;
     double s2[2];
     {
@@ -903,7 +903,7 @@ __device__ __forceinline__ void bicg_a_body(const KJob *__restrict__ jobs, const
     const int k = (kbase ? *kbase : 0) + koff;
     JTile tl;
     const KJob &J = job_of(jobs, tiles, tl);
-    if (J.st->status != K_RUNNING || outer_idle(J)) return;
+    if (wg_status(J.st) != K_RUNNING || outer_idle(J)) return;
     KState *st = J.st;
     const int pk = k & 1, pn = (k + 1) & 1;
     double s5[5];

@@ -166,7 +166,7 @@ __device__ __forceinline__ void for_layer(const MLevel &L, const Agg<DIM> &a, in
 // (re)start whose first iteration is k + 1 (the start cycle runs at k0 - 1)
 __device__ __forceinline__ bool mg_live(const KJob &J, int k)
 {
-    const int s = J.st->status;
+    const int s = wg_status(J.st);
     return s == K_RUNNING || ((s == K_RESTART) && J.st->k0 == k + 1);
 }
 
@@ -388,7 +388,7 @@ __global__ __launch_bounds__(TILE) void k_mg_down0(const KJob *__restrict__ jobs
     const KJob &J = job_of(jobs, tiles, tl);
     if (outer_idle(J)) return;
     KState *st = J.st;
-    if (INIT ? !mg_live(J, k) : st->status != K_RUNNING) return;
+    if (INIT ? !mg_live(J, k) : wg_status(st) != K_RUNNING) return;
     const int pk = k & 1, pn1 = (k + 1) & 1;
     double alpha = 0.0;
     if (!INIT) {
