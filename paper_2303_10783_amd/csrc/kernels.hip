@@ -1,6 +1,7 @@
 // HIP kernels (gfx950) of one time step of the decoupled solidification
-// scheme: term-wise assembly, Jacobi-PCG / Jacobi-BiCGSTAB iterations with
-// fused reductions, divergence / projection, phase update and commit.
+// scheme: term-wise assembly, Jacobi-PCG and BiCGSTAB (one or two Jacobi
+// sweeps as the preconditioner) iterations with fused reductions,
+// divergence / projection, phase update and commit.
 //
 // Launch model: every per-row kernel walks a table of tiles (256 rows each)
 // covering one or many cases; workgroup b takes tile xcd_tile(b) so that the
