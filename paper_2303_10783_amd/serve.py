@@ -3,8 +3,10 @@
 Requests (cases with an arrival time and a step count) are admitted in
 arrival order while their device footprint (sol_footprint_bytes) fits the
 memory budget and the batch has a free slot.  Admitted cases stay on the
-device; every tick advances all admitted cases by one time step in one
-batched launch sequence (sol_batch_step).  A case that has done its steps
+device; every tick advances all admitted cases together in one batched
+launch sequence per step (sol_batch_step), until the next event: a case
+finishing its steps, or an arrival that a free slot could take (judged
+from the measured step time).  A case that has done its steps
 leaves the batch, its fields are read back, its memory is released and the
 next waiting request can take the slot, while the others keep running.
 Latency = time from arrival until the fields are on the host.
@@ -43,12 +45,15 @@ class Request:
 
 class Server:
     def __init__(self, device=None, hbm_budget_bytes: int = 270 * 2 ** 30, max_active: int = 64,
-                 graph: bool = False, keep_results: bool = True):
+                 graph: bool = False, keep_results: bool = True, multi_step: bool = True):
         self.device = device
         self.budget = int(hbm_budget_bytes)
         self.max_active = int(max_active)
         self.graph = graph
         self.keep_results = keep_results
+        # a tick advances the batch until its next event (a request finishes,
+        # or the next arrival could be admitted) instead of by one step
+        self.multi_step = multi_step
         self.log = []                 # (time, event, request id)
 
     def run(self, requests, clock=time.perf_counter, sleep=time.sleep):
@@ -65,6 +70,7 @@ class Server:
         members = None
         t0 = clock()
         cell_steps = 0
+        step_s = None                 # running estimate of one batched step (s)
         while pending or waiting or active:
             now = clock() - t0
             while pending and pending[0].arrival <= now:
@@ -89,10 +95,23 @@ class Server:
                     batch.close()
                 batch = Batch([r.handle for r in active])
                 members = ids
-            batch.step([1] * len(active))
+            k = 1
+            if self.multi_step:
+                k = min(r.steps - r.steps_done for r in active)
+                # an arrival that could be admitted is not kept waiting past
+                # its time by more than one step
+                # (requests already waiting are held by the memory budget or
+                # the slots, and wait for a finish either way)
+                if pending and not waiting and len(active) < self.max_active:
+                    ahead = pending[0].arrival - (clock() - t0)
+                    k = min(k, max(1, int(ahead / step_s))) if step_s else 1
+            ts = clock()
+            batch.step([k] * len(active))
+            dt = (clock() - ts) / k
+            step_s = dt if step_s is None else 0.7 * step_s + 0.3 * dt
             for r in active:
-                r.steps_done += 1
-                cell_steps += r.cells
+                r.steps_done += k
+                cell_steps += r.cells * k
             finished = [r for r in active if r.steps_done >= r.steps]
             if finished:
                 batch.close()
