@@ -58,19 +58,41 @@ static int fail(int code, const char *fmt, ...)
 
 // ------------------------------------------------------------------ memory
 
+// Device memory of a case: one slab of the case's whole footprint, handed
+// out in 256-byte aligned pieces (one allocator call per case instead of
+// about a hundred; with torch's allocator each call crosses into Python).
+// A request beyond the slab gets an allocation of its own.
 struct Mem {
     sol_device_ctx ctx{};
     bool has_ctx = false;
     std::vector<void *> blocks;
     size_t bytes = 0;
-    void *get(size_t n)
+    char *slab = nullptr;
+    size_t slab_size = 0, slab_used = 0;
+    void *raw(size_t n)
     {
-        n = (std::max<size_t>(n, 256) + 255) & ~size_t(255);
         void *p = nullptr;
         if (has_ctx) p = ctx.alloc(n, ctx.user);
         else if (hipMalloc(&p, n) != hipSuccess) p = nullptr;
         if (p) { blocks.push_back(p); bytes += n; }
         return p;
+    }
+    void reserve(size_t n)
+    {
+        n = (n + 255) & ~size_t(255);
+        slab = (char *)raw(n);
+        slab_size = slab ? n : 0;
+        slab_used = 0;
+    }
+    void *get(size_t n)
+    {
+        n = (std::max<size_t>(n, 256) + 255) & ~size_t(255);
+        if (slab && slab_used + n <= slab_size) {
+            void *p = slab + slab_used;
+            slab_used += n;
+            return p;
+        }
+        return raw(n);
     }
     void release()
     {
@@ -80,6 +102,8 @@ struct Mem {
         }
         blocks.clear();
         bytes = 0;
+        slab = nullptr;
+        slab_size = slab_used = 0;
     }
 };
 
@@ -177,10 +201,10 @@ static size_t footprint(const Sizes &z, int precision)
         }
         const size_t nx2 = (size_t)m.n[m.nglob] * m.n[m.nglob];  // dense inverse of the exact level
         b += al(nx2 * D) + al(nx2 * F);
-        b += al((4 * (size_t)m.n[m.nglob] + 1) * D);            // its elimination scratch
+        b += al(mg_gj_work(m.n[m.nglob]) * D);                   // its elimination scratch
         if (m.nbig) {                                            // large grids alone: a larger exact level
             const size_t nb2 = (size_t)m.n[m.nbig] * m.n[m.nbig];
-            b += al(nb2 * D) + al(nb2 * F) + al((4 * (size_t)m.n[m.nbig] + 1) * D);
+            b += al(nb2 * D) + al(nb2 * F) + al(mg_gj_work(m.n[m.nbig]) * D);
         }
         b += al(sizeof(MLevel) * MG_MAXLEV) * (precision ? 2 : 1);
     }
@@ -334,7 +358,9 @@ struct Phase {
 struct Group {
     std::vector<sol_handle *> cs;
     hipStream_t stream = nullptr;
-    std::vector<void *> dmem;            // hipMalloc'd group arrays
+    std::vector<void *> dmem;            // hipMalloc'd chunks of the group arrays
+    char *chunk = nullptr;               // the chunk gmalloc currently cuts from
+    size_t chunk_size = 0, chunk_used = 0;
     CaseDev *cases_d = nullptr;
     KState *ks_d = nullptr;              // [2 * nks]: solves, then inner solves
     double *red_d = nullptr;
@@ -351,11 +377,28 @@ struct Group {
     bool use_graph = false;
 };
 
+// group arrays come out of 1 MiB chunks (256-byte aligned pieces; a larger
+// request gets a chunk of its own), so that building a group takes a few
+// hipMalloc calls instead of one per array: a served batch is rebuilt
+// whenever its membership changes
+constexpr size_t GCHUNK = 1 << 20;
 static void *gmalloc(Group &g, size_t bytes)
 {
+    bytes = (std::max<size_t>(bytes, 256) + 255) & ~size_t(255);
+    if (g.chunk && g.chunk_used + bytes <= g.chunk_size) {
+        void *p = g.chunk + g.chunk_used;
+        g.chunk_used += bytes;
+        return p;
+    }
+    const size_t sz = std::max(bytes, GCHUNK);
     void *p = nullptr;
-    if (hipMalloc(&p, std::max<size_t>(bytes, 256)) != hipSuccess) return nullptr;
+    if (hipMalloc(&p, sz) != hipSuccess) return nullptr;
     g.dmem.push_back(p);
+    if (sz == GCHUNK || !g.chunk) {
+        g.chunk = (char *)p;
+        g.chunk_size = sz;
+        g.chunk_used = bytes;
+    }
     return p;
 }
 
@@ -1332,6 +1375,7 @@ static int alloc_case(sol_handle *h)
 {
     const Sizes &z = h->z;
     Mem &m = h->mem;
+    m.reserve(footprint(z, h->num.precision));
     const size_t D = sizeof(double);
     CaseDev &d = h->cd;
     std::memset(&d, 0, sizeof(d));
@@ -1428,7 +1472,7 @@ static int alloc_case(sol_handle *h)
                 // every solve reads the FP32 copy
                 const size_t n2 = (size_t)L.n * L.n;
                 h->mg_p64 = dal(n2);
-                h->mg_pwork = dal(4 * (size_t)L.n + 1);
+                h->mg_pwork = dal(mg_gj_work(L.n));
                 float *P32 = fal(n2);
                 if (!h->mg_p64 || !h->mg_pwork || !P32) return fail(SOL_ENOMEM, "device allocation failed");
                 L.pinv = P32;
@@ -1437,7 +1481,7 @@ static int alloc_case(sol_handle *h)
             if (md.nbig && l == md.nbig) {
                 const size_t n2 = (size_t)L.n * L.n;
                 h->mg_pbig64 = dal(n2);
-                h->mg_pbigwork = dal(4 * (size_t)L.n + 1);
+                h->mg_pbigwork = dal(mg_gj_work(L.n));
                 float *P32 = fal(n2);
                 if (!h->mg_pbig64 || !h->mg_pbigwork || !P32) return fail(SOL_ENOMEM, "device allocation failed");
                 L.pinv = P32;

@@ -682,11 +682,13 @@ __global__ __launch_bounds__(TILE) void k_mg_exact(const KJob *__restrict__ jobs
 
 // setup: P^-1 of the exactly solved level l (n <= MG_EXACT_MAX_LARGE) by
 // Gauss-Jordan elimination of the symmetric positive definite A + c 1 1^T in
-// place (no pivoting needed), one launch per pivot over all n^2 entries.
-// work[4n + 1]: pivot row and column of step k at work + (k & 1) 2n (row
-// first), c at work[4n].  Step k writes the new pivot row and column of step
-// k + 1 into the other half, so no launch reads an entry another thread of
-// the same launch writes.
+// place (no pivoting needed), in blocks of MG_GJB pivots K, two launches per
+// block: (a) every workgroup inverts the diagonal block D = P[K,K] in LDS;
+// thread j forms the transformed pivot row X[:,j] = D^-1 P[K,j] and copies
+// row j's pivot columns C[j,:] = P[j,K]; (b) P[K,K] = D^-1, P[K,j] = X[:,j],
+// P[i,K] = -C[i,:] D^-1, and P[i,j] -= C[i,:] X[:,j] elsewhere.  Launch (b)
+// reads only its own entry of P and the scratch (a) wrote.  Scratch layout
+// (mg_gj_work): X at 0, C at MG_GJB n, D^-1 at 2 MG_GJB n, c last.
 
 // dense operator from the closed form: -coupling for a neighbour, the
 // diagonal for j = i (thread per entry)
@@ -713,42 +715,86 @@ __global__ __launch_bounds__(TILE) void k_mg_pdense(const MLevel *__restrict__ l
     P[idx] = v;
 }
 
-// c = (sum of the diagonal, in row order) / n^2 (1 for a zero operator)
-__global__ void k_mg_pshift(const double *__restrict__ P, int n, double *work)
+// c = (sum of the diagonal) / n^2 (1 for a zero operator); one workgroup
+__global__ __launch_bounds__(TILE) void k_mg_pshift(const double *__restrict__ P, int n, double *work)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    double t = 0.0;
-    for (int i = 0; i < n; ++i) t += P[(size_t)i * n + i];
-    work[4 * n] = t > 0.0 ? t / ((double)n * n) : 1.0;
+    double t[1] = {0.0};
+    for (int i = threadIdx.x; i < n; i += TILE) t[0] += P[(size_t)i * n + i];
+    __shared__ double sh[4];
+    block_sum<1>(t, sh);
+    if (threadIdx.x == 0) work[mg_gj_work(n) - 1] = t[0] > 0.0 ? t[0] / ((double)n * n) : 1.0;
 }
 
-// P += c; pivot row and column of step 0
-__global__ __launch_bounds__(TILE) void k_mg_padd(double *P, int n, double *work)
+// P += c
+__global__ __launch_bounds__(TILE) void k_mg_padd(double *P, int n, const double *work)
 {
     const int idx = blockIdx.x * TILE + threadIdx.x;
     if (idx >= n * n) return;
-    const int i = idx / n, j = idx - i * n;
-    const double v = P[idx] + work[4 * n];
-    P[idx] = v;
-    if (i == 0) work[j] = v;
-    if (j == 0) work[n + i] = v;
+    P[idx] += work[mg_gj_work(n) - 1];
 }
 
-// elimination step k: row k divided by the pivot, column k eliminated
-__global__ __launch_bounds__(TILE) void k_mg_pgj(double *P, int n, int k, double *work)
+// block K = [k0, k0 + bk), launch (a)
+__global__ __launch_bounds__(TILE) void k_mg_pgj_a(const double *__restrict__ P, int n, int k0, int bk, double *work)
 {
+    constexpr int B = MG_GJB;
+    __shared__ double Dm[2][B][B + 1];
+    const int t = threadIdx.x, r = t / B, c = t % B;     // TILE == B * B
+    if (r < bk && c < bk) Dm[0][r][c] = P[(size_t)(k0 + r) * n + k0 + c];
+    __syncthreads();
+    for (int p = 0; p < bk; ++p) {
+        const int a = p & 1;
+        if (r < bk && c < bk) {
+            const double piv = Dm[a][p][p];
+            const double rk = (c == p ? 1.0 : Dm[a][p][c]) / piv;
+            const double ck = r == p ? 0.0 : Dm[a][r][p];
+            Dm[a ^ 1][r][c] = r == p ? rk : (c == p ? 0.0 : Dm[a][r][c]) - ck * rk;
+        }
+        __syncthreads();
+    }
+    const int f = bk & 1;                                 // the buffer holding D^-1
+    double *X = work, *Cp = work + (size_t)B * n, *Di = work + 2 * (size_t)B * n;
+    if (blockIdx.x == 0 && r < bk && c < bk) Di[r * B + c] = Dm[f][r][c];
+    const int j = blockIdx.x * TILE + t;
+    if (j >= n) return;
+    double pk[B];
+#pragma unroll
+    for (int q = 0; q < B; ++q) pk[q] = q < bk ? P[(size_t)(k0 + q) * n + j] : 0.0;
+#pragma unroll
+    for (int q = 0; q < B; ++q) {
+        if (q >= bk) break;
+        double x = 0.0;
+#pragma unroll
+        for (int w = 0; w < B; ++w)
+            if (w < bk) x += Dm[f][q][w] * pk[w];
+        X[(size_t)q * n + j] = x;
+    }
+#pragma unroll
+    for (int q = 0; q < B; ++q)
+        if (q < bk) Cp[(size_t)j * B + q] = P[(size_t)j * n + k0 + q];
+}
+
+// block K = [k0, k0 + bk), launch (b)
+__global__ __launch_bounds__(TILE) void k_mg_pgj_b(double *P, int n, int k0, int bk, const double *__restrict__ work)
+{
+    constexpr int B = MG_GJB;
     const int idx = blockIdx.x * TILE + threadIdx.x;
     if (idx >= n * n) return;
     const int i = idx / n, j = idx - i * n;
-    const double *rowk = work + (size_t)(k & 1) * 2 * n, *colk = rowk + n;
-    double *rown = work + (size_t)((k + 1) & 1) * 2 * n, *coln = rown + n;
-    const double piv = rowk[k];
-    const double rk = (j == k ? 1.0 : rowk[j]) / piv;
-    const double ck = i == k ? 0.0 : colk[i];
-    const double v = i == k ? rk : (j == k ? 0.0 : P[idx]) - ck * rk;
+    const double *X = work, *Cp = work + (size_t)B * n, *Di = work + 2 * (size_t)B * n;
+    const bool iK = i >= k0 && i < k0 + bk, jK = j >= k0 && j < k0 + bk;
+    double v;
+    if (iK && jK) {
+        v = Di[(i - k0) * B + (j - k0)];
+    } else if (iK) {
+        v = X[(size_t)(i - k0) * n + j];
+    } else if (jK) {
+        v = 0.0;
+        for (int q = 0; q < bk; ++q) v -= Cp[(size_t)i * B + q] * Di[q * B + (j - k0)];
+    } else {
+        v = P[idx];
+        for (int q = 0; q < bk; ++q) v -= Cp[(size_t)i * B + q] * X[(size_t)q * n + j];
+    }
     P[idx] = v;
-    if (i == k + 1) rown[j] = v;
-    if (j == k + 1) coln[i] = v;
 }
 
 __global__ __launch_bounds__(TILE) void k_mg_p32(const double *__restrict__ P, float *P32, int nn)
@@ -764,9 +810,14 @@ void launch_mg_pinv(int dim, const MLevel *lev, int l, int n, double *P, float *
     const dim3 g(ceil_div(nn, TILE)), b(TILE);
     if (dim == 2) hipLaunchKernelGGL(k_mg_pdense<2>, g, b, 0, s, lev, l, P);
     else hipLaunchKernelGGL(k_mg_pdense<3>, g, b, 0, s, lev, l, P);
-    hipLaunchKernelGGL(k_mg_pshift, dim3(1), dim3(64), 0, s, (const double *)P, n, work);
-    hipLaunchKernelGGL(k_mg_padd, g, b, 0, s, P, n, work);
-    for (int k = 0; k < n; ++k) hipLaunchKernelGGL(k_mg_pgj, g, b, 0, s, P, n, k, work);
+    hipLaunchKernelGGL(k_mg_pshift, dim3(1), dim3(TILE), 0, s, (const double *)P, n, work);
+    hipLaunchKernelGGL(k_mg_padd, g, b, 0, s, P, n, (const double *)work);
+    static_assert(MG_GJB * MG_GJB == TILE, "one thread per entry of the diagonal block");
+    for (int k0 = 0; k0 < n; k0 += MG_GJB) {
+        const int bk = std::min(MG_GJB, n - k0);
+        hipLaunchKernelGGL(k_mg_pgj_a, dim3(ceil_div(n, TILE)), b, 0, s, (const double *)P, n, k0, bk, work);
+        hipLaunchKernelGGL(k_mg_pgj_b, g, b, 0, s, P, n, k0, bk, (const double *)work);
+    }
     if (P32) hipLaunchKernelGGL(k_mg_p32, g, b, 0, s, (const double *)P, P32, nn);
 }
 

@@ -42,6 +42,12 @@ constexpr int MG_EXACT_MAX = 1024;
 constexpr int MG_EXACT_MAX_LARGE = 2600;
 constexpr int MG_LARGE_CELLS = 131072;
 constexpr int MG_XROWS = TILE / 64; // rows of the exact solve per workgroup (one per wave)
+// Set-up of the exact level's dense inverse: Gauss-Jordan elimination in
+// blocks of MG_GJB pivots; its scratch holds the block's transformed pivot
+// rows (MG_GJB x n), the previous pivot columns (n x MG_GJB), the inverse of
+// the diagonal block and the shift c.
+constexpr int MG_GJB = 16;
+__host__ __device__ inline size_t mg_gj_work(int n) { return 2 * (size_t)MG_GJB * n + MG_GJB * MG_GJB + 1; }
 constexpr int MG_MAXLEV = 32;
 struct MLevel {
     int32_t n, nx, ny, nz;        // cells of this level and their counts per axis
