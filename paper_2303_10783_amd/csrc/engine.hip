@@ -1129,13 +1129,16 @@ static int solve_mixed(Group &g, Phase &P)
         if (!any_status(g, S, 0, K_RUNNING)) break;
         int k = 0;
         RCHK(start_solves(g, P, I, 1, k, 0));
+        // the chunk queued after the one that showed no inner solve running
+        // is left to run (its launches return at once) while the host queues
+        // the refinement kernels behind it
         int slot;
-        RCHK(iterate(g, P, I, 1, P.pred_inner, k, &S, 0, &slot));
+        RCHK(iterate(g, P, I, 1, P.pred_inner, k, &S, 0, &slot, false));
         // an inner solve that broke down (K_RESTART) continues from its x
         // with a fresh residual before its correction is applied
         for (int rs = 0; rs < 8 && any_status(g, I, slot, K_RESTART); ++rs) {
             RCHK(start_solves(g, P, I, 1, k, 1));
-            RCHK(iterate(g, P, I, 1, std::max(2, P.pred_inner / 4), k, &S, 0, &slot));
+            RCHK(iterate(g, P, I, 1, std::max(2, P.pred_inner / 4), k, &S, 0, &slot, false));
         }
         for (int gi = 0; gi < 2; ++gi) launch_ir_update(gi ? 7 : 5, S.jobs_d, S.tiles_d[gi], S.nt[gi], g.stream);
         for (int gi = 0; gi < 2; ++gi) launch_ir_resid(gi ? 7 : 5, S.jobs_d, S.tiles_d[gi], S.nt[gi], 1, g.stream);
