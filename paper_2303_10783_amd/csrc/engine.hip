@@ -1123,12 +1123,16 @@ static int solve_mixed(Group &g, Phase &P)
     for (int gi = 0; gi < 2; ++gi) launch_ir_resid(gi ? 7 : 5, S.jobs_d, S.tiles_d[gi], S.nt[gi], 0, g.stream);
     launch_ir_decide(S.jobs_d, nj, 0, max_outer, g.stream);
     RCHK(poll_enqueue(g, 0));
+    // Each sweep's inner solves are started right behind the verdict copy,
+    // before the host has read it: the start kernels of a solve whose
+    // refinement is no longer RUNNING return at once (outer_idle), so the
+    // device runs the starts while the host waits for the verdict.
+    int k = 0;
+    RCHK(start_solves(g, P, I, 1, k, 0));
     RCHK(poll_wait(g, 0));
     int mx_inner = 1;
     for (int outer = 0; outer < max_outer + 1; ++outer) {
         if (!any_status(g, S, 0, K_RUNNING)) break;
-        int k = 0;
-        RCHK(start_solves(g, P, I, 1, k, 0));
         // the chunk queued after the one that showed no inner solve running
         // is left to run (its launches return at once) while the host queues
         // the refinement kernels behind it
@@ -1144,6 +1148,8 @@ static int solve_mixed(Group &g, Phase &P)
         for (int gi = 0; gi < 2; ++gi) launch_ir_resid(gi ? 7 : 5, S.jobs_d, S.tiles_d[gi], S.nt[gi], 1, g.stream);
         launch_ir_decide(S.jobs_d, nj, 1, max_outer, g.stream);
         RCHK(poll_enqueue(g, 0));
+        k = 0;
+        RCHK(start_solves(g, P, I, 1, k, 0));
         RCHK(poll_wait(g, 0));
         HIPCHK(hipGetLastError());
         for (size_t j = 0; j < I.jobs.size(); ++j) mx_inner = std::max(mx_inner, (int)g.ks_h[0][I.st_index[j]].it);
