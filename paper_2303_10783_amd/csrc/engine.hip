@@ -199,6 +199,10 @@ static size_t footprint(const Sizes &z, int precision)
             b += 4 * al((size_t)m.n[l] * D);                     // inverse diagonal, rhs, correction, pre-smoothed
             if (precision) b += 4 * al((size_t)m.n[l] * F);
         }
+        if (z.dim == 2) {                                        // level 0 pre-smoothed
+            b += al((size_t)m.n[0] * D);
+            if (precision) b += al((size_t)m.n[0] * F);
+        }
         const size_t nx2 = (size_t)m.n[m.nglob] * m.n[m.nglob];  // dense inverse of the exact level
         b += al(nx2 * D) + al(nx2 * F);
         b += al(mg_gj_work(m.n[m.nglob]) * D);                   // its elimination scratch
@@ -263,10 +267,10 @@ static double row_bytes(int cls, int nd, int dim, int tsize)
     // multigrid (the pressure operator is applied from its closed form, no
     // matrix values are read)
     case SOL_KCLASS_MG_PQ: return 4.0 * tsize;           // z, p_old; p, q
-    case SOL_KCLASS_MG_DOWN0:                            // M, r, q, x, p; x, r; level-1 rhs
-        return (7.0 + 1.0 / (1 << dim)) * tsize;
-    case SOL_KCLASS_MG_UP0:                              // M, r, level-1 correction; z
-        return (3.0 + 1.0 / (1 << dim)) * tsize;
+    case SOL_KCLASS_MG_DOWN0:                            // M, r, q, x, p; x, r; level-1 rhs (2D: and x2)
+        return (7.0 + (dim == 2) + 1.0 / (1 << dim)) * tsize;
+    case SOL_KCLASS_MG_UP0:                              // M, r, level-1 correction (2D: and x2); z
+        return (3.0 + (dim == 2) + 1.0 / (1 << dim)) * tsize;
     case SOL_KCLASS_MG_COARSE: return 0.0;
     case SOL_KCLASS_ASM_MOM: return 16.0 * nd + 8.0 * dim + 48.0;
     case SOL_KCLASS_ASM_TRN: return 24.0 * nd + 8.0 * dim + 56.0;
@@ -1465,6 +1469,11 @@ static int alloc_case(sol_handle *h)
             if (l == 0) {
                 L.minv = d.minv[SP];
                 L32.minv = d.minv32[SP];
+                if (z.dim == 2) {
+                    // the level-0 pre-smoothed value (two sweeps in 2D)
+                    if (!(L.xs = dal(L.n))) return fail(SOL_ENOMEM, "device allocation failed");
+                    if (mixed && !(L32.xs = fal(L.n))) return fail(SOL_ENOMEM, "device allocation failed");
+                }
             } else {
                 const size_t n = L.n;
                 double *mi = dal(n), *bl = dal(n), *el = dal(n), *xl = dal(n);

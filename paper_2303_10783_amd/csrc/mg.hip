@@ -13,7 +13,7 @@
 //
 // Preconditioner z = M r: one V-cycle from a zero initial guess.
 //   levels 0 .. nglob-1: damped-Jacobi sweeps before and after the
-//     coarse correction (two on the coarser levels of a 2D grid, else one), the
+//     coarse correction (two on every level of a 2D grid, one in 3D), the
 //     correction scaled by mg_og (aggregation under-estimates smooth error;
 //     the scaling restores most of the rate);
 //   level nglob (the first with at most MG_EXACT_MAX cells, or
@@ -37,14 +37,15 @@
 //              partials (p_k, q)
 //   down0(k):  alpha = gamma_k / (p_k, q); x += alpha p_k;
 //              r_(k+1) = r_k - alpha q; partial ||r_(k+1)||^2; pre-smooth
-//              on level 0 and restrict the residual to level 1
+//              on level 0 (2D: two sweeps, the result kept) and restrict
+//              the residual to level 1
 //   down(l):   pre-smooth level l (2D: two sweeps, the result kept),
 //              restrict to level l+1                       (l = 1 .. nglob-1)
 //   exact:     e = P^-1 b on level nglob (dense product, one wave per row)
 //   up(l):     prolong onto the pre-smoothed value, post-smooth level l
 //              (2D: two sweeps)                            (l = nglob-1 .. 1)
-//   up0(k):    prolong, post-smooth level 0 -> z_(k+1); partials (r, z),
-//              sum(z), sum(r)
+//   up0(k):    prolong, post-smooth level 0 (2D: two sweeps) -> z_(k+1);
+//              partials (r, z), sum(z), sum(r)
 // Kernels work on coarse cells of the next level: a thread takes one coarse
 // cell and its 2^d children, so a restriction needs no cross-thread sum.
 // Values a stencil needs at neighbour rows are recomputed there from
@@ -171,6 +172,34 @@ __device__ __forceinline__ bool mg_live(const KJob &J, int k)
 }
 
 __device__ __forceinline__ int kidx(const int *kbase, int koff) { return (kbase ? *kbase : 0) + koff; }
+
+// ------------------------------------------------- 2D level 0, two sweeps
+// A thread of the level-0 kernels of a 2D grid holds the window of its
+// aggregate: the 2 x 2 children at window positions (u, v) = (2..3, 2..3)
+// and every cell within two stencil steps of them, inside the 6 x 6 square
+// whose corner (0, 0) is the fine cell (2 cx - 2, 2 cy - 2).  A window cell
+// beyond the grid is loaded from the nearest grid cell; it enters no result,
+// since the coupling across a boundary face is 0.
+constexpr int W2 = 6;
+__host__ __device__ constexpr int wdist(int u, int v)
+{
+    return (u < 2 ? 2 - u : (u > 3 ? u - 3 : 0)) + (v < 2 ? 2 - v : (v > 3 ? v - 3 : 0));
+}
+
+__device__ __forceinline__ int win_idx(const MLevel &L, int gx, int gy)
+{
+    return min(max(gx, 0), L.nx - 1) + L.nx * min(max(gy, 0), L.ny - 1);
+}
+
+// (A f) at window cell (u, v) of a cell within one step of the children:
+// level 0 couples neighbours across a face with 1/h_a^2
+template <class T>
+__device__ __forceinline__ T win_op(const MLevel &L, int gx, int gy, int u, int v, const T (&f)[W2][W2], T c0, T c1)
+{
+    const T fc = f[v][u];
+    return (gx > 0 ? c0 : T(0)) * (fc - f[v][u - 1]) + (gx + 1 < L.nx ? c0 : T(0)) * (fc - f[v][u + 1]) +
+           (gy > 0 ? c1 : T(0)) * (fc - f[v - 1][u]) + (gy + 1 < L.ny ? c1 : T(0)) * (fc - f[v + 1][u]);
+}
 
 // ------------------------------------------------------------- operator
 
@@ -414,6 +443,54 @@ __global__ __launch_bounds__(TILE) void k_mg_down0(const KJob *__restrict__ jobs
     auto bc = G<T>(J.lev[1].b);
     double rr = 0.0;
     const int I0 = tl.t * L.cpt, I1 = min(L.cn, I0 + L.cpt);
+    if constexpr (DIM == 2) {
+        // x1 = w D^-1 r on the window, x2 = x1 + w D^-1 (r - A x1) within
+        // one step of the children, then their residual r - A x2
+        auto xs = G<T>(L.xs);
+        const T c0 = (T)L.ih2[0], c1 = (T)L.ih2[1];
+        for (int I = I0 + threadIdx.x; I < I1; I += TILE) {
+            const Agg<DIM> a = agg_of<DIM>(L, I, icx, icxy);
+            const int X0 = 2 * a.c[0] - 2, Y0 = 2 * a.c[1] - 2;
+            T rw[W2][W2], mw[W2][W2], f1[W2][W2], f2[W2][W2];
+#pragma unroll
+            for (int v = 0; v < W2; ++v)
+#pragma unroll
+                for (int u = 0; u < W2; ++u) {
+                    if (wdist(u, v) > 2) continue;
+                    const int j = win_idx(L, X0 + u, Y0 + v);
+                    rw[v][u] = INIT ? rn[j] : rc[j] - ta * q[j];
+                    mw[v][u] = mi[j];
+                }
+#pragma unroll
+            for (int v = 0; v < W2; ++v)
+#pragma unroll
+                for (int u = 0; u < W2; ++u)
+                    if (wdist(u, v) <= 2) f1[v][u] = w * mw[v][u] * rw[v][u];
+#pragma unroll
+            for (int v = 1; v < W2 - 1; ++v)
+#pragma unroll
+                for (int u = 1; u < W2 - 1; ++u)
+                    if (wdist(u, v) <= 1)
+                        f2[v][u] = f1[v][u] + w * mw[v][u] * (rw[v][u] - win_op(L, X0 + u, Y0 + v, u, v, f1, c0, c1));
+            T bsum = T(0);
+#pragma unroll
+            for (int v = 2; v < 4; ++v)
+#pragma unroll
+                for (int u = 2; u < 4; ++u) {
+                    const int gx = X0 + u, gy = Y0 + v;
+                    if (gx >= L.nx || gy >= L.ny) continue;
+                    const int i = gx + L.nx * gy;
+                    bsum += rw[v][u] - win_op(L, gx, gy, u, v, f2, c0, c1);
+                    xs[i] = f2[v][u];
+                    if (!INIT) {
+                        rn[i] = rw[v][u];
+                        x[i] = x[i] + ta * p[i];
+                    }
+                    rr += (double)rw[v][u] * rw[v][u];
+                }
+            bc[I] = bsum;
+        }
+    } else
     for (int I = I0 + threadIdx.x; I < I1; I += TILE) {
         const Agg<DIM> a = agg_of<DIM>(L, I, icx, icxy);
         T bsum = T(0);
@@ -489,15 +566,16 @@ __device__ __forceinline__ void step_q(const int *q, int ax, int dir, int *qj)
     for (int d = 0; d < 3; ++d) qj[d] = q[d] + (d == ax ? dir : 0);
 }
 
-// In 2D, levels l >= 1 smooth with two damped-Jacobi sweeps before and
-// after the coarse correction (level 0 with one): in a study of the
-// V-cycle-PCG this cuts the iterations from 17 to 14 at 500x300 (measured
-// 13.5 -> 11.5 per step), and these kernels are bound by launch latency, not
-// by the loads the second sweep adds.  The pre-smoothed value x2 is stored
-// (xs) for the post-smoothing; each sweep's value at a neighbour is
-// recomputed there, so a kernel reaches two stencil steps.  3D keeps one
-// sweep: at 128x128x64 the 25-cell reach on the 131072-cell first level
-// cost more than the 2.3 iterations per step it saved (282 -> 265 M
+// In 2D, every level smooths with two damped-Jacobi sweeps before and
+// after the coarse correction: in a study of the V-cycle-PCG two sweeps on
+// the coarse levels cut the iterations from 17 to 14 at 500x300 (measured
+// 13.5 -> 11.5 per step), two on level 0 as well from 14 to 11 (measured
+// 11.5 -> 8.6), and these kernels are bound by launch latency, not by the
+// loads the second sweep adds.  The pre-smoothed value x2 is stored (xs)
+// for the post-smoothing; each sweep's value at a neighbour is recomputed
+// there, so a kernel reaches two stencil steps.  3D keeps one sweep: at
+// 128x128x64 the 25-cell reach on the 131072-cell first level cost more
+// than the 2.3 iterations per step it saved (282 -> 265 M
 // cell-updates/s).
 
 // level l >= 1 (launch level): pre-smooth from zero, x1 = w D^-1 b (3D),
@@ -613,6 +691,54 @@ __global__ __launch_bounds__(TILE) void k_mg_up0(const KJob *__restrict__ jobs, 
     auto ec = R<T>(J.lev[1].e);
     double vv[3] = {0.0, 0.0, 0.0};     // (r, z), sum z, sum r
     const int I0 = tl.t * L.cpt, I1 = min(L.cn, I0 + L.cpt);
+    if constexpr (DIM == 2) {
+        // e0 = x2 + og P e_c on the window, e1 = e0 + w D^-1 (r - A e0)
+        // within one step of the children, z = e1 + w D^-1 (r - A e1)
+        auto xs = R<T>(L.xs);
+        const T c0 = (T)L.ih2[0], c1 = (T)L.ih2[1];
+        for (int I = I0 + threadIdx.x; I < I1; I += TILE) {
+            const Agg<DIM> a = agg_of<DIM>(L, I, icx, icxy);
+            const int X0 = 2 * a.c[0] - 2, Y0 = 2 * a.c[1] - 2;
+            // coarse corrections of the 3 x 3 aggregates the window meets
+            T ew[3][3];
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    ew[b][c] = ec[min(max(a.c[0] - 1 + c, 0), L.cnx - 1) + L.cnx * min(max(a.c[1] - 1 + b, 0), L.cny - 1)];
+            T e0[W2][W2], e1[W2][W2], rw[W2][W2], mw[W2][W2];
+#pragma unroll
+            for (int v = 0; v < W2; ++v)
+#pragma unroll
+                for (int u = 0; u < W2; ++u) {
+                    if (wdist(u, v) > 2) continue;
+                    const int j = win_idx(L, X0 + u, Y0 + v);
+                    e0[v][u] = xs[j] + og * ew[v >> 1][u >> 1];
+                    if (wdist(u, v) <= 1) {
+                        rw[v][u] = r[j];
+                        mw[v][u] = mi[j];
+                    }
+                }
+#pragma unroll
+            for (int v = 1; v < W2 - 1; ++v)
+#pragma unroll
+                for (int u = 1; u < W2 - 1; ++u)
+                    if (wdist(u, v) <= 1)
+                        e1[v][u] = e0[v][u] + w * mw[v][u] * (rw[v][u] - win_op(L, X0 + u, Y0 + v, u, v, e0, c0, c1));
+#pragma unroll
+            for (int v = 2; v < 4; ++v)
+#pragma unroll
+                for (int u = 2; u < 4; ++u) {
+                    const int gx = X0 + u, gy = Y0 + v;
+                    if (gx >= L.nx || gy >= L.ny) continue;
+                    const T zi = e1[v][u] + w * mw[v][u] * (rw[v][u] - win_op(L, gx, gy, u, v, e1, c0, c1));
+                    z[gx + L.nx * gy] = zi;
+                    vv[0] += (double)rw[v][u] * zi;
+                    vv[1] += (double)zi;
+                    vv[2] += (double)rw[v][u];
+                }
+        }
+    } else
     for (int I = I0 + threadIdx.x; I < I1; I += TILE) {
         const Agg<DIM> a = agg_of<DIM>(L, I, icx, icxy);
 #pragma unroll

@@ -59,7 +59,7 @@ struct MLevel {
     double ih2[3];                // 1 / h_a^2 of level 0
     const void *minv;             // Jacobi inverse of the diagonal (levels above the exact one)
     void *b, *e;                  // right-hand side and correction (levels >= 1)
-    void *xs;                     // levels >= 1: the pre-smoothed value, read back by the post-smoothing
+    void *xs;                     // levels >= 1, and level 0 in 2D: the pre-smoothed value, read back by the post-smoothing
     const void *pinv;             // exact level: dense n x n inverse of A + c 1 1^T (symmetric), FP32
 };
 
