@@ -59,15 +59,21 @@ namespace sol {
 
 // damped-Jacobi weight and coarse-correction scaling per dimension, chosen
 // by the PCG iteration count of the V-cycle over grid sizes of the
-// workloads.  2D (50x30 .. 800x480): 0.8 / 1.8; 0.85 gains two iterations at
-// the largest grid and loses two at the smallest.  3D (24x20x16 ..
-// 160x160x80): 0.9 / 1.65 needs 26 iterations at 128x128x64 where the 2D pair
-// needs 31, and 29 instead of 35 at 160x160x80.  Both weights stay below 1,
-// and the spectrum of D^-1 A lies in [0, 2] on every level (diagonally
-// dominant, zero row sums), so the smoother converges in the A-norm and the
-// V-cycle stays positive definite.
+// workloads.  2D (50x30 .. 800x480, two sweeps per level): 0.8 / 2.0 needs
+// 9 iterations at every size, 0.8 / 1.8 needs 9 - 12 (11 at 500x300), 1.9
+// and 2.1 lie between, 0.75 and 0.85 lose one.  3D (24x20x16 .. 160x160x80,
+// one sweep): 0.9 / 1.65 needs 26 iterations at 128x128x64 where the 2D
+// pair of one sweep (0.8 / 1.8) needs 31, and 29 instead of 35 at
+// 160x160x80; 1.8 - 2.0 lose two to five.  Both weights stay below 1, and
+// the spectrum of D^-1 A lies in [0, 2] on every level (diagonally dominant,
+// zero row sums), so the smoother converges in the A-norm.  The V-cycle
+// stays positive definite for any positive scaling: its error operator is
+// the smoother's, S^v (I - og P B_c P^T A) S^v, and the correction term is
+// non-negative in the A-inner product (B_c, the coarse cycle, is itself
+// positive definite), so every eigenvalue stays below that of S^(2v), below
+// 1 off the constants.
 template <int DIM> constexpr double mg_w() { return DIM == 3 ? 0.9 : 0.8; }
-template <int DIM> constexpr double mg_og() { return DIM == 3 ? 1.65 : 1.8; }
+template <int DIM> constexpr double mg_og() { return DIM == 3 ? 1.65 : 2.0; }
 
 // floor(i / d) for 0 <= i < 2^31, 1 <= d, from the double reciprocal inv = 1/d
 __device__ __forceinline__ int fdiv(int i, int d, double inv)
