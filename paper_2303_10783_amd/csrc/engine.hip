@@ -497,16 +497,27 @@ static int finish_set(Group &g, JobSet &S)
     double *part = (double *)gmalloc(g, sizeof(double) * std::max<size_t>(total, 1));
     if (!part) return fail(SOL_ENOMEM, "group allocation failed");
     size_t off = 0;
-    std::vector<std::vector<JTile>> per[2];
     for (size_t j = 0; j < S.jobs.size(); ++j) {
-        KJob &J = S.jobs[j];
-        J.part = part + off;
-        off += (size_t)J.ntile * 2 * NSLOT;
-        const int gi = g.cs[S.case_of[j]]->z.nd == 7 ? 1 : 0;
-        std::vector<JTile> tl;
-        for (int t = 0; t < J.ntile; ++t) tl.push_back({(int)j, t, 0, 0});
-        per[gi].push_back(std::move(tl));
+        S.jobs[j].part = part + off;
+        off += (size_t)S.jobs[j].ntile * 2 * NSLOT;
     }
+    // Within an XCD's range the workgroups are dispatched in list order, and
+    // the two-sweep BiCGSTAB kernels hold two workgroups per CU, fewer than a
+    // launch has: the solves that usually iterate longest are listed first,
+    // so that the workgroups of a solve that has converged (which exit at
+    // once) take the slots left over instead of delaying those of the solves
+    // still running.  The solute solve (its matrix is close to diagonal)
+    // mostly converges in one iteration while the energy solve takes ten.
+    std::vector<std::vector<JTile>> per[2];
+    for (int pass = 0; pass < 2; ++pass)
+        for (size_t j = 0; j < S.jobs.size(); ++j) {
+            if ((S.sys_of[j] == SC) != (pass == 1)) continue;
+            const KJob &J = S.jobs[j];
+            const int gi = g.cs[S.case_of[j]]->z.nd == 7 ? 1 : 0;
+            std::vector<JTile> tl;
+            for (int t = 0; t < J.ntile; ++t) tl.push_back({(int)j, t, 0, 0});
+            per[gi].push_back(std::move(tl));
+        }
     RCHK(upload(g, &S.jobs_d, S.jobs));
     for (int gi = 0; gi < 2; ++gi) {
         const std::vector<JTile> jt = xcd_order(per[gi]);
