@@ -1042,21 +1042,36 @@ __device__ __forceinline__ void bicg_a_body(const KJob *__restrict__ jobs, const
     put_partials<2>(q, J.part, off, tl.t);
 }
 
-// B(k) and A(k) kernels.  One sweep: k_bicg_b / k_bicg_a.  Two sweeps:
-// k_bicg2_b64 / k_bicg2_a64 (FP64) let the compiler use up to two waves' worth
-// of registers per lane, so that a row's 60-180 gathers are issued together
-// rather than in a chain of round trips (measured faster at 500x300);
-// k_bicg2_b32 / k_bicg2_a32 (FP32 inner solves) were faster without it.
+// B(k) and A(k) kernels.  One sweep: k_bicg_b / k_bicg_a.  Two sweeps,
+// FP64: k_bicg2_b64 / k_bicg2_a64.  On 7-point systems (gathers only) they
+// may use up to two waves' worth of registers per lane, so that a row's
+// 60-180 gathers are issued together rather than in a chain of round trips;
+// on 5-point systems (staged through LDS) the registers of four waves per
+// SIMD (127 and 96 VGPRs instead of 215 and 145): four workgroups per CU,
+// every workgroup of a 500x300 launch resident at once (the two-wave form
+// left 10 of 74 per XCD for a second round), measured faster at 500x300
+// (+4 %) and in the 64-cavity batch (+21 %); the 7-point pair lost 3 % with
+// four.  k_bicg2_b32 / k_bicg2_a32 (FP32 inner solves) take the default.
 template <int ND, class T>
 __global__ __launch_bounds__(TILE) void k_bicg_b(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles, const int *kbase, int koff) { bicg_b_body<ND, 1, T>(jobs, tiles, kbase, koff); }
 template <int ND, class T>
 __global__ __launch_bounds__(TILE) void k_bicg_a(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles, const int *kbase, int koff) { bicg_a_body<ND, 1, T>(jobs, tiles, kbase, koff); }
 template <int ND>
-__global__ __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(1, 2)))
-void k_bicg2_b64(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles, const int *kbase, int koff) { bicg_b_body<ND, 2, double>(jobs, tiles, kbase, koff); }
+__global__ void k_bicg2_b64(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles, const int *kbase, int koff);
 template <int ND>
+__global__ void k_bicg2_a64(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles, const int *kbase, int koff);
+template <>
+__global__ __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(1, 4)))
+void k_bicg2_b64<5>(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles, const int *kbase, int koff) { bicg_b_body<5, 2, double>(jobs, tiles, kbase, koff); }
+template <>
+__global__ __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(1, 4)))
+void k_bicg2_a64<5>(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles, const int *kbase, int koff) { bicg_a_body<5, 2, double>(jobs, tiles, kbase, koff); }
+template <>
 __global__ __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(1, 2)))
-void k_bicg2_a64(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles, const int *kbase, int koff) { bicg_a_body<ND, 2, double>(jobs, tiles, kbase, koff); }
+void k_bicg2_b64<7>(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles, const int *kbase, int koff) { bicg_b_body<7, 2, double>(jobs, tiles, kbase, koff); }
+template <>
+__global__ __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(1, 2)))
+void k_bicg2_a64<7>(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles, const int *kbase, int koff) { bicg_a_body<7, 2, double>(jobs, tiles, kbase, koff); }
 template <int ND>
 __global__ __launch_bounds__(TILE) void k_bicg2_b32(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles, const int *kbase, int koff) { bicg_b_body<ND, 2, float>(jobs, tiles, kbase, koff); }
 template <int ND>
