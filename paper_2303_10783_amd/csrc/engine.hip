@@ -1033,7 +1033,7 @@ static int iterate(Group &g, Phase &P, JobSet &S, int fp32, int pred, int &k, co
 {
     int slot = gslot ^ 1;
     const int first = std::max(1, pred - pred / 8);
-    const int later = std::max(2, pred / 16);
+    const int later = std::max(1, pred / 16);
     RCHK(enqueue_iters(g, P, S, fp32, first, k));
     RCHK(poll_enqueue(g, slot));
     for (;;) {
