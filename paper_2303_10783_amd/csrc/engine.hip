@@ -936,7 +936,8 @@ static int start_solves(Group &g, Phase &P, JobSet &S, int fp32, int k, int mode
 {
     if (P.kind != K_MGCG) {
         for (int gi = 0; gi < 2; ++gi)
-            launch_kinit(P.kind, gi ? 7 : 5, fp32, P.two[gi], S.jobs_d, S.tiles_d[gi], S.nt[gi], k, mode, g.stream);
+            launch_kinit(P.kind, gi ? 7 : 5, fp32, P.two[gi], S.jobs_d, S.tiles_d[gi], S.nt[gi], k, mode,
+                         S.iter.empty() ? 0 : S.iter[0].smem[gi], g.stream);
         return SOL_OK;
     }
     for (int gi = 0; gi < 2; ++gi) launch_mg_init(gi ? 7 : 5, fp32, S.jobs_d, S.tiles_d[gi], S.nt[gi], k, mode, g.stream);

@@ -753,7 +753,9 @@ __global__ __launch_bounds__(TILE) void k_bicg_init(const KJob *__restrict__ job
 }
 
 // first iteration of a (re)start at k = k0: convergence test on r_k; p_k =
-// r_k, v_k = A M p_k; partial (rh, v_k)
+// r_k, v_k = A M p_k; partial (rh, v_k).  Two sweeps on a staged 5-point FP64
+// solve: the tile's neighbourhood goes through LDS, as in the iteration
+// kernels.
 template <int ND, int PD, class T>
 __global__ __launch_bounds__(TILE) void k_bicg_first(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles, int k)
 {
@@ -774,6 +776,21 @@ __global__ __launch_bounds__(TILE) void k_bicg_first(const KJob *__restrict__ jo
     auto p = G<T>(pk ? J.p1 : J.p0), vv = G<T>(pk ? J.v1 : J.v0);
     double q = 0.0;
     const int i0 = tl.t * J.rpt, i1 = min(n, i0 + J.rpt);
+    bool done = false;
+    if constexpr (PD == 2 && ND == 5 && sizeof(T) == 8) {
+        if (J.staged) {
+            RO<T> Ad[ND];
+            diag_views<ND, T>(J.A, n, Ad);
+            const auto Mi = R<T>(J.minv), Rr = R<T>(pk ? J.r1 : J.r);
+            stage2_amf<T>(J, i0, i1, Ad, Mi, [&](int j) { return Rr[j]; }, [&](int i, T vi) {
+                p[i] = r[i];
+                vv[i] = vi;
+                q += (double)rh[i] * vi;
+            });
+            done = true;
+        }
+    }
+    if (!done)
     for (int i = i0 + threadIdx.x; i < i1; i += TILE) {
         T vi;
         if constexpr (PD == 1) {
@@ -1541,7 +1558,8 @@ void launch_tune_rhs(void *b, int fp32, int n, hipStream_t s)
 }
 
 template <int ND, class T>
-static void launch_init_nd(int kind, bool two, const KJob *j, const JTile *t, int nt, int k, int mode, hipStream_t s)
+static void launch_init_nd(int kind, bool two, const KJob *j, const JTile *t, int nt, int k, int mode, size_t smem,
+                           hipStream_t s)
 {
     if (kind == K_CG) {
         hipLaunchKernelGGL((k_cg_init_a<ND, T>), GRID(nt), 0, s, j, t, k, mode);
@@ -1549,20 +1567,20 @@ static void launch_init_nd(int kind, bool two, const KJob *j, const JTile *t, in
         return;
     }
     hipLaunchKernelGGL((k_bicg_init<ND, T>), GRID(nt), 0, s, j, t, k, mode);
-    if (two) hipLaunchKernelGGL((k_bicg_first<ND, 2, T>), GRID(nt), 0, s, j, t, k);
+    if (two) hipLaunchKernelGGL((k_bicg_first<ND, 2, T>), dim3(nt), dim3(TILE), smem, s, j, t, k);
     else hipLaunchKernelGGL((k_bicg_first<ND, 1, T>), GRID(nt), 0, s, j, t, k);
 }
 
 void launch_kinit(int kind, int nd, int fp32, bool two, const KJob *j, const JTile *t, int nt, int k, int mode,
-                  hipStream_t s)
+                  size_t smem, hipStream_t s)
 {
     if (nt <= 0) return;
     if (nd == 5) {
-        if (fp32) launch_init_nd<5, float>(kind, two, j, t, nt, k, mode, s);
-        else launch_init_nd<5, double>(kind, two, j, t, nt, k, mode, s);
+        if (fp32) launch_init_nd<5, float>(kind, two, j, t, nt, k, mode, smem, s);
+        else launch_init_nd<5, double>(kind, two, j, t, nt, k, mode, smem, s);
     } else {
-        if (fp32) launch_init_nd<7, float>(kind, two, j, t, nt, k, mode, s);
-        else launch_init_nd<7, double>(kind, two, j, t, nt, k, mode, s);
+        if (fp32) launch_init_nd<7, float>(kind, two, j, t, nt, k, mode, smem, s);
+        else launch_init_nd<7, double>(kind, two, j, t, nt, k, mode, smem, s);
     }
 }
 

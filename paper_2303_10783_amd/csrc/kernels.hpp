@@ -14,7 +14,7 @@ void launch_phase_commit(int dim, const CaseDev *c, const Tile *t, int nt, hipSt
 
 // two: BiCGSTAB preconditioned by two Jacobi sweeps instead of one
 void launch_kinit(int kind, int nd, int fp32, bool two, const KJob *j, const JTile *t, int nt, int k, int mode,
-                  hipStream_t s);
+                  size_t smem, hipStream_t s);
 void launch_kfinish(int nd, const KJob *j, const JTile *t, int nt, hipStream_t s);
 void launch_kdecide(const KJob *j, int njobs, hipStream_t s);
 // iteration kernels, all with the signature (jobs, tiles, const int *kbase,
