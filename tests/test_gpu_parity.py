@@ -594,6 +594,10 @@ def test_multigrid_pressure_solve(sol, dev):
     sj = gj.step(3)
     print("pressure iterations over 3 steps: mg", sm["iters_total"][3], "jacobi", sj["iters_total"][3], flush=True)
     assert sm["iters_total"][3] <= 3 * 60
+    # the cycle of a 2D grid (two damped-Jacobi sweeps on every level,
+    # correction scaled by 2.0) takes 35 iterations here; a weaker smoother
+    # or a wrong window in the level-0 kernels shows as more
+    assert sm["iters_total"][3] <= 42
     assert sm["iters_total"][3] * 10 <= sj["iters_total"][3]
     assert sm["rel_resid"][3] <= 2e-13 * (1 + 1e-6)
     errs = field_errors(gm.read_fields(), gj.read_fields())
