@@ -48,6 +48,11 @@
 //              partials (r, z), sum(z), sum(r)
 // Kernels work on coarse cells of the next level: a thread takes one coarse
 // cell and its 2^d children, so a restriction needs no cross-thread sum.
+// The level-0 kernels of the smoother (and pq in 3D) first load every value
+// their children's stencils reach into a register window, once per thread
+// (3D, one sweep: the 8 children and their 24 face neighbours, 23.5 -> 16.9
+// us per down0 launch at 128x128x64, pq 15.9 -> 12.7, up0 15.2 -> 10.7;
+// 2D, two sweeps: the 24 cells within two steps of the 4 children).
 // Values a stencil needs at neighbour rows are recomputed there from
 // vectors the same kernel does not write (r and p are ping-ponged by
 // iteration parity), as in the other Krylov kernels.
@@ -205,6 +210,37 @@ __device__ __forceinline__ T win_op(const MLevel &L, int gx, int gy, int u, int 
     const T fc = f[v][u];
     return (gx > 0 ? c0 : T(0)) * (fc - f[v][u - 1]) + (gx + 1 < L.nx ? c0 : T(0)) * (fc - f[v][u + 1]) +
            (gy > 0 ? c1 : T(0)) * (fc - f[v - 1][u]) + (gy + 1 < L.ny ? c1 : T(0)) * (fc - f[v + 1][u]);
+}
+
+// 3D level 0: a thread holds the 2 x 2 x 2 children of its aggregate at
+// window positions (1..2)^3 and their face neighbours (one stencil step
+// from the block) in the 4 x 4 x 4 window whose corner (0, 0, 0) is the fine
+// cell (2 cx - 1, 2 cy - 1, 2 cz - 1): each value a child's stencil needs is
+// loaded once per thread instead of once per child that reaches it.  Window
+// cells beyond the grid are handled as in 2D.
+constexpr int W3 = 4;
+__host__ __device__ constexpr int wdist3(int u, int v, int w)
+{
+    return (u < 1 ? 1 - u : (u > 2 ? u - 2 : 0)) + (v < 1 ? 1 - v : (v > 2 ? v - 2 : 0)) +
+           (w < 1 ? 1 - w : (w > 2 ? w - 2 : 0));
+}
+
+__device__ __forceinline__ int win3_idx(const MLevel &L, int gx, int gy, int gz)
+{
+    return min(max(gx, 0), L.nx - 1) + L.nx * (min(max(gy, 0), L.ny - 1) + L.ny * min(max(gz, 0), L.nz - 1));
+}
+
+// (A f) at a child (u, v, w) of the window, in the order of apply_op
+template <class T>
+__device__ __forceinline__ T win3_op(const MLevel &L, int gx, int gy, int gz, int u, int v, int w,
+                                     const T (&f)[W3][W3][W3], T c0, T c1, T c2)
+{
+    const T fc = f[w][v][u];
+    T acc = T(0);
+    acc += (gx > 0 ? c0 : T(0)) * (fc - f[w][v][u - 1]) + (gx + 1 < L.nx ? c0 : T(0)) * (fc - f[w][v][u + 1]);
+    acc += (gy > 0 ? c1 : T(0)) * (fc - f[w][v - 1][u]) + (gy + 1 < L.ny ? c1 : T(0)) * (fc - f[w][v + 1][u]);
+    acc += (gz > 0 ? c2 : T(0)) * (fc - f[w - 1][v][u]) + (gz + 1 < L.nz ? c2 : T(0)) * (fc - f[w + 1][v][u]);
+    return acc;
 }
 
 // ------------------------------------------------------------- operator
@@ -385,6 +421,38 @@ __global__ __launch_bounds__(TILE) void k_mg_pq(const KJob *__restrict__ jobs, c
     auto pn = G<T>(pk ? J.p1 : J.p0);
     double v = 0.0;
     const int I0 = tl.t * L.cpt, I1 = min(L.cn, I0 + L.cpt);
+    if constexpr (DIM == 3) {
+        const T c0 = (T)L.ih2[0], c1 = (T)L.ih2[1], c2 = (T)L.ih2[2];
+        for (int I = I0 + threadIdx.x; I < I1; I += TILE) {
+            const Agg<DIM> a = agg_of<DIM>(L, I, icx, icxy);
+            const int X0 = 2 * a.c[0] - 1, Y0 = 2 * a.c[1] - 1, Z0 = 2 * a.c[2] - 1;
+            T f[W3][W3][W3];
+#pragma unroll
+            for (int w = 0; w < W3; ++w)
+#pragma unroll
+                for (int v2 = 0; v2 < W3; ++v2)
+#pragma unroll
+                    for (int u = 0; u < W3; ++u) {
+                        if (wdist3(u, v2, w) > 1) continue;
+                        const int j = win3_idx(L, X0 + u, Y0 + v2, Z0 + w);
+                        f[w][v2][u] = (z[j] - tz) + tb * po[j];
+                    }
+#pragma unroll
+            for (int w = 1; w < 3; ++w)
+#pragma unroll
+                for (int v2 = 1; v2 < 3; ++v2)
+#pragma unroll
+                    for (int u = 1; u < 3; ++u) {
+                        const int gx = X0 + u, gy = Y0 + v2, gz = Z0 + w;
+                        if (gx >= L.nx || gy >= L.ny || gz >= L.nz) continue;
+                        const int i = gx + L.nx * (gy + L.ny * gz);
+                        const T qv = win3_op(L, gx, gy, gz, u, v2, w, f, c0, c1, c2);
+                        pn[i] = f[w][v2][u];
+                        q[i] = qv;
+                        v += (double)f[w][v2][u] * qv;
+                    }
+        }
+    } else
     for (int I = I0 + threadIdx.x; I < I1; I += TILE) {
         const Agg<DIM> a = agg_of<DIM>(L, I, icx, icxy);
 #pragma unroll
@@ -496,39 +564,45 @@ __global__ __launch_bounds__(TILE) void k_mg_down0(const KJob *__restrict__ jobs
                 }
             bc[I] = bsum;
         }
-    } else
-    for (int I = I0 + threadIdx.x; I < I1; I += TILE) {
-        const Agg<DIM> a = agg_of<DIM>(L, I, icx, icxy);
-        T bsum = T(0);
+    } else {
+        // x1 = w D^-1 r on the window, then the children's residual r - A x1
+        const T c0 = (T)L.ih2[0], c1 = (T)L.ih2[1], c2 = (T)L.ih2[2];
+        for (int I = I0 + threadIdx.x; I < I1; I += TILE) {
+            const Agg<DIM> a = agg_of<DIM>(L, I, icx, icxy);
+            const int X0 = 2 * a.c[0] - 1, Y0 = 2 * a.c[1] - 1, Z0 = 2 * a.c[2] - 1;
+            T rw[W3][W3][W3], f1[W3][W3][W3];
 #pragma unroll
-        for (int cz = 0; cz < (DIM == 3 ? 2 : 1); ++cz) {
-            T rv[4], xv[4], sv[4];
-            int iv[4];
-            bool ok[4];
-            for_layer<DIM>(L, a, cz, [&](int c, bool valid, int i, const int *, const int *qc) {
-                const T ax = apply_op<DIM, T>(L, i, qc, [&](int j, int, int) {
-                    const T rj = INIT ? rn[j] : rc[j] - ta * q[j];
-                    return w * mi[j] * rj;
-                });
-                const T ri = INIT ? rn[i] : rc[i] - ta * q[i];
-                rv[c] = ri;
-                if (!INIT) xv[c] = x[i] + ta * p[i];
-                sv[c] = ri - ax;
-                iv[c] = i;
-                ok[c] = valid;
-            });
+            for (int wz = 0; wz < W3; ++wz)
 #pragma unroll
-            for (int c = 0; c < 4; ++c)
-                if (ok[c]) {
-                    if (!INIT) {
-                        rn[iv[c]] = rv[c];
-                        x[iv[c]] = xv[c];
+                for (int vy = 0; vy < W3; ++vy)
+#pragma unroll
+                    for (int ux = 0; ux < W3; ++ux) {
+                        if (wdist3(ux, vy, wz) > 1) continue;
+                        const int j = win3_idx(L, X0 + ux, Y0 + vy, Z0 + wz);
+                        const T rj = INIT ? rn[j] : rc[j] - ta * q[j];
+                        rw[wz][vy][ux] = rj;
+                        f1[wz][vy][ux] = w * mi[j] * rj;
                     }
-                    rr += (double)rv[c] * rv[c];
-                    bsum += sv[c];
-                }
+            T bsum = T(0);
+#pragma unroll
+            for (int wz = 1; wz < 3; ++wz)
+#pragma unroll
+                for (int vy = 1; vy < 3; ++vy)
+#pragma unroll
+                    for (int ux = 1; ux < 3; ++ux) {
+                        const int gx = X0 + ux, gy = Y0 + vy, gz = Z0 + wz;
+                        if (gx >= L.nx || gy >= L.ny || gz >= L.nz) continue;
+                        const int i = gx + L.nx * (gy + L.ny * gz);
+                        const T ri = rw[wz][vy][ux];
+                        if (!INIT) {
+                            rn[i] = ri;
+                            x[i] = x[i] + ta * p[i];
+                        }
+                        rr += (double)ri * ri;
+                        bsum += ri - win3_op(L, gx, gy, gz, ux, vy, wz, f1, c0, c1, c2);
+                    }
+            bc[I] = bsum;
         }
-        bc[I] = bsum;
     }
     double vv[1] = {rr};
     const int off[1] = {poff(J, pn1, PS_RR)};
@@ -744,33 +818,53 @@ __global__ __launch_bounds__(TILE) void k_mg_up0(const KJob *__restrict__ jobs, 
                     vv[2] += (double)rw[v][u];
                 }
         }
-    } else
-    for (int I = I0 + threadIdx.x; I < I1; I += TILE) {
-        const Agg<DIM> a = agg_of<DIM>(L, I, icx, icxy);
+    } else {
+        // x = w D^-1 r + og P e_c on the window, z = x + w D^-1 (r - A x)
+        // at the children
+        const T c0 = (T)L.ih2[0], c1 = (T)L.ih2[1], c2 = (T)L.ih2[2];
+        for (int I = I0 + threadIdx.x; I < I1; I += TILE) {
+            const Agg<DIM> a = agg_of<DIM>(L, I, icx, icxy);
+            const int X0 = 2 * a.c[0] - 1, Y0 = 2 * a.c[1] - 1, Z0 = 2 * a.c[2] - 1;
+            // coarse corrections of the aggregate and of its six face
+            // neighbours (a window cell off the block lies in one of them)
+            auto cix = [&](int dx, int dy, int dz) {
+                return min(max(a.c[0] + dx, 0), L.cnx - 1) +
+                       L.cnx * (min(max(a.c[1] + dy, 0), L.cny - 1) + L.cny * min(max(a.c[2] + dz, 0), L.cnz - 1));
+            };
+            const T e0 = ec[I], exm = ec[cix(-1, 0, 0)], exp_ = ec[cix(1, 0, 0)], eym = ec[cix(0, -1, 0)],
+                    eyp = ec[cix(0, 1, 0)], ezm = ec[cix(0, 0, -1)], ezp = ec[cix(0, 0, 1)];
+            T xw[W3][W3][W3], rw[W3][W3][W3], mw[W3][W3][W3];
 #pragma unroll
-        for (int cz = 0; cz < (DIM == 3 ? 2 : 1); ++cz) {
-            T zv[4], rv[4];
-            int iv[4];
-            bool ok[4];
-            for_layer<DIM>(L, a, cz, [&](int c, bool valid, int i, const int *cx, const int *qc) {
-                const T ax = apply_op<DIM, T>(L, i, qc, [&](int j, int ax_, int dir) {
-                    return w * mi[j] * r[j] + og * ec[agg_nb<DIM>(L, a, cx, ax_, dir)];
-                });
-                const T ri = r[i];
-                const T xi = w * mi[i] * ri + og * ec[I];
-                zv[c] = xi + w * mi[i] * (ri - ax);
-                rv[c] = ri;
-                iv[c] = i;
-                ok[c] = valid;
-            });
+            for (int wz = 0; wz < W3; ++wz)
 #pragma unroll
-            for (int c = 0; c < 4; ++c)
-                if (ok[c]) {
-                    z[iv[c]] = zv[c];
-                    vv[0] += (double)rv[c] * zv[c];
-                    vv[1] += (double)zv[c];
-                    vv[2] += (double)rv[c];
-                }
+                for (int vy = 0; vy < W3; ++vy)
+#pragma unroll
+                    for (int ux = 0; ux < W3; ++ux) {
+                        if (wdist3(ux, vy, wz) > 1) continue;
+                        const int j = win3_idx(L, X0 + ux, Y0 + vy, Z0 + wz);
+                        const T e = ux == 0 ? exm : ux == 3 ? exp_ : vy == 0 ? eym : vy == 3 ? eyp
+                                  : wz == 0 ? ezm : wz == 3 ? ezp : e0;
+                        const T rj = r[j], mj = mi[j];
+                        rw[wz][vy][ux] = rj;
+                        mw[wz][vy][ux] = mj;
+                        xw[wz][vy][ux] = w * mj * rj + og * e;
+                    }
+#pragma unroll
+            for (int wz = 1; wz < 3; ++wz)
+#pragma unroll
+                for (int vy = 1; vy < 3; ++vy)
+#pragma unroll
+                    for (int ux = 1; ux < 3; ++ux) {
+                        const int gx = X0 + ux, gy = Y0 + vy, gz = Z0 + wz;
+                        if (gx >= L.nx || gy >= L.ny || gz >= L.nz) continue;
+                        const T ri = rw[wz][vy][ux];
+                        const T zi = xw[wz][vy][ux] +
+                                     w * mw[wz][vy][ux] * (ri - win3_op(L, gx, gy, gz, ux, vy, wz, xw, c0, c1, c2));
+                        z[gx + L.nx * (gy + L.ny * gz)] = zi;
+                        vv[0] += (double)ri * zi;
+                        vv[1] += (double)zi;
+                        vv[2] += (double)ri;
+                    }
         }
     }
     const int off[3] = {poff(J, pn1, PS_RHO), poff(J, pn1, PS_Q), poff(J, pn1, PS_TT)};
