@@ -1904,27 +1904,34 @@ static int time_pressure(sol_handle *h, double *ms_per_iter)
     HIPCHK(hipMemcpy((char *)J.st + offsetof(KState, tol2), &zero, sizeof(zero), hipMemcpyHostToDevice));
     if (fp32)
         HIPCHK(hipMemcpy((char *)J.partner + offsetof(KState, status), &running, sizeof(running), hipMemcpyHostToDevice));
-    // multigrid converges in a few tens of iterations: time few enough that
-    // the residual stays far above rounding (no breakdown, no early stop)
+    // Multigrid reduces the residual about tenfold per iteration: a run
+    // must stay far above rounding, or a breakdown restarts the solve and
+    // the launches after it time as no-ops (14 iterations did at 500x300
+    // and picked a tile size that made the step 17 % slower).  So three
+    // short runs from a fresh start, the fastest taken.
     const bool mg = P.kind == K_MGCG;
-    const int warm = mg ? 2 : 8, timed_its = mg ? 12 : 48;
-    RCHK(start_solves(g, P, S, fp32 ? 1 : 0, 0, 0));
-    for (int k = 0; k < warm; ++k)
-        for (const Stage &st : S.iter) RCHK(launch_stage(g, S, st, fp32 ? 1 : 0, k));
+    const int warm = mg ? 1 : 8, timed_its = mg ? 6 : 48, runs = mg ? 3 : 1;
     hipEvent_t a, b;
     HIPCHK(hipEventCreate(&a));
     HIPCHK(hipEventCreate(&b));
-    HIPCHK(hipEventRecord(a, g.stream));
-    for (int k = warm; k < warm + timed_its; ++k)
-        for (const Stage &st : S.iter) RCHK(launch_stage(g, S, st, fp32 ? 1 : 0, k));
-    HIPCHK(hipEventRecord(b, g.stream));
-    HIPCHK(hipEventSynchronize(b));
-    float ms = 0.f;
-    HIPCHK(hipEventElapsedTime(&ms, a, b));
+    float best = 0.f;
+    for (int run = 0; run < runs; ++run) {
+        RCHK(start_solves(g, P, S, fp32 ? 1 : 0, 0, 0));
+        for (int k = 0; k < warm; ++k)
+            for (const Stage &st : S.iter) RCHK(launch_stage(g, S, st, fp32 ? 1 : 0, k));
+        HIPCHK(hipEventRecord(a, g.stream));
+        for (int k = warm; k < warm + timed_its; ++k)
+            for (const Stage &st : S.iter) RCHK(launch_stage(g, S, st, fp32 ? 1 : 0, k));
+        HIPCHK(hipEventRecord(b, g.stream));
+        HIPCHK(hipEventSynchronize(b));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, a, b));
+        if (run == 0 || ms < best) best = ms;
+    }
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
     HIPCHK(hipGetLastError());
-    *ms_per_iter = ms / timed_its;
+    *ms_per_iter = best / timed_its;
     return SOL_OK;
 }
 
