@@ -48,11 +48,12 @@
 //              partials (r, z), sum(z), sum(r)
 // Kernels work on coarse cells of the next level: a thread takes one coarse
 // cell and its 2^d children, so a restriction needs no cross-thread sum.
-// The level-0 kernels of the smoother (and pq in 3D) first load every value
-// their children's stencils reach into a register window, once per thread
-// (3D, one sweep: the 8 children and their 24 face neighbours, 23.5 -> 16.9
-// us per down0 launch at 128x128x64, pq 15.9 -> 12.7, up0 15.2 -> 10.7;
-// 2D, two sweeps: the 24 cells within two steps of the 4 children).
+// The level-0 kernels first load every value their children's stencils
+// reach into a register window, once per thread (3D, one sweep: the 8
+// children and their 24 face neighbours, 23.5 -> 16.9 us per down0 launch
+// at 128x128x64, pq 15.9 -> 12.7, up0 15.2 -> 10.7; 2D: the 24 cells within
+// two steps of the 4 children for the two sweeps of down0 and up0, the 12
+// within one for pq).
 // Values a stencil needs at neighbour rows are recomputed there from
 // vectors the same kernel does not write (r and p are ping-ponged by
 // iteration parity), as in the other Krylov kernels.
@@ -151,26 +152,6 @@ __device__ __forceinline__ void for_children(const MLevel &L, const Agg<DIM> &a,
                 f(a.i0 + cx + L.nx * cy + sxy * cz, c3, q);
             }
         }
-    }
-}
-
-// visit the four child slots of layer cz of aggregate a (2D: the only
-// layer): f(c, valid, i, cx, q) with c = cx + 2 cy; a slot beyond an odd
-// upper end is mapped onto the layer's first child of the aggregate (valid =
-// false) so that every access stays inside the level.  The kernels load and
-// compute a whole layer before storing it: the loads of four children are
-// then issued together, with registers for four children only.
-template <int DIM, class F>
-__device__ __forceinline__ void for_layer(const MLevel &L, const Agg<DIM> &a, int cz, F f)
-{
-    const int sxy = L.nx * L.ny;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        int cx[3] = {c & 1, (c >> 1) & 1, cz};
-        const bool valid = cx[0] < a.w[0] && cx[1] < a.w[1] && cx[2] < a.w[2];
-        if (!valid) cx[0] = cx[1] = cx[2] = 0;
-        const int q[3] = {2 * a.c[0] + cx[0], 2 * a.c[1] + cx[1], 2 * a.c[2] + cx[2]};
-        f(c, valid, a.i0 + cx[0] + L.nx * cx[1] + sxy * cx[2], cx, q);
     }
 }
 
@@ -421,7 +402,36 @@ __global__ __launch_bounds__(TILE) void k_mg_pq(const KJob *__restrict__ jobs, c
     auto pn = G<T>(pk ? J.p1 : J.p0);
     double v = 0.0;
     const int I0 = tl.t * L.cpt, I1 = min(L.cn, I0 + L.cpt);
-    if constexpr (DIM == 3) {
+    if constexpr (DIM == 2) {
+        // p on the children and their neighbours (the 2D window within one
+        // step of the children: positions 1..4), then q = A p at the children
+        const T c0 = (T)L.ih2[0], c1 = (T)L.ih2[1];
+        for (int I = I0 + threadIdx.x; I < I1; I += TILE) {
+            const Agg<DIM> a = agg_of<DIM>(L, I, icx, icxy);
+            const int X0 = 2 * a.c[0] - 2, Y0 = 2 * a.c[1] - 2;
+            T f[W2][W2];
+#pragma unroll
+            for (int vy = 1; vy < W2 - 1; ++vy)
+#pragma unroll
+                for (int ux = 1; ux < W2 - 1; ++ux) {
+                    if (wdist(ux, vy) > 1) continue;
+                    const int j = win_idx(L, X0 + ux, Y0 + vy);
+                    f[vy][ux] = (z[j] - tz) + tb * po[j];
+                }
+#pragma unroll
+            for (int vy = 2; vy < 4; ++vy)
+#pragma unroll
+                for (int ux = 2; ux < 4; ++ux) {
+                    const int gx = X0 + ux, gy = Y0 + vy;
+                    if (gx >= L.nx || gy >= L.ny) continue;
+                    const int i = gx + L.nx * gy;
+                    const T qv = win_op(L, gx, gy, ux, vy, f, c0, c1);
+                    pn[i] = f[vy][ux];
+                    q[i] = qv;
+                    v += (double)f[vy][ux] * qv;
+                }
+        }
+    } else if constexpr (DIM == 3) {
         const T c0 = (T)L.ih2[0], c1 = (T)L.ih2[1], c2 = (T)L.ih2[2];
         for (int I = I0 + threadIdx.x; I < I1; I += TILE) {
             const Agg<DIM> a = agg_of<DIM>(L, I, icx, icxy);
@@ -451,28 +461,6 @@ __global__ __launch_bounds__(TILE) void k_mg_pq(const KJob *__restrict__ jobs, c
                         q[i] = qv;
                         v += (double)f[w][v2][u] * qv;
                     }
-        }
-    } else
-    for (int I = I0 + threadIdx.x; I < I1; I += TILE) {
-        const Agg<DIM> a = agg_of<DIM>(L, I, icx, icxy);
-#pragma unroll
-        for (int cz = 0; cz < (DIM == 3 ? 2 : 1); ++cz) {
-            T pv[4], qv[4];
-            int iv[4];
-            bool ok[4];
-            for_layer<DIM>(L, a, cz, [&](int c, bool valid, int i, const int *, const int *qc) {
-                qv[c] = apply_op<DIM, T>(L, i, qc, [&](int j, int, int) { return (z[j] - tz) + tb * po[j]; });
-                pv[c] = (z[i] - tz) + tb * po[i];
-                iv[c] = i;
-                ok[c] = valid;
-            });
-#pragma unroll
-            for (int c = 0; c < 4; ++c)
-                if (ok[c]) {
-                    pn[iv[c]] = pv[c];
-                    q[iv[c]] = qv[c];
-                    v += (double)pv[c] * qv[c];
-                }
         }
     }
     double vv[1] = {v};
