@@ -216,8 +216,8 @@ static size_t footprint(const Sizes &z, int precision)
 }
 
 // Rows per tile of a solve.  Default: 1..8 rows per thread, aiming at
-// <= ~384 tiles so that the per-kernel totals of the partial sums stay
-// cheap.  sol_autotune replaces the default for a size class (stencil
+// <= ~384 tiles (<= ~192 below MG_LARGE_CELLS rows) so that the per-kernel
+// totals of the partial sums stay cheap.  sol_autotune replaces the default for a size class (stencil
 // width, floor(log2 n)) by the fastest measured choice; the table is
 // process-wide so a case gets the same tiles alone and in a batch.
 static std::mutex g_tune_mu;
@@ -246,7 +246,12 @@ static int rows_per_tile(int n, int nd)
         auto it = g_tuned_rpt.find(size_class(n, nd));
         if (it != g_tuned_rpt.end()) return it->second;
     }
-    const int m = std::max(1, std::min(8, ceil_div(n, TILE * 384)));
+    // below MG_LARGE_CELLS rows (the sizes that run in batches) ~192 tiles:
+    // fewer, larger workgroups per case gave the 64-cavity batch 256 -> 293 M
+    // cell-updates/s (FP64) and 374 -> 399 M (mixed); 500x300 stepped alone
+    // is 1 % faster with ~384
+    const int per = n < MG_LARGE_CELLS ? 192 : 384;
+    const int m = std::max(1, std::min(8, ceil_div(n, TILE * per)));
     return TILE * m;
 }
 
