@@ -175,3 +175,176 @@ def test_still_melt_without_buoyancy_stays_at_rest():
     lam = case["alloy"]["latent"] / case["alloy"]["cp"]
     H0 = (case["init"]["T"] + lam * case["init"]["gl"]).sum()
     assert (f["T"] + lam * f["gl"]).sum() < H0 and (f["gl"] < 1.0).any()
+
+
+# ---------------------------------------------------------------------------
+# Wiring of the time step (Algorithm 1): which face velocity advects C and T*
+# (u^{n+1} after the projection, eqs. 3.10-3.11), which C sets the liquidus of
+# the phase update (C^{n+1}, eq. 3.13), which g_l scales the solute columns
+# (g_l^n, the A_g of eq. 3.9).  Flux-form upwind conserves for any face field
+# and the rest-state pins have u = 0, so these need pins of their own.
+# ---------------------------------------------------------------------------
+
+def _liquid_melt(dT_amp, seed=3, nx=24, ny=16):
+    al = W.sn10pb_alloy()
+    Tl = al["T_m"] + al["m_sp"] * 10.0
+    return W.make_case(2, nx, ny, 1, nx * 1e-3, ny * 1e-3, 1.0, T0=Tl + 5.0, dT_amp=dT_amp,
+                       bcs=W.west_cooled_bcs(), seed=seed, tol_p=1e-12, tol_t=1e-12)
+
+
+def _solve_with(case, fields, sys, vel):
+    """Solve one transport system of a step, assembled from `fields` (level n)
+    with the face field `vel` as the advecting velocity, by a dense solve."""
+    o = oracle.Oracle(case, fields=fields)
+    A, b, _, _ = o.assemble(sys, vel=vel)
+    return np.linalg.solve(A.toarray(), b)
+
+
+def test_solute_advected_by_projected_velocity_stays_uniform():
+    """All-liquid melt (T0 = T_l + 5 K, +-2 K perturbation) with uniform C:
+    thermal buoyancy drives a flow, and C must stay exactly uniform, because
+    the divergence-free u^{n+1} carries the uniform field without sources.
+    Planted mistake: the same step's solute system advected by u* (not yet
+    projected) makes C drift by far more than rounding."""
+    case = _liquid_melt(2.0)
+    o = oracle.Oracle(case)
+    o.step(2)
+    drift_planted = 0.0
+    for _ in range(5):
+        fn = o.fields()
+        o.step(1, keep_intermediate=True)
+        f = o.fields()
+        assert np.ptp(f["C"]) == 0.0 and np.all(f["gl"] == 1.0)
+        assert np.abs(f["u"]).max() > 1e-6          # the melt does move
+        ustar = (o.intermediate["u"], o.intermediate["v"], np.zeros(1))
+        drift_planted = max(drift_planted, np.ptp(_solve_with(case, fn, oracle.SYS_C, ustar)))
+    assert drift_planted > 1e-9 * 10.0, drift_planted
+
+
+def test_temperature_advected_by_projected_velocity_stays_uniform():
+    """Uniform T, adiabatic walls, composition perturbed by +-0.5 wt%:
+    solutal buoyancy drives the flow, and T* (hence T, all liquid) must stay
+    exactly uniform under the divergence-free u^{n+1}.  Planted mistake: the
+    energy system advected by u* drifts."""
+    case = _liquid_melt(0.0)
+    case["bcs"] = [W.face_bc() for _ in range(6)]
+    rng = np.random.default_rng(5)
+    case["init"]["C"] = 10.0 + rng.uniform(-0.5, 0.5, case["init"]["C"].size)
+    case["init"]["Cl"] = case["init"]["C"].copy()
+    o = oracle.Oracle(case)
+    drift_planted = 0.0
+    for _ in range(5):
+        fn = o.fields()
+        o.step(1, keep_intermediate=True)
+        f = o.fields()
+        assert np.ptp(f["T"]) == 0.0 and np.ptp(o.intermediate["Tstar"]) == 0.0
+        assert np.abs(f["u"]).max() > 1e-5
+        ustar = (o.intermediate["u"], o.intermediate["v"], np.zeros(1))
+        drift_planted = max(drift_planted, np.ptp(_solve_with(case, fn, oracle.SYS_T, ustar)))
+    assert drift_planted > 1e-9 * case["T0"], drift_planted
+
+
+def _mushy_state(case, seed=7):
+    """A flowing, partly solid state: random face velocities, g_l in
+    [0.3, 0.95], C around C0, and T on the liquidus of the liquid
+    concentration (eqs. 2.19-2.20), so every cell is mushy."""
+    rng = np.random.default_rng(seed)
+    al = case["alloy"]
+    f = {k: np.array(v, copy=True) for k, v in case["init"].items()}
+    for k in ("u", "v"):
+        f[k] = rng.uniform(-2e-3, 2e-3, f[k].size)
+    n = f["T"].size
+    f["gl"] = rng.uniform(0.3, 0.95, n)
+    f["C"] = 10.0 + rng.uniform(-1.0, 1.0, n)
+    f["Cl"] = f["C"] / (al["k_p"] + (1.0 - al["k_p"]) * f["gl"])
+    f["Cs"] = al["k_p"] * f["Cl"]
+    f["T"] = al["T_m"] + al["m_sp"] * f["Cl"] - rng.uniform(0.0, 0.5, n)
+    return f
+
+
+def test_mushy_cells_sit_on_liquidus_of_new_composition():
+    """After a step through a flowing mush, every cell left mushy satisfies
+    T^{n+1} = T_m + m_sp C_l^{n+1} (eq. 2.20) with C_l^{n+1} from C^{n+1} and
+    g_l^{n+1} (eq. 3.17): the liquidus of the phase update is T_l(C^{n+1})
+    (eq. 3.13).  Planted mistake: the update with T_l(C^n) leaves the cells
+    off that line by the composition change of the step."""
+    case = W.cavity_2d(20, 12, lx=0.02, ly=0.012, tol=1e-13)
+    al = case["alloy"]
+    fn = _mushy_state(case)
+    o = oracle.Oracle(case, fields=fn)
+    o.step(1, keep_intermediate=True)
+    f = o.fields()
+    mush = (f["gl"] > 0.0) & (f["gl"] < 1.0)
+    assert mush.sum() > 0.9 * mush.size
+    off = np.abs(f["T"] - (al["T_m"] + al["m_sp"] * f["Cl"]))[mush]
+    assert off.max() <= 1e-11 * al["T_m"], off.max()
+    assert np.abs(f["C"] - fn["C"]).max() > 1e-3           # composition did move
+    T, g, _, _, _ = o.phase(o.intermediate["Tstar"], fn["gl"], fn["C"])
+    Cl = f["C"] / (1.0 + (1.0 - g) * (al["k_p"] - 1.0))
+    m2 = (g > 0.0) & (g < 1.0)
+    assert np.abs(T - (al["T_m"] + al["m_sp"] * Cl))[m2].max() > 1e-4
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_step_rebuilt_from_forward_matrices(dim):
+    """One whole step of the oracle against the same step rebuilt from the
+    independent forward-method matrices (residual probing, Section 4) and
+    dense direct solves, in the order of Algorithm 1: u* from the level-n
+    fields; phi from u* (eq. 3.4, least squares, mean-free); u^{n+1} by the
+    projection (eq. 3.5); C^{n+1} with u^{n+1} and g_l^n (eq. 3.10); T* with
+    u^{n+1} (eq. 3.11); phase update with T*, g_l^n and C^{n+1}
+    (eqs. 3.12-3.18)."""
+    from oracle import forward
+    if dim == 2:
+        case = W.cavity_2d(9, 7, lx=0.009, ly=0.007, tol=1e-14)
+    else:
+        case = W.box_3d(6, 5, 4, lx=0.006, ly=0.005, lz=0.004, tol=1e-14)
+    case["numerics"]["tol_p"] = 1e-14
+    fn = _mushy_state(case) if dim == 2 else dict(case["init"])
+    if dim == 3:
+        rng = np.random.default_rng(8)
+        fn = {k: np.array(v, copy=True) for k, v in fn.items()}
+        for k in ("u", "v", "w"):
+            fn[k] = rng.uniform(-2e-3, 2e-3, fn[k].size)
+        fn["gl"] = rng.uniform(0.3, 1.0, fn["gl"].size)
+        fn["T"] = fn["T"] - rng.uniform(0.0, 3.0, fn["T"].size)
+    al, nm = case["alloy"], case["numerics"]
+    g = case["grid"]
+    n = (g["nx"], g["ny"], g["nz"] if dim == 3 else 1)
+    h = (g["lx"] / n[0], g["ly"] / n[1], (g["lz"] / n[2]) if dim == 3 else 1.0)
+    fw = dict(fn)
+    if dim == 2:
+        fw["w"] = np.zeros(0)
+    ustar = []
+    for d in range(dim):
+        A, b = forward.forward_assemble(case, fw, d)
+        ustar.append(np.linalg.solve(A.toarray(), b))
+    A, b = forward.forward_assemble(case, fw, oracle.SYS_P, vel=tuple(ustar) + ((np.zeros(0),) if dim == 2 else ()))
+    phi = np.linalg.lstsq(A.toarray(), b, rcond=None)[0]
+    phi = phi - phi.mean()
+    P = phi.reshape(n[2], n[1], n[0])
+    unew = []
+    for d in range(dim):
+        ax = 2 - d
+        grad = np.diff(P, axis=ax) / h[d]
+        unew.append(ustar[d] - nm["dt"] / al["rho"] * grad.ravel())
+    vel = tuple(unew) + ((np.zeros(0),) if dim == 2 else ())
+    A, b = forward.forward_assemble(case, fw, oracle.SYS_C, vel=vel)
+    Cnew = np.linalg.solve(A.toarray(), b)
+    A, b = forward.forward_assemble(case, fw, oracle.SYS_T, vel=vel, t_new=nm["dt"])
+    Tstar = np.linalg.solve(A.toarray(), b)
+    o = oracle.Oracle(case, fields=fn)
+    T, gl, Cl, Cs, _ = o.phase(Tstar, fn["gl"], Cnew)
+    o.step(1, keep_intermediate=True)
+    f = o.fields()
+    def r(a, b):
+        return np.linalg.norm(a - b) / np.linalg.norm(b)
+    for d, k in enumerate("uvw"[:dim]):
+        assert r(o.intermediate[k], ustar[d]) < 1e-10, k
+        assert r(f[k], unew[d]) < 1e-10, k
+    assert r(o.intermediate["phi"], phi) < 1e-10
+    assert r(f["p"], fn["p"] + phi) < 1e-10 or np.linalg.norm(f["p"] - fn["p"] - phi) < 1e-10
+    assert r(f["C"], Cnew) < 1e-12
+    assert r(o.intermediate["Tstar"], Tstar) < 1e-12
+    assert r(f["T"], T) < 1e-12 and np.abs(f["gl"] - gl).max() < 1e-10
+    assert r(f["Cl"], Cl) < 1e-12 and r(f["Cs"], Cs) < 1e-12
