@@ -142,50 +142,96 @@ typedef struct {
                                     again with every check in order (cumulative)   */
 } sol_step_stats;
 
-/* Create a case: validates every argument (e.g. nx < 2, dt <= 0,
-   k_p outside (0,1), m_sp >= 0, D_l != 0 -> SOL_EINVAL), allocates device
-   memory, builds the constant-coefficient systems (transient, diffusion,
-   wall terms, pressure Laplacian) on the device, and sets the initial state
-   u = v = w = p = 0, C = C_ref, g_l = 1, C_l = C_ref, C_s = 0,
-   T = T_ref.  ctx may be NULL.  *out receives the handle. */
+/* Create a case.  Defined by the problem statement of Algorithm 1 (given the
+   initial fields and the boundary conditions, advance the scheme), the alloy
+   properties of Table 1 and the wall conditions of Section 5 (convective
+   cooling q = h (T - T_ext), adiabatic, rigid no-slip and free-slip walls,
+   prescribed wall temperature T0 - b t), on the staggered grid of Section 3
+   (spatial discretization).
+   Validates every argument (e.g. nx < 2, dt <= 0, k_p outside (0,1),
+   m_sp >= 0, D_l < 0 -> SOL_EINVAL), allocates device memory, builds the
+   constant-coefficient systems of the term-wise split of Section 4
+   (transient, diffusion, wall terms, pressure Laplacian) on the device, and
+   sets the initial state u = v = w = p = 0, C = C_ref, g_l = 1,
+   C_l = C_ref, C_s = 0, T = T_ref.  ctx may be NULL (hipMalloc and the
+   default stream).  *out receives the handle; on an error *out is set to
+   NULL and nothing stays allocated. */
 int sol_create(const sol_grid *grid, const sol_alloy *alloy, const sol_bcs *bcs,
                const sol_numerics *num, const sol_device_ctx *ctx, sol_handle **out);
 void sol_destroy(sol_handle *h);
 
-/* Copy host fields (SOL_F_U..SOL_F_CS bits only) into the handle.  host_src is
-   an array of SOL_NFIELDS pointers indexed by bit position; entries for unset
-   bits are ignored.  Non-finite values -> SOL_ENONFINITE (nothing written).
-   Synchronous with respect to the caller's buffers. */
+/* Write the level-n state of the scheme: the velocity and pressure of the
+   momentum step (eqs. 3.3-3.5), the temperature and liquid fraction of the
+   split energy step (eqs. 3.11-3.12), the mixture concentration of the
+   solute step (eq. 3.10) and the phase concentrations of eqs. 3.17-3.18
+   (initial state or restart).  Copies host fields (SOL_F_U..SOL_F_CS bits
+   only) into the handle; host_src is an array of SOL_NFIELDS pointers
+   indexed by bit position (layouts above), entries for unset bits are
+   ignored; the caller keeps ownership.  Non-finite values ->
+   SOL_ENONFINITE, a NULL pointer for a set bit or a bit outside
+   SOL_F_U..SOL_F_CS -> SOL_EINVAL (nothing written in either case).
+   Synchronous with respect to the caller's buffers.  Resets the time
+   extrapolation of the initial guesses. */
 int sol_write_fields(sol_handle *h, uint32_t mask, const double *const *host_src);
 
-/* Copy fields to host buffers (synchronous).  Intermediates (SOL_F_USTAR ..
-   SOL_F_TSTAR) are those of the last completed step or sol_assemble call. */
+/* Read the fields the scheme produces: u, v, w, p (eqs. 3.3-3.5), T and g_l
+   (eqs. 3.11-3.16), C (eq. 3.10), C_l and C_s (eqs. 3.17-3.18), and the
+   intermediates u* (eq. 3.3), the pressure correction phi = p^{n+1} - p^n
+   (eq. 3.4, zero mean) and T* (eq. 3.11).  Copies to caller-owned host
+   buffers sized from the grid (layouts above), synchronously.  Intermediates
+   (SOL_F_USTAR .. SOL_F_TSTAR) are those of the last completed step or
+   sol_assemble call.  A NULL pointer for a set bit -> SOL_EINVAL. */
 int sol_read_fields(sol_handle *h, uint32_t mask, double *const *host_dst);
 
-/* Number of rows and structural nonzeros of a system (5- / 7-point pattern,
-   in-domain neighbours only). */
+/* Number of rows and structural nonzeros of a system: the 5- / 7-point
+   pattern of the staggered-grid stencils (Section 4, the matrix picture of
+   eq. 4.2), in-domain neighbours only.  Unknown system -> SOL_EINVAL. */
 int sol_system_size(const sol_handle *h, int32_t system, int32_t *rows, int32_t *nnz);
 
 /* Assemble, for the current state, the systems in system_mask (bit s =
-   SOL_SYS_s) without solving.  The momentum systems use the level-n fields;
-   the pressure system takes the current velocity as u*; the solute and
-   energy systems take the current velocity as the advecting field and the
-   next time level for prescribed wall temperatures. */
+   SOL_SYS_s) without solving: Section 4's matrix assembly (eqs. 4.1-4.4:
+   upwind convection rows, diffusion rows, transient diagonal) with the
+   term-wise split (constant terms built once at sol_create, convection,
+   Carman-Kozeny drag of eq. 2.8, Boussinesq force of eq. 2.9 and the
+   right-hand sides per call), for the momentum predictor (eq. 3.3), the
+   pressure correction (eq. 3.4), the solute system with its A_g scaling
+   (eqs. 3.9-3.10) and the energy system (eq. 3.11).  The momentum systems
+   use the level-n fields; the pressure system takes the current velocity
+   as u*; the solute and energy systems take the current velocity as the
+   advecting field and the next time level for prescribed wall
+   temperatures.  Bits beyond SOL_SYS_T -> SOL_EINVAL; SOL_EBUSY while the
+   handle belongs to a batch. */
 int sol_assemble(sol_handle *h, uint32_t system_mask);
 
-/* Export the last assembled system as CSR (int32 row_ptr[rows+1],
-   col_idx[nnz] ascending per row, val[nnz], rhs[rows]; host buffers). */
+/* Export the last assembled system (sol_assemble) as CSR: the matrix and
+   right-hand side of Section 4 (eqs. 4.1-4.4) in the row order of eq. 4.2.
+   Caller-owned host buffers sized from sol_system_size: int32
+   row_ptr[rows+1], col_idx[nnz] ascending per row, val[nnz], rhs[rows].
+   The values are those of the system's last assembly, by sol_assemble or
+   by the last step (the solute and energy systems of a step are assembled
+   with u^{n+1}).  The CSR pattern is built on the device at the first
+   export of a system (device memory held by the handle).  Unknown system
+   or a NULL buffer -> SOL_EINVAL. */
 int sol_read_matrix(sol_handle *h, int32_t system, int32_t *row_ptr, int32_t *col_idx,
                     double *val, double *rhs);
 
-/* Advance nsteps time steps (Algorithm 1).  stats may be NULL.  On
-   SOL_ENOCONV / SOL_ENONFINITE the handle stays at the last completed step. */
+/* Advance nsteps time steps of Algorithm 1: momentum predictor (eq. 3.3),
+   pressure correction (eq. 3.4), projection (eq. 3.5), solute (eq. 3.10),
+   liquidus (eq. 3.13), energy (eqs. 3.11-3.12), phase update (eqs.
+   3.14-3.16 and the eutectic rule after eq. 3.16), C_l and C_s (eqs.
+   3.17-3.18).  stats may be NULL.  On SOL_ENOCONV / SOL_ENONFINITE the
+   handle stays at the last completed step.  nsteps < 0 -> SOL_EINVAL;
+   SOL_EBUSY while the handle belongs to a batch. */
 int sol_step(sol_handle *h, int32_t nsteps, sol_step_stats *stats);
 
-/* Device bytes a case of this size would allocate (admission control). */
+/* Device bytes sol_create would allocate for a case of this grid and
+   precision (the state of Algorithm 1 on the grid of Section 3, the
+   systems of Section 4 and the solver work space): admission control of
+   served requests.  Invalid grid -> SOL_EINVAL. */
 int sol_footprint_bytes(const sol_grid *grid, const sol_numerics *num, size_t *out);
 
-/* Batches: n handles advanced together, every kernel of the step launched
+/* Batches: n handles advanced together by Algorithm 1 (each case its own
+   scheme, as sol_step), every kernel of the step launched
    once for all cases (uneven sizes allowed).  The handles keep their state
    and may not be stepped alone while the batch lives (SOL_EBUSY).  All
    handles must share one stream.  nsteps_per_case[i] steps for case i (a

@@ -120,3 +120,26 @@ def test_set_option_rejects_null_handle(sol):
     L = sol.load()
     for opt, val in ((B.OPT_GRAPH, 1), (B.OPT_PRECOND, 0), (B.OPT_TPRECOND, 2)):
         assert L.sol_set_option(None, opt, val) == B.SOL_EINVAL
+
+
+# the calls of the problem statement: each declaration's comment names the
+# passage of the paper that defines the operation
+PAPER_CALLS = ("sol_create", "sol_write_fields", "sol_read_fields", "sol_system_size", "sol_assemble",
+               "sol_read_matrix", "sol_step", "sol_footprint_bytes", "sol_batch_create", "sol_batch_step")
+
+
+def _comment_before(txt, name):
+    """The comment block closest above the declaration of `name` (a comment
+    may head a group of declarations, as for the two batch calls)."""
+    i = re.search(r"\b(int|void|const char \*)\s+" + name + r"\s*\(", txt).start()
+    j = txt.rfind("*/", 0, i)
+    k = txt.rfind("/*", 0, j)
+    assert 0 <= k < j, name
+    return txt[k:j]
+
+
+@pytest.mark.parametrize("name", PAPER_CALLS)
+def test_header_cites_defining_passage(name):
+    txt = open(HEADER).read()
+    c = _comment_before(txt, name)
+    assert re.search(r"(eqs?\.\s*\d\.\d+|Algorithm 1|Section \d|Table 1)", c), (name, c)
