@@ -2,7 +2,9 @@
 
 Requests (cases with an arrival time and a step count) are admitted in
 arrival order while their device footprint (sol_footprint_bytes) fits the
-memory budget and the batch has a free slot.  Admitted cases stay on the
+memory budget and the batch has a free slot.  A request whose footprint
+exceeds the whole budget is refused on its own (listed under "rejected",
+with the reason) and the rest of the stream is served.  Admitted cases stay on the
 device; every tick advances all admitted cases together in one batched
 launch sequence per step (sol_batch_step), until the next event: a case
 finishing its steps, or an arrival that a free slot could take (judged
@@ -36,6 +38,7 @@ class Request:
     finished: float = -1.0
     result: dict | None = None
     steps_done: int = 0
+    error: str | None = None          # set when the request is refused
     handle: Case | None = field(default=None, repr=False)
 
     @property
@@ -45,8 +48,11 @@ class Request:
 
 class Server:
     def __init__(self, device=None, hbm_budget_bytes: int = 270 * 2 ** 30, max_active: int = 64,
-                 graph: bool = False, keep_results: bool = True, multi_step: bool = True):
+                 graph: bool = False, keep_results: bool = True, multi_step: bool = True,
+                 backfill: bool = True, max_wait_s: float = 2.0):
         self.device = device
+        self.backfill = backfill
+        self.max_wait_s = float(max_wait_s)
         self.budget = int(hbm_budget_bytes)
         self.max_active = int(max_active)
         self.graph = graph
@@ -57,13 +63,19 @@ class Server:
         self.log = []                 # (time, event, request id)
 
     def run(self, requests, clock=time.perf_counter, sleep=time.sleep):
-        pending = deque(sorted(requests, key=lambda r: r.arrival))
-        for i, r in enumerate(pending):
+        pending = deque()
+        rejected = []
+        for r in sorted(requests, key=lambda r: r.arrival):
             g = r.case["grid"]
             r.cells = g["nx"] * g["ny"] * (g["nz"] if g["dim"] == 3 else 1)
             r.footprint = sol_footprint_bytes(r.case)
             if r.footprint > self.budget:
-                raise ValueError(f"request {r.rid} needs {r.footprint} B, over the budget")
+                # can never be admitted: refused on its own, the stream goes on
+                r.error = f"needs {r.footprint} B of device memory, over the budget of {self.budget} B"
+                rejected.append(r)
+                self.log.append((r.arrival, "reject", r.rid))
+            else:
+                pending.append(r)
         waiting, active, done = deque(), [], []
         used = 0
         batch = None
@@ -75,9 +87,21 @@ class Server:
             now = clock() - t0
             while pending and pending[0].arrival <= now:
                 waiting.append(pending.popleft())
-            # admission in arrival order, by footprint and free slots
-            while waiting and len(active) < self.max_active and used + waiting[0].footprint <= self.budget:
-                r = waiting.popleft()
+            # admission in arrival order, by footprint and free slots; when
+            # the oldest waiting request does not fit the memory left, later
+            # ones that do fit may go ahead of it (backfill) until it has
+            # waited max_wait_s, after which admission holds for it
+            while waiting and len(active) < self.max_active:
+                head = waiting[0]
+                if used + head.footprint <= self.budget:
+                    r = waiting.popleft()
+                elif self.backfill and now - head.arrival < self.max_wait_s:
+                    r = next((x for x in waiting if used + x.footprint <= self.budget), None)
+                    if r is None:
+                        break
+                    waiting.remove(r)
+                else:
+                    break
                 r.handle = Case(r.case, device=self.device)
                 if self.graph:
                     r.handle.set_graph(True)
@@ -130,11 +154,15 @@ class Server:
         if batch is not None:
             batch.close()
         wall = clock() - t0
+        if not done:
+            return dict(requests=0, rejected=rejected, wall_s=wall, cell_updates_per_s=0.0,
+                        p50_latency_s=float("nan"), p99_latency_s=float("nan"), mean_latency_s=float("nan"),
+                        offered_cell_updates_per_s=0.0, done=done)
         lat = np.array([r.latency for r in done])
         span = max(r.arrival for r in done) - min(r.arrival for r in done) if len(done) > 1 else 0.0
         offered = sum(r.cells * r.steps for r in done) / span if span > 0 else float("inf")
         return dict(
-            requests=len(done), wall_s=wall,
+            requests=len(done), rejected=rejected, wall_s=wall,
             cell_updates_per_s=cell_steps / wall if wall > 0 else 0.0,
             p50_latency_s=float(np.percentile(lat, 50)), p99_latency_s=float(np.percentile(lat, 99)),
             mean_latency_s=float(lat.mean()), offered_cell_updates_per_s=offered,

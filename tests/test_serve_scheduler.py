@@ -112,3 +112,42 @@ def test_free_slot_arrival_is_not_held_back(monkeypatch):
     srv, out, log = _run(monkeypatch, [a, b], True, step_s=0.002, max_active=4)
     rb = [r for r in out["done"] if r.rid == 1][0]
     assert rb.admitted - rb.arrival <= 2 * 0.002 + 1e-9
+
+
+def test_over_budget_request_is_refused_alone(monkeypatch):
+    """A request larger than the whole memory budget is refused with a reason;
+    every other request of the stream is still served."""
+    reqs = _requests(8)
+    reqs[3].case["fp"] = 10_000
+    srv, out, _ = _run(monkeypatch, reqs, True, hbm_budget_bytes=700, max_active=4)
+    assert out["requests"] == 7
+    assert [r.rid for r in out["rejected"]] == [3]
+    assert "over the budget" in out["rejected"][0].error
+    assert ("reject" in [ev for _, ev, _ in srv.log])
+
+
+def test_backfill_lets_small_request_pass_a_waiting_large_one(monkeypatch):
+    """While a large request waits for memory, a later small one that fits is
+    admitted ahead of it; without backfill it waits behind the large one."""
+    def reqs():
+        mk = lambda rid, fp, steps, t: S.Request(case={"grid": {"dim": 2, "nx": 4, "ny": 4}, "rid": rid, "fp": fp},
+                                                   steps=steps, arrival=t, rid=rid)
+        return [mk(0, 600, 200, 0.0), mk(1, 600, 5, 0.001), mk(2, 100, 5, 0.002)]
+    _, out, _ = _run(monkeypatch, reqs(), True, hbm_budget_bytes=800, max_active=4)
+    adm = {r.rid: r.admitted for r in out["done"]}
+    assert adm[2] < adm[1]
+    _, out, _ = _run(monkeypatch, reqs(), True, hbm_budget_bytes=800, max_active=4, backfill=False)
+    adm = {r.rid: r.admitted for r in out["done"]}
+    assert adm[2] >= adm[1]
+
+
+def test_backfill_stops_once_the_head_waited_too_long(monkeypatch):
+    """A stream of small requests cannot hold a large one back forever: once
+    it has waited max_wait_s no later request goes ahead of it."""
+    mk = lambda rid, fp, steps, t: S.Request(case={"grid": {"dim": 2, "nx": 4, "ny": 4}, "rid": rid, "fp": fp},
+                                               steps=steps, arrival=t, rid=rid)
+    reqs = [mk(0, 500, 30, 0.0), mk(1, 600, 5, 0.001)] + [mk(2 + i, 100, 30, 0.002 + 0.01 * i) for i in range(40)]
+    _, out, _ = _run(monkeypatch, reqs, True, hbm_budget_bytes=800, max_active=8, max_wait_s=0.05)
+    r1 = [r for r in out["done"] if r.rid == 1][0]
+    late = [r for r in out["done"] if r.rid >= 2 and r.arrival > r1.arrival + 0.05]
+    assert late and all(r.admitted >= r1.admitted for r in late)
