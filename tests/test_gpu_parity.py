@@ -189,34 +189,38 @@ def test_wide_rows_match_oracle(sol, dev, precond):
 
 def test_cavity_50x30_200_steps(sol, dev):
     """The 50x30 cavity (cooled west wall, Sn-10%Pb-type constants), 200 steps:
-    GPU vs oracle with the pressure solved to 1e-13 and the transport systems
-    to 1e-14 (gate 3e-9), and the spread at the workload tolerance 1e-10
-    reported.  A T* difference inside the solver tolerance reaches u and p
-    amplified ~5e3-fold by the buoyancy (T - T_ref ~ 0.1 K) and accumulates
-    over the steps; the two sides start their solves from different initial
+    GPU vs oracle per field within 1e-9, and the spread at the workload
+    tolerance 1e-10 reported.
+
+    A T* difference inside the solver tolerance reaches u and p amplified
+    ~5e3-fold by the buoyancy (T - T_ref ~ 0.1 K) and accumulates over the
+    steps, and the two sides start their solves from different initial
     guesses (the oracle from the level-n field, the library by extrapolation
-    in time), so they end at different points of the tolerance band: the
-    gated run pins the systems tighter than the gate (measured 7e-10 with
-    linear guesses, 1.2e-9 in u once quadratic guesses start the solves
-    nearer the solution and they stop nearer the band edge; T and C stay
-    at ~4e-14), and at 1e-10 the spread (measured 1.5e-5 in p) is bounded
-    by 1e-4."""
-    case = W.cavity_2d(50, 30, tol=1e-13, seed=0)
-    case["numerics"]["tol_t"] = 1e-14
-    print("[gpu] 50x30 cavity, 200 steps, tol_p 1e-13, tol_t 1e-14", flush=True)
+    in time), so each ends at its own point of the tolerance band.  The gate
+    therefore needs solves tight enough that the band is far below it: the
+    oracle alone moves by 1.3e-9 in u between (pressure, transport)
+    tolerances (1e-13, 1e-14) and (1e-14, 1e-15), and by 2.8e-12 between
+    (1e-14, 1e-15) and (5e-15, 1e-15), so both sides solve at (1e-14, 1e-15),
+    which this small grid's pressure system reaches above its FP64 floor.
+    At 1e-10 the spread (measured 1.5e-5 in p) is reported and bounded by
+    1e-4."""
+    case = W.cavity_2d(50, 30, tol=1e-14, seed=0)
+    case["numerics"]["tol_t"] = 1e-15
+    print("[gpu] 50x30 cavity, 200 steps, tol_p 1e-14, tol_t 1e-15", flush=True)
     g = sol.Case(case, device=dev)
-    o = oracle.Oracle(case)
+    o = oracle.Oracle(case, threads=8)
     st = g.step(200)
     o.step(200)
     errs = field_errors(g.read_fields(), o.fields())
-    print("rel L2 (tol 1e-13 / 1e-14):", {k: f"{v:.1e}" for k, v in errs.items()})
-    assert max(errs.values()) < 3e-9, errs
+    print("rel L2 (tol 1e-14 / 1e-15):", {k: f"{v:.1e}" for k, v in errs.items()}, "redone", st["redone"])
+    for k, e in errs.items():
+        assert e < 1e-9, (k, errs)
     assert max(errs[k] for k in ("T", "C")) < 1e-12, errs
     assert (g.read_fields()["gl"] < 1).any()        # solidification has started
     g.close()
     case = W.cavity_2d(50, 30, tol=1e-10, seed=0)
     g = sol.Case(case, device=dev)
-    o = oracle.Oracle(case)
+    o = oracle.Oracle(case, threads=8)
     g.step(200)
     o.step(200)
     errs = field_errors(g.read_fields(), o.fields())
@@ -394,12 +398,15 @@ def _mixed(case):
 def test_mixed_precision_fields_within_1e8(sol, dev, name, shape):
     """FP32 Krylov inside FP64 iterative refinement.  With every system solved
     to a true residual that pins the fields below the gate (pressure 1e-13,
-    transport 1e-14, both sides) the per-field relative L2 error against the
-    FP64 oracle stays within 1e-8 after 20 steps.  At the workload tolerance
-    1e-10 any two solvers that start or iterate differently end at different
-    points of the tolerance band, and the buoyancy (T - T_ref ~ 0.1 K)
-    amplifies a T* difference of that size ~5e3-fold into u and p; the mixed
-    path against the FP64 path there is reported and bounded by 1e-4."""
+    transport 1e-14, both sides) each field's relative L2 error against the
+    FP64 oracle stays within 1e-8 after 20 steps, every velocity component
+    on its own (the weakest, the y-velocity of the 3D box cooled through one
+    x-face, is a secondary flow ~100x weaker than u and w).  At the workload
+    tolerance 1e-10 any two solvers that start or iterate differently end at
+    different points of the tolerance band, and the buoyancy
+    (T - T_ref ~ 0.1 K) amplifies a T* difference of that size ~5e3-fold into
+    u and p; the mixed path against the FP64 path there is reported per
+    field and bounded by 1e-4."""
     def mk(tol, tol_t=None):
         if len(shape) == 2:
             c = W.cavity_2d(*shape, tol=tol, seed=21)
@@ -415,14 +422,11 @@ def test_mixed_precision_fields_within_1e8(sol, dev, name, shape):
     o.step(20)
     got, ref = g.read_fields(), o.fields()
     errs = field_errors(got, ref)
-    vel = rel(np.concatenate([got[k] for k in "uvw"]), np.concatenate([ref[k] for k in "uvw"]))
     mags = {k: float(np.linalg.norm(ref[k])) for k in "uvw" if ref[k].size}
-    print("mixed vs oracle at 1e-13 / 1e-14:", {k: f"{v:.1e}" for k, v in errs.items()}, f"velocity {vel:.1e}",
+    print("mixed vs oracle at 1e-13 / 1e-14, per field:", {k: f"{v:.1e}" for k, v in errs.items()},
           "|u|,|v|,|w|:", {k: f"{v:.1e}" for k, v in mags.items()}, "iters", st["iters"])
-    # velocity gated as one vector: a weak secondary component (the y-velocity
-    # of the 3D box cooled through one x-face) carries a larger relative error
-    assert vel < 1e-8, vel
-    assert max(v for k, v in errs.items() if k not in "uvw") < 1e-8, errs
+    for k, e in errs.items():
+        assert e < 1e-8, (k, errs)
     for s in range(6):
         assert st["rel_resid"][s] <= (1e-13 if s == 3 else 1e-14) * (1 + 1e-6)
     g.close()
@@ -430,12 +434,10 @@ def test_mixed_precision_fields_within_1e8(sol, dev, name, shape):
     gd = sol.Case(mk(1e-10), device=dev)
     gm.step(20)
     gd.step(20)
-    fm, fd = gm.read_fields(), gd.read_fields()
-    errs = field_errors(fm, fd)
-    vel = rel(np.concatenate([fm[k] for k in "uvw"]), np.concatenate([fd[k] for k in "uvw"]))
-    print("mixed vs FP64 path at 1e-10:", {k: f"{v:.1e}" for k, v in errs.items()}, f"velocity {vel:.1e}")
-    assert vel < 1e-4, vel
-    assert max(v for k, v in errs.items() if k not in "uvw") < 1e-4, errs
+    errs = field_errors(gm.read_fields(), gd.read_fields())
+    print("mixed vs FP64 path at 1e-10, per field:", {k: f"{v:.1e}" for k, v in errs.items()})
+    for k, e in errs.items():
+        assert e < 1e-4, (k, errs)
     gm.close()
     gd.close()
 
