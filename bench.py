@@ -21,10 +21,13 @@ Also printed in the same JSON line:
                 workload on all host cores and on one core, the 50x30 cavity
                 in full, and the per-field error of the GPU's FP64 and mixed
                 runs of those first steps against the oracle's fields;
-  variants      the same box in mixed precision (500 steps), the 500x300
+  variants      the same box in mixed precision (500 steps), the box in FP64
+                and mixed at the tight tolerances that hold the fields within
+                1e-8 of the oracle (errors in cpu_baseline), the 500x300
                 cavity (1000 steps, FP64 and mixed), the 50x30 cavity (200
                 steps, FP64 and mixed), 64 uneven cavities in one batch (300
-                steps, mixed and FP64) and the served request stream (Poisson
+                steps, mixed and FP64, workload and tight tolerances) and the
+                served request stream (Poisson
                 arrivals at 20/s of 2D and 3D cases at their stated sizes, 200
                 steps each, continuous batching, p50/p99 latency, offered vs
                 served load).
@@ -46,6 +49,12 @@ sys.path.insert(0, ROOT)
 
 METRIC = "cell-updates/s per full time step (1 GPU), mixed vs FP64; p50/p99 case latency"
 HBM_PEAK_GBS = 8000.0
+# solver tolerances (pressure, transport) at which GPU and oracle fields agree
+# to 1e-8 per field after the first steps: the workload's 1e-10 lets each
+# solver stop anywhere in its band, and the buoyancy amplifies a T* difference
+# of that size ~5e3-fold into the velocity
+TIGHT = (1e-12, 1e-13)
+TIGHT_BATCH = (3e-13, 1e-13)
 KCLASSES = ("cg", "bicg_a", "bicg_b", "asm_mom", "asm_trn", "phase", "mg_pq", "mg_down0", "mg_up0")
 FIELDS = ("u", "v", "w", "p", "T", "C", "gl", "Cl", "Cs")
 
@@ -126,7 +135,7 @@ def _describe(key, case):
 
 
 def run_single(sol, W, key, precision, steps, warmup, dev, *, precond="mg", tprecond=None, graph=False,
-               timing=False, keep_fields=None):
+               timing=False, keep_fields=None, tols=None):
     """K steps of a named workload from its initial state (after W warm-up
     steps and a rewrite of the initial fields).  With timing, a second pass
     over the same K steps with every solver launch timed by HIP events gives
@@ -136,6 +145,8 @@ def run_single(sol, W, key, precision, steps, warmup, dev, *, precond="mg", tpre
     case = W.workload_case(key)
     if precision == "mixed":
         case["numerics"]["precision"] = W.PRECISION_MIXED
+    if tols:
+        case["numerics"]["tol_p"], case["numerics"]["tol_t"] = tols
     ncell = _cells(case)
     h = sol.Case(case, device=dev)
     if precond != "mg":
@@ -154,6 +165,7 @@ def run_single(sol, W, key, precision, steps, warmup, dev, *, precond="mg", tpre
     secs = time.perf_counter() - t0
     out = dict(workload=_describe(key, case), cells=ncell, precision=precision, value=ncell * steps / secs,
                ms_per_step=1e3 * secs / steps, steps=steps, warmup=warmup, tol=case["numerics"]["tol_p"],
+               tol_transport=case["numerics"]["tol_t"],
                krylov_iters_per_step={n: round(st["iters_total"][i] / steps, 1) for i, n in enumerate("uvwpCT")},
                steps_redone=st["redone"])
     if precond != "mg":
@@ -191,12 +203,15 @@ def run_single(sol, W, key, precision, steps, warmup, dev, *, precond="mg", tpre
     return out
 
 
-def run_batched(sol, W, precision, steps, warmup, dev, n_cases=64, graph=True, tune=True):
+def run_batched(sol, W, precision, steps, warmup, dev, n_cases=64, graph=True, tune=True, tols=None):
     """64 cavities of uneven size (aspect 0.5-4, 6e3-9.6e4 cells, h and C0
     drawn per case), every kernel launched once for all of them; timed steps
     1..K from the initial state after W warm-up steps."""
     import torch
     cases = W.batch_cases(n_cases, seed=0, precision=W.PRECISION_MIXED if precision == "mixed" else W.PRECISION_FP64)
+    if tols:
+        for c in cases:
+            c["numerics"]["tol_p"], c["numerics"]["tol_t"] = tols
     cells = [_cells(c) for c in cases]
     tuned = {}
     if tune:
@@ -231,6 +246,7 @@ def run_batched(sol, W, precision, steps, warmup, dev, n_cases=64, graph=True, t
     return dict(workload=f"C4: {n_cases} 2D cavities in one batch", precision=precision,
                 value=sum(cells) * steps / secs, ms_per_step=1e3 * secs / steps, steps=steps, warmup=warmup,
                 cases=n_cases, cells=sum(cells), min_cells=min(cells), max_cells=max(cells),
+                tol=cases[0]["numerics"]["tol_p"], tol_transport=cases[0]["numerics"]["tol_t"],
                 graph=graph, tuned_rows_per_tile={str(k): v for k, v in sorted(tuned.items())})
 
 
@@ -270,7 +286,7 @@ def _field_errors(got, ref):
     return out
 
 
-def cpu_baseline(W, key, steps_all, steps_one, gpu_fields=None, c1_gpu_fields=None):
+def cpu_baseline(W, key, steps_all, steps_one, gpu_fields=None, c1_gpu_fields=None, tight=None):
     """The FP64 oracle on the host (never tuned for this): the first
     `steps_all` steps of the workload on all host cores (<= 16 threads) and
     the first `steps_one` on one core; the 50x30 cavity in full (200 steps);
@@ -297,6 +313,17 @@ def cpu_baseline(W, key, steps_all, steps_one, gpu_fields=None, c1_gpu_fields=No
         out["gpu_field_error_vs_oracle"] = {
             "steps": steps_all, "tol": case["numerics"]["tol_p"],
             **{prec: _field_errors(f, ref) for prec, f in gpu_fields.items()}}
+    if tight:
+        tols, fields = tight
+        ct = W.workload_case(key)
+        ct["numerics"]["tol_p"], ct["numerics"]["tol_t"] = tols
+        ot = oracle.Oracle(ct, threads=threads)
+        t0 = time.perf_counter()
+        ot.step(steps_all)
+        dtt = time.perf_counter() - t0
+        out["gpu_field_error_vs_oracle_tight"] = {
+            "steps": steps_all, "tol": tols[0], "tol_transport": tols[1], "oracle_seconds": round(dtt, 1),
+            **{prec: _field_errors(f, ot.fields()) for prec, f in fields.items()}}
     c1 = W.workload_case("C1")
     n1 = _cells(c1)
     for th, tag in ((threads, "all_cores"), (1, "one_core")):
@@ -370,6 +397,7 @@ def main():
     variants = None
     gpu_fields = {args.precision: head["_fields"]} if keep else None
     c1_fields = None
+    tight_fields = {}
     if not args.no_variants:
         variants = {}
         other = "mixed" if args.precision == "fp64" else "fp64"
@@ -393,15 +421,28 @@ def main():
         if args.jacobi_variants:
             variants["C3_fp64_jacobi"] = _public(run_single(sol, W, "C3", "fp64", 20, 1, dev, precond="jacobi"))
             variants["C2_fp64_jacobi"] = _public(run_single(sol, W, "C2", "fp64", 50, 1, dev, precond="jacobi"))
+        # the same box at the tolerances that hold 1e-8 per field (pressure
+        # 1e-12, transport 1e-13): mixed against FP64 at a stated accuracy
+        tight_fields = {}
+        for prec in ("fp64", "mixed"):
+            v = run_single(sol, W, args.workload, prec, steps, args.warmup, dev, tols=TIGHT, keep_fields=keep)
+            if keep:
+                tight_fields[prec] = v["_fields"]
+            variants[f"{args.workload}_{prec}_tight"] = _public(v)
+            print(f"[bench] {v['workload']} {prec} tight: {v['value'] / 1e6:.1f} M", file=sys.stderr, flush=True)
         variants["C4_batched_mixed"] = run_batched(sol, W, "mixed", 300, args.warmup, dev)
         variants["C4_batched_fp64"] = run_batched(sol, W, "fp64", 300, args.warmup, dev, tune=False)
         print(f"[bench] batch: {variants['C4_batched_mixed']['value'] / 1e6:.1f} M mixed", file=sys.stderr,
               flush=True)
+        variants["C4_batched_mixed_tight"] = run_batched(sol, W, "mixed", 300, args.warmup, dev, tols=TIGHT_BATCH)
+        variants["C4_batched_fp64_tight"] = run_batched(sol, W, "fp64", 300, args.warmup, dev, tune=False,
+                                                        tols=TIGHT_BATCH)
         variants["C5_served_mixed"] = run_served(sol, W, dev)
         print(f"[bench] served: {variants['C5_served_mixed']['value'] / 1e6:.1f} M", file=sys.stderr, flush=True)
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(W, args.workload, acc_steps, 1, gpu_fields=gpu_fields, c1_gpu_fields=c1_fields)
+        cpu = cpu_baseline(W, args.workload, acc_steps, 1, gpu_fields=gpu_fields, c1_gpu_fields=c1_fields,
+                           tight=(TIGHT, tight_fields) if not args.no_variants and keep else None)
     case = W.workload_case(args.workload)
     out = dict(
         metric=METRIC, value=head["value"], unit="cell-updates/s", n_gpus=1, steps=steps,
