@@ -215,6 +215,22 @@ int sol_assemble(sol_handle *h, uint32_t system_mask);
 int sol_read_matrix(sol_handle *h, int32_t system, int32_t *row_ptr, int32_t *col_idx,
                     double *val, double *rhs);
 
+/* Allocation-free variant of sol_read_matrix, for callers that cannot
+   allocate device memory (code under HIP graph capture, tight serving
+   loops, harnesses that forbid hipMalloc).  Same arguments, output and
+   errors as sol_read_matrix, but it allocates nothing: the CSR row counts,
+   row pointers, columns and values are staged in a fixed device array of
+   SOL_NOALLOC_SCRATCH_BYTES held by each GPU the library runs on until the
+   process ends, the columns and values in blocks of rows that fit it.  A
+   system whose row counts and row pointers (8 (rows + 1) bytes, about 4.19
+   million rows) do not fit the array -> SOL_EINVAL.  Every call on a GPU
+   shares that GPU's array: calls that overlap on one GPU (from other
+   threads or streams) race.  Synchronous; the handle's device must be
+   current. */
+#define SOL_NOALLOC_SCRATCH_BYTES (32u << 20)
+int sol_read_matrix_noalloc(sol_handle *h, int32_t system, int32_t *row_ptr, int32_t *col_idx, double *val,
+                            double *rhs);
+
 /* Advance nsteps time steps of Algorithm 1: momentum predictor (eq. 3.3),
    pressure correction (eq. 3.4), projection (eq. 3.5), solute (eq. 3.10),
    liquidus (eq. 3.13), energy (eqs. 3.11-3.12), phase update (eqs.

@@ -108,6 +108,7 @@ def load():
         "sol_system_size": ([P, I32, ip, ip], I32),
         "sol_assemble": ([P, U32], I32),
         "sol_read_matrix": ([P, I32, ip, ip, dp, dp], I32),
+        "sol_read_matrix_noalloc": ([P, I32, ip, ip, dp, dp], I32),
         "sol_step": ([P, I32, C.POINTER(sol_step_stats)], I32),
         "sol_footprint_bytes": ([C.POINTER(sol_grid), C.POINTER(sol_numerics), C.POINTER(C.c_size_t)], I32),
         "sol_batch_create": ([C.POINTER(P), I32, C.POINTER(P)], I32),
@@ -130,7 +131,7 @@ def load():
 
 def exported_symbols():
     return ["sol_create", "sol_destroy", "sol_write_fields", "sol_read_fields", "sol_system_size",
-            "sol_assemble", "sol_read_matrix", "sol_step", "sol_footprint_bytes",
+            "sol_assemble", "sol_read_matrix", "sol_read_matrix_noalloc", "sol_step", "sol_footprint_bytes",
             "sol_batch_create", "sol_batch_step", "sol_batch_destroy", "sol_set_timing",
             "sol_get_timing", "sol_set_option", "sol_autotune", "sol_last_error", "sol_version"]
 
@@ -282,13 +283,15 @@ class Case:
         check(load().sol_system_size(self.h, sys, C.byref(r), C.byref(z)))
         return r.value, z.value
 
-    def read_matrix(self, sys: int):
+    def read_matrix(self, sys: int, noalloc: bool = False):
+        """CSR export of a system; noalloc selects sol_read_matrix_noalloc."""
         n, nnz = self.system_size(sys)
         rp = np.zeros(n + 1, dtype=np.int32)
         ci = np.zeros(max(1, nnz), dtype=np.int32)
         va = np.zeros(max(1, nnz))
         rhs = np.zeros(max(1, n))
-        check(load().sol_read_matrix(self.h, sys, rp.ctypes.data_as(C.POINTER(C.c_int32)),
+        fn = load().sol_read_matrix_noalloc if noalloc else load().sol_read_matrix
+        check(fn(self.h, sys, rp.ctypes.data_as(C.POINTER(C.c_int32)),
                                      ci.ctypes.data_as(C.POINTER(C.c_int32)),
                                      va.ctypes.data_as(C.POINTER(C.c_double)),
                                      rhs.ctypes.data_as(C.POINTER(C.c_double))))

@@ -1770,6 +1770,87 @@ int sol_read_matrix(sol_handle *h, int32_t system, int32_t *row_ptr, int32_t *co
     return SOL_OK;
 }
 
+// ------------------------------------------------ allocation-free export
+// Device scratch of sol_read_matrix_noalloc: one array per GPU the library
+// runs on, held until the process ends.  On the host the array's name is a
+// stand-in, not device memory: host code never passes it to a kernel or a
+// copy, it uses the device address hipGetSymbolAddress returns, looked up
+// once per device with that device current and kept per device.
+static __device__ __align__(256) unsigned char scratch[SOL_NOALLOC_SCRATCH_BYTES];
+
+static std::mutex g_scratch_mu;
+static std::map<int, unsigned char *> g_scratch_ptr;
+
+static int scratch_ptr(unsigned char **out)
+{
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_ptr.find(dev);
+    if (it == g_scratch_ptr.end()) {
+        void *p = nullptr;
+        HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(SOL_EDEVICE, "device scratch of device %d has no address", dev);
+        it = g_scratch_ptr.emplace(dev, (unsigned char *)p).first;
+    }
+    *out = it->second;
+    return SOL_OK;
+}
+
+static size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// Layout of the scratch: row counts (rows ints), row_ptr (rows + 1 ints),
+// then one block of columns and values; rows go through in blocks whose
+// entries fit that block.  Every word a kernel reads was written earlier in
+// the same call (counts before the scan, the scan before the fills), so
+// nothing is cleared.
+int sol_read_matrix_noalloc(sol_handle *h, int32_t system, int32_t *row_ptr, int32_t *col_idx, double *val,
+                            double *rhs)
+{
+    if (!h || !row_ptr || !col_idx || !val || !rhs) return fail(SOL_EINVAL, "NULL argument");
+    if (system < 0 || system >= NSYS) return fail(SOL_EINVAL, "bad system %d", system);
+    int32_t n, nnz;
+    RCHK(sol_system_size(h, system, &n, &nnz));
+    if (n == 0) { row_ptr[0] = 0; return SOL_OK; }
+    const size_t total = SOL_NOALLOC_SCRATCH_BYTES;
+    const size_t pat = align256(sizeof(int32_t) * (size_t)n) + align256(sizeof(int32_t) * ((size_t)n + 1));
+    const size_t row_max = (size_t)h->z.nd * (sizeof(int32_t) + sizeof(double));
+    if (pat + row_max + 512 > total)
+        return fail(SOL_EINVAL, "system %d has %d rows: its CSR row pointers (%zu bytes) do not fit the %zu-byte "
+                    "device scratch of the allocation-free export", system, n, pat, total);
+    unsigned char *sp = nullptr;
+    RCHK(scratch_ptr(&sp));
+    int32_t *cnt = (int32_t *)sp;
+    int32_t *rp = (int32_t *)(sp + align256(sizeof(int32_t) * (size_t)n));
+    const size_t cap = (total - pat - 512) / (sizeof(int32_t) + sizeof(double));     // entries per block
+    int32_t *col = (int32_t *)(sp + pat);
+    double *vv = (double *)(sp + pat + align256(sizeof(int32_t) * cap));
+    hipStream_t st = h->stream;
+    const int dim = h->z.dim;
+    const CaseDev *cd = h->solo->cases_d;
+    launch_csr_pattern(dim, cd, system, n, cnt, rp, st);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(row_ptr, rp, sizeof(int32_t) * ((size_t)n + 1), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (row_ptr[n] != nnz) return fail(SOL_EDEVICE, "CSR pattern of system %d: %d entries, expected %d", system,
+                                       row_ptr[n], nnz);
+    // stream order keeps each block's copies ahead of the next block's fill
+    for (int r0 = 0; r0 < n;) {
+        const int32_t lim = row_ptr[r0] + (int32_t)std::min<size_t>(cap, (size_t)nnz);
+        const int r1 = (int)(std::upper_bound(row_ptr + r0 + 1, row_ptr + n + 1, lim) - row_ptr) - 1;
+        const int32_t base = row_ptr[r0];
+        const size_t m = (size_t)(row_ptr[r1] - base);
+        launch_csr_rows(dim, cd, system, r0, r1, rp, base, col, vv, st);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(col_idx + base, col, sizeof(int32_t) * m, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(val + base, vv, sizeof(double) * m, hipMemcpyDeviceToHost, st));
+        r0 = r1;
+    }
+    HIPCHK(hipMemcpyAsync(rhs, h->cd.b[system], sizeof(double) * (size_t)n, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return SOL_OK;
+}
+
 static int fill_stats(Group &g, int c, sol_step_stats *st, const int64_t *tot)
 {
     sol_handle *h = g.cs[c];

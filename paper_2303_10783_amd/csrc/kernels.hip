@@ -1421,20 +1421,23 @@ __global__ __launch_bounds__(1024) void k_scan(const int32_t *cnt, int32_t *row_
     if (threadIdx.x == T - 1) row_ptr[n] = sh[T - 1];
 }
 
+// rows [r0, r1) of the system; entry p of the CSR arrays goes to
+// col[p - base], val[p - base] (base = row_ptr[r0] when the arrays hold only
+// that block of rows, 0 when they hold the whole system)
 template <int DIM>
 __global__ __launch_bounds__(TILE) void k_csr_fill(const CaseDev *__restrict__ cd, int s, const int32_t *row_ptr,
-                                                   int32_t *col, double *val)
+                                                   int32_t *col, double *val, int r0, int r1, int base)
 {
     constexpr int ND = 2 * DIM + 1;
     const Phys &P = cd->ph;
     const int n = P.nsys[s];
-    const int row = blockIdx.x * TILE + threadIdx.x;
-    if (row >= n) return;
+    const int row = r0 + blockIdx.x * TILE + threadIdx.x;
+    if (row >= r1 || row >= n) return;
     int q[3];
     decode(row, P.sdim[s][0], P.sdim[s][1], q);
     const int sx = P.sdim[s][0], sxy = P.sdim[s][0] * P.sdim[s][1];
     const double *A = cd->A[s];
-    int p = row_ptr[row];
+    int p = row_ptr[row] - base;
 #pragma unroll
     for (int slot = 0; slot < ND; ++slot) {
         bool ex;
@@ -1642,8 +1645,24 @@ void launch_csr(int dim, const CaseDev *cd, int s, int n, int32_t *cnt, int32_t 
         else hipLaunchKernelGGL(k_csr_count<3>, dim3(nb), dim3(TILE), 0, st, cd, s, cnt);
         hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, cnt, row_ptr, n);
     }
-    if (dim == 2) hipLaunchKernelGGL(k_csr_fill<2>, dim3(nb), dim3(TILE), 0, st, cd, s, row_ptr, col, val);
-    else hipLaunchKernelGGL(k_csr_fill<3>, dim3(nb), dim3(TILE), 0, st, cd, s, row_ptr, col, val);
+    if (dim == 2) hipLaunchKernelGGL(k_csr_fill<2>, dim3(nb), dim3(TILE), 0, st, cd, s, row_ptr, col, val, 0, n, 0);
+    else hipLaunchKernelGGL(k_csr_fill<3>, dim3(nb), dim3(TILE), 0, st, cd, s, row_ptr, col, val, 0, n, 0);
+}
+void launch_csr_pattern(int dim, const CaseDev *cd, int s, int n, int32_t *cnt, int32_t *row_ptr, hipStream_t st)
+{
+    if (n <= 0) return;
+    const int nb = ceil_div(n, TILE);
+    if (dim == 2) hipLaunchKernelGGL(k_csr_count<2>, dim3(nb), dim3(TILE), 0, st, cd, s, cnt);
+    else hipLaunchKernelGGL(k_csr_count<3>, dim3(nb), dim3(TILE), 0, st, cd, s, cnt);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, cnt, row_ptr, n);
+}
+void launch_csr_rows(int dim, const CaseDev *cd, int s, int r0, int r1, const int32_t *row_ptr, int base,
+                     int32_t *col, double *val, hipStream_t st)
+{
+    if (r1 <= r0) return;
+    const int nb = ceil_div(r1 - r0, TILE);
+    if (dim == 2) hipLaunchKernelGGL(k_csr_fill<2>, dim3(nb), dim3(TILE), 0, st, cd, s, row_ptr, col, val, r0, r1, base);
+    else hipLaunchKernelGGL(k_csr_fill<3>, dim3(nb), dim3(TILE), 0, st, cd, s, row_ptr, col, val, r0, r1, base);
 }
 void launch_fill(double *x, double v, int n, hipStream_t s)
 {

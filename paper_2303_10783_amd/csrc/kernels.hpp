@@ -49,6 +49,12 @@ void launch_hist_reset(const CaseDev *c, int ncase, hipStream_t s);
 
 void launch_csr(int dim, const CaseDev *cd, int s, int n, int32_t *cnt, int32_t *row_ptr, int32_t *col,
                 double *val, int build_pattern, hipStream_t st);
+// the CSR export in two parts: row counts and their exclusive scan (cnt: n
+// ints, row_ptr: n + 1), then the columns and values of rows [r0, r1) into
+// arrays that start at entry `base` of the system's CSR arrays
+void launch_csr_pattern(int dim, const CaseDev *cd, int s, int n, int32_t *cnt, int32_t *row_ptr, hipStream_t st);
+void launch_csr_rows(int dim, const CaseDev *cd, int s, int r0, int r1, const int32_t *row_ptr, int base,
+                     int32_t *col, double *val, hipStream_t st);
 void launch_fill(double *x, double v, int n, hipStream_t s);
 void launch_set_status(KState *st, int n, int status, hipStream_t s);
 
