@@ -52,6 +52,7 @@ class _Case(C.Structure):
         ("T_ramp", C.c_double * 6), ("velocity", C.c_int32 * 6),
         ("dt", C.c_double), ("tol_p", C.c_double), ("tol_t", C.c_double),
         ("max_iter", C.c_int32), ("literal_ag_order", C.c_int32),
+        ("D_l", C.c_double),
     ]
 
 
@@ -136,6 +137,7 @@ def make_case_struct(case: dict, literal_ag_order: bool = False) -> _Case:
     s.dt, s.tol_p, s.tol_t = nm["dt"], nm["tol_p"], nm["tol_t"]
     s.max_iter = nm["max_iter"]
     s.literal_ag_order = 1 if literal_ag_order else 0
+    s.D_l = float(al.get("D_l", 0.0) or 0.0)
     return s
 
 

@@ -158,7 +158,9 @@ def eq_poisson(case, ustar, phi):
 
 
 def eq_solute(case, fields, unew, C):
-    """Residual of eq. (3.10): (C - C^n)/dt + div(u C_l), C_l = A_g C."""
+    """Residual of eq. (3.10): (C - C^n)/dt + div(u C_l) - div(g_l D_l grad C_l),
+    C_l = A_g C (the diffusion term is eq. 3.7's; g_l on a face is the mean
+    of its two cells, zero flux through walls)."""
     G = Geometry(case)
     al, nm = case["alloy"], case["numerics"]
     C = np.asarray(C, dtype=np.float64).reshape(G.cell_shape)
@@ -171,6 +173,13 @@ def eq_solute(case, fields, unew, C):
         p = _pad(Cl, a, 1, 1)
         flux = _upwind_flux(vel[a], _take(p, a, slice(0, -1)), _take(p, a, slice(1, None)))
         res = res + (_take(flux, a, slice(1, None)) - _take(flux, a, slice(0, -1))) / G.h[a]
+    D = al.get("D_l", 0.0) or 0.0
+    if D > 0.0:
+        for a in range(G.dim):
+            h = G.h[a]
+            gface = 0.5 * (_take(gl, a, slice(1, None)) + _take(gl, a, slice(0, -1)))
+            dflux = _pad(D * gface * (_take(Cl, a, slice(1, None)) - _take(Cl, a, slice(0, -1))) / h, a, 1, 1)
+            res = res - (_take(dflux, a, slice(1, None)) - _take(dflux, a, slice(0, -1))) / h
     return res.ravel()
 
 

@@ -21,7 +21,8 @@
  *   - momentum predictor eq. (3.3) (momentum form 2.7) with Carman-Kozeny
  *     drag eq. (2.8) and Boussinesq force eq. (2.9);
  *   - pressure-correction Poisson eq. (3.4) and projection eq. (3.5);
- *   - matrix-based solute transport eqs. (3.6), (3.8)-(3.10);
+ *   - matrix-based solute transport eqs. (3.6), (3.8)-(3.10), with the
+ *     liquid diffusion of eq. (3.7) when D_l > 0;
  *   - split energy equation eqs. (3.11)-(3.12), liquidus eq. (3.13), lever
  *     rule eq. (3.14), quadratic eqs. (3.15)-(3.16), eutectic rule (text after
  *     eq. 3.16), concentration update eqs. (3.17)-(3.18);
@@ -63,6 +64,8 @@ typedef struct {
        matrix instead of A_con*A_g; only for a test that shows its solute
        conservation defect */
     int32_t literal_ag_order;
+    /* liquid solute diffusivity D_l of eq. (3.7); 0 = the minimal model */
+    double D_l;
 } oc_case;
 
 typedef struct {
@@ -325,7 +328,12 @@ static void assemble_poisson(const oc_case *c, double *const ustar[3], oc_csr *m
    reading: C_l^{n+1} = A_g C^{n+1} substituted into the convection term gives
    A_con A_g (column scaling); the printed A_g*A_con (row scaling) is kept
    behind literal_ag_order for a test.  Flux-form upwind with the face
-   velocities u^{n+1}; walls carry no flux; D_l = 0 (minimal model). */
+   velocities u^{n+1}; walls carry no flux.
+   Liquid diffusion (eq. 3.7, the A_lap term of eq. 3.9): the diffusive flux
+   g_l^n D_l grad C_l^{n+1} across a face, with g_l on the face the mean of
+   its two cells (reading, as for the drag), C_l = A_g C substituted as for
+   convection (columns scaled); zero flux through walls; D_l = 0 is the
+   minimal model. */
 static void assemble_solute(const oc_case *c, const oc_fields *f, double *const unew[3], oc_csr *m)
 {
     int n[3];
@@ -341,7 +349,7 @@ static void assemble_solute(const oc_case *c, const oc_fields *f, double *const 
         row_t r;
         row_clear(&r);
         double agP = 1.0 / (1.0 - (1.0 - c->k_p) * (1.0 - f->gl[row]));
-        double conv_diag = 0.0;
+        double conv_diag = 0.0, dif_diag = 0.0;
         for (int a = 0; a < c->dim; ++a) {
             double h = h_of(c, a);
             double vm = face_vel(c, unew, a, q, q[a]);
@@ -355,11 +363,14 @@ static void assemble_solute(const oc_case *c, const oc_fields *f, double *const 
                 if (!r.has[a][s]) continue;
                 int nb = row + (s == 0 ? -off[a] : off[a]);
                 double agN = 1.0 / (1.0 - (1.0 - c->k_p) * (1.0 - f->gl[nb]));
-                double cf = (s == 0) ? cw : ce;
+                double gface = 0.5 * (f->gl[row] + f->gl[nb]);
+                double dcoef = c->D_l * gface / (h * h);
+                double cf = ((s == 0) ? cw : ce) - dcoef;
+                dif_diag += dcoef;
                 r.nb[a][s] = c->literal_ag_order ? agP * cf : cf * agN;
             }
         }
-        r.diag = 1.0 / c->dt + conv_diag * agP;
+        r.diag = 1.0 / c->dt + (conv_diag + dif_diag) * agP;
         r.rhs = f->C[row] / c->dt;
         csr_put(m, n, row, &r, &pos);
     }

@@ -35,10 +35,13 @@ def _cases():
     c2fs["bcs"][3] = W.face_bc(W.THERMAL_DIRICHLET, T0=480.0, b=0.5)
     c3 = W.box_3d(5, 4, 3, lx=0.05, ly=0.04, lz=0.03)
     c3["bcs"][5] = W.face_bc(W.THERMAL_ROBIN, h=50.0, T_ext=400.0, velocity=W.VELOCITY_FREESLIP)
-    return [c2, c2fs, c3]
+    # liquid solute diffusion (eq. 3.7), large enough to dominate the solute rows
+    c2d = W.cavity_2d(7, 5, alloy=W.sn10pb_alloy(D_l=2e-4))
+    c3d = W.box_3d(5, 4, 3, lx=0.05, ly=0.04, lz=0.03, alloy=W.sn10pb_alloy(D_l=2e-4))
+    return [c2, c2fs, c3, c2d, c3d]
 
 
-@pytest.mark.parametrize("case", _cases(), ids=["2d", "2d-freeslip-dirichlet", "3d"])
+@pytest.mark.parametrize("case", _cases(), ids=["2d", "2d-freeslip-dirichlet", "3d", "2d-Dl", "3d-Dl"])
 def test_forward_probe_equals_stencil_assembly(case):
     """Forward method (colour probes of a residual function) reproduces the
     directly assembled matrices and right-hand sides up to rounding."""
@@ -325,3 +328,71 @@ def test_momentum_advecting_velocity_exact_for_linear():
         val = conv @ phi
         inner = (X > 1.5 * hx) & (X < lx - 1.5 * hx) & (Y > hy) & (Y < ly - hy)
         np.testing.assert_allclose(val[inner], U0 * 2.0 + V0 * 7.0, rtol=1e-10)
+
+
+
+# ----------------------------------------------------- liquid diffusion
+
+def _dl_case(D=1e-4, nx=9, ny=7, nz=1):
+    al = W.sn10pb_alloy(D_l=D)
+    if nz == 1:
+        return W.make_case(2, nx, ny, 1, nx * 1e-3, ny * 1e-3, 1.0, alloy=al)
+    return W.make_case(3, nx, ny, nz, nx * 1e-3, ny * 1e-3, nz * 1e-3, alloy=al)
+
+
+@pytest.mark.parametrize("nz", [1, 5])
+def test_liquid_diffusion_exact_for_quadratic_Cl_and_linear_gl(nz):
+    """The diffusion rows of the solute matrix (eq. 3.7) acting on C = C_l /
+    A_g give -div(g_l D_l grad C_l) exactly on rows away from the walls when
+    g_l is linear and C_l quadratic in every axis (face means of a linear g_l
+    are exact, differences of a quadratic C_l are exact face gradients, and
+    the central difference of the quadratic flux is exact)."""
+    case = _dl_case(nz=nz)
+    al = case["alloy"]
+    D, kp = al["D_l"], al["k_p"]
+    g = case["grid"]
+    n = (g["nx"], g["ny"], g["nz"])
+    h = (g["lx"] / n[0], g["ly"] / n[1], g["lz"] / n[2])
+    dim = g["dim"]
+    k, j, i = np.meshgrid(*(np.arange(n[a]) for a in (2, 1, 0)), indexing="ij")
+    x = [((i + 0.5) * h[0]).ravel(), ((j + 0.5) * h[1]).ravel(), ((k + 0.5) * h[2]).ravel()]
+    a_g, b_g = (0.3, 40.0, 25.0, 30.0), None
+    gl = a_g[0] + sum(a_g[1 + a] * x[a] for a in range(dim))
+    cq = (2.0, 500.0, -300.0, 400.0)
+    Cl = 10.0 + sum(cq[a] * x[a] + 1e4 * (a + 1) * x[a] ** 2 for a in range(dim))
+    f = oracle.Oracle(case).fields()
+    f["gl"] = gl
+    o = oracle.Oracle(case, fields=f)
+    zero = tuple(np.zeros(max(1, f[kk].size)) for kk in ("u", "v", "w"))
+    A, _, _, _ = o.assemble(SYS.SYS_C, vel=zero)
+    C = Cl * (kp + (1.0 - kp) * gl)
+    lhs = A @ C - C / case["numerics"]["dt"]
+    # -sum_a d/dx_a (g D dCl/dx_a) = -D sum_a (g_a' Cl_a' + g Cl_a'')
+    exact = -D * sum(a_g[1 + a] * (cq[a] + 2e4 * (a + 1) * x[a]) + gl * 2e4 * (a + 1) for a in range(dim))
+    inner = np.ones(C.size, bool)
+    for a, idx in enumerate((i.ravel(), j.ravel(), k.ravel())[:dim]):
+        inner &= (idx >= 1) & (idx <= n[a] - 2)
+    np.testing.assert_allclose(lhs[inner], exact[inner], rtol=1e-9, atol=1e-9 * abs(exact).max())
+
+
+def test_liquid_diffusion_conserves_solute():
+    """With diffusion the solute matrix still has column sums 1/dt (zero-flux
+    walls, symmetric face coefficients), so sum C is conserved for any g_l
+    and flow; the printed row order breaks it."""
+    case = _dl_case(D=3e-4)
+    rng = np.random.default_rng(12)
+    f = oracle.Oracle(case).fields()
+    f["gl"] = rng.uniform(0.0, 1.0, f["gl"].size)
+    vel = tuple(rng.uniform(-1e-3, 1e-3, max(1, f[kk].size)) for kk in ("u", "v", "w"))
+    dt = case["numerics"]["dt"]
+    A = oracle.Oracle(case, fields=f).assemble(SYS.SYS_C, vel=vel)[0].toarray()
+    np.testing.assert_allclose(A.sum(axis=0), 1.0 / dt, rtol=1e-13)
+    f0 = dict(f, gl=np.ones(f["gl"].size))
+    zero = tuple(np.zeros(max(1, f[kk].size)) for kk in ("u", "v", "w"))
+    A1 = oracle.Oracle(case, fields=f0).assemble(SYS.SYS_C, vel=zero)[0].toarray()
+    L = A1 - np.eye(A1.shape[0]) / dt                   # g_l = 1: D_l times the Neumann Laplacian
+    np.testing.assert_allclose(L, L.T, rtol=0, atol=1e-12 * abs(L).max())
+    np.testing.assert_allclose(L.sum(axis=1), 0.0, atol=1e-12 * abs(L).max())
+    assert np.all(np.diag(L) > 0)
+    Al = oracle.Oracle(case, fields=f, literal_ag_order=True).assemble(SYS.SYS_C, vel=vel)[0].toarray()
+    assert abs(Al.sum(axis=0) - 1.0 / dt).max() > 1e-3

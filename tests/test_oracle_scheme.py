@@ -348,3 +348,63 @@ def test_step_rebuilt_from_forward_matrices(dim):
     assert r(o.intermediate["Tstar"], Tstar) < 1e-12
     assert r(f["T"], T) < 1e-12 and np.abs(f["gl"] - gl).max() < 1e-10
     assert r(f["Cl"], Cl) < 1e-12 and r(f["Cs"], Cs) < 1e-12
+
+
+# ---------------------------------------------- liquid solute diffusion
+
+def test_liquid_diffusion_cosine_mode_decays_at_the_discrete_rate():
+    """Eq. (3.7) in a still, fully liquid 1D bar (no buoyancy, adiabatic
+    walls): C - C0 = A cos(pi x / L) is an eigenvector of the discrete
+    Neumann Laplacian (DCT-II mode 1) with eigenvalue
+    (4 D_l / h^2) sin^2(pi h / (2 L)), so each implicit step divides its
+    amplitude by 1 + dt lambda_h exactly; the mean stays C0."""
+    nx, L, D, dt, A0, nsteps = 40, 0.04, 1e-5, 0.5, 0.5, 20
+    al = W.sn10pb_alloy(beta_T=0.0, beta_C=0.0, D_l=D)
+    Tl = al["T_m"] + al["m_sp"] * 10.0
+    case = W.make_case(2, nx, 1, 1, L, 1e-3, 1.0, alloy=al, T0=Tl + 20.0, dT_amp=0.0, dt=dt,
+                       tol_p=1e-14, tol_t=1e-14)
+    h = L / nx
+    x = (np.arange(nx) + 0.5) * h
+    mode = np.cos(np.pi * x / L)
+    case["init"]["C"] = 10.0 + A0 * mode
+    case["init"]["Cl"] = case["init"]["C"].copy()
+    o = oracle.Oracle(case)
+    o.step(nsteps)
+    f = o.fields()
+    assert np.all(f["gl"] == 1.0) and not f["u"].any()
+    lam = 4.0 * D / h ** 2 * math.sin(math.pi * h / (2.0 * L)) ** 2
+    expect = 10.0 + A0 * mode * (1.0 + dt * lam) ** (-nsteps)
+    np.testing.assert_allclose(f["C"], expect, rtol=1e-12)
+    assert abs(f["C"].mean() - 10.0) < 1e-13 * 10.0
+    assert (1.0 + dt * lam) ** (-nsteps) < 0.6         # the mode did decay
+
+
+def test_liquid_diffusion_acts_on_the_liquid_concentration():
+    """A mushy, still state (no buoyancy, u = 0) whose liquid concentration
+    C_l = C / (k_p + (1 - k_p) g_l) is uniform while g_l and hence C vary:
+    eq. (3.7) diffuses C_l, so C^{n+1} = C^n.  Planted mistake: diffusing the
+    mixture C itself (A_g = I, the same face coefficients) moves C."""
+    al = W.sn10pb_alloy(beta_T=0.0, beta_C=0.0, D_l=1e-4)
+    case = W.make_case(2, 12, 9, 1, 0.012, 0.009, 1.0, alloy=al, dT_amp=0.0, tol_p=1e-14, tol_t=1e-14)
+    rng = np.random.default_rng(21)
+    n = case["init"]["T"].size
+    kp = al["k_p"]
+    gl = rng.uniform(0.3, 0.9, n)
+    Cl0 = 12.0
+    f = {k: np.array(v, copy=True) for k, v in case["init"].items()}
+    f["gl"] = gl
+    f["Cl"] = np.full(n, Cl0)
+    f["C"] = Cl0 * (kp + (1.0 - kp) * gl)
+    f["Cs"] = kp * f["Cl"]
+    f["T"] = al["T_m"] + al["m_sp"] * Cl0 + 0.0 * gl
+    o = oracle.Oracle(case, fields=f)
+    o.step(1)
+    assert np.array_equal(o.fields()["C"], f["C"])
+    # planted: the mixture diffused instead (A_g = I), same face g_l
+    o2 = oracle.Oracle(case, fields=f)
+    A, b, _, _ = o2.assemble(oracle.SYS_C, vel=tuple(np.zeros(max(1, f[k].size)) for k in ("u", "v", "w")))
+    Id = np.eye(n) / case["numerics"]["dt"]
+    ag = 1.0 / (kp + (1.0 - kp) * gl)
+    M = (A.toarray() - Id) / ag[None, :]               # the diffusion rows without the A_g columns
+    planted = np.linalg.solve(Id + M, b)
+    assert np.abs(planted - f["C"]).max() > 1e-6
