@@ -1325,7 +1325,7 @@ static int validate(const sol_grid *g, const sol_alloy *a, const sol_bcs *b, con
     if (!(a->k_p > 0 && a->k_p < 1)) return fail(SOL_EINVAL, "k_p must lie in (0,1)");
     if (!(a->m_sp < 0)) return fail(SOL_EINVAL, "liquidus slope m_sp must be < 0");
     if (!(a->C_e > 0)) return fail(SOL_EINVAL, "C_e must be > 0");
-    if (a->D_l != 0.0) return fail(SOL_EINVAL, "liquid diffusion D_l is not supported (minimal model)");
+    if (!(a->D_l >= 0)) return fail(SOL_EINVAL, "liquid diffusivity D_l must be >= 0");
     if (!(a->darcy_eps >= 0)) return fail(SOL_EINVAL, "darcy_eps must be >= 0");
     if (a->g < 0) return fail(SOL_EINVAL, "g must be >= 0");
     const int nf = g->dim == 3 ? 6 : 4;
@@ -1374,6 +1374,7 @@ static void make_phys(const sol_handle &h, Phys &P)
     P.Tref = a.T_ref; P.Cref = a.C_ref; P.grav = a.g;
     P.betaT = a.beta_T; P.betaC = a.beta_C; P.lambda2 = a.lambda2; P.eps = a.darcy_eps;
     P.rcp = a.rho * a.cp; P.kcond = a.k;
+    P.Dl = a.D_l;
     for (int f = 0; f < 6; ++f) {
         const sol_face_bc &fb = h.bcs.face[f];
         const bool used = f < 2 * z.dim;

@@ -209,9 +209,12 @@ __global__ __launch_bounds__(TILE) void k_asm_momentum(const CaseDev *__restrict
 }
 
 // ---------------------------------------------- solute + energy assembly
-// Solute (eqs. 3.8-3.10): I/dt + A_con(u^{n+1}) A_g, A_g = diag(1/(1 - (1-k_p)
-// (1-g_l^n))) applied to the columns (C_l = A_g C substituted into the
-// convection term); b = C^n/dt.  Energy (eq. 3.11): const (1/dt, alpha
+// Solute (eqs. 3.8-3.10): I/dt + (A_con(u^{n+1}) - A_dif) A_g, A_g =
+// diag(1/(1 - (1-k_p)(1-g_l^n))) applied to the columns (C_l = A_g C
+// substituted into the convection and diffusion terms); A_dif is the
+// liquid diffusion div(g_l^n D_l grad .) of eq. 3.7 with g_l on a face the
+// mean of its two cells and no flux through walls (absent when D_l = 0);
+// b = C^n/dt.  Energy (eq. 3.11): const (1/dt, alpha
 // diffusion, wall conductances) + A_con(u^{n+1}); b = T^n/dt + wall terms at
 // t_{n+1}.  vel_src 1: advecting field = projected u^{n+1} (the step);
 // 0: the level-n field (stand-alone assembly).
@@ -235,7 +238,8 @@ __global__ __launch_bounds__(TILE) void k_asm_transport(const CaseDev *__restric
     double aC[ND], aT[ND];
 #pragma unroll
     for (int k = 0; k < ND; ++k) { aC[k] = 0.0; aT[k] = AcT[(size_t)k * n + ci]; }
-    double dconv = 0.0;
+    double dconv = 0.0, ddif = 0.0;
+    const double gP = c.gl[ci];
     double bT = c.T[ci] * P.idt;
     const int stride[3] = {1, P.nx, P.nx * P.ny};
 #pragma unroll
@@ -250,8 +254,11 @@ __global__ __launch_bounds__(TILE) void k_asm_transport(const CaseDev *__restric
         const bool em = q[ax] >= 1, ep = q[ax] <= nax - 2;
         const int sm = DIM - 1 - ax, sp = DIM + 1 + ax;
         if (em) {
-            const double agm = 1.0 / (1.0 - omk * (1.0 - c.gl[ci - stride[ax]]));
-            aC[sm] = cw * agm;
+            const double gm = c.gl[ci - stride[ax]];
+            const double agm = 1.0 / (1.0 - omk * (1.0 - gm));
+            const double dm = P.Dl * (0.5 * (gP + gm)) * P.ih2[ax];
+            ddif += dm;
+            aC[sm] = (cw - dm) * agm;
             aT[sm] += cw;
         } else {
             aT[sm] = 0.0;
@@ -259,8 +266,11 @@ __global__ __launch_bounds__(TILE) void k_asm_transport(const CaseDev *__restric
             if (U > 0.0) bT += U * wall_temp(P, 2 * ax, t_new) / (P.rcp * P.h[ax]);
         }
         if (ep) {
-            const double agp = 1.0 / (1.0 - omk * (1.0 - c.gl[ci + stride[ax]]));
-            aC[sp] = ce * agp;
+            const double gp = c.gl[ci + stride[ax]];
+            const double agp = 1.0 / (1.0 - omk * (1.0 - gp));
+            const double dp = P.Dl * (0.5 * (gP + gp)) * P.ih2[ax];
+            ddif += dp;
+            aC[sp] = (ce - dp) * agp;
             aT[sp] += ce;
         } else {
             aT[sp] = 0.0;
@@ -268,7 +278,7 @@ __global__ __launch_bounds__(TILE) void k_asm_transport(const CaseDev *__restric
             if (U > 0.0) bT += U * wall_temp(P, 2 * ax + 1, t_new) / (P.rcp * P.h[ax]);
         }
     }
-    aC[DIM] = P.idt + dconv * agP;
+    aC[DIM] = P.idt + (dconv + ddif) * agP;
     aT[DIM] += dconv;
     double *AC = c.A[SC], *AT = c.A[ST];
 #pragma unroll

@@ -98,6 +98,7 @@ struct Phys {
     double h[3], ih[3], ih2[3];
     double rho, mu, nu, dt, idt, alpha, lam, kp, Tm, msp, Ce, Tref, Cref;
     double grav, betaT, betaC, lambda2, eps, rcp, kcond;
+    double Dl;                // liquid solute diffusivity (eq. 3.7); 0 = minimal model
     int32_t thermal[6], slip[6];
     double hc[6], Text[6], Tw0[6], Tramp[6];
 };

@@ -53,7 +53,7 @@ def _structs(sol, case):
     (lambda c: c["alloy"].update(k_p=1.2), "k_p"),
     (lambda c: c["alloy"].update(m_sp=2.33), "m_sp"),
     (lambda c: c["alloy"].update(rho=-1.0), "rho"),
-    (lambda c: c["alloy"].update(D_l=1e-9), "D_l"),
+    (lambda c: c["alloy"].update(D_l=-1e-9), "D_l"),
     (lambda c: c["bcs"][0].update(h=-5.0), "Robin"),
     (lambda c: c["grid"].update(lx=0.0), "lengths"),
 ])
