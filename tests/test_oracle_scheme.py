@@ -408,3 +408,45 @@ def test_liquid_diffusion_acts_on_the_liquid_concentration():
     M = (A.toarray() - Id) / ag[None, :]               # the diffusion rows without the A_g columns
     planted = np.linalg.solve(Id + M, b)
     assert np.abs(planted - f["C"]).max() > 1e-6
+
+
+# ------------------------------------------- freckle cavity (Example 2)
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_freckle_recipe_perturbation_and_symmetry(dim):
+    """Example 2's set-up: Pb-48%Sn at 216 degC, bottom wall T0 - b t, top
+    wall T0, C = 1.0001 C0 on the vertical centre line.  The perturbation
+    sits on the middle columns only; the Sn-rich (lighter, beta_C > 0)
+    centre column rises; the cavity and its perturbation are mirror
+    symmetric about the centre plane(s), so the velocity is too (to the
+    solver tolerance)."""
+    c = W.freckle_case(dim, tol=1e-13, mesh=(30, 90, 1) if dim == 2 else (12, 12, 36),
+                       slip_sides=(dim == 3))
+    c["numerics"]["tol_t"] = 1e-14
+    g = c["grid"]
+    nx, ny, nz = g["nx"], g["ny"], g["nz"]
+    C = c["init"]["C"].reshape(nz, ny, nx)
+    C0 = c["C0"]
+    mid = [nx // 2 - 1, nx // 2]
+    hot = np.zeros_like(C, bool)
+    if dim == 2:
+        hot[:, :, mid] = True
+    else:
+        hot[:, ny // 2 - 1:ny // 2 + 1, nx // 2 - 1:nx // 2 + 1] = True
+    assert np.all(C[hot] == 1.0001 * C0) and np.all(C[~hot] == C0)
+    bot, top = (2, 3) if dim == 2 else (4, 5)
+    assert c["bcs"][bot]["thermal"] == W.THERMAL_DIRICHLET and c["bcs"][bot]["b"] == 0.05
+    assert c["bcs"][top]["thermal"] == W.THERMAL_DIRICHLET and c["bcs"][top]["b"] == 0.0
+    assert abs(c["bcs"][top]["T0"] - (216.0 + 273.15)) < 1e-12
+    o = oracle.Oracle(c)
+    o.step(10)
+    f = o.fields()
+    if dim == 2:
+        v = f["v"].reshape(ny - 1, nx)
+        assert np.all(v[ny // 3:2 * ny // 3, mid] > 0)
+        assert np.abs(v - v[:, ::-1]).max() <= 1e-10 * np.abs(v).max()
+    else:
+        w = f["w"].reshape(nz - 1, ny, nx)
+        assert np.all(w[nz // 3:2 * nz // 3, ny // 2 - 1:ny // 2 + 1, nx // 2 - 1:nx // 2 + 1] > 0)
+        for ax in (1, 2):
+            assert np.abs(w - np.flip(w, axis=ax)).max() <= 1e-10 * np.abs(w).max()

@@ -63,6 +63,19 @@ def sn10pb_alloy(**override) -> dict:
     return a
 
 
+def pb48sn_alloy(**override) -> dict:
+    """Pb-48%Sn column of the alloy property table (Table 1), temperatures
+    converted to kelvin (melting point 327.5 degC)."""
+    a = dict(
+        rho=9000.0, mu=1.0e-3, cp=200.0, k=50.0, latent=5.35e4,
+        beta_T=1.0e-4, beta_C=4.5e-3, lambda2=40.0e-6,
+        T_m=327.5 + 273.15, m_sp=-2.334, k_p=0.307, C_e=61.9,
+        g=9.81, D_l=0.0, darcy_eps=1.0e-3, T_ref=None, C_ref=None,
+    )
+    a.update(override)
+    return a
+
+
 def face_bc(thermal=THERMAL_ADIABATIC, h=0.0, T_ext=0.0, T0=0.0, b=0.0,
             velocity=VELOCITY_NOSLIP) -> dict:
     return dict(thermal=int(thermal), h=float(h), T_ext=float(T_ext),
@@ -238,3 +251,53 @@ def served_arrivals(n_requests, seed=0, *, rate=20.0, p3d=0.5,
         case["arrival_s"] = t
         out.append(case)
     return out
+
+
+# ---------------------------------------------------------------------------
+# Freckle cavities (Example 2 of the paper): Pb-48%Sn, C0 = 48 wt%, a still
+# melt at T0 = 216 degC, the bottom wall held at T(t) = T0 - b t with
+# b = 0.05 K/s, the top wall at T0, the side walls adiabatic; the solute
+# perturbation C = 1.0001 C0 on the vertical centre line starts the density
+# inversion.  Meshes 30 x 90 (R = 1:3) and 90 x 30 (R = 3:1) in 2D,
+# 30 x 30 x 90 and 90 x 30 x 30 in 3D, dt = 0.01 s.  The cavity dimensions
+# are not given in the text: square cells of `cell` metres (1 mm) are taken.
+# The centre line is the middle column of cells (the two middle columns, or
+# the 2 x 2 middle columns in 3D, when the count is even).
+# ---------------------------------------------------------------------------
+
+FRECKLE_MESHES = {
+    (2, "1:3"): (30, 90, 1), (2, "3:1"): (90, 30, 1),
+    (3, "1:1:3"): (30, 30, 90), (3, "3:1:1"): (90, 30, 30),
+}
+
+
+def _middle(n):
+    return [n // 2] if n % 2 else [n // 2 - 1, n // 2]
+
+
+def freckle_case(dim=2, R=None, *, cell=1e-3, T0_C=216.0, b=0.05, C0=48.0, slip_sides=False,
+                 dt=0.01, tol=1e-10, precision=PRECISION_FP64, mesh=None, name=None) -> dict:
+    """The freckle-formation cavity with its centre-line solute perturbation;
+    `mesh` overrides the paper's mesh (same recipe on another grid)."""
+    R = R or ("1:3" if dim == 2 else "1:1:3")
+    nx, ny, nz = mesh or FRECKLE_MESHES[(dim, R)]
+    T0 = T0_C + 273.15
+    vert = VELOCITY_FREESLIP if slip_sides else VELOCITY_NOSLIP
+    bcs = [face_bc(velocity=vert) for _ in range(6)]
+    bot, top = (2, 3) if dim == 2 else (4, 5)
+    bcs[bot] = face_bc(THERMAL_DIRICHLET, T0=T0, b=b)
+    bcs[top] = face_bc(THERMAL_DIRICHLET, T0=T0, b=0.0)
+    case = make_case(dim, nx, ny, nz, nx * cell, ny * cell, nz * cell, C0=C0, alloy=pb48sn_alloy(),
+                     bcs=bcs, dt=dt, tol_p=tol, tol_t=tol, precision=precision, T0=T0, dT_amp=0.0,
+                     name=name or f"freckle{dim}d_{R}")
+    C = case["init"]["C"].reshape(nz if dim == 3 else 1, ny, nx)
+    if dim == 2:
+        for i in _middle(nx):
+            C[:, :, i] = 1.0001 * C0
+    else:
+        for j in _middle(ny):
+            for i in _middle(nx):
+                C[:, j, i] = 1.0001 * C0
+    case["init"]["C"] = C.ravel()
+    case["init"]["Cl"] = case["init"]["C"].copy()      # fully liquid: C_l = C
+    return case
