@@ -21,7 +21,9 @@ Also printed in the same JSON line:
                 workload on all host cores and on one core, the 50x30 cavity
                 in full, and the per-field error of the GPU's FP64 and mixed
                 runs of those first steps against the oracle's fields;
-  variants      the same box in mixed precision (500 steps), the box in FP64
+  variants      the same box in mixed precision (500 steps), with the forward
+                (residual-probing) assembly route and its assembly kernels'
+                times next to the stencil route's, the box in FP64
                 and mixed at the tight tolerances that hold the fields within
                 1e-8 of the oracle (errors in cpu_baseline), the 500x300
                 cavity (1000 steps, FP64 and mixed), the 50x30 cavity (200
@@ -135,7 +137,7 @@ def _describe(key, case):
 
 
 def run_single(sol, W, key, precision, steps, warmup, dev, *, precond="mg", tprecond=None, graph=False,
-               timing=False, keep_fields=None, tols=None):
+               timing=False, keep_fields=None, tols=None, assembly=None):
     """K steps of a named workload from its initial state (after W warm-up
     steps and a rewrite of the initial fields).  With timing, a second pass
     over the same K steps with every solver launch timed by HIP events gives
@@ -155,6 +157,8 @@ def run_single(sol, W, key, precision, steps, warmup, dev, *, precond="mg", tpre
         h.set_tprecond(tprecond)
     if graph:
         h.set_graph(True)
+    if assembly:
+        h.set_assembly(assembly)
     if warmup:
         h.step(warmup)
         h.write_fields(case["init"])
@@ -170,6 +174,8 @@ def run_single(sol, W, key, precision, steps, warmup, dev, *, precond="mg", tpre
                steps_redone=st["redone"])
     if precond != "mg":
         out["pressure_precond"] = precond
+    if assembly:
+        out["assembly"] = assembly
     if graph:
         out["graph"] = True
     if timing:
@@ -421,6 +427,16 @@ def main():
         if args.jacobi_variants:
             variants["C3_fp64_jacobi"] = _public(run_single(sol, W, "C3", "fp64", 20, 1, dev, precond="jacobi"))
             variants["C2_fp64_jacobi"] = _public(run_single(sol, W, "C2", "fp64", 50, 1, dev, precond="jacobi"))
+        # the forward (residual-probing) assembly route: its assembly
+        # kernels against the stencil route's, same steps
+        v = run_single(sol, W, args.workload, args.precision, steps, args.warmup, dev, assembly="forward",
+                       timing=True)
+        fw = {k: v["_classes"][k] for k in ("asm_mom", "asm_trn") if k in v["_classes"]}
+        st_cls = head.get("_classes", {})
+        variants[f"{args.workload}_{args.precision}_forward_assembly"] = dict(
+            _public(v), assembly_kernels=fw,
+            stencil_assembly_kernels={k: st_cls[k] for k in ("asm_mom", "asm_trn") if k in st_cls})
+        print(f"[bench] forward assembly: {v['value'] / 1e6:.1f} M", file=sys.stderr, flush=True)
         # the same box at the tolerances that hold 1e-8 per field (pressure
         # 1e-12, transport 1e-13): mixed against FP64 at a stated accuracy
         tight_fields = {}

@@ -313,6 +313,21 @@ int sol_get_timing(sol_handle *h, int32_t kclass, int64_t *launches, double *tot
 #define SOL_TPRECOND_JACOBI  0
 #define SOL_TPRECOND_JACOBI2 1
 #define SOL_TPRECOND_AUTO    2
+/* SOL_OPT_ASSEMBLY: route of the per-step assembly of the momentum
+   (eq. 3.3), solute (eqs. 3.7-3.10) and energy (eq. 3.11) systems.
+   SOL_ASSEMBLY_STENCIL (default): each row's coefficients from the
+   closed-form stencil rows (eq. 4.4, diffusion eq. 3.26).
+   SOL_ASSEMBLY_FORWARD: the forward method of Section 4 (eqs. 4.5-4.7): the
+   step-varying part of each discrete equation is evaluated as a residual
+   Eq(phi) = A phi - b, b = -Eq(0), and the entries are the responses to the
+   9 (2D) / 27 (3D) colour probes; the constant part of the term-wise split
+   is the same offline assembly.  Both give the same systems up to rounding
+   (a few ulp of the row scale).  Not allowed while the handle is part of a
+   batch (SOL_EBUSY); the handles of one batch must share it (SOL_EINVAL at
+   sol_batch_create). */
+#define SOL_OPT_ASSEMBLY 4
+#define SOL_ASSEMBLY_STENCIL 0
+#define SOL_ASSEMBLY_FORWARD 1
 int sol_set_option(sol_handle *h, int32_t option, int64_t value);
 
 /* Tile-size autotuner: times iterations of this case's pressure solve

@@ -27,7 +27,8 @@ STATE_FIELDS = ("u", "v", "w", "p", "T", "C", "gl", "Cl", "Cs")
 NFIELDS = 14
 KCLASS = dict(cg=0, bicg_a=1, bicg_b=2, bicg_c=3, asm_mom=4, asm_trn=5, phase=6,
               mg_pq=7, mg_down0=8, mg_up0=9, mg_coarse=10)
-OPT_GRAPH, OPT_PRECOND, OPT_TPRECOND = 1, 2, 3
+OPT_GRAPH, OPT_PRECOND, OPT_TPRECOND, OPT_ASSEMBLY = 1, 2, 3, 4
+ASSEMBLY = dict(stencil=0, forward=1)
 PRECOND = dict(jacobi=0, mg=1)
 TPRECOND = dict(jacobi=0, jacobi2=1, auto=2)
 
@@ -303,6 +304,10 @@ class Case:
     def set_precond(self, name: str):
         """Pressure-CG preconditioner: 'mg' (default) or 'jacobi'."""
         check(load().sol_set_option(self.h, OPT_PRECOND, PRECOND[name]))
+
+    def set_assembly(self, name: str):
+        """'stencil' (closed-form rows) or 'forward' (residual probing)."""
+        check(load().sol_set_option(self.h, OPT_ASSEMBLY, ASSEMBLY[name]))
 
     def set_tprecond(self, name: str):
         """BiCGSTAB preconditioner of the momentum, solute and energy solves:

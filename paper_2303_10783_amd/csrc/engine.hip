@@ -307,6 +307,7 @@ struct sol_handle {
     bool opt_graph = false;
     int precond = SOL_PRECOND_MG;
     int tprecond = SOL_TPRECOND_AUTO;
+    int assembly = SOL_ASSEMBLY_STENCIL;
     double *mg_pwork = nullptr;           // scratch of the exact-level inverse (set-up)
     double *mg_p64 = nullptr;             // FP64 exact-level inverse (set-up; solves read its FP32 copy)
     // large grids: level mg_nbig (> 0) is solved exactly instead of mg_nglob
@@ -1249,8 +1250,9 @@ static int group_step_once(Group &g, bool speculate)
 {
     hipStream_t s = g.stream;
     // 1: momentum predictor
+    const int fwd = g.cs[0]->assembly == SOL_ASSEMBLY_FORWARD;
     timed(g, SOL_KCLASS_ASM_MOM, [&] {
-        for (int gi = 0; gi < 2; ++gi) launch_asm_momentum(gi ? 3 : 2, g.cases_d, g.t_mom[gi], g.n_mom[gi], s);
+        for (int gi = 0; gi < 2; ++gi) launch_asm_momentum(gi ? 3 : 2, g.cases_d, g.t_mom[gi], g.n_mom[gi], s, fwd);
     });
     RCHK(group_solve(g, g.ph[0], speculate));
     // 2: pressure correction (and the initial guesses of phi and T*)
@@ -1264,7 +1266,8 @@ static int group_step_once(Group &g, bool speculate)
     for (int gi = 0; gi < 2; ++gi) launch_project(g.cases_d, g.t_mom[gi], g.n_mom[gi], s);
     // 4-6: solute and energy systems (both only need u^{n+1})
     timed(g, SOL_KCLASS_ASM_TRN, [&] {
-        for (int gi = 0; gi < 2; ++gi) launch_asm_transport(gi ? 3 : 2, g.cases_d, g.t_cell[gi], g.n_cell[gi], 1, s);
+        for (int gi = 0; gi < 2; ++gi)
+            launch_asm_transport(gi ? 3 : 2, g.cases_d, g.t_cell[gi], g.n_cell[gi], 1, s, fwd);
     });
     RCHK(group_solve(g, g.ph[2]));
     if (g.ph[0].pending || g.ph[1].pending) {
@@ -1734,12 +1737,13 @@ int sol_assemble(sol_handle *h, uint32_t mask)
     hipStream_t s = h->stream;
     const int gi = h->z.dim == 3 ? 1 : 0;
     const int dim = h->z.dim;
-    if (mask & 7u) launch_asm_momentum(dim, g.cases_d, g.t_mom[gi], g.n_mom[gi], s);
+    const int fwd = h->assembly == SOL_ASSEMBLY_FORWARD;
+    if (mask & 7u) launch_asm_momentum(dim, g.cases_d, g.t_mom[gi], g.n_mom[gi], s, fwd);
     if (mask & (1u << SP)) {
         launch_div_rhs(dim, g.cases_d, g.t_cell[gi], g.n_cell[gi], 0, s);
         launch_sub_mean(g.cases_d, g.t_cell[gi], g.n_cell[gi], s);
     }
-    if (mask & ((1u << SC) | (1u << ST))) launch_asm_transport(dim, g.cases_d, g.t_cell[gi], g.n_cell[gi], 0, s);
+    if (mask & ((1u << SC) | (1u << ST))) launch_asm_transport(dim, g.cases_d, g.t_cell[gi], g.n_cell[gi], 0, s, fwd);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(s));
     return SOL_OK;
@@ -1970,6 +1974,13 @@ int sol_set_option(sol_handle *h, int32_t option, int64_t value)
         h->solo = nullptr;
         return group_create({h}, &h->solo);
     }
+    case SOL_OPT_ASSEMBLY: {
+        if (value != SOL_ASSEMBLY_STENCIL && value != SOL_ASSEMBLY_FORWARD)
+            return fail(SOL_EINVAL, "unknown assembly route %lld", (long long)value);
+        if (h->batch) return fail(SOL_EBUSY, "handle is part of a batch");
+        h->assembly = (int)value;
+        return SOL_OK;
+    }
     }
     return fail(SOL_EINVAL, "unknown option %d", option);
 }
@@ -2089,6 +2100,8 @@ int sol_batch_create(sol_handle *const *cases, int32_t n, sol_batch **out)
             return fail(SOL_EINVAL, "handles of one batch must share one pressure preconditioner");
         if (cases[i]->tprecond != cases[0]->tprecond)
             return fail(SOL_EINVAL, "handles of one batch must share one transport preconditioner");
+        if (cases[i]->assembly != cases[0]->assembly)
+            return fail(SOL_EINVAL, "handles of one batch must share one assembly route");
         for (int j = 0; j < i; ++j)
             if (cases[j] == cases[i]) return fail(SOL_EINVAL, "handle %d given twice", i);
     }

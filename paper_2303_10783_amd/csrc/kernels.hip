@@ -1475,6 +1475,219 @@ __global__ void k_set_status(KState *st, int n, int status)
     if (i < n) st[i].status = status;
 }
 
+// ------------------------------------------ forward (probing) assembly
+// The paper's second route to the same systems (Section 4, the forward
+// method, eqs. 4.5-4.7): the discrete equation of every unknown is written
+// as a residual Eq(phi) = A phi - b, so that b = -Eq(0) and the entry of
+// column j in row i is Eq(e)_i - Eq(0)_i for a probe vector e that is 1 on
+// every cell of j's colour (i mod 3, j mod 3[, k mod 3]) and 0 elsewhere: no
+// two cells of one colour meet in a 5/7-point stencil, so 9 (2D) or 27 (3D)
+// probes recover every entry.  Only the terms that change every step are
+// probed; the constant part (transient, diffusion, wall conductances of the
+// term-wise split) comes from the offline assembly.  No probe vector is
+// stored: a row sees a probe only on its own stencil, where a colour is 1 on
+// at most one slot, so each row evaluates its residual once at phi = 0 and
+// once per in-domain slot with phi = 1 on that slot's cell -- the probes of
+// the colours that meet its stencil; the others give Eq(0) again.  The
+// residuals are written with face fluxes (upwind value times the advecting
+// velocity), not with the coefficient rows of the stencil kernels above.
+
+// upwind face flux: advecting velocity times the upstream value (eq. 3.28)
+__device__ __forceinline__ double upw(double v, double left, double right)
+{
+    return v >= 0.0 ? v * left : v * right;
+}
+
+// momentum predictor (eq. 3.3), varying part: convection + drag - b
+template <int DIM>
+__global__ __launch_bounds__(TILE) void k_fwd_momentum(const CaseDev *__restrict__ cases, const Tile *__restrict__ tiles)
+{
+    constexpr int ND = 2 * DIM + 1;
+    const Tile tl = tiles[xcd_tile(blockIdx.x, gridDim.x)];
+    const CaseDev &c = cases[tl.c];
+    const Phys &P = c.ph;
+    const int d = tl.s;
+    const int n = P.nsys[d];
+    const int row = tl.t * TILE + threadIdx.x;
+    if (row >= n) return;
+    int q[3];
+    decode(row, P.sdim[d][0], P.sdim[d][1], q);
+    int lo[3] = {q[0], q[1], q[2]}, hi[3] = {q[0], q[1], q[2]};
+    hi[d] += 1;
+    const int clo = cell_index(P, lo[0], lo[1], lo[2]);
+    const int chi = cell_index(P, hi[0], hi[1], hi[2]);
+    double *const vel[3] = {c.u, c.v, c.w};
+    // advecting velocities on the faces of the control volume
+    double vm[3], vp[3];
+    bool in[ND];
+    const int F = q[d] + 1;
+#pragma unroll
+    for (int ax = 0; ax < DIM; ++ax) {
+        if (ax == d) {
+            const double uc = face_vel(P, vel, d, lo, F);
+            vm[ax] = 0.5 * (face_vel(P, vel, d, lo, F - 1) + uc);
+            vp[ax] = 0.5 * (uc + face_vel(P, vel, d, lo, F + 1));
+        } else {
+            vm[ax] = 0.5 * (face_vel(P, vel, ax, lo, q[ax]) + face_vel(P, vel, ax, hi, q[ax]));
+            vp[ax] = 0.5 * (face_vel(P, vel, ax, lo, q[ax] + 1) + face_vel(P, vel, ax, hi, q[ax] + 1));
+        }
+        in[DIM - 1 - ax] = q[ax] >= 1;
+        in[DIM + 1 + ax] = q[ax] <= P.sdim[d][ax] - 2;
+    }
+    in[DIM] = true;
+    const double gf = 0.5 * (c.gl[clo] + c.gl[chi]);
+    const double sol = 1.0 - gf;
+    const double drag = P.nu * 180.0 * sol * sol / (P.lambda2 * P.lambda2 * (gf * gf * gf + P.eps));
+    double b = vel[d][row] * P.idt - (c.p[chi] - c.p[clo]) / (P.rho * P.h[d]);
+    if (d == DIM - 1) {
+        const double Tf = 0.5 * (c.T[clo] + c.T[chi]);
+        const double Cf = 0.5 * (c.Cl[clo] + c.Cl[chi]);
+        b += P.grav * (P.betaT * (Tf - P.Tref) + P.betaC * (Cf - P.Cref));
+    }
+    // Eq(phi) on the stencil: phi[k] is the probe's value on slot k
+    auto eq = [&](const double *phi) {
+        double r = 0.0;
+#pragma unroll
+        for (int ax = 0; ax < DIM; ++ax)
+            r += (upw(vp[ax], phi[DIM], phi[DIM + 1 + ax]) - upw(vm[ax], phi[DIM - 1 - ax], phi[DIM])) * P.ih[ax];
+        return r + drag * phi[DIM] - b;
+    };
+    double phi[ND];
+#pragma unroll
+    for (int k = 0; k < ND; ++k) phi[k] = 0.0;
+    const double r0 = eq(phi);
+    const double *Ac = c.Ac[d];
+    double a[ND];
+#pragma unroll
+    for (int k = 0; k < ND; ++k) {
+        a[k] = 0.0;
+        if (in[k]) {
+            phi[k] = 1.0;
+            a[k] = Ac[(size_t)k * n + row] + (eq(phi) - r0);
+            phi[k] = 0.0;
+        }
+    }
+    double *A = c.A[d];
+#pragma unroll
+    for (int k = 0; k < ND; ++k) A[(size_t)k * n + row] = a[k];
+    const double mi = 1.0 / a[DIM];
+    c.minv[d][row] = mi;
+    c.b[d][row] = -r0;
+    if (c.A32[d]) {
+#pragma unroll
+        for (int k = 0; k < ND; ++k) c.A32[d][(size_t)k * n + row] = (float)a[k];
+        c.minv32[d][row] = (float)mi;
+    }
+}
+
+// solute (eqs. 3.7-3.10: transient, convection and liquid diffusion of
+// C_l = A_g C) and energy (eq. 3.11, varying part: convection) residuals
+template <int DIM>
+__global__ __launch_bounds__(TILE) void k_fwd_transport(const CaseDev *__restrict__ cases, const Tile *__restrict__ tiles,
+                                                        int vel_src)
+{
+    constexpr int ND = 2 * DIM + 1;
+    const Tile tl = tiles[xcd_tile(blockIdx.x, gridDim.x)];
+    const CaseDev &c = cases[tl.c];
+    const Phys &P = c.ph;
+    const int n = P.ncell;
+    const int ci = tl.t * TILE + threadIdx.x;
+    if (ci >= n) return;
+    int q[3];
+    decode(ci, P.nx, P.ny, q);
+    double *const vel[3] = {vel_src ? c.un[0] : c.u, vel_src ? c.un[1] : c.v, vel_src ? c.un[2] : c.w};
+    const double t_new = (double)(*c.step + 1) * P.dt;
+    const double omk = 1.0 - P.kp;
+    const int stride[3] = {1, P.nx, P.nx * P.ny};
+    double vm[3], vp[3], dm[3], dp[3], ag[ND];
+    bool in[ND];
+    const double gP = c.gl[ci];
+    ag[DIM] = 1.0 / (1.0 - omk * (1.0 - gP));
+    in[DIM] = true;
+    double bT = c.T[ci] * P.idt;
+#pragma unroll
+    for (int ax = 0; ax < DIM; ++ax) {
+        vm[ax] = face_vel(P, vel, ax, q, q[ax]);
+        vp[ax] = face_vel(P, vel, ax, q, q[ax] + 1);
+        const int sm = DIM - 1 - ax, sp = DIM + 1 + ax;
+        in[sm] = q[ax] >= 1;
+        in[sp] = q[ax] <= P.sdim[SC][ax] - 2;
+        dm[ax] = dp[ax] = 0.0;
+        ag[sm] = ag[sp] = 0.0;
+        if (in[sm]) {
+            const double g = c.gl[ci - stride[ax]];
+            ag[sm] = 1.0 / (1.0 - omk * (1.0 - g));
+            dm[ax] = P.Dl * (0.5 * (gP + g)) * P.ih2[ax];
+        } else {
+            const double U = wall_cond(P, 2 * ax, P.h[ax]);
+            if (U > 0.0) bT += U * wall_temp(P, 2 * ax, t_new) / (P.rcp * P.h[ax]);
+        }
+        if (in[sp]) {
+            const double g = c.gl[ci + stride[ax]];
+            ag[sp] = 1.0 / (1.0 - omk * (1.0 - g));
+            dp[ax] = P.Dl * (0.5 * (gP + g)) * P.ih2[ax];
+        } else {
+            const double U = wall_cond(P, 2 * ax + 1, P.h[ax]);
+            if (U > 0.0) bT += U * wall_temp(P, 2 * ax + 1, t_new) / (P.rcp * P.h[ax]);
+        }
+    }
+    const double bC = c.C[ci] * P.idt;
+    // solute: phi is C on the stencil, the fluxes act on C_l = A_g C; walls
+    // carry no flux (zero face velocity, zero diffusive flux)
+    auto eqC = [&](const double *phi) {
+        double r = phi[DIM] * P.idt - bC;
+        const double lP = ag[DIM] * phi[DIM];
+#pragma unroll
+        for (int ax = 0; ax < DIM; ++ax) {
+            const double lW = ag[DIM - 1 - ax] * phi[DIM - 1 - ax], lE = ag[DIM + 1 + ax] * phi[DIM + 1 + ax];
+            r += (upw(vp[ax], lP, lE) - upw(vm[ax], lW, lP)) * P.ih[ax];
+            r -= dp[ax] * (lE - lP) - dm[ax] * (lP - lW);
+        }
+        return r;
+    };
+    // energy: convection of T* (the constant part, with the walls, is in Ac)
+    auto eqT = [&](const double *phi) {
+        double r = -bT;
+#pragma unroll
+        for (int ax = 0; ax < DIM; ++ax)
+            r += (upw(vp[ax], phi[DIM], phi[DIM + 1 + ax]) - upw(vm[ax], phi[DIM - 1 - ax], phi[DIM])) * P.ih[ax];
+        return r;
+    };
+    double phi[ND];
+#pragma unroll
+    for (int k = 0; k < ND; ++k) phi[k] = 0.0;
+    const double r0C = eqC(phi), r0T = eqT(phi);
+    const double *AcT = c.Ac[ST];
+    double aC[ND], aT[ND];
+#pragma unroll
+    for (int k = 0; k < ND; ++k) {
+        aC[k] = aT[k] = 0.0;
+        if (in[k]) {
+            phi[k] = 1.0;
+            aC[k] = eqC(phi) - r0C;
+            aT[k] = AcT[(size_t)k * n + ci] + (eqT(phi) - r0T);
+            phi[k] = 0.0;
+        }
+    }
+    double *AC = c.A[SC], *AT = c.A[ST];
+#pragma unroll
+    for (int k = 0; k < ND; ++k) { AC[(size_t)k * n + ci] = aC[k]; AT[(size_t)k * n + ci] = aT[k]; }
+    c.b[SC][ci] = -r0C;
+    c.b[ST][ci] = -r0T;
+    const double miC = 1.0 / aC[DIM], miT = 1.0 / aT[DIM];
+    c.minv[SC][ci] = miC;
+    c.minv[ST][ci] = miT;
+    if (c.A32[SC]) {
+#pragma unroll
+        for (int k = 0; k < ND; ++k) {
+            c.A32[SC][(size_t)k * n + ci] = (float)aC[k];
+            c.A32[ST][(size_t)k * n + ci] = (float)aT[k];
+        }
+        c.minv32[SC][ci] = (float)miC;
+        c.minv32[ST][ci] = (float)miT;
+    }
+}
+
 // ============================================================ launchers
 
 #define GRID(n) dim3((unsigned)(n)), dim3(TILE)
@@ -1485,15 +1698,25 @@ void launch_asm_const(int dim, const CaseDev *c, const Tile *t, int nt, hipStrea
     if (dim == 2) hipLaunchKernelGGL(k_asm_const<2>, GRID(nt), 0, s, c, t);
     else hipLaunchKernelGGL(k_asm_const<3>, GRID(nt), 0, s, c, t);
 }
-void launch_asm_momentum(int dim, const CaseDev *c, const Tile *t, int nt, hipStream_t s)
+void launch_asm_momentum(int dim, const CaseDev *c, const Tile *t, int nt, hipStream_t s, int fwd)
 {
     if (nt <= 0) return;
+    if (fwd) {
+        if (dim == 2) hipLaunchKernelGGL(k_fwd_momentum<2>, GRID(nt), 0, s, c, t);
+        else hipLaunchKernelGGL(k_fwd_momentum<3>, GRID(nt), 0, s, c, t);
+        return;
+    }
     if (dim == 2) hipLaunchKernelGGL(k_asm_momentum<2>, GRID(nt), 0, s, c, t);
     else hipLaunchKernelGGL(k_asm_momentum<3>, GRID(nt), 0, s, c, t);
 }
-void launch_asm_transport(int dim, const CaseDev *c, const Tile *t, int nt, int vel_src, hipStream_t s)
+void launch_asm_transport(int dim, const CaseDev *c, const Tile *t, int nt, int vel_src, hipStream_t s, int fwd)
 {
     if (nt <= 0) return;
+    if (fwd) {
+        if (dim == 2) hipLaunchKernelGGL(k_fwd_transport<2>, GRID(nt), 0, s, c, t, vel_src);
+        else hipLaunchKernelGGL(k_fwd_transport<3>, GRID(nt), 0, s, c, t, vel_src);
+        return;
+    }
     if (dim == 2) hipLaunchKernelGGL(k_asm_transport<2>, GRID(nt), 0, s, c, t, vel_src);
     else hipLaunchKernelGGL(k_asm_transport<3>, GRID(nt), 0, s, c, t, vel_src);
 }

@@ -5,8 +5,10 @@
 namespace sol {
 
 void launch_asm_const(int dim, const CaseDev *c, const Tile *t, int nt, hipStream_t s);
-void launch_asm_momentum(int dim, const CaseDev *c, const Tile *t, int nt, hipStream_t s);
-void launch_asm_transport(int dim, const CaseDev *c, const Tile *t, int nt, int vel_src, hipStream_t s);
+// fwd: the forward (residual-probing) assembly kernels instead of the
+// stencil kernels (same systems, up to rounding)
+void launch_asm_momentum(int dim, const CaseDev *c, const Tile *t, int nt, hipStream_t s, int fwd = 0);
+void launch_asm_transport(int dim, const CaseDev *c, const Tile *t, int nt, int vel_src, hipStream_t s, int fwd = 0);
 void launch_div_rhs(int dim, const CaseDev *c, const Tile *t, int nt, int vel_src, hipStream_t s);
 void launch_sub_mean(const CaseDev *c, const Tile *t, int nt, hipStream_t s);
 void launch_project(const CaseDev *c, const Tile *t, int nt, hipStream_t s);
