@@ -1,7 +1,8 @@
 """GPU parity of the HIP path (through the C ABI) against the FP64 oracle.
 
-Bars: sparsity patterns bit-exact; assembled values within 16 ulp of the row
-scale (same formulas, different summation order); fields after N steps
+Bars: sparsity patterns bit-exact; assembled values within 4 ulp of the row
+scale (summed over the row's entries; same formulas, different summation
+order and fused multiply-adds); fields after N steps
 within 1e-9 relative L2 (solver tolerance 1e-13 on both sides, so the
 Krylov stopping points cannot separate them); full-size workloads checked
 stage by stage on the oracle's own assembly of the GPU's inputs."""
@@ -85,11 +86,14 @@ def compare_system(sol_case, orc, sysid, vel):
     A, b, orp, oci = orc.assemble(sysid, vel=vel)
     assert np.array_equal(rp, orp), f"row_ptr differs for system {sysid}"
     assert np.array_equal(ci, oci), f"col_idx differs for system {sysid}"
-    scale = np.add.reduceat(np.abs(A.data), A.indptr[:-1]) + np.abs(b) if A.shape[0] else np.zeros(0)
+    if not A.shape[0]:
+        return 0.0
+    scale = np.add.reduceat(np.abs(A.data), A.indptr[:-1]) + np.abs(b)
     dv = np.abs(va - A.data)
-    drow = np.add.reduceat(dv, A.indptr[:-1]) if A.shape[0] else np.zeros(0)
-    assert np.all(drow <= 16 * EPS * scale), (sysid, (drow / scale).max())
-    assert np.all(np.abs(rhs - b) <= 16 * EPS * scale), (sysid, (np.abs(rhs - b) / scale).max())
+    drow = np.add.reduceat(dv, A.indptr[:-1])
+    ulps = max((drow / scale).max(), (np.abs(rhs - b) / scale).max()) / EPS
+    assert ulps <= 4.0, (sysid, ulps)
+    return ulps
 
 
 def _cases_small():
@@ -115,10 +119,12 @@ def test_assembly_pattern_and_values(sol, dev, case):
     g.assemble(0x3F)
     orc = oracle.Oracle(case, fields=f)
     vel = (f["u"], f["v"], f["w"] if f["w"].size else np.zeros(1))
+    worst = {}
     for s in range(6):
         if case["grid"]["dim"] == 2 and s == 2:
             continue
-        compare_system(g, orc, s, vel if s >= 3 else None)
+        worst[s] = round(compare_system(g, orc, s, vel if s >= 3 else None), 2)
+    print("assembly vs oracle, ulp of the row scale per system:", worst)
     g.close()
 
 
@@ -405,10 +411,12 @@ def _stagewise(sol, dev, case, tag, precond="mg"):
     orc2 = oracle.Oracle(case, fields=f1)
     orc2.step_index = st["step"]
     vel = (f1["u"], f1["v"], f1["w"] if f1["w"].size else np.zeros(1))
+    worst = {}
     for s in range(6):
         if case["grid"]["dim"] == 2 and s == 2:
             continue
-        compare_system(g, orc2, s, vel if s >= 3 else None)
+        worst[s] = round(compare_system(g, orc2, s, vel if s >= 3 else None), 2)
+    print(f"{tag}: assembly vs oracle, ulp of the row scale per system:", worst)
     g.close()
 
 
