@@ -82,7 +82,11 @@ __device__ __forceinline__ void put_partials(double (&v)[K], double *part, const
 }
 
 // out[k] = sum_{q < ntile} part[off[k] + q], identical in every thread and
-// every workgroup
+// every workgroup: thread t adds q = t, t + 256, ... in that order, each
+// wave adds its lanes in the fixed DPP tree, and after one barrier every
+// thread adds the four wave totals in wave order.  (Broadcasting a total
+// from thread 0 took two more barriers, each of which also waits for every
+// load the waves have in flight.)
 template <int K>
 __device__ __forceinline__ void sum_partials(const double *part, const int (&off)[K], int ntile, double (&out)[K])
 {
@@ -94,15 +98,29 @@ __device__ __forceinline__ void sum_partials(const double *part, const int (&off
 #pragma unroll
         for (int k = 0; k < K; ++k) acc[k] += part[off[k] + q];
     }
-    block_sum<K>(acc, sh);
-    if (threadIdx.x == 0) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
-        for (int k = 0; k < K; ++k) sh[k] = acc[k];
+    for (int k = 0; k < K; ++k) acc[k] = wave_sum(acc[k]);
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) sh[w * K + k] = acc[k];
     }
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < K; ++k) out[k] = sh[k];
-    __syncthreads();
+    for (int k = 0; k < K; ++k) out[k] = (sh[k] + sh[K + k]) + (sh[2 * K + k] + sh[3 * K + k]);
+}
+
+// two consecutive elements of a vector (T = double or float) in one load;
+// i must be even and the vector 2 sizeof(T)-aligned
+template <class T>
+struct Pair { T x, y; };
+template <class T>
+__device__ __forceinline__ Pair<T> load_pair(const void *base, int i)
+{
+    typedef T V __attribute__((ext_vector_type(2)));
+    const V v = *(const __attribute__((address_space(1))) V *)((const __attribute__((address_space(1))) char *)base +
+                                                                (unsigned)i * (unsigned)sizeof(T));
+    return Pair<T>{v.x, v.y};
 }
 
 // neighbour offset of DIA slot s (slot order -sxy, -sx, -1, 0, +1, +sx, +sxy)

@@ -367,6 +367,8 @@ __global__ __launch_bounds__(TILE) void k_mg_init(const KJob *__restrict__ jobs,
 
 // ------------------------------------------------------------- iteration
 
+// pq(k).  On a grid with an even x count the two children of a window row
+// come in one 16-byte (FP32: 8-byte) load.
 template <int DIM, class T>
 __global__ __launch_bounds__(TILE) void k_mg_pq(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles,
                                                 const int *kbase, int koff)
@@ -378,6 +380,70 @@ __global__ __launch_bounds__(TILE) void k_mg_pq(const KJob *__restrict__ jobs, c
     KState *st = J.st;
     const int pk = k & 1, pm = (k + 1) & 1;
     const bool first = k == st->k0;
+    const MLevel &L = J.lev[0];
+    const double icx = 1.0 / L.cnx, icxy = 1.0 / ((double)L.cnx * L.cny);
+    const void *zb = J.v0, *pb = pm ? J.p1 : J.p0;
+    auto z = R<T>(zb);
+    auto q = G<T>(J.v1);
+    auto po = R<T>(pb);
+    auto pn = G<T>(pk ? J.p1 : J.p0);
+    const bool pairs = (L.nx & 1) == 0;
+    const int I0 = tl.t * L.cpt, I1 = min(L.cn, I0 + L.cpt);
+    int I = I0 + threadIdx.x;
+    // raw window values: zr = z, pr = p_(k-1) on the window cells
+    constexpr int WN = DIM == 2 ? W2 : W3;
+    T zr[DIM == 3 ? W3 : 1][WN][WN], pr[DIM == 3 ? W3 : 1][WN][WN];
+    auto load_window = [&](int Ia) {
+        const Agg<DIM> ag = agg_of<DIM>(L, Ia, icx, icxy);
+        if constexpr (DIM == 2) {
+            // the 12 cells within one step of the 2 x 2 children (positions 1..4)
+            const int X0 = 2 * ag.c[0] - 2, Y0 = 2 * ag.c[1] - 2;
+#pragma unroll
+            for (int vy = 1; vy < W2 - 1; ++vy) {
+                const int row = L.nx * min(max(Y0 + vy, 0), L.ny - 1);
+                if (pairs && 2 * ag.c[0] + 1 < L.nx) {
+                    const Pair<T> zz = load_pair<T>(zb, row + 2 * ag.c[0]), pp = load_pair<T>(pb, row + 2 * ag.c[0]);
+                    zr[0][vy][2] = zz.x; zr[0][vy][3] = zz.y; pr[0][vy][2] = pp.x; pr[0][vy][3] = pp.y;
+                } else {
+#pragma unroll
+                    for (int ux = 2; ux < 4; ++ux) {
+                        const int j = win_idx(L, X0 + ux, Y0 + vy);
+                        zr[0][vy][ux] = z[j]; pr[0][vy][ux] = po[j];
+                    }
+                }
+                if (vy == 2 || vy == 3) {
+                    const int jm = win_idx(L, X0 + 1, Y0 + vy), jp = win_idx(L, X0 + 4, Y0 + vy);
+                    zr[0][vy][1] = z[jm]; pr[0][vy][1] = po[jm];
+                    zr[0][vy][4] = z[jp]; pr[0][vy][4] = po[jp];
+                }
+            }
+        } else {
+            // the 8 children and their 24 face neighbours (positions 0..3)
+            const int X0 = 2 * ag.c[0] - 1, Y0 = 2 * ag.c[1] - 1, Z0 = 2 * ag.c[2] - 1;
+#pragma unroll
+            for (int w = 0; w < W3; ++w)
+#pragma unroll
+                for (int v2 = 0; v2 < W3; ++v2) {
+                    if (wdist3(1, v2, w) > 1) continue;
+                    const int row = L.nx * (min(max(Y0 + v2, 0), L.ny - 1) + L.ny * min(max(Z0 + w, 0), L.nz - 1));
+                    if (pairs && 2 * ag.c[0] + 1 < L.nx) {
+                        const Pair<T> zz = load_pair<T>(zb, row + 2 * ag.c[0]), pp = load_pair<T>(pb, row + 2 * ag.c[0]);
+                        zr[w][v2][1] = zz.x; zr[w][v2][2] = zz.y; pr[w][v2][1] = pp.x; pr[w][v2][2] = pp.y;
+                    } else {
+#pragma unroll
+                        for (int u = 1; u < 3; ++u) {
+                            const int j = win3_idx(L, X0 + u, Y0 + v2, Z0 + w);
+                            zr[w][v2][u] = z[j]; pr[w][v2][u] = po[j];
+                        }
+                    }
+                    if (wdist3(0, v2, w) <= 1) {
+                        const int jm = win3_idx(L, X0, Y0 + v2, Z0 + w), jp = win3_idx(L, X0 + 3, Y0 + v2, Z0 + w);
+                        zr[w][v2][0] = z[jm]; pr[w][v2][0] = po[jm];
+                        zr[w][v2][3] = z[jp]; pr[w][v2][3] = po[jp];
+                    }
+                }
+        }
+    };
     double s5[5];
     {
         const int off[5] = {poff(J, pk, PS_RHO), poff(J, pk, PS_RR), poff(J, pk, PS_BB), poff(J, pk, PS_Q),
@@ -394,20 +460,13 @@ __global__ __launch_bounds__(TILE) void k_mg_pq(const KJob *__restrict__ jobs, c
     const double beta = first ? 0.0 : gam / st->gamma[pm];
     if (tl.t == 0 && threadIdx.x == 0) st->gamma[pk] = gam;
     const T tb = (T)beta, tz = (T)zbar;
-    const MLevel &L = J.lev[0];
-    const double icx = 1.0 / L.cnx, icxy = 1.0 / ((double)L.cnx * L.cny);
-    auto z = R<T>(J.v0);
-    auto q = G<T>(J.v1);
-    auto po = R<T>(pm ? J.p1 : J.p0);
-    auto pn = G<T>(pk ? J.p1 : J.p0);
     double v = 0.0;
-    const int I0 = tl.t * L.cpt, I1 = min(L.cn, I0 + L.cpt);
-    if constexpr (DIM == 2) {
-        // p on the children and their neighbours (the 2D window within one
-        // step of the children: positions 1..4), then q = A p at the children
-        const T c0 = (T)L.ih2[0], c1 = (T)L.ih2[1];
-        for (int I = I0 + threadIdx.x; I < I1; I += TILE) {
-            const Agg<DIM> a = agg_of<DIM>(L, I, icx, icxy);
+    for (; I < I1; I += TILE) {
+        load_window(I);
+        const Agg<DIM> a = agg_of<DIM>(L, I, icx, icxy);
+        if constexpr (DIM == 2) {
+            // p on the children and their neighbours, then q = A p at the children
+            const T c0 = (T)L.ih2[0], c1 = (T)L.ih2[1];
             const int X0 = 2 * a.c[0] - 2, Y0 = 2 * a.c[1] - 2;
             T f[W2][W2];
 #pragma unroll
@@ -415,8 +474,7 @@ __global__ __launch_bounds__(TILE) void k_mg_pq(const KJob *__restrict__ jobs, c
 #pragma unroll
                 for (int ux = 1; ux < W2 - 1; ++ux) {
                     if (wdist(ux, vy) > 1) continue;
-                    const int j = win_idx(L, X0 + ux, Y0 + vy);
-                    f[vy][ux] = (z[j] - tz) + tb * po[j];
+                    f[vy][ux] = (zr[0][vy][ux] - tz) + tb * pr[0][vy][ux];
                 }
 #pragma unroll
             for (int vy = 2; vy < 4; ++vy)
@@ -430,11 +488,8 @@ __global__ __launch_bounds__(TILE) void k_mg_pq(const KJob *__restrict__ jobs, c
                     q[i] = qv;
                     v += (double)f[vy][ux] * qv;
                 }
-        }
-    } else if constexpr (DIM == 3) {
-        const T c0 = (T)L.ih2[0], c1 = (T)L.ih2[1], c2 = (T)L.ih2[2];
-        for (int I = I0 + threadIdx.x; I < I1; I += TILE) {
-            const Agg<DIM> a = agg_of<DIM>(L, I, icx, icxy);
+        } else {
+            const T c0 = (T)L.ih2[0], c1 = (T)L.ih2[1], c2 = (T)L.ih2[2];
             const int X0 = 2 * a.c[0] - 1, Y0 = 2 * a.c[1] - 1, Z0 = 2 * a.c[2] - 1;
             T f[W3][W3][W3];
 #pragma unroll
@@ -444,8 +499,7 @@ __global__ __launch_bounds__(TILE) void k_mg_pq(const KJob *__restrict__ jobs, c
 #pragma unroll
                     for (int u = 0; u < W3; ++u) {
                         if (wdist3(u, v2, w) > 1) continue;
-                        const int j = win3_idx(L, X0 + u, Y0 + v2, Z0 + w);
-                        f[w][v2][u] = (z[j] - tz) + tb * po[j];
+                        f[w][v2][u] = (zr[w][v2][u] - tz) + tb * pr[w][v2][u];
                     }
 #pragma unroll
             for (int w = 1; w < 3; ++w)
@@ -500,9 +554,12 @@ __global__ __launch_bounds__(TILE) void k_mg_down0(const KJob *__restrict__ jobs
     auto x = G<T>(J.x);
     auto p = R<T>(pk ? J.p1 : J.p0);
     auto q = R<T>(J.v1);
-    auto rc = R<T>(pk ? J.rh : J.r);
-    auto rn = G<T>(pn1 ? J.rh : J.r);
+    const void *rcb = pk ? J.rh : J.r;
+    void *rnb = pn1 ? J.rh : J.r;
+    auto rc = R<T>(rcb);
+    auto rn = G<T>(rnb);
     auto bc = G<T>(J.lev[1].b);
+    const bool pairs = (L.nx & 1) == 0;
     double rr = 0.0;
     const int I0 = tl.t * L.cpt, I1 = min(L.cn, I0 + L.cpt);
     if constexpr (DIM == 2) {
@@ -559,18 +616,40 @@ __global__ __launch_bounds__(TILE) void k_mg_down0(const KJob *__restrict__ jobs
             const Agg<DIM> a = agg_of<DIM>(L, I, icx, icxy);
             const int X0 = 2 * a.c[0] - 1, Y0 = 2 * a.c[1] - 1, Z0 = 2 * a.c[2] - 1;
             T rw[W3][W3][W3], f1[W3][W3][W3];
+            auto cell = [&](int wz, int vy, int ux, T rv, T qv, T mv) {
+                const T rj = INIT ? rv : rv - ta * qv;
+                rw[wz][vy][ux] = rj;
+                f1[wz][vy][ux] = w * mv * rj;
+            };
 #pragma unroll
             for (int wz = 0; wz < W3; ++wz)
 #pragma unroll
-                for (int vy = 0; vy < W3; ++vy)
+                for (int vy = 0; vy < W3; ++vy) {
+                    if (wdist3(1, vy, wz) > 1) continue;
+                    if (pairs && 2 * a.c[0] + 1 < L.nx) {
+                        // the window row's two children in one load per vector
+                        const int j = L.nx * (min(max(Y0 + vy, 0), L.ny - 1) + L.ny * min(max(Z0 + wz, 0), L.nz - 1)) +
+                                      2 * a.c[0];
+                        const Pair<T> rr2 = load_pair<T>(INIT ? (const void *)rnb : rcb, j);
+                        const Pair<T> qq2 = INIT ? Pair<T>{T(0), T(0)} : load_pair<T>(J.v1, j);
+                        const Pair<T> mm2 = load_pair<T>(J.minv, j);
+                        cell(wz, vy, 1, rr2.x, qq2.x, mm2.x);
+                        cell(wz, vy, 2, rr2.y, qq2.y, mm2.y);
+                    } else {
 #pragma unroll
-                    for (int ux = 0; ux < W3; ++ux) {
-                        if (wdist3(ux, vy, wz) > 1) continue;
-                        const int j = win3_idx(L, X0 + ux, Y0 + vy, Z0 + wz);
-                        const T rj = INIT ? rn[j] : rc[j] - ta * q[j];
-                        rw[wz][vy][ux] = rj;
-                        f1[wz][vy][ux] = w * mi[j] * rj;
+                        for (int ux = 1; ux < 3; ++ux) {
+                            const int j = win3_idx(L, X0 + ux, Y0 + vy, Z0 + wz);
+                            cell(wz, vy, ux, INIT ? rn[j] : rc[j], INIT ? T(0) : q[j], mi[j]);
+                        }
                     }
+                    if (wdist3(0, vy, wz) <= 1) {
+#pragma unroll
+                        for (int ux = 0; ux < W3; ux += 3) {
+                            const int j = win3_idx(L, X0 + ux, Y0 + vy, Z0 + wz);
+                            cell(wz, vy, ux, INIT ? rn[j] : rc[j], INIT ? T(0) : q[j], mi[j]);
+                        }
+                    }
+                }
             T bsum = T(0);
 #pragma unroll
             for (int wz = 1; wz < 3; ++wz)
