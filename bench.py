@@ -366,6 +366,8 @@ def main():
     ap.add_argument("--tprecond", default=None, choices=["jacobi", "jacobi2", "auto"],
                     help="BiCGSTAB preconditioner: one or two Jacobi sweeps, or the library's default "
                          "(auto: two in 2D, one in 3D)")
+    ap.add_argument("--batch-only", choices=["mixed", "fp64"], default=None,
+                    help="run only the 64-cavity batch (300 steps) in this precision and print its line")
     ap.add_argument("--copy-reference", action="store_true",
                     help="run only the plain 256 MiB device copy used to calibrate the traffic counters")
     args = ap.parse_args()
@@ -384,6 +386,10 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = sol.TorchDevice(0)
+    if args.batch_only:
+        v = run_batched(sol, W, args.batch_only, args.steps or 300, args.warmup, dev, tune=args.batch_only == "mixed")
+        print(json.dumps(v))
+        return
     steps = args.steps or W.WORKLOADS[args.workload]["steps"]
     acc_steps = 2 if args.workload == "C3" else 5
     keep = acc_steps if not args.no_cpu_baseline else None
