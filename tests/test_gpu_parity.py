@@ -191,12 +191,15 @@ def test_steps_match_oracle(sol, dev, name, case, nsteps, precond):
 @pytest.mark.parametrize("precond", PRECONDS)
 def test_wide_rows_match_oracle(sol, dev, precond):
     """Rows 1200 cells long: a two-sweep tile's neighbourhood exceeds the LDS
-    budget in FP64, so the 2D solves take the per-row gather path.  The
-    sliver (1200 x 3 cells) solves its pressure near the FP64 floor: the
-    oracle itself moves by 0.5-1e-9 in u, v, p between tolerances 1e-13 and
-    5e-14 on such domains, so the velocity and pressure gate is 1e-8; T, C
-    and the phase fields are gated at 1e-12."""
-    case = W.cavity_2d(1200, 3, lx=0.12, ly=0.0003, tol=1e-13, seed=9)
+    budget in FP64, so the 2D solves take the per-row gather path.  Every
+    field within 1e-9, with the pressure solved to 5e-14 and the transport
+    systems to 1e-14 on both sides: the oracle alone moves by 7.6e-11 (v)
+    between pressure tolerances 1e-13 and 5e-14 on this sliver and by 1.3e-11
+    between 5e-14 and 7e-14, while at 1e-13 the library's solves, stopping
+    at their own points of that band, left v up to 1.0e-9 away; 1e-15 for the
+    transport systems is below the sliver's FP64 floor."""
+    case = W.cavity_2d(1200, 3, lx=0.12, ly=0.0003, tol=5e-14, seed=9)
+    case["numerics"]["tol_t"] = 1e-14
     print(f"[gpu] wide rows 1200x3 ({precond})", flush=True)
     g = make(sol, dev, case, precond)
     o = oracle.Oracle(case)
@@ -205,9 +208,10 @@ def test_wide_rows_match_oracle(sol, dev, precond):
     errs = field_errors(g.read_fields(), o.fields())
     print("rel L2", {k: f"{v:.1e}" for k, v in errs.items()}, flush=True)
     assert max(errs[k] for k in ("T", "C", "gl", "Cl", "Cs")) < 1e-12, errs
-    assert max(errs.values()) < 1e-8, errs
+    for k, e in errs.items():
+        assert e < 1e-9, (k, errs)
     for s in range(6):
-        assert st["rel_resid"][s] <= 1e-13 * (1 + 1e-6)
+        assert st["rel_resid"][s] <= (5e-14 if s == 3 else 1e-14) * (1 + 1e-6)
     g.close()
 
 
