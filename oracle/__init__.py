@@ -53,6 +53,7 @@ class _Case(C.Structure):
         ("dt", C.c_double), ("tol_p", C.c_double), ("tol_t", C.c_double),
         ("max_iter", C.c_int32), ("literal_ag_order", C.c_int32),
         ("D_l", C.c_double),
+        ("mom_form", C.c_int32),
     ]
 
 
@@ -138,6 +139,7 @@ def make_case_struct(case: dict, literal_ag_order: bool = False) -> _Case:
     s.max_iter = nm["max_iter"]
     s.literal_ag_order = 1 if literal_ag_order else 0
     s.D_l = float(al.get("D_l", 0.0) or 0.0)
+    s.mom_form = int(case.get("momentum", 0))
     return s
 
 

@@ -69,7 +69,11 @@ def _upwind_flux(vel, phi_minus, phi_plus):
 
 
 def eq_momentum(case, fields, d, phi):
-    """Residual of eq. (3.3) for velocity component d: A phi - b."""
+    """Residual of eq. (3.3) for velocity component d: A phi - b.  With the
+    momentum form of eq. (2.6) (case["momentum"] == 1) the convection is
+    that of the advecting velocity u/g~ and the pressure gradient, the drag
+    and the force carry g (g: g_l on the face, the mean of its two cells;
+    g~ = max(g, darcy_eps^(1/3)), the reading of the stencil oracle)."""
     G = Geometry(case)
     al, nm, bcs = case["alloy"], case["numerics"], case["bcs"]
     nu = al["mu"] / al["rho"]
@@ -78,6 +82,16 @@ def eq_momentum(case, fields, d, phi):
     phi = np.asarray(phi, dtype=np.float64).reshape(shp)
     un = np.asarray(fields["uvw"[d]], dtype=np.float64).reshape(shp)
     vel = [G.full_face(fields["uvw"[a]], a) if a < G.dim else None for a in range(3)]
+    # the upwind choice depends on the sign of the advecting velocity only,
+    # so the flux difference divided by g~ > 0 is the convection of u/g~
+    gl = np.asarray(fields["gl"], dtype=np.float64).reshape(G.cell_shape)
+    gf = 0.5 * (_take(gl, d, slice(0, -1)) + _take(gl, d, slice(1, None)))
+    if int(case.get("momentum", 0)) == 1:
+        gt = np.maximum(gf, np.cbrt(al["darcy_eps"]))
+        gw = gf
+    else:
+        gt = np.ones_like(gf)
+        gw = np.ones_like(gf)
     res = (phi - un) / dt
     phi_full = _pad(phi, d, 1, 1)          # face numbers 0..n_d, walls 0
     for a in range(G.dim):
@@ -88,7 +102,7 @@ def eq_momentum(case, fields, d, phi):
             vcv = 0.5 * (_take(vf, d, slice(0, -1)) + _take(vf, d, slice(1, None)))
             flux = _upwind_flux(vcv, _take(phi_full, d, slice(0, -1)),
                                 _take(phi_full, d, slice(1, None)))
-            res = res + (_take(flux, d, slice(1, None)) - _take(flux, d, slice(0, -1))) / h
+            res = res + ((_take(flux, d, slice(1, None)) - _take(flux, d, slice(0, -1))) / h) / gt
             grad = (_take(phi_full, d, slice(1, None)) - _take(phi_full, d, slice(0, -1))) / h
             lap = (_take(grad, d, slice(1, None)) - _take(grad, d, slice(0, -1))) / h
             res = res - nu * lap
@@ -99,7 +113,7 @@ def eq_momentum(case, fields, d, phi):
             vcv = 0.5 * (_take(va, d, slice(0, -1)) + _take(va, d, slice(1, None)))
             php = _pad(phi, a, 1, 1)
             flux = _upwind_flux(vcv, _take(php, a, slice(0, -1)), _take(php, a, slice(1, None)))
-            res = res + (_take(flux, a, slice(1, None)) - _take(flux, a, slice(0, -1))) / h
+            res = res + ((_take(flux, a, slice(1, None)) - _take(flux, a, slice(0, -1))) / h) / gt
             inner = (_take(phi, a, slice(1, None)) - _take(phi, a, slice(0, -1))) / h
             lo_wall = 2.0 * _take(phi, a, slice(0, 1)) / h        # (phi - 0)/(h/2)
             hi_wall = -2.0 * _take(phi, a, slice(-1, None)) / h    # (0 - phi)/(h/2)
@@ -111,13 +125,11 @@ def eq_momentum(case, fields, d, phi):
             lap = (_take(grad, a, slice(1, None)) - _take(grad, a, slice(0, -1))) / h
             res = res - nu * lap
     # Carman-Kozeny drag on the face, eq. (2.8)
-    gl = np.asarray(fields["gl"], dtype=np.float64).reshape(G.cell_shape)
-    gf = 0.5 * (_take(gl, d, slice(0, -1)) + _take(gl, d, slice(1, None)))
     kinv = 180.0 * (1.0 - gf) ** 2 / (al["lambda2"] ** 2 * (gf ** 3 + al["darcy_eps"]))
-    res = res + nu * kinv * phi
+    res = res + nu * gt * kinv * phi
     # pressure gradient at level n
     p = np.asarray(fields["p"], dtype=np.float64).reshape(G.cell_shape)
-    res = res + (_take(p, d, slice(1, None)) - _take(p, d, slice(0, -1))) / (al["rho"] * G.h[d])
+    res = res + gw * (_take(p, d, slice(1, None)) - _take(p, d, slice(0, -1))) / (al["rho"] * G.h[d])
     # Boussinesq force on the vertical component, eq. (2.9)
     if d == G.dim - 1:
         T = np.asarray(fields["T"], dtype=np.float64).reshape(G.cell_shape)
@@ -125,7 +137,7 @@ def eq_momentum(case, fields, d, phi):
         Tf = 0.5 * (_take(T, d, slice(0, -1)) + _take(T, d, slice(1, None)))
         Cf = 0.5 * (_take(Cl, d, slice(0, -1)) + _take(Cl, d, slice(1, None)))
         f = al["g"] * (al["beta_T"] * (Tf - al["T_ref"]) + al["beta_C"] * (Cf - al["C_ref"]))
-        res = res - f
+        res = res - gw * f
     return res.ravel()
 
 

@@ -18,8 +18,9 @@
  *   - central fully implicit diffusion, eq. (3.26); implicit first-order upwind
  *     convection in flux form, eqs. (3.27)-(3.28) and the coefficient rows of
  *     eq. (4.4);
- *   - momentum predictor eq. (3.3) (momentum form 2.7) with Carman-Kozeny
- *     drag eq. (2.8) and Boussinesq force eq. (2.9);
+ *   - momentum predictor eq. (3.3) (momentum form 2.7, or the minimal
+ *     model's form 2.6 on request) with Carman-Kozeny drag eq. (2.8) and
+ *     Boussinesq force eq. (2.9);
  *   - pressure-correction Poisson eq. (3.4) and projection eq. (3.5);
  *   - matrix-based solute transport eqs. (3.6), (3.8)-(3.10), with the
  *     liquid diffusion of eq. (3.7) when D_l > 0;
@@ -46,6 +47,7 @@
 enum { SYS_U = 0, SYS_V = 1, SYS_W = 2, SYS_P = 3, SYS_C = 4, SYS_T = 5, NSYS = 6 };
 enum { TH_ADIABATIC = 0, TH_ROBIN = 1, TH_DIRICHLET = 2 };
 enum { VEL_NOSLIP = 0, VEL_FREESLIP = 1 };
+enum { MOM_PLAIN = 0, MOM_MINIMAL = 1 };   /* momentum form: eq. (2.7) / eq. (2.6) */
 
 typedef struct {
     int32_t dim, nx, ny, nz;
@@ -66,6 +68,9 @@ typedef struct {
     int32_t literal_ag_order;
     /* liquid solute diffusivity D_l of eq. (3.7); 0 = the minimal model */
     double D_l;
+    /* momentum form of the predictor: MOM_PLAIN, eq. (2.7) (the form the
+       scheme's eq. 3.3 discretises), or MOM_MINIMAL, eq. (2.6) */
+    int32_t mom_form;
 } oc_case;
 
 typedef struct {
@@ -209,7 +214,19 @@ static double darcy(const oc_case *c, double g)
    the unknown act through a half-cell ghost (2 nu / h^2 on the diagonal);
    free-slip walls carry no shear; a wall-normal neighbour is a Dirichlet 0;
    Boussinesq force on the vertical component only, hydrostatic part dropped,
-   T and C_l at level n averaged onto the face. */
+   T and C_l at level n averaged onto the face.
+   Momentum form (2.6) (mom_form = MOM_MINIMAL): the same predictor with the
+   advecting velocity u/g_l, the pressure gradient, the drag and the force
+   multiplied by g_l:
+     A = I/dt + Conv(u^n / g~) - nu Lap + (mu/rho) g~ K^{-1}(g)
+     b = u^n/dt - (g/rho) d p^n / dx_d + g f_d
+   readings: g is g_l^n on the face, the mean of its two cells (as for the
+   drag of eq. 2.8);  g~ = max(g, darcy_eps^(1/3)), the liquid fraction below
+   which the regularisation of g^3 in eq. (2.8) dominates, so that 1/g~
+   stays finite and the drag g~ K^{-1} stays large in solid cells (with g
+   itself it would vanish there);  the pressure correction and the
+   projection, eqs. (3.4)-(3.5), are unchanged, so a steady state (phi = 0)
+   satisfies the discrete (2.6). */
 static void assemble_momentum(const oc_case *c, const oc_fields *f, int d, oc_csr *m)
 {
     int n[3], sd[3];
@@ -218,6 +235,8 @@ static void assemble_momentum(const oc_case *c, const oc_fields *f, int d, oc_cs
     double *const vel[3] = {f->u, f->v, f->w};
     const double nu = c->mu / c->rho;
     const int vert = c->dim - 1;
+    const int minimal = c->mom_form == MOM_MINIMAL;
+    const double gfloor = cbrt(c->darcy_eps);
     int pos = 0;
     m->row_ptr[0] = 0;
     for (int k = 0; k < sd[2]; ++k)
@@ -230,6 +249,9 @@ static void assemble_momentum(const oc_case *c, const oc_fields *f, int d, oc_cs
         lo[d] = F - 1; hi[d] = F;         /* the two cells sharing the face */
         int clo = lin(n, lo[0], lo[1], lo[2]);
         int chi = lin(n, hi[0], hi[1], hi[2]);
+        double gf = 0.5 * (f->gl[clo] + f->gl[chi]);
+        double gt = minimal ? dmax(gf, gfloor) : 1.0;   /* g~ of form (2.6) */
+        double gw = minimal ? gf : 1.0;                 /* g on p and f   */
         row_t r;
         row_clear(&r);
         for (int a = 0; a < c->dim; ++a) {
@@ -239,7 +261,7 @@ static void assemble_momentum(const oc_case *c, const oc_fields *f, int d, oc_cs
                 /* neighbours: faces F-1 and F+1 along d */
                 double vm = 0.5 * (face_vel(c, vel, d, lo, F - 1) + face_vel(c, vel, d, lo, F));
                 double vp = 0.5 * (face_vel(c, vel, d, lo, F) + face_vel(c, vel, d, lo, F + 1));
-                upwind(vm, vp, h, &cw, &cp, &ce);
+                upwind(vm / gt, vp / gt, h, &cw, &cp, &ce);
                 r.has[a][0] = (q[a] >= 1);
                 r.has[a][1] = (q[a] <= sd[a] - 2);
                 r.diag += 2.0 * nu / (h * h) + cp;
@@ -250,7 +272,7 @@ static void assemble_momentum(const oc_case *c, const oc_fields *f, int d, oc_cs
                    control-volume faces = mean over the two cells lo/hi */
                 double vm = 0.5 * (face_vel(c, vel, a, lo, q[a]) + face_vel(c, vel, a, hi, q[a]));
                 double vp = 0.5 * (face_vel(c, vel, a, lo, q[a] + 1) + face_vel(c, vel, a, hi, q[a] + 1));
-                upwind(vm, vp, h, &cw, &cp, &ce);
+                upwind(vm / gt, vp / gt, h, &cw, &cp, &ce);
                 r.diag += cp;
                 for (int s = 0; s < 2; ++s) {
                     int exists = s == 0 ? (q[a] >= 1) : (q[a] <= sd[a] - 2);
@@ -264,15 +286,14 @@ static void assemble_momentum(const oc_case *c, const oc_fields *f, int d, oc_cs
                 }
             }
         }
-        double gf = 0.5 * (f->gl[clo] + f->gl[chi]);
-        r.diag += 1.0 / c->dt + darcy(c, gf);
-        r.rhs = vel[d][row] / c->dt - (f->p[chi] - f->p[clo]) / (c->rho * h_of(c, d));
+        r.diag += 1.0 / c->dt + gt * darcy(c, gf);
+        r.rhs = vel[d][row] / c->dt - gw * ((f->p[chi] - f->p[clo]) / (c->rho * h_of(c, d)));
         if (d == vert) {
             double Tf = 0.5 * (f->T[clo] + f->T[chi]);
             double Cf = 0.5 * (f->Cl[clo] + f->Cl[chi]);
             /* f = g(1 - beta_T (T - T_ref) - beta_C (C_l - C_ref)) along -z:
                vertical component without the hydrostatic part */
-            r.rhs += c->grav * (c->beta_T * (Tf - c->T_ref) + c->beta_C * (Cf - c->C_ref));
+            r.rhs += gw * (c->grav * (c->beta_T * (Tf - c->T_ref) + c->beta_C * (Cf - c->C_ref)));
         }
         csr_put(m, sd, row, &r, &pos);
     }

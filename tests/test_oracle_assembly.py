@@ -38,10 +38,14 @@ def _cases():
     # liquid solute diffusion (eq. 3.7), large enough to dominate the solute rows
     c2d = W.cavity_2d(7, 5, alloy=W.sn10pb_alloy(D_l=2e-4))
     c3d = W.box_3d(5, 4, 3, lx=0.05, ly=0.04, lz=0.03, alloy=W.sn10pb_alloy(D_l=2e-4))
-    return [c2, c2fs, c3, c2d, c3d]
+    # momentum form (2.6); the perturbed g_l spans solid cells and the floor
+    c2m = W.with_momentum(c2fs, W.MOMENTUM_MINIMAL)
+    c3m = W.with_momentum(c3, W.MOMENTUM_MINIMAL)
+    return [c2, c2fs, c3, c2d, c3d, c2m, c3m]
 
 
-@pytest.mark.parametrize("case", _cases(), ids=["2d", "2d-freeslip-dirichlet", "3d", "2d-Dl", "3d-Dl"])
+@pytest.mark.parametrize("case", _cases(), ids=["2d", "2d-freeslip-dirichlet", "3d", "2d-Dl", "3d-Dl",
+                                                "2d-mom26", "3d-mom26"])
 def test_forward_probe_equals_stencil_assembly(case):
     """Forward method (colour probes of a residual function) reproduces the
     directly assembled matrices and right-hand sides up to rounding."""

@@ -35,6 +35,9 @@ VELOCITY_FREESLIP = 1
 PRECISION_FP64 = 0
 PRECISION_MIXED = 1     # FP32 Krylov inside FP64 iterative refinement
 
+MOMENTUM_PLAIN = 0      # momentum form of eq. (2.7), the one the scheme's eq. (3.3) discretises
+MOMENTUM_MINIMAL = 1    # the minimal model's form, eq. (2.6)
+
 FIELD_NAMES = ("u", "v", "w", "p", "T", "C", "gl", "Cl", "Cs")
 
 
@@ -85,7 +88,7 @@ def face_bc(thermal=THERMAL_ADIABATIC, h=0.0, T_ext=0.0, T0=0.0, b=0.0,
 def make_case(dim, nx, ny, nz, lx, ly, lz, *, C0=10.0, alloy=None, bcs=None,
               dt=0.01, tol_p=1e-10, tol_t=1e-10, max_iter=200000,
               precision=PRECISION_FP64, seed=0, T0=None, dT_amp=0.1,
-              name="case") -> dict:
+              name="case", momentum=MOMENTUM_PLAIN) -> dict:
     """Return a case: parameters plus seeded initial fields.
 
     Initial state (a still, fully liquid melt): u = v = w = p = 0, C = C0,
@@ -93,7 +96,8 @@ def make_case(dim, nx, ny, nz, lx, ly, lz, *, C0=10.0, alloy=None, bcs=None,
     T = T0 + U(-dT_amp, dT_amp) drawn per cell in lexicographic order
     (x fastest) from numpy's default_rng(seed).  T0 defaults to the liquidus
     temperature at C0 (the examples start at T0 = T_l), computed from the
-    straight liquidus line T_m + m_sp C0 of the alloy.
+    straight liquidus line T_m + m_sp C0 of the alloy.  `momentum` selects
+    the momentum form (MOMENTUM_PLAIN or MOMENTUM_MINIMAL).
     """
     if dim == 2:
         nz, lz = 1, 1.0
@@ -128,7 +132,19 @@ def make_case(dim, nx, ny, nz, lx, ly, lz, *, C0=10.0, alloy=None, bcs=None,
     )
     return dict(name=name, grid=grid, alloy=alloy, bcs=bcs,
                 numerics=numerics, init=init, seed=int(seed), C0=float(C0),
-                T0=float(T0))
+                T0=float(T0), momentum=int(momentum))
+
+
+def momentum_form(case) -> int:
+    """Momentum form of a case (cases built before the key existed: PLAIN)."""
+    return int(case.get("momentum", MOMENTUM_PLAIN))
+
+
+def with_momentum(case, form) -> dict:
+    """Copy of `case` with the momentum form set (fields shared by value)."""
+    c = copy.deepcopy(case)
+    c["momentum"] = int(form)
+    return c
 
 
 def field_sizes(grid) -> dict:
