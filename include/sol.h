@@ -97,7 +97,8 @@ typedef struct { int32_t dim, nx, ny, nz; double lx, ly, lz; } sol_grid;  /* dim
    T = T_m + m_sp C_l (eq. 2.20), partition k_p (eq. 2.19), eutectic C_e.
    Boussinesq reference state T_ref, C_ref (eq. 2.9).  Carman-Kozeny drag
    with secondary arm spacing lambda2 and g^3 regularised by darcy_eps
-   (eq. 2.8).  D_l must be 0 (minimal model, eq. 3.6). */
+   (eq. 2.8).  D_l >= 0: liquid solute diffusivity of eq. (3.7) (0: no
+   diffusion, the minimal model's eq. 3.6). */
 typedef struct {
     double rho, mu, cp, k, latent, beta_T, beta_C, lambda2;
     double T_m, m_sp, k_p, C_e, T_ref, C_ref, g, D_l, darcy_eps;
@@ -328,6 +329,21 @@ int sol_get_timing(sol_handle *h, int32_t kclass, int64_t *launches, double *tot
 #define SOL_OPT_ASSEMBLY 4
 #define SOL_ASSEMBLY_STENCIL 0
 #define SOL_ASSEMBLY_FORWARD 1
+/* SOL_OPT_MOMENTUM: the momentum equation the predictor (eq. 3.3)
+   discretises.  SOL_MOMENTUM_PLAIN (default): eq. (2.7), the form of the
+   scheme.  SOL_MOMENTUM_MINIMAL: eq. (2.6), the minimal model's form, whose
+   advecting velocity is u/g_l and whose pressure gradient, Carman-Kozeny
+   drag (eq. 2.8) and force carry a factor g_l; the two coincide where
+   g_l = 1 (fully liquid melt), bit for bit.  g_l of a velocity face is the
+   mean of its two cells; 1/g_l and the g_l of the drag use
+   max(g_l, darcy_eps^(1/3)), so that the advecting velocity stays finite
+   and the drag large in solid cells; the pressure correction and the
+   projection (eqs. 3.4-3.5) are unchanged.  A per-case property: the cases
+   of a batch may differ.  Not allowed while the handle is part of a batch
+   (SOL_EBUSY). */
+#define SOL_OPT_MOMENTUM 5
+#define SOL_MOMENTUM_PLAIN   0
+#define SOL_MOMENTUM_MINIMAL 1
 int sol_set_option(sol_handle *h, int32_t option, int64_t value);
 
 /* Tile-size autotuner: times iterations of this case's pressure solve

@@ -27,8 +27,9 @@ STATE_FIELDS = ("u", "v", "w", "p", "T", "C", "gl", "Cl", "Cs")
 NFIELDS = 14
 KCLASS = dict(cg=0, bicg_a=1, bicg_b=2, bicg_c=3, asm_mom=4, asm_trn=5, phase=6,
               mg_pq=7, mg_down0=8, mg_up0=9, mg_coarse=10)
-OPT_GRAPH, OPT_PRECOND, OPT_TPRECOND, OPT_ASSEMBLY = 1, 2, 3, 4
+OPT_GRAPH, OPT_PRECOND, OPT_TPRECOND, OPT_ASSEMBLY, OPT_MOMENTUM = 1, 2, 3, 4, 5
 ASSEMBLY = dict(stencil=0, forward=1)
+MOMENTUM_PLAIN, MOMENTUM_MINIMAL = 0, 1     # eq. (2.7) / eq. (2.6)
 PRECOND = dict(jacobi=0, mg=1)
 TPRECOND = dict(jacobi=0, jacobi2=1, auto=2)
 
@@ -230,6 +231,9 @@ class Case:
                           w=nx * ny * (nz - 1) if g["dim"] == 3 else 0,
                           p=n, T=n, C=n, gl=n, Cl=n, Cs=n)
         self.sizes.update(ustar=self.sizes["u"], vstar=self.sizes["v"], wstar=self.sizes["w"], phi=n, Tstar=n)
+        form = int(case.get("momentum", MOMENTUM_PLAIN))
+        if form != MOMENTUM_PLAIN:
+            self.set_momentum(form)
         if write_init:
             self.write_fields(case["init"])
 
@@ -308,6 +312,11 @@ class Case:
     def set_assembly(self, name: str):
         """'stencil' (closed-form rows) or 'forward' (residual probing)."""
         check(load().sol_set_option(self.h, OPT_ASSEMBLY, ASSEMBLY[name]))
+
+    def set_momentum(self, form: int):
+        """Momentum form of the predictor: MOMENTUM_PLAIN (eq. 2.7, default)
+        or MOMENTUM_MINIMAL (eq. 2.6)."""
+        check(load().sol_set_option(self.h, OPT_MOMENTUM, int(form)))
 
     def set_tprecond(self, name: str):
         """BiCGSTAB preconditioner of the momentum, solute and energy solves:

@@ -308,6 +308,7 @@ struct sol_handle {
     int precond = SOL_PRECOND_MG;
     int tprecond = SOL_TPRECOND_AUTO;
     int assembly = SOL_ASSEMBLY_STENCIL;
+    int momentum = SOL_MOMENTUM_PLAIN;    // SOL_OPT_MOMENTUM: form of the momentum predictor
     double *mg_pwork = nullptr;           // scratch of the exact-level inverse (set-up)
     double *mg_p64 = nullptr;             // FP64 exact-level inverse (set-up; solves read its FP32 copy)
     // large grids: level mg_nbig (> 0) is solved exactly instead of mg_nglob
@@ -1378,6 +1379,8 @@ static void make_phys(const sol_handle &h, Phys &P)
     P.betaT = a.beta_T; P.betaC = a.beta_C; P.lambda2 = a.lambda2; P.eps = a.darcy_eps;
     P.rcp = a.rho * a.cp; P.kcond = a.k;
     P.Dl = a.D_l;
+    P.gfloor = std::cbrt(a.darcy_eps);
+    P.mom1 = h.momentum == SOL_MOMENTUM_MINIMAL ? 1 : 0;
     for (int f = 0; f < 6; ++f) {
         const sol_face_bc &fb = h.bcs.face[f];
         const bool used = f < 2 * z.dim;
@@ -1980,6 +1983,19 @@ int sol_set_option(sol_handle *h, int32_t option, int64_t value)
         if (h->batch) return fail(SOL_EBUSY, "handle is part of a batch");
         h->assembly = (int)value;
         return SOL_OK;
+    }
+    case SOL_OPT_MOMENTUM: {
+        if (value != SOL_MOMENTUM_PLAIN && value != SOL_MOMENTUM_MINIMAL)
+            return fail(SOL_EINVAL, "unknown momentum form %lld", (long long)value);
+        if (h->batch) return fail(SOL_EBUSY, "handle is part of a batch");
+        if (h->momentum == (int)value) return SOL_OK;
+        (void)hipStreamSynchronize(h->stream);
+        h->momentum = (int)value;
+        h->cd.ph.mom1 = h->momentum == SOL_MOMENTUM_MINIMAL ? 1 : 0;
+        // the case's groups hold a device copy of its Phys
+        group_free(h->solo);
+        h->solo = nullptr;
+        return group_create({h}, &h->solo);
     }
     }
     return fail(SOL_EINVAL, "unknown option %d", option);

@@ -142,6 +142,12 @@ __global__ __launch_bounds__(TILE) void k_asm_const(const CaseDev *__restrict__ 
 // form, advecting velocity = mean of the two nearest level-n velocities of
 // that component) + Carman-Kozeny drag (eq. 2.8) on the face;
 // b = u^n/dt - (1/rho) dp^n/dx + Boussinesq force (eq. 2.9, vertical only).
+// In the form of eq. (2.6) (P.mom1) the advecting velocity is u/g~ and the
+// drag g~ (mu/rho) K^-1, the pressure gradient and the force carry g, with g
+// = g_l^n on the face (mean of its two cells) and g~ = max(g, darcy_eps^(1/3)):
+// below that liquid fraction the regularisation of g^3 in eq. (2.8)
+// dominates, and g~ keeps 1/g finite and the drag large in solid cells.
+// Form (2.7) multiplies by 1 and divides by 1, bit for bit the plain rows.
 template <int DIM>
 __global__ __launch_bounds__(TILE) void k_asm_momentum(const CaseDev *__restrict__ cases, const Tile *__restrict__ tiles)
 {
@@ -164,6 +170,9 @@ __global__ __launch_bounds__(TILE) void k_asm_momentum(const CaseDev *__restrict
     double a[ND];
 #pragma unroll
     for (int k = 0; k < ND; ++k) a[k] = Ac[(size_t)k * n + row];
+    const double gf = 0.5 * (c.gl[clo] + c.gl[chi]);
+    const double gt = P.mom1 ? fmax(gf, P.gfloor) : 1.0;
+    const double gw = P.mom1 ? gf : 1.0;
     double dconv = 0.0;
     const int F = q[d] + 1;
 #pragma unroll
@@ -177,6 +186,8 @@ __global__ __launch_bounds__(TILE) void k_asm_momentum(const CaseDev *__restrict
             vm = 0.5 * (face_vel(P, vel, ax, lo, q[ax]) + face_vel(P, vel, ax, hi, q[ax]));
             vp = 0.5 * (face_vel(P, vel, ax, lo, q[ax] + 1) + face_vel(P, vel, ax, hi, q[ax] + 1));
         }
+        vm = vm / gt;
+        vp = vp / gt;
         const double cw = -fmax(vm, 0.0) * P.ih[ax];
         const double cp = (fmax(vp, 0.0) - fmin(vm, 0.0)) * P.ih[ax];
         const double ce = fmin(vp, 0.0) * P.ih[ax];
@@ -185,20 +196,19 @@ __global__ __launch_bounds__(TILE) void k_asm_momentum(const CaseDev *__restrict
         a[DIM - 1 - ax] = em ? a[DIM - 1 - ax] + cw : 0.0;
         a[DIM + 1 + ax] = ep ? a[DIM + 1 + ax] + ce : 0.0;
     }
-    const double gf = 0.5 * (c.gl[clo] + c.gl[chi]);
     const double sol = 1.0 - gf;
-    const double drag = P.nu * 180.0 * sol * sol / (P.lambda2 * P.lambda2 * (gf * gf * gf + P.eps));
+    const double drag = gt * (P.nu * 180.0 * sol * sol / (P.lambda2 * P.lambda2 * (gf * gf * gf + P.eps)));
     a[DIM] += dconv + drag;
     double *A = c.A[d];
 #pragma unroll
     for (int k = 0; k < ND; ++k) A[(size_t)k * n + row] = a[k];
     const double mi = 1.0 / a[DIM];
     c.minv[d][row] = mi;
-    double rhs = vel[d][row] * P.idt - (c.p[chi] - c.p[clo]) / (P.rho * P.h[d]);
+    double rhs = vel[d][row] * P.idt - gw * ((c.p[chi] - c.p[clo]) / (P.rho * P.h[d]));
     if (d == DIM - 1) {
         const double Tf = 0.5 * (c.T[clo] + c.T[chi]);
         const double Cf = 0.5 * (c.Cl[clo] + c.Cl[chi]);
-        rhs += P.grav * (P.betaT * (Tf - P.Tref) + P.betaC * (Cf - P.Cref));
+        rhs += gw * (P.grav * (P.betaT * (Tf - P.Tref) + P.betaC * (Cf - P.Cref)));
     }
     c.b[d][row] = rhs;
     if (c.A32[d]) {
@@ -1498,7 +1508,9 @@ __device__ __forceinline__ double upw(double v, double left, double right)
     return v >= 0.0 ? v * left : v * right;
 }
 
-// momentum predictor (eq. 3.3), varying part: convection + drag - b
+// momentum predictor (eq. 3.3), varying part: convection + drag - b; the
+// form of eq. (2.6) as in k_asm_momentum (advecting velocity u/g~; drag,
+// pressure gradient and force scaled)
 template <int DIM>
 __global__ __launch_bounds__(TILE) void k_fwd_momentum(const CaseDev *__restrict__ cases, const Tile *__restrict__ tiles)
 {
@@ -1521,6 +1533,9 @@ __global__ __launch_bounds__(TILE) void k_fwd_momentum(const CaseDev *__restrict
     double vm[3], vp[3];
     bool in[ND];
     const int F = q[d] + 1;
+    const double gf = 0.5 * (c.gl[clo] + c.gl[chi]);
+    const double gt = P.mom1 ? fmax(gf, P.gfloor) : 1.0;
+    const double gw = P.mom1 ? gf : 1.0;
 #pragma unroll
     for (int ax = 0; ax < DIM; ++ax) {
         if (ax == d) {
@@ -1531,18 +1546,19 @@ __global__ __launch_bounds__(TILE) void k_fwd_momentum(const CaseDev *__restrict
             vm[ax] = 0.5 * (face_vel(P, vel, ax, lo, q[ax]) + face_vel(P, vel, ax, hi, q[ax]));
             vp[ax] = 0.5 * (face_vel(P, vel, ax, lo, q[ax] + 1) + face_vel(P, vel, ax, hi, q[ax] + 1));
         }
+        vm[ax] = vm[ax] / gt;
+        vp[ax] = vp[ax] / gt;
         in[DIM - 1 - ax] = q[ax] >= 1;
         in[DIM + 1 + ax] = q[ax] <= P.sdim[d][ax] - 2;
     }
     in[DIM] = true;
-    const double gf = 0.5 * (c.gl[clo] + c.gl[chi]);
     const double sol = 1.0 - gf;
-    const double drag = P.nu * 180.0 * sol * sol / (P.lambda2 * P.lambda2 * (gf * gf * gf + P.eps));
-    double b = vel[d][row] * P.idt - (c.p[chi] - c.p[clo]) / (P.rho * P.h[d]);
+    const double drag = gt * (P.nu * 180.0 * sol * sol / (P.lambda2 * P.lambda2 * (gf * gf * gf + P.eps)));
+    double b = vel[d][row] * P.idt - gw * ((c.p[chi] - c.p[clo]) / (P.rho * P.h[d]));
     if (d == DIM - 1) {
         const double Tf = 0.5 * (c.T[clo] + c.T[chi]);
         const double Cf = 0.5 * (c.Cl[clo] + c.Cl[chi]);
-        b += P.grav * (P.betaT * (Tf - P.Tref) + P.betaC * (Cf - P.Cref));
+        b += gw * (P.grav * (P.betaT * (Tf - P.Tref) + P.betaC * (Cf - P.Cref)));
     }
     // Eq(phi) on the stencil: phi[k] is the probe's value on slot k
     auto eq = [&](const double *phi) {

@@ -99,6 +99,8 @@ struct Phys {
     double rho, mu, nu, dt, idt, alpha, lam, kp, Tm, msp, Ce, Tref, Cref;
     double grav, betaT, betaC, lambda2, eps, rcp, kcond;
     double Dl;                // liquid solute diffusivity (eq. 3.7); 0 = minimal model
+    double gfloor;            // darcy_eps^(1/3): lower bound of g_l in 1/g_l and the drag of form (2.6)
+    int32_t mom1;             // momentum predictor in the form of eq. (2.6) instead of eq. (2.7)
     int32_t thermal[6], slip[6];
     double hc[6], Text[6], Tw0[6], Tramp[6];
 };

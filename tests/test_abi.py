@@ -107,6 +107,11 @@ def test_binding_constants_match_header():
     for name in ("SOL_OK", "SOL_EINVAL", "SOL_ENOMEM", "SOL_ENOCONV", "SOL_ENONFINITE", "SOL_EDEVICE", "SOL_EBUSY"):
         assert getattr(B, name) == d[name], name
     assert (B.OPT_GRAPH, B.OPT_PRECOND, B.OPT_TPRECOND) == (d["SOL_OPT_GRAPH"], d["SOL_OPT_PRECOND"], d["SOL_OPT_TPRECOND"])
+    assert (B.OPT_ASSEMBLY, B.OPT_MOMENTUM) == (d["SOL_OPT_ASSEMBLY"], d["SOL_OPT_MOMENTUM"])
+    assert B.ASSEMBLY == dict(stencil=d["SOL_ASSEMBLY_STENCIL"], forward=d["SOL_ASSEMBLY_FORWARD"])
+    assert (B.MOMENTUM_PLAIN, B.MOMENTUM_MINIMAL) == (d["SOL_MOMENTUM_PLAIN"], d["SOL_MOMENTUM_MINIMAL"])
+    import workloads as W
+    assert (W.MOMENTUM_PLAIN, W.MOMENTUM_MINIMAL) == (d["SOL_MOMENTUM_PLAIN"], d["SOL_MOMENTUM_MINIMAL"])
     assert B.PRECOND == dict(jacobi=d["SOL_PRECOND_JACOBI"], mg=d["SOL_PRECOND_MG"])
     assert B.TPRECOND == dict(jacobi=d["SOL_TPRECOND_JACOBI"], jacobi2=d["SOL_TPRECOND_JACOBI2"],
                               auto=d["SOL_TPRECOND_AUTO"])
@@ -118,7 +123,8 @@ def test_binding_constants_match_header():
 def test_set_option_rejects_null_handle(sol):
     from paper_2303_10783_amd import binding as B
     L = sol.load()
-    for opt, val in ((B.OPT_GRAPH, 1), (B.OPT_PRECOND, 0), (B.OPT_TPRECOND, 2)):
+    for opt, val in ((B.OPT_GRAPH, 1), (B.OPT_PRECOND, 0), (B.OPT_TPRECOND, 2), (B.OPT_ASSEMBLY, 1),
+                     (B.OPT_MOMENTUM, 1)):
         assert L.sol_set_option(None, opt, val) == B.SOL_EINVAL
 
 

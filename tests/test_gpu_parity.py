@@ -160,6 +160,12 @@ def _step_cases():
     c = W.freckle_case(3, tol=1e-13, mesh=(12, 12, 36), slip_sides=True)
     c["numerics"]["tol_t"] = 1e-14
     out.append(("freckle-3d-12x12x36", c, 5))
+    # momentum predictor in the minimal model's form (eq. 2.6), developing mush
+    c = W.cavity_2d(37, 23, tol=1e-13, seed=21, T_ext=250.0, h=2000.0, momentum=W.MOMENTUM_MINIMAL)
+    out.append(("2d-mom26", c, 6))
+    c = W.box_3d(9, 7, 5, lx=0.009, ly=0.007, lz=0.005, tol=1e-13, seed=22, T_ext=250.0, h=2000.0,
+                 momentum=W.MOMENTUM_MINIMAL)
+    out.append(("3d-mom26", c, 4))
     return out
 
 

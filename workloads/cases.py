@@ -169,21 +169,24 @@ def west_cooled_bcs(h=400.0, T_ext=298.0, velocity=VELOCITY_NOSLIP):
 
 def cavity_2d(nx=50, ny=30, *, lx=0.10, ly=0.06, C0=10.0, h=400.0,
               T_ext=298.0, dt=0.01, tol=1e-10, precision=PRECISION_FP64,
-              seed=0, max_iter=200000, name=None, alloy=None) -> dict:
+              seed=0, max_iter=200000, name=None, alloy=None,
+              momentum=MOMENTUM_PLAIN) -> dict:
     return make_case(2, nx, ny, 1, lx, ly, 1.0, C0=C0, alloy=alloy,
                      bcs=west_cooled_bcs(h, T_ext), dt=dt, tol_p=tol,
                      tol_t=tol, max_iter=max_iter, precision=precision,
-                     seed=seed, name=name or f"cavity2d_{nx}x{ny}")
+                     seed=seed, name=name or f"cavity2d_{nx}x{ny}",
+                     momentum=momentum)
 
 
 def box_3d(nx=128, ny=128, nz=64, *, lx=0.10, ly=0.10, lz=0.05, C0=10.0,
            h=400.0, T_ext=298.0, dt=0.01, tol=1e-10,
            precision=PRECISION_FP64, seed=0, max_iter=200000, name=None,
-           alloy=None) -> dict:
+           alloy=None, momentum=MOMENTUM_PLAIN) -> dict:
     return make_case(3, nx, ny, nz, lx, ly, lz, C0=C0, alloy=alloy,
                      bcs=west_cooled_bcs(h, T_ext), dt=dt, tol_p=tol,
                      tol_t=tol, max_iter=max_iter, precision=precision,
-                     seed=seed, name=name or f"box3d_{nx}x{ny}x{nz}")
+                     seed=seed, name=name or f"box3d_{nx}x{ny}x{nz}",
+                     momentum=momentum)
 
 
 # Named workloads (grid, steps).  C1 is small enough for the oracle to run in
