@@ -21,7 +21,9 @@ Also printed in the same JSON line:
                 workload on all host cores and on one core, the 50x30 cavity
                 in full, and the per-field error of the GPU's FP64 and mixed
                 runs of those first steps against the oracle's fields;
-  variants      the same box in mixed precision (500 steps), with the forward
+  variants      the same box in mixed precision (500 steps), with the coarse
+                multigrid levels one launch each instead of fused in pairs
+                (the box and the 500x300 cavity), with the forward
                 (residual-probing) assembly route and its assembly kernels'
                 times next to the stencil route's, the box in FP64
                 and mixed at the tight tolerances that hold the fields within
@@ -137,7 +139,7 @@ def _describe(key, case):
 
 
 def run_single(sol, W, key, precision, steps, warmup, dev, *, precond="mg", tprecond=None, graph=False,
-               timing=False, keep_fields=None, tols=None, assembly=None):
+               timing=False, keep_fields=None, tols=None, assembly=None, mg_fuse=None):
     """K steps of a named workload from its initial state (after W warm-up
     steps and a rewrite of the initial fields).  With timing, a second pass
     over the same K steps with every solver launch timed by HIP events gives
@@ -159,6 +161,8 @@ def run_single(sol, W, key, precision, steps, warmup, dev, *, precond="mg", tpre
         h.set_graph(True)
     if assembly:
         h.set_assembly(assembly)
+    if mg_fuse is not None:
+        h.set_mg_fuse(mg_fuse)
     if warmup:
         h.step(warmup)
         h.write_fields(case["init"])
@@ -178,6 +182,8 @@ def run_single(sol, W, key, precision, steps, warmup, dev, *, precond="mg", tpre
         out["assembly"] = assembly
     if graph:
         out["graph"] = True
+    if mg_fuse is not None:
+        out["coarse_levels_fused"] = bool(mg_fuse)
     if timing:
         h.write_fields(case["init"])
         h.set_timing(True)
@@ -361,6 +367,8 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--jacobi-variants", action="store_true", help="also time Jacobi-PCG pressure solves")
     ap.add_argument("--graph", action="store_true", help="replay Krylov chunks as HIP graphs")
+    ap.add_argument("--mg-per-level", action="store_true",
+                    help="coarse multigrid levels one launch each (default: fused in pairs)")
     ap.add_argument("--precond", default="mg", choices=["mg", "jacobi"],
                     help="pressure-CG preconditioner (multigrid V-cycle or Jacobi)")
     ap.add_argument("--tprecond", default=None, choices=["jacobi", "jacobi2", "auto"],
@@ -394,7 +402,8 @@ def main():
     acc_steps = 2 if args.workload == "C3" else 5
     keep = acc_steps if not args.no_cpu_baseline else None
     head = run_single(sol, W, args.workload, args.precision, steps, args.warmup, dev, precond=args.precond,
-                      tprecond=args.tprecond, graph=args.graph, timing=not args.no_roofline, keep_fields=keep)
+                      tprecond=args.tprecond, graph=args.graph, timing=not args.no_roofline, keep_fields=keep,
+                      mg_fuse=False if args.mg_per_level else None)
     print(f"[bench] headline {head['workload']} {args.precision}: {head['value'] / 1e6:.1f} M cell-updates/s",
           file=sys.stderr, flush=True)
     roof = None
@@ -433,6 +442,14 @@ def main():
         if args.jacobi_variants:
             variants["C3_fp64_jacobi"] = _public(run_single(sol, W, "C3", "fp64", 20, 1, dev, precond="jacobi"))
             variants["C2_fp64_jacobi"] = _public(run_single(sol, W, "C2", "fp64", 50, 1, dev, precond="jacobi"))
+        # coarse multigrid levels one launch each (fused in pairs by
+        # default): the same steps, the time the fusion saves
+        for key in dict.fromkeys((args.workload, "C2")):
+            nst = steps if key == args.workload else W.WORKLOADS[key]["steps"]
+            v = run_single(sol, W, key, args.precision, nst, args.warmup, dev, mg_fuse=False)
+            variants[f"{key}_{args.precision}_mg_per_level"] = _public(v)
+            print(f"[bench] {key} coarse levels one launch each: {v['value'] / 1e6:.1f} M", file=sys.stderr,
+                  flush=True)
         # the forward (residual-probing) assembly route: its assembly
         # kernels against the stencil route's, same steps
         v = run_single(sol, W, args.workload, args.precision, steps, args.warmup, dev, assembly="forward",

@@ -344,6 +344,14 @@ int sol_get_timing(sol_handle *h, int32_t kclass, int64_t *launches, double *tot
 #define SOL_OPT_MOMENTUM 5
 #define SOL_MOMENTUM_PLAIN   0
 #define SOL_MOMENTUM_MINIMAL 1
+/* SOL_OPT_MG_FUSE (0/1, default 1): run two consecutive coarse levels of the
+   multigrid V-cycle (both smoothed, above the exactly solved level) in one
+   launch each way, each workgroup recomputing in local memory the halo its
+   results depend on; with 0 every level is its own launch.  The two give
+   the same results; the option exists to time them against each other.
+   Not allowed while the handle is part of a batch (SOL_EBUSY); a batch
+   follows its first handle. */
+#define SOL_OPT_MG_FUSE 6
 int sol_set_option(sol_handle *h, int32_t option, int64_t value);
 
 /* Tile-size autotuner: times iterations of this case's pressure solve

@@ -27,7 +27,7 @@ STATE_FIELDS = ("u", "v", "w", "p", "T", "C", "gl", "Cl", "Cs")
 NFIELDS = 14
 KCLASS = dict(cg=0, bicg_a=1, bicg_b=2, bicg_c=3, asm_mom=4, asm_trn=5, phase=6,
               mg_pq=7, mg_down0=8, mg_up0=9, mg_coarse=10)
-OPT_GRAPH, OPT_PRECOND, OPT_TPRECOND, OPT_ASSEMBLY, OPT_MOMENTUM = 1, 2, 3, 4, 5
+OPT_GRAPH, OPT_PRECOND, OPT_TPRECOND, OPT_ASSEMBLY, OPT_MOMENTUM, OPT_MG_FUSE = 1, 2, 3, 4, 5, 6
 ASSEMBLY = dict(stencil=0, forward=1)
 MOMENTUM_PLAIN, MOMENTUM_MINIMAL = 0, 1     # eq. (2.7) / eq. (2.6)
 PRECOND = dict(jacobi=0, mg=1)
@@ -312,6 +312,10 @@ class Case:
     def set_assembly(self, name: str):
         """'stencil' (closed-form rows) or 'forward' (residual probing)."""
         check(load().sol_set_option(self.h, OPT_ASSEMBLY, ASSEMBLY[name]))
+
+    def set_mg_fuse(self, on: bool):
+        """Coarse multigrid levels in fused pairs (default) or one launch each."""
+        check(load().sol_set_option(self.h, OPT_MG_FUSE, 1 if on else 0))
 
     def set_momentum(self, form: int):
         """Momentum form of the predictor: MOMENTUM_PLAIN (eq. 2.7, default)

@@ -309,6 +309,7 @@ struct sol_handle {
     int tprecond = SOL_TPRECOND_AUTO;
     int assembly = SOL_ASSEMBLY_STENCIL;
     int momentum = SOL_MOMENTUM_PLAIN;    // SOL_OPT_MOMENTUM: form of the momentum predictor
+    bool mg_fuse = true;                  // SOL_OPT_MG_FUSE: coarse multigrid levels in pairs
     double *mg_pwork = nullptr;           // scratch of the exact-level inverse (set-up)
     double *mg_p64 = nullptr;             // FP64 exact-level inverse (set-up; solves read its FP32 copy)
     // large grids: level mg_nbig (> 0) is solved exactly instead of mg_nglob
@@ -386,6 +387,7 @@ struct Group {
     sol_handle *timer = nullptr;          // handle that collects kernel timing (solo groups)
     int *kbase_d = nullptr;               // iteration index base of graph-replayed chunks
     bool use_graph = false;
+    bool mg_fuse = true;                  // coarse multigrid levels fused in pairs
 };
 
 // group arrays come out of 1 MiB chunks (256-byte aligned pieces; a larger
@@ -566,31 +568,41 @@ static int build_stages(Group &g, JobSet &S, int kind, const bool (&two)[2], int
         return SOL_OK;
     }
     // multigrid CG: pq, down0, down(1..G-1), exact, up(G-1..1), up0; the start
-    // cycle is the same without pq, with the start variant of down0
+    // cycle is the same without pq, with the start variant of down0.  With
+    // fused coarse levels the levels 1..G-1 go in slots of two: a slot at
+    // level l runs levels l and l+1 in one launch each way for the solves
+    // with l + 1 < G, and level l alone for those with G = l + 1.
     int gmax = 1;
     for (size_t j = 0; j < S.jobs.size(); ++j) gmax = std::max(gmax, case_nglob(g, g.cs[S.case_of[j]]));
-    std::vector<Stage> down(gmax), up(gmax);
-    for (int l = 1; l < gmax; ++l) {
-        std::vector<std::vector<JTile>> per[2];
+    const bool fuse = g.mg_fuse;
+    std::vector<Stage> down, up;          // in the down order; up runs them reversed
+    for (int l = 1; l < gmax; l += fuse ? 2 : 1) {
+        std::vector<std::vector<JTile>> per[2][2];   // [single, pair][stencil width]
         for (size_t j = 0; j < S.jobs.size(); ++j) {
             const sol_handle *h = g.cs[S.case_of[j]];
-            if (case_nglob(g, h) <= l) continue;
+            const int G = case_nglob(g, h);
+            if (G <= l) continue;
             const int gi = h->z.nd == 7 ? 1 : 0;
+            const int pair = fuse && G >= l + 2 ? 1 : 0;
+            const int nt = pair ? mg_fused_bricks(h->z.dim, h->mg_h[l + 1]) : h->mg_h[l].ntile;
             std::vector<JTile> tl;
-            for (int t = 0; t < h->mg_h[l].ntile; ++t) tl.push_back({(int)j, t, l, 0});
-            per[gi].push_back(std::move(tl));
+            for (int t = 0; t < nt; ++t) tl.push_back({(int)j, t, l, 0});
+            per[pair][gi].push_back(std::move(tl));
         }
-        Stage st;
-        st.which = KI_MG_DOWN;
-        st.cls = SOL_KCLASS_MG_COARSE;
-        for (int gi = 0; gi < 2; ++gi) {
-            const std::vector<JTile> jt = xcd_order(per[gi]);
-            RCHK(upload(g, &st.tiles_d[gi], jt));
-            st.nt[gi] = (int)jt.size();
+        for (int pair = 1; pair >= 0; --pair) {
+            Stage st;
+            st.which = pair ? KI_MG_DOWN2 : KI_MG_DOWN;
+            st.cls = SOL_KCLASS_MG_COARSE;
+            for (int gi = 0; gi < 2; ++gi) {
+                const std::vector<JTile> jt = xcd_order(per[pair][gi]);
+                if (!jt.empty()) RCHK(upload(g, &st.tiles_d[gi], jt));
+                st.nt[gi] = (int)jt.size();
+            }
+            if (st.nt[0] + st.nt[1] == 0) continue;
+            down.push_back(st);
+            st.which = pair ? KI_MG_UP2 : KI_MG_UP;
+            up.push_back(st);
         }
-        down[l] = st;
-        up[l] = st;
-        up[l].which = KI_MG_UP;
     }
     Stage exact;
     exact.which = KI_MG_EXACT;
@@ -610,9 +622,9 @@ static int build_stages(Group &g, JobSet &S, int kind, const bool (&two)[2], int
     }
     auto cycle = [&](std::vector<Stage> &out, int down0) {
         out.push_back(row_stage(down0, SOL_KCLASS_MG_DOWN0));
-        for (int l = 1; l < gmax; ++l) out.push_back(down[l]);
+        for (const Stage &st : down) out.push_back(st);
         out.push_back(exact);
-        for (int l = gmax - 1; l >= 1; --l) out.push_back(up[l]);
+        for (size_t i = up.size(); i-- > 0;) out.push_back(up[i]);
         out.push_back(row_stage(KI_MG_UP0, SOL_KCLASS_MG_UP0));
     };
     S.iter.push_back(row_stage(KI_MG_PQ, SOL_KCLASS_MG_PQ));
@@ -797,6 +809,7 @@ static int group_create(const std::vector<sol_handle *> &cs, Group **out)
     Group *g = new Group();
     g->cs = cs;
     g->stream = cs[0]->stream;
+    g->mg_fuse = cs[0]->mg_fuse;          // a batch follows its first handle
     int rc = group_build(*g);
     if (rc != SOL_OK) { group_free(g); return rc; }
     *out = g;
@@ -1983,6 +1996,16 @@ int sol_set_option(sol_handle *h, int32_t option, int64_t value)
         if (h->batch) return fail(SOL_EBUSY, "handle is part of a batch");
         h->assembly = (int)value;
         return SOL_OK;
+    }
+    case SOL_OPT_MG_FUSE: {
+        if (value != 0 && value != 1) return fail(SOL_EINVAL, "SOL_OPT_MG_FUSE takes 0 or 1");
+        if (h->batch) return fail(SOL_EBUSY, "handle is part of a batch");
+        if (h->mg_fuse == (value != 0)) return SOL_OK;
+        (void)hipStreamSynchronize(h->stream);
+        h->mg_fuse = value != 0;
+        group_free(h->solo);
+        h->solo = nullptr;
+        return group_create({h}, &h->solo);
     }
     case SOL_OPT_MOMENTUM: {
         if (value != SOL_MOMENTUM_PLAIN && value != SOL_MOMENTUM_MINIMAL)

@@ -24,12 +24,15 @@ void launch_kdecide(const KJob *j, int njobs, hipStream_t s);
 enum KIter {
     KI_CG = 0, KI_BICG_A = 1, KI_BICG_B = 2,
     KI_MG_PQ = 4, KI_MG_DOWN0 = 5, KI_MG_DOWN = 6, KI_MG_EXACT = 7, KI_MG_UP = 8, KI_MG_UP0 = 9,
-    KI_MG_DOWN0_INIT = 10
+    KI_MG_DOWN0_INIT = 10,
+    KI_MG_DOWN2 = 11, KI_MG_UP2 = 12       // two coarse levels in one launch
 };
 // kernel address of an iteration kernel (direct launches and graph nodes);
 // two selects the two-sweep BiCGSTAB kernels
 const void *kiter_fn(int which, int nd, int fp32, bool two);
 const void *mg_fn(int which, int nd, int fp32);
+// workgroups of a fused pair of coarse levels (l, l+1); M = level l+1
+int mg_fused_bricks(int dim, const MLevel &M);
 // multigrid: start of the solves (r = b - A x, p = 0, partial (b, b)) and
 // the inverse diagonal of level l >= 1 (FP32 copy when mi32 is given)
 void launch_mg_init(int nd, int fp32, const KJob *j, const JTile *t, int nt, int k, int mode, hipStream_t s);

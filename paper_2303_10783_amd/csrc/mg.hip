@@ -265,7 +265,9 @@ __device__ __forceinline__ T op_diag(const MLevel &L, const int *q)
 // f(j, axis, direction) (direction 0: the cell itself).  Branch-free: a
 // missing neighbour is replaced by the cell itself with a zero coupling, so
 // every value is loaded unconditionally and the loads can be issued together.
-template <int DIM, class T, class F>
+// NOFMA: the sum without contraction into fused multiply-adds (the coarse
+// levels, whose fused and per-level kernels must round alike).
+template <int DIM, class T, bool NOFMA = false, class F>
 __device__ __forceinline__ T apply_op(const MLevel &L, int i, const int *q, F f)
 {
     T co[3];
@@ -279,7 +281,12 @@ __device__ __forceinline__ T apply_op(const MLevel &L, int i, const int *q, F f)
         const bool lo = q[a] > 0, hi = q[a] + 1 < nn[a];
         const T vlo = f(lo ? i - st[a] : i, a, lo ? -1 : 0);
         const T vhi = f(hi ? i + st[a] : i, a, hi ? 1 : 0);
-        acc += (lo ? co[a] : T(0)) * (fi - vlo) + (hi ? co[a] : T(0)) * (fi - vhi);
+        if constexpr (NOFMA) {
+#pragma clang fp contract(off)
+            acc += (lo ? co[a] : T(0)) * (fi - vlo) + (hi ? co[a] : T(0)) * (fi - vhi);
+        } else {
+            acc += (lo ? co[a] : T(0)) * (fi - vlo) + (hi ? co[a] : T(0)) * (fi - vhi);
+        }
     }
     return acc;
 }
@@ -732,6 +739,7 @@ template <int DIM, class T>
 __global__ __launch_bounds__(TILE) void k_mg_down(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles,
                                                   const int *kbase, int koff)
 {
+#pragma clang fp contract(off)
     const int k = kidx(kbase, koff);
     JTile tl;
     const KJob &J = job_of(jobs, tiles, tl);
@@ -748,10 +756,10 @@ __global__ __launch_bounds__(TILE) void k_mg_down(const KJob *__restrict__ jobs,
         auto x1 = [&](int j, int, int) { return w * mi[j] * b[j]; };
         if constexpr (DIM == 2) {
             auto x2 = [&](int j, const int *qj) {
-                return x1(j, 0, 0) + w * mi[j] * (b[j] - apply_op<DIM, T>(L, j, qj, x1));
+                return x1(j, 0, 0) + w * mi[j] * (b[j] - apply_op<DIM, T, true>(L, j, qj, x1));
             };
             const T x2i = x2(i, q);
-            const T ax = apply_op<DIM, T>(L, i, q, [&](int j, int ax_, int dir) {
+            const T ax = apply_op<DIM, T, true>(L, i, q, [&](int j, int ax_, int dir) {
                 int qj[3];
                 step_q(q, ax_, dir, qj);
                 return x2(j, qj);
@@ -759,7 +767,7 @@ __global__ __launch_bounds__(TILE) void k_mg_down(const KJob *__restrict__ jobs,
             G<T>(L.xs)[i] = x2i;
             v = b[i] - ax;
         } else {
-            v = b[i] - apply_op<DIM, T>(L, i, q, x1);
+            v = b[i] - apply_op<DIM, T, true>(L, i, q, x1);
         }
     }
     // sum over the 2^d children (consecutive lanes), fixed order
@@ -778,6 +786,7 @@ template <int DIM, class T>
 __global__ __launch_bounds__(TILE) void k_mg_up(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles,
                                                 const int *kbase, int koff)
 {
+#pragma clang fp contract(off)
     const int k = kidx(kbase, koff);
     JTile tl;
     const KJob &J = job_of(jobs, tiles, tl);
@@ -794,7 +803,7 @@ __global__ __launch_bounds__(TILE) void k_mg_up(const KJob *__restrict__ jobs, c
     int cx[3], q[3], i, I;
     if (!child_of<DIM>(L, tl.t, icx, icxy, a, cx, q, i, I)) return;
     if constexpr (DIM == 3) {
-        const T ax = apply_op<DIM, T>(L, i, q, [&](int j, int ax_, int dir) {
+        const T ax = apply_op<DIM, T, true>(L, i, q, [&](int j, int ax_, int dir) {
             return w * mi[j] * b[j] + og * ec[agg_nb<DIM>(L, a, cx, ax_, dir)];
         });
         const T xi = w * mi[i] * b[i] + og * ec[I];
@@ -803,14 +812,14 @@ __global__ __launch_bounds__(TILE) void k_mg_up(const KJob *__restrict__ jobs, c
     }
     auto e0 = [&](int j, const int *qj) { return xs[j] + og * ec[agg_index(L, qj)]; };
     auto e1 = [&](int j, const int *qj) {
-        const T aj = apply_op<DIM, T>(L, j, qj, [&](int jj, int ax_, int dir) {
+        const T aj = apply_op<DIM, T, true>(L, j, qj, [&](int jj, int ax_, int dir) {
             int qjj[3];
             step_q(qj, ax_, dir, qjj);
             return e0(jj, qjj);
         });
         return e0(j, qj) + w * mi[j] * (b[j] - aj);
     };
-    const T ax = apply_op<DIM, T>(L, i, q, [&](int j, int ax_, int dir) {
+    const T ax = apply_op<DIM, T, true>(L, i, q, [&](int j, int ax_, int dir) {
         int qj[3];
         step_q(q, ax_, dir, qj);
         return e1(j, qj);
@@ -936,6 +945,531 @@ __global__ __launch_bounds__(TILE) void k_mg_up0(const KJob *__restrict__ jobs, 
     }
     const int off[3] = {poff(J, pn1, PS_RHO), poff(J, pn1, PS_Q), poff(J, pn1, PS_TT)};
     put_partials<3>(vv, J.part, off, tl.t);
+}
+
+// ------------------------------------------------ fused coarse-level pairs
+// Two consecutive coarse levels l, l+1 (both smoothed, l+1 < nglob) in one
+// launch each way instead of two.  A workgroup owns a brick of level-(l+2)
+// cells and recomputes, in LDS, every value its brick's results depend on
+// within the stencil reach of the sweeps (a halo of the finer levels),
+// instead of reading them back from memory after a launch boundary: the
+// only grid-wide dependencies of the V-cycle are the exact level and
+// level 0's partial sums.  Each value is formed by the expression of the
+// per-level kernels above in the same order (region_op is apply_op on an
+// LDS region), and contraction into fused multiply-adds is off in both (the
+// compiler's choice of which product to fuse may differ between the two
+// kernels), so the two paths give the same results bit for bit; values the
+// owning workgroup does not own are recomputed by every workgroup whose
+// halo holds them.
+//
+// Brick edge in level-(l+2) cells: 2 in 3D (8 cells: level l+1 owned 4^3,
+// with its one-step halo 6^3, level l 12^3 plus its halo 14^3), 4 in 2D
+// (level l+1 owned 8^2, two-sweep halo 12^2; level l 24^2, load halo 28^2).
+constexpr int FZ3 = 2, FZ2 = 4;
+
+__host__ __device__ constexpr int fused_brick(int dim) { return dim == 3 ? FZ3 : FZ2; }
+
+// (A f) at the level cell with coordinates q whose value sits at o in an
+// LDS region with row stride RX and plane stride RXY: apply_op's arithmetic
+// (a missing neighbour enters through a zero coupling with the cell's own
+// value); every read stays inside the region, because cells are only
+// evaluated at least one step inside it
+template <int DIM, class T, int RX, int RXY>
+__device__ __forceinline__ T region_op(const MLevel &L, const int *q, const T *f, int o)
+{
+#pragma clang fp contract(off)
+    T co[3];
+    couplings<DIM, T>(L, q, co);
+    const int st[3] = {1, RX, RXY};
+    const int nn[3] = {L.nx, L.ny, L.nz};
+    const T fi = f[o];
+    T acc = T(0);
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        const bool lo = q[a] > 0, hi = q[a] + 1 < nn[a];
+        const T vlo = f[lo ? o - st[a] : o];
+        const T vhi = f[hi ? o + st[a] : o];
+        acc += (lo ? co[a] : T(0)) * (fi - vlo) + (hi ? co[a] : T(0)) * (fi - vhi);
+    }
+    return acc;
+}
+
+__device__ __forceinline__ bool in_level(const MLevel &L, int x, int y, int z)
+{
+    return x >= 0 && y >= 0 && z >= 0 && x < L.nx && y < L.ny && z < L.nz;
+}
+
+// brick coordinates of tile t over the level-(l+2) counts of M (= level l+1)
+template <int DIM>
+__device__ __forceinline__ void brick_of(const MLevel &M, int t, int *bq)
+{
+    constexpr int B = DIM == 3 ? FZ3 : FZ2;
+    const int nbx = ceil_div(M.cnx, B), nby = ceil_div(M.cny, B);
+    bq[2] = DIM == 3 ? t / (nbx * nby) : 0;
+    const int rem = t - bq[2] * nbx * nby;
+    bq[1] = rem / nbx;
+    bq[0] = rem - bq[1] * nbx;
+}
+
+// level l+2 rhs of the owned children: lanes 2^d c .. 2^d c + 2^d - 1 hold
+// the residuals of the children of brick cell c (zero for a child off the
+// grid); summed in k_mg_down's order and written by the first lane
+template <int DIM, class T>
+__device__ __forceinline__ void restrict_owned(const MLevel &M, const KJob &J, int lv, const int *bq, T v)
+{
+    constexpr int B = DIM == 3 ? FZ3 : FZ2;
+#pragma unroll
+    for (int o = 1; o < (1 << DIM); o <<= 1) v += __shfl_xor(v, o, 64);
+    const int a = (int)threadIdx.x >> DIM;
+    if ((threadIdx.x & ((1 << DIM) - 1)) == 0 && a < (DIM == 3 ? B * B * B : B * B)) {
+        const int ax = a % B, ay = (a / B) % B, az = DIM == 3 ? a / (B * B) : 0;
+        const int X = B * bq[0] + ax, Y = B * bq[1] + ay, Z = B * bq[2] + az;
+        if (X < M.cnx && Y < M.cny && Z < M.cnz) G<T>(J.lev[lv + 2].b)[X + M.cnx * (Y + M.cny * Z)] = v;
+    }
+}
+
+// pre-smooth levels l and l+1 and restrict twice (3D: one sweep from zero
+// per level, x1 = w D^-1 b).  Every global load of the launch is issued
+// first, held in registers, so that they are in flight together: one round
+// trip instead of one per pass over the region.  The loads are
+// unconditional (a cell off the grid reads element 0, and its value is
+// replaced by 0): a load under a branch made the compiler wait for all
+// earlier loads before the branch, one round trip per cell again.
+template <class T>
+__global__ __launch_bounds__(TILE) void k_mg_down2_3(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles,
+                                                     const int *kbase, int koff)
+{
+#pragma clang fp contract(off)
+    constexpr int R1 = 2 * FZ3 + 2, RR = 2 * R1, RL = RR + 2;
+    constexpr int NL = RL * RL * RL, NIL = (NL + TILE - 1) / TILE, N1 = R1 * R1 * R1;
+    static_assert(N1 <= TILE, "one level-(l+1) region cell per thread");
+    __shared__ T X[NL];                  // level l: x1 on the load region
+    __shared__ T Bv[RR * RR * RR];       // level l: b, then the residual, on the residual region
+    __shared__ T Xc[N1];                 // level l+1: x1
+    __shared__ T Bc[N1];                 // level l+1: b (the restricted residual)
+    const int k = kidx(kbase, koff);
+    JTile tl;
+    const KJob &J = job_of(jobs, tiles, tl);
+    if (outer_idle(J) || !mg_live(J, k)) return;
+    // level tables by value: read once into registers (through a reference
+    // the compiler reloads the counts inside the loops, a wait each time)
+    const MLevel L = J.lev[tl.lv], M = J.lev[tl.lv + 1];
+    const T w = (T)mg_w<3>();
+    int bq[3];
+    brick_of<3>(M, tl.t, bq);
+    int o1[3], oR[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        o1[a] = 2 * FZ3 * bq[a] - 1;      // level l+1 region origin
+        oR[a] = 2 * o1[a];                // level l residual region origin (load region: oR - 1)
+    }
+    const int U = threadIdx.x % R1, V = (threadIdx.x / R1) % R1, W = threadIdx.x / (R1 * R1);
+    const int g1[3] = {o1[0] + U, o1[1] + V, o1[2] + W};
+    const bool c1 = (int)threadIdx.x < N1 && in_level(M, g1[0], g1[1], g1[2]);
+    const int I1 = g1[0] + M.nx * (g1[1] + M.ny * g1[2]);
+    T bl[NIL], ml[NIL], mc = T(0);
+    {
+        auto mi = G<T>(L.minv);
+        auto b = G<T>(L.b);
+#pragma unroll
+        for (int it = 0; it < NIL; ++it) {
+            const int id = threadIdx.x + it * TILE;
+            const int u = id % RL, v = (id / RL) % RL, s = id / (RL * RL);
+            const int gx = oR[0] - 1 + u, gy = oR[1] - 1 + v, gz = oR[2] - 1 + s;
+            const bool ok = id < NL && in_level(L, gx, gy, gz);
+            const int j = ok ? gx + L.nx * (gy + L.ny * gz) : 0;
+            const T bv = b[j], mv = mi[j];
+            bl[it] = ok ? bv : T(0);
+            ml[it] = ok ? mv : T(0);
+        }
+        const T m1 = G<T>(M.minv)[c1 ? I1 : 0];
+        mc = c1 ? m1 : T(0);
+    }
+#pragma unroll
+    for (int it = 0; it < NIL; ++it) {
+        const int id = threadIdx.x + it * TILE;
+        if (id < NL) {
+            const int u = id % RL, v = (id / RL) % RL, s = id / (RL * RL);
+            X[id] = w * ml[it] * bl[it];
+            if (u >= 1 && v >= 1 && s >= 1 && u <= RR && v <= RR && s <= RR)
+                Bv[(u - 1) + RR * ((v - 1) + RR * (s - 1))] = bl[it];
+        }
+    }
+    __syncthreads();
+    for (int id = threadIdx.x; id < RR * RR * RR; id += TILE) {
+        const int u = id % RR, v = (id / RR) % RR, s = id / (RR * RR);
+        const int q[3] = {oR[0] + u, oR[1] + v, oR[2] + s};
+        T r = T(0);
+        if (in_level(L, q[0], q[1], q[2]))
+            r = Bv[id] - region_op<3, T, RL, RL * RL>(L, q, X, (u + 1) + RL * ((v + 1) + RL * (s + 1)));
+        Bv[id] = r;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < N1) {
+        T bc = T(0), xc = T(0);
+        if (c1) {
+            auto rr = [&](int cx, int cy, int cz) {
+                return Bv[(2 * U + cx) + RR * ((2 * V + cy) + RR * (2 * W + cz))];
+            };
+            bc = ((rr(0, 0, 0) + rr(1, 0, 0)) + (rr(0, 1, 0) + rr(1, 1, 0))) +
+                 ((rr(0, 0, 1) + rr(1, 0, 1)) + (rr(0, 1, 1) + rr(1, 1, 1)));
+            if (U >= 1 && V >= 1 && W >= 1 && U < R1 - 1 && V < R1 - 1 && W < R1 - 1) G<T>(M.b)[I1] = bc;
+            xc = w * mc * bc;
+        }
+        Bc[threadIdx.x] = bc;
+        Xc[threadIdx.x] = xc;
+    }
+    __syncthreads();
+    // owned level-(l+1) cells: 8 lanes per brick cell (threads 0..63)
+    T v = T(0);
+    {
+        const int c = threadIdx.x & 7, a = (int)threadIdx.x >> 3;
+        if (a < FZ3 * FZ3 * FZ3) {
+            const int Uo = 1 + 2 * (a % FZ3) + (c & 1), Vo = 1 + 2 * ((a / FZ3) % FZ3) + ((c >> 1) & 1),
+                      Wo = 1 + 2 * (a / (FZ3 * FZ3)) + ((c >> 2) & 1);
+            const int q[3] = {o1[0] + Uo, o1[1] + Vo, o1[2] + Wo};
+            if (in_level(M, q[0], q[1], q[2])) {
+                const int o = Uo + R1 * (Vo + R1 * Wo);
+                v = Bc[o] - region_op<3, T, R1, R1 * R1>(M, q, Xc, o);
+            }
+        }
+    }
+    restrict_owned<3, T>(M, J, tl.lv, bq, v);
+}
+
+// 2D: two sweeps per level, the pre-smoothed x2 stored for the
+// post-smoothing (xs of levels l and l+1); loads first, as in 3D
+template <class T>
+__global__ __launch_bounds__(TILE) void k_mg_down2_2(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles,
+                                                     const int *kbase, int koff)
+{
+#pragma clang fp contract(off)
+    constexpr int R1 = 2 * FZ2 + 4, RR = 2 * R1, RL = RR + 4;
+    constexpr int NL = RL * RL, NIL = (NL + TILE - 1) / TILE, N1 = R1 * R1;
+    static_assert(N1 <= TILE, "one level-(l+1) region cell per thread");
+    __shared__ T X1[NL], X2[NL], Bl[NL], Ml[NL];           // level l on the load region
+    __shared__ T Rr[RR * RR];                              // level l residual
+    __shared__ T C1[N1], C2[N1], Bc[N1], Mc[N1];           // level l+1
+    const int k = kidx(kbase, koff);
+    JTile tl;
+    const KJob &J = job_of(jobs, tiles, tl);
+    if (outer_idle(J) || !mg_live(J, k)) return;
+    // level tables by value: read once into registers (through a reference
+    // the compiler reloads the counts inside the loops, a wait each time)
+    const MLevel L = J.lev[tl.lv], M = J.lev[tl.lv + 1];
+    const T w = (T)mg_w<2>();
+    int bq[3];
+    brick_of<2>(M, tl.t, bq);
+    const int o1[2] = {2 * FZ2 * bq[0] - 2, 2 * FZ2 * bq[1] - 2};   // level l+1 region origin
+    const int oL[2] = {2 * o1[0] - 2, 2 * o1[1] - 2};               // level l load region origin
+    const int U = threadIdx.x % R1, V = threadIdx.x / R1;
+    const int g1[2] = {o1[0] + U, o1[1] + V};
+    const bool c1 = (int)threadIdx.x < N1 && in_level(M, g1[0], g1[1], 0);
+    const int I1 = g1[0] + M.nx * g1[1];
+    T bl[NIL], ml[NIL], mc = T(0);
+    {
+        auto mi = G<T>(L.minv);
+        auto b = G<T>(L.b);
+#pragma unroll
+        for (int it = 0; it < NIL; ++it) {
+            const int id = threadIdx.x + it * TILE;
+            const int gx = oL[0] + id % RL, gy = oL[1] + id / RL;
+            const bool ok = id < NL && in_level(L, gx, gy, 0);
+            const int j = ok ? gx + L.nx * gy : 0;
+            const T bv = b[j], mv = mi[j];
+            bl[it] = ok ? bv : T(0);
+            ml[it] = ok ? mv : T(0);
+        }
+        const T m1 = G<T>(M.minv)[c1 ? I1 : 0];
+        mc = c1 ? m1 : T(0);
+    }
+#pragma unroll
+    for (int it = 0; it < NIL; ++it) {
+        const int id = threadIdx.x + it * TILE;
+        if (id < NL) {
+            Bl[id] = bl[it];
+            Ml[id] = ml[it];
+            X1[id] = w * ml[it] * bl[it];
+        }
+    }
+    __syncthreads();
+    for (int id = threadIdx.x; id < NL; id += TILE) {
+        const int u = id % RL, v = id / RL;
+        const int q[3] = {oL[0] + u, oL[1] + v, 0};
+        T x2 = T(0);
+        if (u >= 1 && v >= 1 && u < RL - 1 && v < RL - 1 && in_level(L, q[0], q[1], 0))
+            x2 = X1[id] + w * Ml[id] * (Bl[id] - region_op<2, T, RL, RL * RL>(L, q, X1, id));
+        X2[id] = x2;
+    }
+    __syncthreads();
+    {
+        auto xs = G<T>(L.xs);
+        for (int id = threadIdx.x; id < RR * RR; id += TILE) {
+            const int u = id % RR, v = id / RR;
+            const int o = (u + 2) + RL * (v + 2);
+            const int q[3] = {oL[0] + u + 2, oL[1] + v + 2, 0};
+            T r = T(0);
+            if (in_level(L, q[0], q[1], 0)) {
+                r = Bl[o] - region_op<2, T, RL, RL * RL>(L, q, X2, o);
+                if (u >= 4 && v >= 4 && u < RR - 4 && v < RR - 4) xs[q[0] + L.nx * q[1]] = X2[o];
+            }
+            Rr[id] = r;
+        }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < N1) {
+        T bc = T(0), xc = T(0);
+        if (c1) {
+            bc = (Rr[2 * U + RR * (2 * V)] + Rr[2 * U + 1 + RR * (2 * V)]) +
+                 (Rr[2 * U + RR * (2 * V + 1)] + Rr[2 * U + 1 + RR * (2 * V + 1)]);
+            if (U >= 2 && V >= 2 && U < R1 - 2 && V < R1 - 2) G<T>(M.b)[I1] = bc;
+            xc = w * mc * bc;
+        }
+        Bc[threadIdx.x] = bc;
+        Mc[threadIdx.x] = mc;
+        C1[threadIdx.x] = xc;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < N1) {
+        const int q[3] = {g1[0], g1[1], 0};
+        T x2 = T(0);
+        if (U >= 1 && V >= 1 && U < R1 - 1 && V < R1 - 1 && c1)
+            x2 = C1[threadIdx.x] + w * Mc[threadIdx.x] * (Bc[threadIdx.x] -
+                                                        region_op<2, T, R1, R1 * R1>(M, q, C1, threadIdx.x));
+        C2[threadIdx.x] = x2;
+    }
+    __syncthreads();
+    // owned level-(l+1) cells: 4 lanes per brick cell (threads 0..63)
+    T v = T(0);
+    {
+        const int c = threadIdx.x & 3, a = (int)threadIdx.x >> 2;
+        if (a < FZ2 * FZ2) {
+            const int Uo = 2 + 2 * (a % FZ2) + (c & 1), Vo = 2 + 2 * (a / FZ2) + (c >> 1);
+            const int q[3] = {o1[0] + Uo, o1[1] + Vo, 0};
+            if (in_level(M, q[0], q[1], 0)) {
+                const int o = Uo + R1 * Vo;
+                v = Bc[o] - region_op<2, T, R1, R1 * R1>(M, q, C2, o);
+                G<T>(M.xs)[q[0] + M.nx * q[1]] = C2[o];
+            }
+        }
+    }
+    restrict_owned<2, T>(M, J, tl.lv, bq, v);
+}
+
+// prolong onto and post-smooth levels l+1 and l (3D, one sweep per level):
+// e = x + w D^-1 (b - A x), x = w D^-1 b + mg_og P e_c; the loads of both
+// levels first
+template <class T>
+__global__ __launch_bounds__(TILE) void k_mg_up2_3(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles,
+                                                   const int *kbase, int koff)
+{
+#pragma clang fp contract(off)
+    constexpr int RX1 = 2 * FZ3 + 4, RE = RX1 - 2;   // level l+1: x region 8^3, e region 6^3
+    constexpr int RXL = 4 * FZ3 + 2;                 // level l: x region 10^3 (owned 8^3)
+    constexpr int NC = RX1 * RX1 * RX1, NIC = (NC + TILE - 1) / TILE;
+    constexpr int NLv = RXL * RXL * RXL, NIL = (NLv + TILE - 1) / TILE;
+    __shared__ T Xc[NC], Bc[NC], Mc[NC];
+    __shared__ T Ec[RE * RE * RE];
+    __shared__ T Xl[NLv], Bl[NLv], Ml[NLv];
+    const int k = kidx(kbase, koff);
+    JTile tl;
+    const KJob &J = job_of(jobs, tiles, tl);
+    if (outer_idle(J) || !mg_live(J, k)) return;
+    // level tables by value: read once into registers (through a reference
+    // the compiler reloads the counts inside the loops, a wait each time)
+    const MLevel L = J.lev[tl.lv], M = J.lev[tl.lv + 1];
+    const T w = (T)mg_w<3>(), og = (T)mg_og<3>();
+    int bq[3];
+    brick_of<3>(M, tl.t, bq);
+    int oX1[3], oE[3], oXL[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        oX1[a] = 2 * FZ3 * bq[a] - 2;    // level l+1 x region origin
+        oE[a] = oX1[a] + 1;              // level l+1 e region origin
+        oXL[a] = 4 * FZ3 * bq[a] - 1;    // level l x region origin
+    }
+    T bc[NIC], mc[NIC], ecv[NIC], bl[NIL], ml[NIL];
+    {
+        auto mi = G<T>(M.minv);
+        auto b = G<T>(M.b);
+        auto ec = G<T>(J.lev[tl.lv + 2].e);
+#pragma unroll
+        for (int it = 0; it < NIC; ++it) {
+            const int id = threadIdx.x + it * TILE;
+            const int q[3] = {oX1[0] + id % RX1, oX1[1] + (id / RX1) % RX1, oX1[2] + id / (RX1 * RX1)};
+            const bool ok = id < NC && in_level(M, q[0], q[1], q[2]);
+            const int j = ok ? q[0] + M.nx * (q[1] + M.ny * q[2]) : 0;
+            const int je = ok ? agg_index(M, q) : 0;
+            const T bv = b[j], mv = mi[j], ev = ec[je];
+            bc[it] = ok ? bv : T(0);
+            mc[it] = ok ? mv : T(0);
+            ecv[it] = ok ? ev : T(0);
+        }
+        auto mil = G<T>(L.minv);
+        auto bll = G<T>(L.b);
+#pragma unroll
+        for (int it = 0; it < NIL; ++it) {
+            const int id = threadIdx.x + it * TILE;
+            const int gx = oXL[0] + id % RXL, gy = oXL[1] + (id / RXL) % RXL, gz = oXL[2] + id / (RXL * RXL);
+            const bool ok = id < NLv && in_level(L, gx, gy, gz);
+            const int j = ok ? gx + L.nx * (gy + L.ny * gz) : 0;
+            const T bv = bll[j], mv = mil[j];
+            bl[it] = ok ? bv : T(0);
+            ml[it] = ok ? mv : T(0);
+        }
+    }
+#pragma unroll
+    for (int it = 0; it < NIC; ++it) {
+        const int id = threadIdx.x + it * TILE;
+        if (id < NC) {
+            Bc[id] = bc[it];
+            Mc[id] = mc[it];
+            Xc[id] = w * mc[it] * bc[it] + og * ecv[it];   // exactly 0 off the grid
+        }
+    }
+    __syncthreads();
+    for (int id = threadIdx.x; id < RE * RE * RE; id += TILE) {
+        const int u = id % RE, v = (id / RE) % RE, s = id / (RE * RE);
+        const int q[3] = {oE[0] + u, oE[1] + v, oE[2] + s};
+        T e = T(0);
+        if (in_level(M, q[0], q[1], q[2])) {
+            const int o = (u + 1) + RX1 * ((v + 1) + RX1 * (s + 1));
+            e = Xc[o] + w * Mc[o] * (Bc[o] - region_op<3, T, RX1, RX1 * RX1>(M, q, Xc, o));
+        }
+        Ec[id] = e;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < NIL; ++it) {
+        const int id = threadIdx.x + it * TILE;
+        if (id < NLv) {
+            const int gx = oXL[0] + id % RXL, gy = oXL[1] + (id / RXL) % RXL, gz = oXL[2] + id / (RXL * RXL);
+            T xv = T(0);
+            if (in_level(L, gx, gy, gz)) {
+                const int ce = ((gx >> 1) - oE[0]) + RE * (((gy >> 1) - oE[1]) + RE * ((gz >> 1) - oE[2]));
+                xv = w * ml[it] * bl[it] + og * Ec[ce];
+            }
+            Bl[id] = bl[it];
+            Ml[id] = ml[it];
+            Xl[id] = xv;
+        }
+    }
+    __syncthreads();
+    auto e = G<T>(L.e);
+    constexpr int RO = RXL - 2;
+    for (int id = threadIdx.x; id < RO * RO * RO; id += TILE) {
+        const int u = id % RO, v = (id / RO) % RO, s = id / (RO * RO);
+        const int q[3] = {oXL[0] + 1 + u, oXL[1] + 1 + v, oXL[2] + 1 + s};
+        if (!in_level(L, q[0], q[1], q[2])) continue;
+        const int o = (u + 1) + RXL * ((v + 1) + RXL * (s + 1));
+        e[q[0] + L.nx * (q[1] + L.ny * q[2])] =
+            Xl[o] + w * Ml[o] * (Bl[o] - region_op<3, T, RXL, RXL * RXL>(L, q, Xl, o));
+    }
+}
+
+// 2D: two post-sweeps per level from e0 = x2 + mg_og P e_c; loads first
+template <class T>
+__global__ __launch_bounds__(TILE) void k_mg_up2_2(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles,
+                                                   const int *kbase, int koff)
+{
+#pragma clang fp contract(off)
+    constexpr int RC = 2 * FZ2 + 6;        // level l+1: e0 region 14 (e1 12, e 10)
+    constexpr int RLX = 4 * FZ2 + 4;       // level l: e0 region 20 (e1 18, owned 16)
+    constexpr int NC = RC * RC, NLv = RLX * RLX, NIL = (NLv + TILE - 1) / TILE;
+    static_assert(NC <= TILE, "one level-(l+1) region cell per thread");
+    __shared__ T E0c[NC], E1c[NC], Ec[NC], Bc[NC], Mc[NC];
+    __shared__ T E0[NLv], E1[NLv], Bl[NLv], Ml[NLv];
+    const int k = kidx(kbase, koff);
+    JTile tl;
+    const KJob &J = job_of(jobs, tiles, tl);
+    if (outer_idle(J) || !mg_live(J, k)) return;
+    // level tables by value: read once into registers (through a reference
+    // the compiler reloads the counts inside the loops, a wait each time)
+    const MLevel L = J.lev[tl.lv], M = J.lev[tl.lv + 1];
+    const T w = (T)mg_w<2>(), og = (T)mg_og<2>();
+    int bq[3];
+    brick_of<2>(M, tl.t, bq);
+    const int oC[2] = {2 * FZ2 * bq[0] - 3, 2 * FZ2 * bq[1] - 3};   // level l+1 region origin
+    const int oL[2] = {4 * FZ2 * bq[0] - 2, 4 * FZ2 * bq[1] - 2};   // level l region origin
+    const int Uc = threadIdx.x % RC, Vc = threadIdx.x / RC;
+    const int qc[3] = {oC[0] + Uc, oC[1] + Vc, 0};
+    const bool cc = (int)threadIdx.x < NC && in_level(M, qc[0], qc[1], 0);
+    T bcv = T(0), mcv = T(0), xsc = T(0), ecv = T(0), bl[NIL], ml[NIL], xl[NIL];
+    {
+        {
+            const int j = cc ? qc[0] + M.nx * qc[1] : 0;
+            const int je = cc ? agg_index(M, qc) : 0;
+            const T b1 = G<T>(M.b)[j], m1 = G<T>(M.minv)[j], x1 = G<T>(M.xs)[j], e1 = G<T>(J.lev[tl.lv + 2].e)[je];
+            bcv = cc ? b1 : T(0);
+            mcv = cc ? m1 : T(0);
+            xsc = cc ? x1 : T(0);
+            ecv = cc ? e1 : T(0);
+        }
+        auto mi = G<T>(L.minv);
+        auto b = G<T>(L.b);
+        auto xs = G<T>(L.xs);
+#pragma unroll
+        for (int it = 0; it < NIL; ++it) {
+            const int id = threadIdx.x + it * TILE;
+            const int gx = oL[0] + id % RLX, gy = oL[1] + id / RLX;
+            const bool ok = id < NLv && in_level(L, gx, gy, 0);
+            const int j = ok ? gx + L.nx * gy : 0;
+            const T bv = b[j], mv = mi[j], xv = xs[j];
+            bl[it] = ok ? bv : T(0);
+            ml[it] = ok ? mv : T(0);
+            xl[it] = ok ? xv : T(0);
+        }
+    }
+    if ((int)threadIdx.x < NC) {
+        Bc[threadIdx.x] = bcv;
+        Mc[threadIdx.x] = mcv;
+        E0c[threadIdx.x] = cc ? xsc + og * ecv : T(0);
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < NC) {
+        T e1 = T(0);
+        if (Uc >= 1 && Vc >= 1 && Uc < RC - 1 && Vc < RC - 1 && cc)
+            e1 = E0c[threadIdx.x] + w * Mc[threadIdx.x] * (Bc[threadIdx.x] -
+                                                          region_op<2, T, RC, RC * RC>(M, qc, E0c, threadIdx.x));
+        E1c[threadIdx.x] = e1;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < NC) {
+        T ev = T(0);
+        if (Uc >= 2 && Vc >= 2 && Uc < RC - 2 && Vc < RC - 2 && cc)
+            ev = E1c[threadIdx.x] + w * Mc[threadIdx.x] * (Bc[threadIdx.x] -
+                                                          region_op<2, T, RC, RC * RC>(M, qc, E1c, threadIdx.x));
+        Ec[threadIdx.x] = ev;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < NIL; ++it) {
+        const int id = threadIdx.x + it * TILE;
+        if (id < NLv) {
+            const int gx = oL[0] + id % RLX, gy = oL[1] + id / RLX;
+            Bl[id] = bl[it];
+            Ml[id] = ml[it];
+            E0[id] = in_level(L, gx, gy, 0) ? xl[it] + og * Ec[((gx >> 1) - oC[0]) + RC * ((gy >> 1) - oC[1])]
+                                            : T(0);
+        }
+    }
+    __syncthreads();
+    for (int id = threadIdx.x; id < NLv; id += TILE) {
+        const int u = id % RLX, v = id / RLX;
+        const int q[3] = {oL[0] + u, oL[1] + v, 0};
+        T e1 = T(0);
+        if (u >= 1 && v >= 1 && u < RLX - 1 && v < RLX - 1 && in_level(L, q[0], q[1], 0))
+            e1 = E0[id] + w * Ml[id] * (Bl[id] - region_op<2, T, RLX, RLX * RLX>(L, q, E0, id));
+        E1[id] = e1;
+    }
+    __syncthreads();
+    auto e = G<T>(L.e);
+    for (int id = threadIdx.x; id < NLv; id += TILE) {
+        const int u = id % RLX, v = id / RLX;
+        const int q[3] = {oL[0] + u, oL[1] + v, 0};
+        if (u < 2 || v < 2 || u >= RLX - 2 || v >= RLX - 2 || !in_level(L, q[0], q[1], 0)) continue;
+        e[q[0] + L.nx * q[1]] = E1[id] + w * Ml[id] * (Bl[id] - region_op<2, T, RLX, RLX * RLX>(L, q, E1, id));
+    }
 }
 
 // ------------------------------------------------------------- exact level
@@ -1127,8 +1661,16 @@ static const void *mg_fn_t(int which)
     case KI_MG_EXACT: return (const void *)&k_mg_exact<T>;
     case KI_MG_UP: return (const void *)&k_mg_up<DIM, T>;
     case KI_MG_UP0: return (const void *)&k_mg_up0<DIM, T>;
+    case KI_MG_DOWN2: return DIM == 3 ? (const void *)&k_mg_down2_3<T> : (const void *)&k_mg_down2_2<T>;
+    case KI_MG_UP2: return DIM == 3 ? (const void *)&k_mg_up2_3<T> : (const void *)&k_mg_up2_2<T>;
     }
     return nullptr;
+}
+
+int mg_fused_bricks(int dim, const MLevel &M)
+{
+    const int B = fused_brick(dim);
+    return ceil_div(M.cnx, B) * ceil_div(M.cny, B) * (dim == 3 ? ceil_div(M.cnz, B) : 1);
 }
 
 const void *mg_fn(int which, int nd, int fp32)

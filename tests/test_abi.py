@@ -107,7 +107,8 @@ def test_binding_constants_match_header():
     for name in ("SOL_OK", "SOL_EINVAL", "SOL_ENOMEM", "SOL_ENOCONV", "SOL_ENONFINITE", "SOL_EDEVICE", "SOL_EBUSY"):
         assert getattr(B, name) == d[name], name
     assert (B.OPT_GRAPH, B.OPT_PRECOND, B.OPT_TPRECOND) == (d["SOL_OPT_GRAPH"], d["SOL_OPT_PRECOND"], d["SOL_OPT_TPRECOND"])
-    assert (B.OPT_ASSEMBLY, B.OPT_MOMENTUM) == (d["SOL_OPT_ASSEMBLY"], d["SOL_OPT_MOMENTUM"])
+    assert (B.OPT_ASSEMBLY, B.OPT_MOMENTUM, B.OPT_MG_FUSE) == (d["SOL_OPT_ASSEMBLY"], d["SOL_OPT_MOMENTUM"],
+                                                               d["SOL_OPT_MG_FUSE"])
     assert B.ASSEMBLY == dict(stencil=d["SOL_ASSEMBLY_STENCIL"], forward=d["SOL_ASSEMBLY_FORWARD"])
     assert (B.MOMENTUM_PLAIN, B.MOMENTUM_MINIMAL) == (d["SOL_MOMENTUM_PLAIN"], d["SOL_MOMENTUM_MINIMAL"])
     import workloads as W
@@ -124,7 +125,7 @@ def test_set_option_rejects_null_handle(sol):
     from paper_2303_10783_amd import binding as B
     L = sol.load()
     for opt, val in ((B.OPT_GRAPH, 1), (B.OPT_PRECOND, 0), (B.OPT_TPRECOND, 2), (B.OPT_ASSEMBLY, 1),
-                     (B.OPT_MOMENTUM, 1)):
+                     (B.OPT_MOMENTUM, 1), (B.OPT_MG_FUSE, 0)):
         assert L.sol_set_option(None, opt, val) == B.SOL_EINVAL
 
 
