@@ -167,12 +167,15 @@ def run_single(sol, W, key, precision, steps, warmup, dev, *, precond="mg", tpre
         h.step(warmup)
         h.write_fields(case["init"])
     torch.cuda.synchronize()
+    d0 = sol.binding.dispatch_count()
     t0 = time.perf_counter()
     st = h.step(steps)
     torch.cuda.synchronize()
     secs = time.perf_counter() - t0
+    launches = (sol.binding.dispatch_count() - d0) / steps
     out = dict(workload=_describe(key, case), cells=ncell, precision=precision, value=ncell * steps / secs,
-               ms_per_step=1e3 * secs / steps, steps=steps, warmup=warmup, tol=case["numerics"]["tol_p"],
+               ms_per_step=1e3 * secs / steps, launches_per_step=round(launches, 1),
+               steps=steps, warmup=warmup, tol=case["numerics"]["tol_p"],
                tol_transport=case["numerics"]["tol_t"],
                krylov_iters_per_step={n: round(st["iters_total"][i] / steps, 1) for i, n in enumerate("uvwpCT")},
                steps_redone=st["redone"])
@@ -248,15 +251,18 @@ def run_batched(sol, W, precision, steps, warmup, dev, n_cases=64, graph=True, t
             h.write_fields(c["init"])
         b = sol.Batch(hs)
     torch.cuda.synchronize()
+    d0 = sol.binding.dispatch_count()
     t0 = time.perf_counter()
     b.step(steps)
     torch.cuda.synchronize()
     secs = time.perf_counter() - t0
+    launches = (sol.binding.dispatch_count() - d0) / steps
     b.close()
     for h in hs:
         h.close()
     return dict(workload=f"C4: {n_cases} 2D cavities in one batch", precision=precision,
-                value=sum(cells) * steps / secs, ms_per_step=1e3 * secs / steps, steps=steps, warmup=warmup,
+                value=sum(cells) * steps / secs, ms_per_step=1e3 * secs / steps,
+                launches_per_step=round(launches, 1), steps=steps, warmup=warmup,
                 cases=n_cases, cells=sum(cells), min_cells=min(cells), max_cells=max(cells),
                 tol=cases[0]["numerics"]["tol_p"], tol_transport=cases[0]["numerics"]["tol_t"],
                 graph=graph, tuned_rows_per_tile={str(k): v for k, v in sorted(tuned.items())})
@@ -485,7 +491,8 @@ def main():
     case = W.workload_case(args.workload)
     out = dict(
         metric=METRIC, value=head["value"], unit="cell-updates/s", n_gpus=1, steps=steps,
-        warmup=args.warmup, ms_per_step=head["ms_per_step"], higher_is_better=True,
+        warmup=args.warmup, ms_per_step=head["ms_per_step"], launches_per_step=head["launches_per_step"],
+        higher_is_better=True,
         scaling="weak", vs_baseline=None, dtype="f64" if args.precision == "fp64" else "f32+f64", data="synthetic",
         config=dict(workload=head["workload"] + f", {steps} steps from the initial state",
                     cells=head["cells"], dt=case["numerics"]["dt"], tol=case["numerics"]["tol_p"],

@@ -284,6 +284,13 @@ int sol_set_timing(sol_handle *h, int32_t enable);
 int sol_get_timing(sol_handle *h, int32_t kclass, int64_t *launches, double *total_ms,
                    double *bytes);
 
+/* Number of device work items the library has queued in this process, over
+   all handles and batches: kernel dispatches (each node of a replayed graph
+   counts) and device-to-host copies of solver state; monotonic.  The
+   difference over a run of sol_step calls, divided by the steps, is the
+   launches per time step.  NULL -> SOL_EINVAL. */
+int sol_dispatch_count(int64_t *count);
+
 /* Options.  SOL_OPT_GRAPH (0/1): replay chunks of 16 Krylov iterations as
    instantiated HIP graphs (the iteration index comes from a device counter
    the graph advances) instead of launching each kernel; batches follow the

@@ -119,6 +119,7 @@ def load():
         "sol_set_timing": ([P, I32], I32),
         "sol_get_timing": ([P, I32, C.POINTER(C.c_int64), dp, dp], I32),
         "sol_set_option": ([P, I32, C.c_int64], I32),
+        "sol_dispatch_count": ([C.POINTER(C.c_int64)], I32),
         "sol_autotune": ([P, ip], I32),
         "sol_last_error": ([], C.c_char_p),
         "sol_version": ([], C.c_char_p),
@@ -135,7 +136,16 @@ def exported_symbols():
     return ["sol_create", "sol_destroy", "sol_write_fields", "sol_read_fields", "sol_system_size",
             "sol_assemble", "sol_read_matrix", "sol_read_matrix_noalloc", "sol_step", "sol_footprint_bytes",
             "sol_batch_create", "sol_batch_step", "sol_batch_destroy", "sol_set_timing",
-            "sol_get_timing", "sol_set_option", "sol_autotune", "sol_last_error", "sol_version"]
+            "sol_get_timing", "sol_set_option", "sol_autotune", "sol_last_error", "sol_version",
+            "sol_dispatch_count"]
+
+
+def dispatch_count() -> int:
+    """Device work items (kernel dispatches, graph nodes, state copies) the
+    library has queued in this process so far."""
+    n = C.c_int64(0)
+    check(load().sol_dispatch_count(C.byref(n)))
+    return n.value
 
 
 def check(rc):

@@ -350,6 +350,7 @@ struct JobSet {
     int nt[2] = {0, 0};
     hipGraph_t graph = nullptr;          // GCH iterations + advance of the index base
     hipGraphExec_t exec = nullptr;
+    int graph_nodes = 0;                 // kernel nodes of the graph
     std::vector<Stage> iter;             // launches of one iteration
     std::vector<Stage> start;            // multigrid: the V-cycle of the start (after its init kernel)
 };
@@ -911,6 +912,7 @@ static int build_chunk_graph(Group &g, Phase &P, JobSet &S, int fp32)
                 hipGraphNode_t node;
                 HIPCHK(hipGraphAddKernelNode(&node, S.graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp));
                 prev = node;
+                ++S.graph_nodes;
             }
     {
         int *kb = g.kbase_d;
@@ -924,6 +926,7 @@ static int build_chunk_graph(Group &g, Phase &P, JobSet &S, int fp32)
         kp.kernelParams = args;
         hipGraphNode_t node;
         HIPCHK(hipGraphAddKernelNode(&node, S.graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp));
+        ++S.graph_nodes;
     }
     HIPCHK(hipGraphInstantiate(&S.exec, S.graph, nullptr, nullptr, 0));
     return SOL_OK;
@@ -942,6 +945,7 @@ static int launch_stage(Group &g, const JobSet &S, const Stage &st, int fp32, in
         const int *kb = nullptr;
         void *args[] = {(void *)&jobs, (void *)&tiles, (void *)&kb, (void *)&koff};
         const void *fn = kiter_fn(st.which, gi ? 7 : 5, fp32, st.two[gi]);
+        note_dispatch(1);
         if (ta && tb)
             HIPCHK(hipExtLaunchKernel(fn, dim3((unsigned)st.nt[gi]), dim3(TILE), args, st.smem[gi], g.stream, ta, tb, 0));
         else
@@ -980,6 +984,7 @@ static int enqueue_iters(Group &g, Phase &P, JobSet &S, int fp32, int nits, int 
         launch_kbase_set(g.kbase_d, k, g.stream);
         const int chunks = ceil_div(nits, GCH);
         for (int c = 0; c < chunks; ++c) HIPCHK(hipGraphLaunch(S.exec, g.stream));
+        note_dispatch((long)chunks * S.graph_nodes);
         k += chunks * GCH;
         P.launched += chunks * GCH;
         return SOL_OK;
@@ -1015,6 +1020,7 @@ static int enqueue_iters(Group &g, Phase &P, JobSet &S, int fp32, int nits, int 
 
 static int poll_enqueue(Group &g, int slot)
 {
+    note_dispatch(1);
     HIPCHK(hipMemcpyAsync(g.ks_h[slot], g.ks_d, sizeof(KState) * 2 * g.nks, hipMemcpyDeviceToHost, g.stream));
     HIPCHK(hipEventRecord(g.ev[slot], g.stream));
     return SOL_OK;
@@ -1878,6 +1884,7 @@ static int fill_stats(Group &g, int c, sol_step_stats *st, const int64_t *tot)
     KState ks[NSYS];
     double red[16];
     int64_t step = 0;
+    note_dispatch(3);
     HIPCHK(hipMemcpyAsync(ks, g.ks_d + c * NSYS, sizeof(ks), hipMemcpyDeviceToHost, g.stream));
     HIPCHK(hipMemcpyAsync(red, g.red_d + 16 * c, sizeof(red), hipMemcpyDeviceToHost, g.stream));
     HIPCHK(hipMemcpyAsync(&step, h->cd.step, sizeof(step), hipMemcpyDeviceToHost, g.stream));
@@ -1942,6 +1949,13 @@ int sol_step(sol_handle *h, int32_t nsteps, sol_step_stats *stats)
     }
     if (stats) RCHK(fill_stats(g, 0, stats, tot));
     else HIPCHK(hipStreamSynchronize(h->stream));
+    return SOL_OK;
+}
+
+int sol_dispatch_count(int64_t *count)
+{
+    if (!count) return fail(SOL_EINVAL, "NULL argument");
+    *count = (int64_t)dispatch_count();
     return SOL_OK;
 }
 

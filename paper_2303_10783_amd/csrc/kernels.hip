@@ -13,7 +13,13 @@
 #include "kcommon.hpp"
 #include "kernels.hpp"
 
+#include <atomic>
+
 namespace sol {
+
+static std::atomic<long> g_dispatches{0};
+void note_dispatch(long n) { g_dispatches.fetch_add(n, std::memory_order_relaxed); }
+long dispatch_count() { return g_dispatches.load(std::memory_order_relaxed); }
 
 // ----------------------------------------------------------- grid helpers
 
@@ -1711,52 +1717,52 @@ __global__ __launch_bounds__(TILE) void k_fwd_transport(const CaseDev *__restric
 void launch_asm_const(int dim, const CaseDev *c, const Tile *t, int nt, hipStream_t s)
 {
     if (nt <= 0) return;
-    if (dim == 2) hipLaunchKernelGGL(k_asm_const<2>, GRID(nt), 0, s, c, t);
-    else hipLaunchKernelGGL(k_asm_const<3>, GRID(nt), 0, s, c, t);
+    if (dim == 2) SOL_LAUNCH(k_asm_const<2>, GRID(nt), 0, s, c, t);
+    else SOL_LAUNCH(k_asm_const<3>, GRID(nt), 0, s, c, t);
 }
 void launch_asm_momentum(int dim, const CaseDev *c, const Tile *t, int nt, hipStream_t s, int fwd)
 {
     if (nt <= 0) return;
     if (fwd) {
-        if (dim == 2) hipLaunchKernelGGL(k_fwd_momentum<2>, GRID(nt), 0, s, c, t);
-        else hipLaunchKernelGGL(k_fwd_momentum<3>, GRID(nt), 0, s, c, t);
+        if (dim == 2) SOL_LAUNCH(k_fwd_momentum<2>, GRID(nt), 0, s, c, t);
+        else SOL_LAUNCH(k_fwd_momentum<3>, GRID(nt), 0, s, c, t);
         return;
     }
-    if (dim == 2) hipLaunchKernelGGL(k_asm_momentum<2>, GRID(nt), 0, s, c, t);
-    else hipLaunchKernelGGL(k_asm_momentum<3>, GRID(nt), 0, s, c, t);
+    if (dim == 2) SOL_LAUNCH(k_asm_momentum<2>, GRID(nt), 0, s, c, t);
+    else SOL_LAUNCH(k_asm_momentum<3>, GRID(nt), 0, s, c, t);
 }
 void launch_asm_transport(int dim, const CaseDev *c, const Tile *t, int nt, int vel_src, hipStream_t s, int fwd)
 {
     if (nt <= 0) return;
     if (fwd) {
-        if (dim == 2) hipLaunchKernelGGL(k_fwd_transport<2>, GRID(nt), 0, s, c, t, vel_src);
-        else hipLaunchKernelGGL(k_fwd_transport<3>, GRID(nt), 0, s, c, t, vel_src);
+        if (dim == 2) SOL_LAUNCH(k_fwd_transport<2>, GRID(nt), 0, s, c, t, vel_src);
+        else SOL_LAUNCH(k_fwd_transport<3>, GRID(nt), 0, s, c, t, vel_src);
         return;
     }
-    if (dim == 2) hipLaunchKernelGGL(k_asm_transport<2>, GRID(nt), 0, s, c, t, vel_src);
-    else hipLaunchKernelGGL(k_asm_transport<3>, GRID(nt), 0, s, c, t, vel_src);
+    if (dim == 2) SOL_LAUNCH(k_asm_transport<2>, GRID(nt), 0, s, c, t, vel_src);
+    else SOL_LAUNCH(k_asm_transport<3>, GRID(nt), 0, s, c, t, vel_src);
 }
 void launch_div_rhs(int dim, const CaseDev *c, const Tile *t, int nt, int vel_src, hipStream_t s)
 {
     if (nt <= 0) return;
-    if (dim == 2) hipLaunchKernelGGL(k_div_rhs<2>, GRID(nt), 0, s, c, t, vel_src);
-    else hipLaunchKernelGGL(k_div_rhs<3>, GRID(nt), 0, s, c, t, vel_src);
+    if (dim == 2) SOL_LAUNCH(k_div_rhs<2>, GRID(nt), 0, s, c, t, vel_src);
+    else SOL_LAUNCH(k_div_rhs<3>, GRID(nt), 0, s, c, t, vel_src);
 }
 void launch_sub_mean(const CaseDev *c, const Tile *t, int nt, hipStream_t s)
 {
     if (nt <= 0) return;
-    hipLaunchKernelGGL(k_sub_mean, GRID(nt), 0, s, c, t);
+    SOL_LAUNCH(k_sub_mean, GRID(nt), 0, s, c, t);
 }
 void launch_project(const CaseDev *c, const Tile *t, int nt, hipStream_t s)
 {
     if (nt <= 0) return;
-    hipLaunchKernelGGL(k_project, GRID(nt), 0, s, c, t);
+    SOL_LAUNCH(k_project, GRID(nt), 0, s, c, t);
 }
 void launch_phase_commit(int dim, const CaseDev *c, const Tile *t, int nt, hipStream_t s)
 {
     if (nt <= 0) return;
-    if (dim == 2) hipLaunchKernelGGL(k_phase_commit<2>, GRID(nt), 0, s, c, t);
-    else hipLaunchKernelGGL(k_phase_commit<3>, GRID(nt), 0, s, c, t);
+    if (dim == 2) SOL_LAUNCH(k_phase_commit<2>, GRID(nt), 0, s, c, t);
+    else SOL_LAUNCH(k_phase_commit<3>, GRID(nt), 0, s, c, t);
 }
 
 template <int ND, class T>
@@ -1790,7 +1796,7 @@ const void *kbase_add_fn() { return (const void *)&k_kbase_add; }
 
 void launch_kbase_set(int *kbase, int v, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_kbase_set, dim3(1), dim3(64), 0, s, kbase, v);
+    SOL_LAUNCH(k_kbase_set, dim3(1), dim3(64), 0, s, kbase, v);
 }
 
 // deterministic right-hand side for the tile-size tuner: +1, -1, +1, ...
@@ -1805,8 +1811,8 @@ __global__ void k_tune_rhs(T *b, int n)
 void launch_tune_rhs(void *b, int fp32, int n, hipStream_t s)
 {
     if (n <= 0) return;
-    if (fp32) hipLaunchKernelGGL(k_tune_rhs<float>, dim3(ceil_div(n, TILE)), dim3(TILE), 0, s, (float *)b, n);
-    else hipLaunchKernelGGL(k_tune_rhs<double>, dim3(ceil_div(n, TILE)), dim3(TILE), 0, s, (double *)b, n);
+    if (fp32) SOL_LAUNCH(k_tune_rhs<float>, dim3(ceil_div(n, TILE)), dim3(TILE), 0, s, (float *)b, n);
+    else SOL_LAUNCH(k_tune_rhs<double>, dim3(ceil_div(n, TILE)), dim3(TILE), 0, s, (double *)b, n);
 }
 
 template <int ND, class T>
@@ -1814,13 +1820,13 @@ static void launch_init_nd(int kind, bool two, const KJob *j, const JTile *t, in
                            hipStream_t s)
 {
     if (kind == K_CG) {
-        hipLaunchKernelGGL((k_cg_init_a<ND, T>), GRID(nt), 0, s, j, t, k, mode);
-        hipLaunchKernelGGL((k_cg_init_b<ND, T>), GRID(nt), 0, s, j, t, k, mode);
+        SOL_LAUNCH((k_cg_init_a<ND, T>), GRID(nt), 0, s, j, t, k, mode);
+        SOL_LAUNCH((k_cg_init_b<ND, T>), GRID(nt), 0, s, j, t, k, mode);
         return;
     }
-    hipLaunchKernelGGL((k_bicg_init<ND, T>), GRID(nt), 0, s, j, t, k, mode);
-    if (two) hipLaunchKernelGGL((k_bicg_first<ND, 2, T>), dim3(nt), dim3(TILE), smem, s, j, t, k);
-    else hipLaunchKernelGGL((k_bicg_first<ND, 1, T>), GRID(nt), 0, s, j, t, k);
+    SOL_LAUNCH((k_bicg_init<ND, T>), GRID(nt), 0, s, j, t, k, mode);
+    if (two) SOL_LAUNCH((k_bicg_first<ND, 2, T>), dim3(nt), dim3(TILE), smem, s, j, t, k);
+    else SOL_LAUNCH((k_bicg_first<ND, 1, T>), GRID(nt), 0, s, j, t, k);
 }
 
 void launch_kinit(int kind, int nd, int fp32, bool two, const KJob *j, const JTile *t, int nt, int k, int mode,
@@ -1839,50 +1845,50 @@ void launch_kinit(int kind, int nd, int fp32, bool two, const KJob *j, const JTi
 void launch_kfinish(int nd, const KJob *j, const JTile *t, int nt, hipStream_t s)
 {
     if (nt <= 0) return;
-    if (nd == 5) hipLaunchKernelGGL(k_kfinish<5>, GRID(nt), 0, s, j, t);
-    else hipLaunchKernelGGL(k_kfinish<7>, GRID(nt), 0, s, j, t);
+    if (nd == 5) SOL_LAUNCH(k_kfinish<5>, GRID(nt), 0, s, j, t);
+    else SOL_LAUNCH(k_kfinish<7>, GRID(nt), 0, s, j, t);
 }
 void launch_kdecide(const KJob *j, int njobs, hipStream_t s)
 {
     if (njobs <= 0) return;
-    hipLaunchKernelGGL(k_kdecide, dim3(njobs), dim3(TILE), 0, s, j, njobs);
+    SOL_LAUNCH(k_kdecide, dim3(njobs), dim3(TILE), 0, s, j, njobs);
 }
 void launch_ir_resid(int nd, const KJob *j, const JTile *t, int nt, int mode, hipStream_t s)
 {
     if (nt <= 0) return;
-    if (nd == 5) hipLaunchKernelGGL(k_ir_resid<5>, GRID(nt), 0, s, j, t, mode);
-    else hipLaunchKernelGGL(k_ir_resid<7>, GRID(nt), 0, s, j, t, mode);
+    if (nd == 5) SOL_LAUNCH(k_ir_resid<5>, GRID(nt), 0, s, j, t, mode);
+    else SOL_LAUNCH(k_ir_resid<7>, GRID(nt), 0, s, j, t, mode);
 }
 void launch_ir_decide(const KJob *j, int njobs, int mode, int max_outer, hipStream_t s)
 {
     if (njobs <= 0) return;
-    hipLaunchKernelGGL(k_ir_decide, dim3(njobs), dim3(TILE), 0, s, j, njobs, mode, max_outer);
+    SOL_LAUNCH(k_ir_decide, dim3(njobs), dim3(TILE), 0, s, j, njobs, mode, max_outer);
 }
 void launch_ir_update(int nd, const KJob *j, const JTile *t, int nt, hipStream_t s)
 {
     if (nt <= 0) return;
-    if (nd == 5) hipLaunchKernelGGL(k_ir_update<5>, GRID(nt), 0, s, j, t);
-    else hipLaunchKernelGGL(k_ir_update<7>, GRID(nt), 0, s, j, t);
+    if (nd == 5) SOL_LAUNCH(k_ir_update<5>, GRID(nt), 0, s, j, t);
+    else SOL_LAUNCH(k_ir_update<7>, GRID(nt), 0, s, j, t);
 }
 void launch_ir_close(const KJob *j, int njobs, hipStream_t s)
 {
     if (njobs <= 0) return;
-    hipLaunchKernelGGL(k_ir_close, dim3(ceil_div(njobs, 64)), dim3(64), 0, s, j, njobs);
+    SOL_LAUNCH(k_ir_close, dim3(ceil_div(njobs, 64)), dim3(64), 0, s, j, njobs);
 }
 void launch_guess(const CaseDev *c, const Tile *t, int nt, hipStream_t s)
 {
     if (nt <= 0) return;
-    hipLaunchKernelGGL(k_guess, GRID(nt), 0, s, c, t);
+    SOL_LAUNCH(k_guess, GRID(nt), 0, s, c, t);
 }
 void launch_hist_reset(const CaseDev *c, int ncase, hipStream_t s)
 {
     if (ncase <= 0) return;
-    hipLaunchKernelGGL(k_hist_reset, dim3(ceil_div(ncase, 64)), dim3(64), 0, s, c, ncase);
+    SOL_LAUNCH(k_hist_reset, dim3(ceil_div(ncase, 64)), dim3(64), 0, s, c, ncase);
 }
 void launch_case_stats(const CaseDev *c, const int32_t *cidx, int ncase, hipStream_t s)
 {
     if (ncase <= 0) return;
-    hipLaunchKernelGGL(k_case_stats, dim3(ncase), dim3(TILE), 0, s, c, cidx);
+    SOL_LAUNCH(k_case_stats, dim3(ncase), dim3(TILE), 0, s, c, cidx);
 }
 void launch_csr(int dim, const CaseDev *cd, int s, int n, int32_t *cnt, int32_t *row_ptr, int32_t *col,
                 double *val, int build_pattern, hipStream_t st)
@@ -1890,38 +1896,38 @@ void launch_csr(int dim, const CaseDev *cd, int s, int n, int32_t *cnt, int32_t 
     if (n <= 0) return;
     const int nb = ceil_div(n, TILE);
     if (build_pattern) {
-        if (dim == 2) hipLaunchKernelGGL(k_csr_count<2>, dim3(nb), dim3(TILE), 0, st, cd, s, cnt);
-        else hipLaunchKernelGGL(k_csr_count<3>, dim3(nb), dim3(TILE), 0, st, cd, s, cnt);
-        hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, cnt, row_ptr, n);
+        if (dim == 2) SOL_LAUNCH(k_csr_count<2>, dim3(nb), dim3(TILE), 0, st, cd, s, cnt);
+        else SOL_LAUNCH(k_csr_count<3>, dim3(nb), dim3(TILE), 0, st, cd, s, cnt);
+        SOL_LAUNCH(k_scan, dim3(1), dim3(1024), 0, st, cnt, row_ptr, n);
     }
-    if (dim == 2) hipLaunchKernelGGL(k_csr_fill<2>, dim3(nb), dim3(TILE), 0, st, cd, s, row_ptr, col, val, 0, n, 0);
-    else hipLaunchKernelGGL(k_csr_fill<3>, dim3(nb), dim3(TILE), 0, st, cd, s, row_ptr, col, val, 0, n, 0);
+    if (dim == 2) SOL_LAUNCH(k_csr_fill<2>, dim3(nb), dim3(TILE), 0, st, cd, s, row_ptr, col, val, 0, n, 0);
+    else SOL_LAUNCH(k_csr_fill<3>, dim3(nb), dim3(TILE), 0, st, cd, s, row_ptr, col, val, 0, n, 0);
 }
 void launch_csr_pattern(int dim, const CaseDev *cd, int s, int n, int32_t *cnt, int32_t *row_ptr, hipStream_t st)
 {
     if (n <= 0) return;
     const int nb = ceil_div(n, TILE);
-    if (dim == 2) hipLaunchKernelGGL(k_csr_count<2>, dim3(nb), dim3(TILE), 0, st, cd, s, cnt);
-    else hipLaunchKernelGGL(k_csr_count<3>, dim3(nb), dim3(TILE), 0, st, cd, s, cnt);
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, cnt, row_ptr, n);
+    if (dim == 2) SOL_LAUNCH(k_csr_count<2>, dim3(nb), dim3(TILE), 0, st, cd, s, cnt);
+    else SOL_LAUNCH(k_csr_count<3>, dim3(nb), dim3(TILE), 0, st, cd, s, cnt);
+    SOL_LAUNCH(k_scan, dim3(1), dim3(1024), 0, st, cnt, row_ptr, n);
 }
 void launch_csr_rows(int dim, const CaseDev *cd, int s, int r0, int r1, const int32_t *row_ptr, int base,
                      int32_t *col, double *val, hipStream_t st)
 {
     if (r1 <= r0) return;
     const int nb = ceil_div(r1 - r0, TILE);
-    if (dim == 2) hipLaunchKernelGGL(k_csr_fill<2>, dim3(nb), dim3(TILE), 0, st, cd, s, row_ptr, col, val, r0, r1, base);
-    else hipLaunchKernelGGL(k_csr_fill<3>, dim3(nb), dim3(TILE), 0, st, cd, s, row_ptr, col, val, r0, r1, base);
+    if (dim == 2) SOL_LAUNCH(k_csr_fill<2>, dim3(nb), dim3(TILE), 0, st, cd, s, row_ptr, col, val, r0, r1, base);
+    else SOL_LAUNCH(k_csr_fill<3>, dim3(nb), dim3(TILE), 0, st, cd, s, row_ptr, col, val, r0, r1, base);
 }
 void launch_fill(double *x, double v, int n, hipStream_t s)
 {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_fill, dim3(ceil_div(n, TILE)), dim3(TILE), 0, s, x, v, n);
+    SOL_LAUNCH(k_fill, dim3(ceil_div(n, TILE)), dim3(TILE), 0, s, x, v, n);
 }
 void launch_set_status(KState *st, int n, int status, hipStream_t s)
 {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_set_status, dim3(ceil_div(n, 64)), dim3(64), 0, s, st, n, status);
+    SOL_LAUNCH(k_set_status, dim3(ceil_div(n, 64)), dim3(64), 0, s, st, n, status);
 }
 
 }  // namespace sol

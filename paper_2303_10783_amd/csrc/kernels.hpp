@@ -4,6 +4,17 @@
 
 namespace sol {
 
+// Process-wide count of the device work items the library has queued:
+// kernel dispatches (graph nodes included) and device copies.  Every kernel
+// launch of the library goes through SOL_LAUNCH.
+void note_dispatch(long n);
+long dispatch_count();
+#define SOL_LAUNCH(...)                \
+    do {                               \
+        ::sol::note_dispatch(1);       \
+        hipLaunchKernelGGL(__VA_ARGS__); \
+    } while (0)
+
 void launch_asm_const(int dim, const CaseDev *c, const Tile *t, int nt, hipStream_t s);
 // fwd: the forward (residual-probing) assembly kernels instead of the
 // stencil kernels (same systems, up to rounding)

@@ -324,8 +324,8 @@ void launch_mg_minv(int dim, const MLevel *lev, int l, int n, double *mi, float 
 {
     if (n <= 0) return;
     const dim3 g(ceil_div(n, TILE)), b(TILE);
-    if (dim == 2) hipLaunchKernelGGL(k_mg_minv<2>, g, b, 0, s, lev, l, mi, mi32);
-    else hipLaunchKernelGGL(k_mg_minv<3>, g, b, 0, s, lev, l, mi, mi32);
+    if (dim == 2) SOL_LAUNCH(k_mg_minv<2>, g, b, 0, s, lev, l, mi, mi32);
+    else SOL_LAUNCH(k_mg_minv<3>, g, b, 0, s, lev, l, mi, mi32);
 }
 
 // ------------------------------------------------------------- start
@@ -1635,17 +1635,17 @@ void launch_mg_pinv(int dim, const MLevel *lev, int l, int n, double *P, float *
     if (n <= 0) return;
     const int nn = n * n;
     const dim3 g(ceil_div(nn, TILE)), b(TILE);
-    if (dim == 2) hipLaunchKernelGGL(k_mg_pdense<2>, g, b, 0, s, lev, l, P);
-    else hipLaunchKernelGGL(k_mg_pdense<3>, g, b, 0, s, lev, l, P);
-    hipLaunchKernelGGL(k_mg_pshift, dim3(1), dim3(TILE), 0, s, (const double *)P, n, work);
-    hipLaunchKernelGGL(k_mg_padd, g, b, 0, s, P, n, (const double *)work);
+    if (dim == 2) SOL_LAUNCH(k_mg_pdense<2>, g, b, 0, s, lev, l, P);
+    else SOL_LAUNCH(k_mg_pdense<3>, g, b, 0, s, lev, l, P);
+    SOL_LAUNCH(k_mg_pshift, dim3(1), dim3(TILE), 0, s, (const double *)P, n, work);
+    SOL_LAUNCH(k_mg_padd, g, b, 0, s, P, n, (const double *)work);
     static_assert(MG_GJB * MG_GJB == TILE, "one thread per entry of the diagonal block");
     for (int k0 = 0; k0 < n; k0 += MG_GJB) {
         const int bk = std::min(MG_GJB, n - k0);
-        hipLaunchKernelGGL(k_mg_pgj_a, dim3(ceil_div(n, TILE)), b, 0, s, (const double *)P, n, k0, bk, work);
-        hipLaunchKernelGGL(k_mg_pgj_b, g, b, 0, s, P, n, k0, bk, (const double *)work);
+        SOL_LAUNCH(k_mg_pgj_a, dim3(ceil_div(n, TILE)), b, 0, s, (const double *)P, n, k0, bk, work);
+        SOL_LAUNCH(k_mg_pgj_b, g, b, 0, s, P, n, k0, bk, (const double *)work);
     }
-    if (P32) hipLaunchKernelGGL(k_mg_p32, g, b, 0, s, (const double *)P, P32, nn);
+    if (P32) SOL_LAUNCH(k_mg_p32, g, b, 0, s, (const double *)P, P32, nn);
 }
 
 // ------------------------------------------------------------- launchers
@@ -1684,11 +1684,11 @@ void launch_mg_init(int nd, int fp32, const KJob *j, const JTile *t, int nt, int
     if (nt <= 0) return;
     const dim3 g(nt), b(TILE);
     if (nd == 5) {
-        if (fp32) hipLaunchKernelGGL((k_mg_init<2, float>), g, b, 0, s, j, t, k, mode);
-        else hipLaunchKernelGGL((k_mg_init<2, double>), g, b, 0, s, j, t, k, mode);
+        if (fp32) SOL_LAUNCH((k_mg_init<2, float>), g, b, 0, s, j, t, k, mode);
+        else SOL_LAUNCH((k_mg_init<2, double>), g, b, 0, s, j, t, k, mode);
     } else {
-        if (fp32) hipLaunchKernelGGL((k_mg_init<3, float>), g, b, 0, s, j, t, k, mode);
-        else hipLaunchKernelGGL((k_mg_init<3, double>), g, b, 0, s, j, t, k, mode);
+        if (fp32) SOL_LAUNCH((k_mg_init<3, float>), g, b, 0, s, j, t, k, mode);
+        else SOL_LAUNCH((k_mg_init<3, double>), g, b, 0, s, j, t, k, mode);
     }
 }
 

@@ -79,6 +79,17 @@ def test_null_arguments(sol):
     assert L.sol_batch_create(None, 0, C.byref(h)) == binding.SOL_EINVAL
     L.sol_destroy(None)
     L.sol_batch_destroy(None)
+    assert L.sol_dispatch_count(None) == binding.SOL_EINVAL
+
+
+def test_dispatch_count_without_device_work(sol):
+    """The dispatch counter is readable without a device and does not move
+    for calls rejected before any device work."""
+    from paper_2303_10783_amd import binding
+    n0 = binding.dispatch_count()
+    L = sol.load()
+    assert L.sol_step(None, 1, None) == binding.SOL_EINVAL
+    assert binding.dispatch_count() == n0 >= 0
 
 
 def test_footprint_scales_with_cells(sol):
