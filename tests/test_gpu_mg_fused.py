@@ -33,14 +33,19 @@ def dev(sol):
 
 def _case(shape, precision, seed):
     if len(shape) == 2:
+        nx, ny = shape
+        if ny < 8:
+            return W.cavity_2d(nx, ny, lx=nx * 1e-4, ly=ny * 1e-4, seed=seed, precision=precision)
         return W.cavity_2d(*shape, seed=seed, precision=precision)
     nx, ny, nz = shape
     return W.box_3d(nx, ny, nz, lx=nx * 1e-3, ly=ny * 1e-3, lz=nz * 1e-3, seed=seed, precision=precision)
 
 
 # coarse levels above the exact one: (301, 183) and the 3D grids have two
-# (one fused pair); (600, 400) has three (a pair and a single level)
-SHAPES = [(301, 183), (600, 400), (72, 40, 40), (97, 75, 53)]
+# (one fused pair); (600, 400) has three (a pair and a single level);
+# (8000, 2) is one cell high from level 1 on and (256, 256, 2) one cell deep,
+# so their bricks straddle single-cell axes
+SHAPES = [(301, 183), (600, 400), (72, 40, 40), (97, 75, 53), (8000, 2), (256, 256, 2)]
 
 
 @pytest.mark.parametrize("precision", [W.PRECISION_FP64, W.PRECISION_MIXED], ids=["fp64", "mixed"])
