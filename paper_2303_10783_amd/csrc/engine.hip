@@ -338,6 +338,7 @@ struct Stage {
     int nt[2] = {0, 0};
     size_t smem[2] = {0, 0};
     bool two[2] = {false, false};        // BiCGSTAB: two Jacobi sweeps (per stencil width)
+    bool s1[2] = {false, false};         // BiCGSTAB, one sweep: every solve of the width staged in LDS
 };
 
 // A set of solves launched together (one kernel launch serves all of them).
@@ -500,6 +501,14 @@ static int stage2_fits(bool two5, int rpt, int sx, size_t tsize)
     return two5 && 4 * sx + 4 <= 4 * rpt && (size_t)stage2_values(rpt, sx) * tsize <= (size_t)STAGE2_LDS_MAX ? 1 : 0;
 }
 
+// a one-sweep 7-point FP64 solve goes through LDS on the same terms, its halo
+// (one grid row on either side) at most the tile: at 128x128x64 the A kernel
+// of the momentum group measured 130 -> 107 us, the same arithmetic
+static int stage1_fits(bool one7, int rpt, int sx, size_t tsize)
+{
+    return one7 && 2 * sx <= rpt && (size_t)stage1_values(rpt, sx) * tsize <= (size_t)STAGE2_LDS_MAX ? 1 : 0;
+}
+
 static int finish_set(Group &g, JobSet &S)
 {
     size_t total = 0;
@@ -558,14 +567,33 @@ static int build_stages(Group &g, JobSet &S, int kind, const bool (&two)[2], int
         return SOL_OK;
     }
     if (kind == K_BICGSTAB) {
-        // 5-point two-sweep solves staged in LDS: the launch reserves the
-        // largest tile neighbourhood among them
-        size_t lds = 0;
-        for (const KJob &J : S.jobs)
-            if (J.staged) lds = std::max(lds, (size_t)stage2_values(J.rpt, J.sx) * (fp32 ? sizeof(float) : sizeof(double)));
+        // solves staged in LDS: 5-point two-sweep ones per solve inside the
+        // two-sweep kernels; 7-point one-sweep ones through kernels of their
+        // own, taken when every 7-point solve of the launch is staged.  The
+        // launch of each stencil width reserves the largest tile
+        // neighbourhood among its staged solves.
+        size_t lds[2] = {0, 0};
+        bool all7 = true, any7 = false;
+        const size_t ts = fp32 ? sizeof(float) : sizeof(double);
+        for (size_t j = 0; j < S.jobs.size(); ++j) {
+            const KJob &J = S.jobs[j];
+            const bool seven = g.cs[S.case_of[j]]->z.nd == 7;
+            if (seven) {
+                any7 = true;
+                all7 = all7 && J.staged;
+            }
+            if (!J.staged) continue;
+            const size_t v = seven ? (size_t)stage1_values(J.rpt, J.sx) : (size_t)stage2_values(J.rpt, J.sx);
+            lds[seven] = std::max(lds[seven], v * ts);
+        }
+        const bool s1 = any7 && all7 && !two[1];
         S.iter.push_back(row_stage(KI_BICG_B, SOL_KCLASS_BICG_B));
         S.iter.push_back(row_stage(KI_BICG_A, SOL_KCLASS_BICG_A));
-        for (Stage &st : S.iter) st.smem[0] = lds;
+        for (Stage &st : S.iter) {
+            st.smem[0] = lds[0];
+            st.smem[1] = s1 ? lds[1] : 0;
+            st.s1[1] = s1;
+        }
         return SOL_OK;
     }
     // multigrid CG: pq, down0, down(1..G-1), exact, up(G-1..1), up0; the start
@@ -783,7 +811,8 @@ static int group_build(Group &g)
                     P.inner.case_of.push_back(c);
                     P.inner.sys_of.push_back(s);
                 }
-                J.staged = stage2_fits(P.two[0] && h->z.nd == 5, J.rpt, J.sx, sizeof(double));
+                J.staged = h->z.nd == 5 ? stage2_fits(P.two[0], J.rpt, J.sx, sizeof(double))
+                                        : stage1_fits(P.kind == K_BICGSTAB && !P.two[1], J.rpt, J.sx, sizeof(double));
                 P.main.jobs.push_back(J);
                 P.main.st_index.push_back(c * NSYS + s);
                 P.main.case_of.push_back(c);
@@ -903,7 +932,7 @@ static int build_chunk_graph(Group &g, Phase &P, JobSet &S, int fp32)
                 void *args[] = {(void *)&jobs, (void *)&tiles, (void *)&kb, (void *)&koff};
                 hipKernelNodeParams kp;
                 std::memset(&kp, 0, sizeof(kp));
-                kp.func = (void *)kiter_fn(st.which, gi ? 7 : 5, fp32, st.two[gi]);
+                kp.func = (void *)kiter_fn(st.which, gi ? 7 : 5, fp32, st.two[gi], st.s1[gi]);
                 kp.gridDim = dim3((unsigned)st.nt[gi]);
                 kp.blockDim = dim3(TILE);
                 kp.sharedMemBytes = (unsigned)st.smem[gi];
@@ -944,7 +973,7 @@ static int launch_stage(Group &g, const JobSet &S, const Stage &st, int fp32, in
         const JTile *tiles = st.tiles_d[gi];
         const int *kb = nullptr;
         void *args[] = {(void *)&jobs, (void *)&tiles, (void *)&kb, (void *)&koff};
-        const void *fn = kiter_fn(st.which, gi ? 7 : 5, fp32, st.two[gi]);
+        const void *fn = kiter_fn(st.which, gi ? 7 : 5, fp32, st.two[gi], st.s1[gi]);
         note_dispatch(1);
         if (ta && tb)
             HIPCHK(hipExtLaunchKernel(fn, dim3((unsigned)st.nt[gi]), dim3(TILE), args, st.smem[gi], g.stream, ta, tb, 0));
@@ -960,8 +989,8 @@ static int start_solves(Group &g, Phase &P, JobSet &S, int fp32, int k, int mode
 {
     if (P.kind != K_MGCG) {
         for (int gi = 0; gi < 2; ++gi)
-            launch_kinit(P.kind, gi ? 7 : 5, fp32, P.two[gi], S.jobs_d, S.tiles_d[gi], S.nt[gi], k, mode,
-                         S.iter.empty() ? 0 : S.iter[0].smem[gi], g.stream);
+            launch_kinit(P.kind, gi ? 7 : 5, fp32, P.two[gi], !S.iter.empty() && S.iter[0].s1[gi], S.jobs_d,
+                         S.tiles_d[gi], S.nt[gi], k, mode, S.iter.empty() ? 0 : S.iter[0].smem[gi], g.stream);
         return SOL_OK;
     }
     for (int gi = 0; gi < 2; ++gi) launch_mg_init(gi ? 7 : 5, fp32, S.jobs_d, S.tiles_d[gi], S.nt[gi], k, mode, g.stream);

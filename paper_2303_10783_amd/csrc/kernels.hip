@@ -736,6 +736,42 @@ __device__ __forceinline__ void stage2_amf(const KJob &J, int i0, int i1, const 
     }
 }
 
+// PD 1 on a 7-point system, the tile [i0, i1) staged through LDS (KJob::
+// staged): pass 1 writes y = fy(j) (= M f at row j) for the rows within one
+// grid row of the tile, [i0 - sx, i1 + sx) (0 outside [0, n): only exact-0
+// coefficients reach those), pass 2 hands (A y)_i of each own row to out(i, .),
+// its x and y neighbours read from LDS and its two z neighbours (a plane
+// away, in other tiles) recomputed by fy from memory.  A row's M f is loaded
+// once per workgroup instead of once per row whose stencil reaches it; the
+// products and their order are kstencil's.  The dynamic LDS holds
+// stage1_values(rpt, sx) values.
+template <class T, class FY, class FO>
+__device__ __forceinline__ void stage1_amf7(const KJob &J, int i0, int i1, const RO<T> (&Ad)[7], FY fy, FO out)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    T *Y = reinterpret_cast<T *>(lds_raw);
+    const int n = J.n, sx = J.sx, sxy = J.sxy;
+    const int ylo = i0 - sx, yn = (i1 - i0) + 2 * sx;
+    for (int q = threadIdx.x; q < yn; q += TILE) {
+        const int j = ylo + q;
+        Y[q] = (j >= 0 && j < n) ? fy(j) : T(0);
+    }
+    __syncthreads();
+    for (int i = i0 + threadIdx.x; i < i1; i += TILE) {
+        const int c = i - ylo;
+        const int jm = i - sxy < 0 ? 0 : i - sxy, jp = i + sxy >= n ? n - 1 : i + sxy;
+        T acc = T(0);
+        acc += Ad[0][i] * fy(jm);
+        acc += Ad[1][i] * Y[c - sx];
+        acc += Ad[2][i] * Y[c - 1];
+        acc += Ad[3][i] * Y[c];
+        acc += Ad[4][i] * Y[c + 1];
+        acc += Ad[5][i] * Y[c + sx];
+        acc += Ad[6][i] * fy(jp);
+        out(i, acc);
+    }
+}
+
 // Start at iteration index k (mode 0: every solve, x = x0 or 0; mode 1:
 // solves in K_RESTART, keep x): r_k = b - A x, rh = r_k; partials (rh, r_k),
 // (r_k, r_k), (b, b).
@@ -782,7 +818,7 @@ __global__ __launch_bounds__(TILE) void k_bicg_init(const KJob *__restrict__ job
 // r_k, v_k = A M p_k; partial (rh, v_k).  Two sweeps on a staged 5-point FP64
 // solve: the tile's neighbourhood goes through LDS, as in the iteration
 // kernels.
-template <int ND, int PD, class T>
+template <int ND, int PD, class T, bool S1 = false>
 __global__ __launch_bounds__(TILE) void k_bicg_first(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles, int k)
 {
     JTile tl;
@@ -816,6 +852,18 @@ __global__ __launch_bounds__(TILE) void k_bicg_first(const KJob *__restrict__ jo
             done = true;
         }
     }
+    if constexpr (S1) {
+        static_assert(ND == 7 && PD == 1, "one-sweep 7-point staging");
+        RO<T> Ad[ND];
+        diag_views<ND, T>(J.A, n, Ad);
+        const auto Mi = R<T>(J.minv), Rr = R<T>(pk ? J.r1 : J.r);
+        stage1_amf7<T>(J, i0, i1, Ad, [&](int j) { return Mi[j] * Rr[j]; }, [&](int i, T vi) {
+            p[i] = r[i];
+            vv[i] = vi;
+            q += (double)rh[i] * vi;
+        });
+        done = true;
+    }
     if (!done)
     for (int i = i0 + threadIdx.x; i < i1; i += TILE) {
         T vi;
@@ -845,7 +893,7 @@ __global__ __launch_bounds__(TILE) void k_bicg_first(const KJob *__restrict__ jo
 }
 
 // B(k); kernels below
-template <int ND, int PD, class T>
+template <int ND, int PD, class T, bool S1 = false>
 __device__ __forceinline__ void bicg_b_body(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles, const int *kbase, int koff)
 {
     const int k = (kbase ? *kbase : 0) + koff;
@@ -872,7 +920,22 @@ __device__ __forceinline__ void bicg_b_body(const KJob *__restrict__ jobs, const
     auto t = G<T>(J.t);
     double v[4] = {0.0, 0.0, 0.0, 0.0};     // (t,s) (t,t) (rh,s) (rh,t)
     const int i0 = tl.t * J.rpt, i1 = min(n, i0 + J.rpt);
-    if constexpr (PD == 2) {
+    if constexpr (S1) {
+        static_assert(ND == 7 && PD == 1, "one-sweep 7-point staging");
+        RO<T> Ad[ND];
+        diag_views<ND, T>(J.A, n, Ad);
+        const auto Mi = R<T>(J.minv), Rr = R<T>(pk ? J.r1 : J.r), Vk = R<T>(pk ? J.v1 : J.v0), Rh = R<T>(J.rh);
+        stage1_amf7<T>(J, i0, i1, Ad, [&](int j) { return Mi[j] * (Rr[j] - alpha * Vk[j]); }, [&](int i, T ti) {
+            const T si = Rr[i] - alpha * Vk[i];
+            const T hi = Rh[i];
+            t[i] = ti;
+            const double sd = si, td = ti, hd = hi;
+            v[0] += td * sd;
+            v[1] += td * td;
+            v[2] += hd * sd;
+            v[3] += hd * td;
+        });
+    } else if constexpr (PD == 2) {
         constexpr int NC = Ring2<ND>::NC;
         RO<T> Ad[ND];
         diag_views<ND, T>(J.A, n, Ad);
@@ -941,7 +1004,7 @@ __device__ __forceinline__ void bicg_b_body(const KJob *__restrict__ jobs, const
 }
 
 // A(k); kernels below
-template <int ND, int PD, class T>
+template <int ND, int PD, class T, bool S1 = false>
 __device__ __forceinline__ void bicg_a_body(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles, const int *kbase, int koff)
 {
     const int k = (kbase ? *kbase : 0) + koff;
@@ -985,7 +1048,25 @@ __device__ __forceinline__ void bicg_a_body(const KJob *__restrict__ jobs, const
         const T rj = (rk[j] - ta * vk[j]) - tw * t[j];
         return rj + tb * (pkv[j] - tw * vk[j]);
     };
-    if constexpr (PD == 2) {
+    if constexpr (S1) {
+        static_assert(ND == 7 && PD == 1, "one-sweep 7-point staging");
+        RO<T> Ad[ND];
+        diag_views<ND, T>(J.A, n, Ad);
+        const auto Mi = R<T>(J.minv);
+        stage1_amf7<T>(J, i0, i1, Ad, [&](int j) { return Mi[j] * pnext(j); }, [&](int i, T vi) {
+            const T si = rk[i] - ta * vk[i];
+            const T xi = x[i] + mi[i] * (ta * pkv[i] + tw * si);
+            const T ri = si - tw * t[i];
+            const T pi = pnext(i);
+            const T hi = rh[i];
+            x[i] = xi;
+            rn[i] = ri;
+            pnv[i] = pi;
+            vn[i] = vi;
+            q[0] += (double)hi * vi;
+            q[1] += (double)ri * ri;
+        });
+    } else if constexpr (PD == 2) {
         constexpr int NC = Ring2<ND>::NC, C = ND / 2;
         constexpr Ring2<ND> RG = Ring2Tab<ND>::R;
         RO<T> Ad[ND];
@@ -1099,6 +1180,13 @@ template <int ND, class T>
 __global__ __launch_bounds__(TILE) void k_bicg_b(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles, const int *kbase, int koff) { bicg_b_body<ND, 1, T>(jobs, tiles, kbase, koff); }
 template <int ND, class T>
 __global__ __launch_bounds__(TILE) void k_bicg_a(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles, const int *kbase, int koff) { bicg_a_body<ND, 1, T>(jobs, tiles, kbase, koff); }
+// one sweep on 7-point systems whose tiles all go through LDS (stage1_amf7):
+// kernels of their own, so that the gathering kernels keep their register
+// budget and these theirs (72 VGPRs in the A kernel against 166)
+template <class T>
+__global__ __launch_bounds__(TILE) void k_bicg_b1s(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles, const int *kbase, int koff) { bicg_b_body<7, 1, T, true>(jobs, tiles, kbase, koff); }
+template <class T>
+__global__ __launch_bounds__(TILE) void k_bicg_a1s(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles, const int *kbase, int koff) { bicg_a_body<7, 1, T, true>(jobs, tiles, kbase, koff); }
 template <int ND>
 __global__ void k_bicg2_b64(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles, const int *kbase, int koff);
 template <int ND>
@@ -1766,26 +1854,28 @@ void launch_phase_commit(int dim, const CaseDev *c, const Tile *t, int nt, hipSt
 }
 
 template <int ND, class T>
-static const void *iter_fn_t(int which, bool two)
+static const void *iter_fn_t(int which, bool two, bool s1)
 {
     constexpr bool f64 = sizeof(T) == 8;
     switch (which) {
     case KI_CG: return (const void *)&k_cg<ND, T>;
     case KI_BICG_A:
+        if (ND == 7 && !two && s1) return (const void *)&k_bicg_a1s<T>;
         if (!two) return (const void *)&k_bicg_a<ND, T>;
         return f64 ? (const void *)&k_bicg2_a64<ND> : (const void *)&k_bicg2_a32<ND>;
     case KI_BICG_B:
+        if (ND == 7 && !two && s1) return (const void *)&k_bicg_b1s<T>;
         if (!two) return (const void *)&k_bicg_b<ND, T>;
         return f64 ? (const void *)&k_bicg2_b64<ND> : (const void *)&k_bicg2_b32<ND>;
     }
     return nullptr;
 }
 
-const void *kiter_fn(int which, int nd, int fp32, bool two)
+const void *kiter_fn(int which, int nd, int fp32, bool two, bool s1)
 {
     if (which >= KI_MG_PQ) return mg_fn(which, nd, fp32);
-    if (nd == 5) return fp32 ? iter_fn_t<5, float>(which, two) : iter_fn_t<5, double>(which, two);
-    return fp32 ? iter_fn_t<7, float>(which, two) : iter_fn_t<7, double>(which, two);
+    if (nd == 5) return fp32 ? iter_fn_t<5, float>(which, two, false) : iter_fn_t<5, double>(which, two, false);
+    return fp32 ? iter_fn_t<7, float>(which, two, s1) : iter_fn_t<7, double>(which, two, s1);
 }
 
 // iteration index base of graph-replayed chunks
@@ -1816,8 +1906,8 @@ void launch_tune_rhs(void *b, int fp32, int n, hipStream_t s)
 }
 
 template <int ND, class T>
-static void launch_init_nd(int kind, bool two, const KJob *j, const JTile *t, int nt, int k, int mode, size_t smem,
-                           hipStream_t s)
+static void launch_init_nd(int kind, bool two, bool s1, const KJob *j, const JTile *t, int nt, int k, int mode,
+                           size_t smem, hipStream_t s)
 {
     if (kind == K_CG) {
         SOL_LAUNCH((k_cg_init_a<ND, T>), GRID(nt), 0, s, j, t, k, mode);
@@ -1826,19 +1916,22 @@ static void launch_init_nd(int kind, bool two, const KJob *j, const JTile *t, in
     }
     SOL_LAUNCH((k_bicg_init<ND, T>), GRID(nt), 0, s, j, t, k, mode);
     if (two) SOL_LAUNCH((k_bicg_first<ND, 2, T>), dim3(nt), dim3(TILE), smem, s, j, t, k);
-    else SOL_LAUNCH((k_bicg_first<ND, 1, T>), GRID(nt), 0, s, j, t, k);
+    else if constexpr (ND == 7) {
+        if (s1) SOL_LAUNCH((k_bicg_first<7, 1, T, true>), dim3(nt), dim3(TILE), smem, s, j, t, k);
+        else SOL_LAUNCH((k_bicg_first<ND, 1, T>), GRID(nt), 0, s, j, t, k);
+    } else SOL_LAUNCH((k_bicg_first<ND, 1, T>), GRID(nt), 0, s, j, t, k);
 }
 
-void launch_kinit(int kind, int nd, int fp32, bool two, const KJob *j, const JTile *t, int nt, int k, int mode,
-                  size_t smem, hipStream_t s)
+void launch_kinit(int kind, int nd, int fp32, bool two, bool s1, const KJob *j, const JTile *t, int nt, int k,
+                  int mode, size_t smem, hipStream_t s)
 {
     if (nt <= 0) return;
     if (nd == 5) {
-        if (fp32) launch_init_nd<5, float>(kind, two, j, t, nt, k, mode, smem, s);
-        else launch_init_nd<5, double>(kind, two, j, t, nt, k, mode, smem, s);
+        if (fp32) launch_init_nd<5, float>(kind, two, false, j, t, nt, k, mode, smem, s);
+        else launch_init_nd<5, double>(kind, two, false, j, t, nt, k, mode, smem, s);
     } else {
-        if (fp32) launch_init_nd<7, float>(kind, two, j, t, nt, k, mode, smem, s);
-        else launch_init_nd<7, double>(kind, two, j, t, nt, k, mode, smem, s);
+        if (fp32) launch_init_nd<7, float>(kind, two, s1, j, t, nt, k, mode, smem, s);
+        else launch_init_nd<7, double>(kind, two, s1, j, t, nt, k, mode, smem, s);
     }
 }
 

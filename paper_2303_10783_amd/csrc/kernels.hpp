@@ -25,9 +25,10 @@ void launch_sub_mean(const CaseDev *c, const Tile *t, int nt, hipStream_t s);
 void launch_project(const CaseDev *c, const Tile *t, int nt, hipStream_t s);
 void launch_phase_commit(int dim, const CaseDev *c, const Tile *t, int nt, hipStream_t s);
 
-// two: BiCGSTAB preconditioned by two Jacobi sweeps instead of one
-void launch_kinit(int kind, int nd, int fp32, bool two, const KJob *j, const JTile *t, int nt, int k, int mode,
-                  size_t smem, hipStream_t s);
+// two: BiCGSTAB preconditioned by two Jacobi sweeps instead of one; s1: the
+// one-sweep 7-point solves of the launch all go through LDS (KJob::staged)
+void launch_kinit(int kind, int nd, int fp32, bool two, bool s1, const KJob *j, const JTile *t, int nt, int k,
+                  int mode, size_t smem, hipStream_t s);
 void launch_kfinish(int nd, const KJob *j, const JTile *t, int nt, hipStream_t s);
 void launch_kdecide(const KJob *j, int njobs, hipStream_t s);
 // iteration kernels, all with the signature (jobs, tiles, const int *kbase,
@@ -39,8 +40,8 @@ enum KIter {
     KI_MG_DOWN2 = 11, KI_MG_UP2 = 12       // two coarse levels in one launch
 };
 // kernel address of an iteration kernel (direct launches and graph nodes);
-// two selects the two-sweep BiCGSTAB kernels
-const void *kiter_fn(int which, int nd, int fp32, bool two);
+// two selects the two-sweep BiCGSTAB kernels, s1 the staged one-sweep ones
+const void *kiter_fn(int which, int nd, int fp32, bool two, bool s1);
 const void *mg_fn(int which, int nd, int fp32);
 // workgroups of a fused pair of coarse levels (l, l+1); M = level l+1
 int mg_fused_bricks(int dim, const MLevel &M);

@@ -158,7 +158,8 @@ struct KJob {
     int32_t nlev;             // multigrid: levels (0 for the other solves)
     const MLevel *lev;        // multigrid: level table (device), vectors of type T
     int32_t nglob;            // multigrid: the exactly solved level (levels 0..nglob-1 are smoothed)
-    int32_t staged;           // BiCGSTAB, two sweeps, 5-point, FP64: the tile's neighbourhood goes through LDS
+    int32_t staged;           // BiCGSTAB, FP64: the tile's neighbourhood goes through LDS (two sweeps on a
+                              // 5-point system, one sweep on a 7-point system)
 };
 
 enum KRole { ROLE_PLAIN = 0, ROLE_REFINE = 1, ROLE_INNER = 2 };
@@ -176,5 +177,8 @@ __host__ __device__ inline int ceil_div(int a, int b) { return (a + b - 1) / b; 
 // STAGE2_LDS_MAX bytes.
 __host__ __device__ inline int stage2_values(int rpt, int sx) { return 2 * rpt + 6 * sx + 6; }
 constexpr int STAGE2_LDS_MAX = 60 * 1024;
+// One-sweep BiCGSTAB on a 7-point system staged in LDS: the tile's rows and
+// one grid row on either side (the same budget)
+__host__ __device__ inline int stage1_values(int rpt, int sx) { return rpt + 2 * sx; }
 
 }  // namespace sol
