@@ -224,6 +224,39 @@ __device__ __forceinline__ T win3_op(const MLevel &L, int gx, int gy, int gz, in
     return acc;
 }
 
+// Jacobi inverse of the level-0 (pressure) diagonal.  The assembled row of a
+// cell adds 1/h_a^2 once per face it has inside the grid, axis by axis (low
+// face, then high face), and the stored inverse is 1 / that sum (1 for a cell
+// without neighbours).  The sum depends only on the number of such faces per
+// axis (0, 1 or 2), so the level-0 smoothers take the inverse from a
+// workgroup table of the 3^d values, formed by the same additions in the same
+// order (the stored values, bit for bit), instead of loading it for every
+// window cell.  Entry kx + 3 ky + 9 kz; written before the workgroup's first
+// barrier, read after it.
+template <int DIM>
+__device__ __forceinline__ void write_minv0(const MLevel &L, double *tab)
+{
+    const int t = threadIdx.x;
+    if (t < (DIM == 3 ? 27 : 9)) {
+        const int k[3] = {t % 3, (t / 3) % 3, t / 9};
+        double d = 0.0;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            if (k[a] >= 1) d += L.ih2[a];
+            if (k[a] == 2) d += L.ih2[a];
+        }
+        tab[t] = d > 0.0 ? 1.0 / d : 1.0;
+    }
+}
+
+// faces inside the grid along one axis of n cells of the cell at g, clamped
+// into [0, n) as the window's loads are
+__device__ __forceinline__ int faces_in(int g, int n)
+{
+    const int c = min(max(g, 0), n - 1);
+    return (c > 0 ? 1 : 0) + (c + 1 < n ? 1 : 0);
+}
+
 // ------------------------------------------------------------- operator
 
 // couplings of the level-l cell with coordinates q to its neighbours along
@@ -539,6 +572,8 @@ __global__ __launch_bounds__(TILE) void k_mg_down0(const KJob *__restrict__ jobs
     JTile tl;
     const KJob &J = job_of(jobs, tiles, tl);
     if (outer_idle(J)) return;
+    __shared__ double tab[27];
+    write_minv0<DIM>(J.lev[0], tab);
     KState *st = J.st;
     if (INIT ? !mg_live(J, k) : wg_status(st) != K_RUNNING) return;
     const int pk = k & 1, pn1 = (k + 1) & 1;
@@ -557,7 +592,6 @@ __global__ __launch_bounds__(TILE) void k_mg_down0(const KJob *__restrict__ jobs
     const T ta = (T)alpha, w = (T)mg_w<DIM>();
     const MLevel &L = J.lev[0];
     const double icx = 1.0 / L.cnx, icxy = 1.0 / ((double)L.cnx * L.cny);
-    auto mi = R<T>(J.minv);
     auto x = G<T>(J.x);
     auto p = R<T>(pk ? J.p1 : J.p0);
     auto q = R<T>(J.v1);
@@ -577,6 +611,12 @@ __global__ __launch_bounds__(TILE) void k_mg_down0(const KJob *__restrict__ jobs
         for (int I = I0 + threadIdx.x; I < I1; I += TILE) {
             const Agg<DIM> a = agg_of<DIM>(L, I, icx, icxy);
             const int X0 = 2 * a.c[0] - 2, Y0 = 2 * a.c[1] - 2;
+            int kx[W2], ky[W2];
+#pragma unroll
+            for (int u = 0; u < W2; ++u) {
+                kx[u] = faces_in(X0 + u, L.nx);
+                ky[u] = 3 * faces_in(Y0 + u, L.ny);
+            }
             T rw[W2][W2], mw[W2][W2], f1[W2][W2], f2[W2][W2];
 #pragma unroll
             for (int v = 0; v < W2; ++v)
@@ -585,7 +625,7 @@ __global__ __launch_bounds__(TILE) void k_mg_down0(const KJob *__restrict__ jobs
                     if (wdist(u, v) > 2) continue;
                     const int j = win_idx(L, X0 + u, Y0 + v);
                     rw[v][u] = INIT ? rn[j] : rc[j] - ta * q[j];
-                    mw[v][u] = mi[j];
+                    mw[v][u] = (T)tab[kx[u] + ky[v]];
                 }
 #pragma unroll
             for (int v = 0; v < W2; ++v)
@@ -622,9 +662,17 @@ __global__ __launch_bounds__(TILE) void k_mg_down0(const KJob *__restrict__ jobs
         for (int I = I0 + threadIdx.x; I < I1; I += TILE) {
             const Agg<DIM> a = agg_of<DIM>(L, I, icx, icxy);
             const int X0 = 2 * a.c[0] - 1, Y0 = 2 * a.c[1] - 1, Z0 = 2 * a.c[2] - 1;
+            int kx[W3], kyz[W3][W3];
+#pragma unroll
+            for (int u = 0; u < W3; ++u) kx[u] = faces_in(X0 + u, L.nx);
+#pragma unroll
+            for (int wz = 0; wz < W3; ++wz)
+#pragma unroll
+                for (int vy = 0; vy < W3; ++vy) kyz[wz][vy] = 3 * faces_in(Y0 + vy, L.ny) + 9 * faces_in(Z0 + wz, L.nz);
             T rw[W3][W3][W3], f1[W3][W3][W3];
-            auto cell = [&](int wz, int vy, int ux, T rv, T qv, T mv) {
+            auto cell = [&](int wz, int vy, int ux, T rv, T qv) {
                 const T rj = INIT ? rv : rv - ta * qv;
+                const T mv = (T)tab[kx[ux] + kyz[wz][vy]];
                 rw[wz][vy][ux] = rj;
                 f1[wz][vy][ux] = w * mv * rj;
             };
@@ -639,21 +687,20 @@ __global__ __launch_bounds__(TILE) void k_mg_down0(const KJob *__restrict__ jobs
                                       2 * a.c[0];
                         const Pair<T> rr2 = load_pair<T>(INIT ? (const void *)rnb : rcb, j);
                         const Pair<T> qq2 = INIT ? Pair<T>{T(0), T(0)} : load_pair<T>(J.v1, j);
-                        const Pair<T> mm2 = load_pair<T>(J.minv, j);
-                        cell(wz, vy, 1, rr2.x, qq2.x, mm2.x);
-                        cell(wz, vy, 2, rr2.y, qq2.y, mm2.y);
+                        cell(wz, vy, 1, rr2.x, qq2.x);
+                        cell(wz, vy, 2, rr2.y, qq2.y);
                     } else {
 #pragma unroll
                         for (int ux = 1; ux < 3; ++ux) {
                             const int j = win3_idx(L, X0 + ux, Y0 + vy, Z0 + wz);
-                            cell(wz, vy, ux, INIT ? rn[j] : rc[j], INIT ? T(0) : q[j], mi[j]);
+                            cell(wz, vy, ux, INIT ? rn[j] : rc[j], INIT ? T(0) : q[j]);
                         }
                     }
                     if (wdist3(0, vy, wz) <= 1) {
 #pragma unroll
                         for (int ux = 0; ux < W3; ux += 3) {
                             const int j = win3_idx(L, X0 + ux, Y0 + vy, Z0 + wz);
-                            cell(wz, vy, ux, INIT ? rn[j] : rc[j], INIT ? T(0) : q[j], mi[j]);
+                            cell(wz, vy, ux, INIT ? rn[j] : rc[j], INIT ? T(0) : q[j]);
                         }
                     }
                 }
@@ -836,12 +883,14 @@ __global__ __launch_bounds__(TILE) void k_mg_up0(const KJob *__restrict__ jobs, 
     const int k = kidx(kbase, koff);
     JTile tl;
     const KJob &J = job_of(jobs, tiles, tl);
-    if (outer_idle(J) || !mg_live(J, k)) return;
+    if (outer_idle(J)) return;
+    __shared__ double tab[27];
+    write_minv0<DIM>(J.lev[0], tab);
+    if (!mg_live(J, k)) return;
     const int pn1 = (k + 1) & 1;
     const MLevel &L = J.lev[0];
     const double icx = 1.0 / L.cnx, icxy = 1.0 / ((double)L.cnx * L.cny);
     const T w = (T)mg_w<DIM>(), og = (T)mg_og<DIM>();
-    auto mi = R<T>(J.minv);
     auto r = R<T>(pn1 ? J.rh : J.r);
     auto z = G<T>(J.v0);
     auto ec = R<T>(J.lev[1].e);
@@ -862,6 +911,12 @@ __global__ __launch_bounds__(TILE) void k_mg_up0(const KJob *__restrict__ jobs, 
 #pragma unroll
                 for (int c = 0; c < 3; ++c)
                     ew[b][c] = ec[min(max(a.c[0] - 1 + c, 0), L.cnx - 1) + L.cnx * min(max(a.c[1] - 1 + b, 0), L.cny - 1)];
+            int kx[W2], ky[W2];
+#pragma unroll
+            for (int u = 0; u < W2; ++u) {
+                kx[u] = faces_in(X0 + u, L.nx);
+                ky[u] = 3 * faces_in(Y0 + u, L.ny);
+            }
             T e0[W2][W2], e1[W2][W2], rw[W2][W2], mw[W2][W2];
 #pragma unroll
             for (int v = 0; v < W2; ++v)
@@ -872,7 +927,7 @@ __global__ __launch_bounds__(TILE) void k_mg_up0(const KJob *__restrict__ jobs, 
                     e0[v][u] = xs[j] + og * ew[v >> 1][u >> 1];
                     if (wdist(u, v) <= 1) {
                         rw[v][u] = r[j];
-                        mw[v][u] = mi[j];
+                        mw[v][u] = (T)tab[kx[u] + ky[v]];
                     }
                 }
 #pragma unroll
@@ -909,6 +964,13 @@ __global__ __launch_bounds__(TILE) void k_mg_up0(const KJob *__restrict__ jobs, 
             };
             const T e0 = ec[I], exm = ec[cix(-1, 0, 0)], exp_ = ec[cix(1, 0, 0)], eym = ec[cix(0, -1, 0)],
                     eyp = ec[cix(0, 1, 0)], ezm = ec[cix(0, 0, -1)], ezp = ec[cix(0, 0, 1)];
+            int kx[W3], ky[W3], kz[W3];
+#pragma unroll
+            for (int u = 0; u < W3; ++u) {
+                kx[u] = faces_in(X0 + u, L.nx);
+                ky[u] = 3 * faces_in(Y0 + u, L.ny);
+                kz[u] = 9 * faces_in(Z0 + u, L.nz);
+            }
             T xw[W3][W3][W3], rw[W3][W3][W3], mw[W3][W3][W3];
 #pragma unroll
             for (int wz = 0; wz < W3; ++wz)
@@ -920,7 +982,7 @@ __global__ __launch_bounds__(TILE) void k_mg_up0(const KJob *__restrict__ jobs, 
                         const int j = win3_idx(L, X0 + ux, Y0 + vy, Z0 + wz);
                         const T e = ux == 0 ? exm : ux == 3 ? exp_ : vy == 0 ? eym : vy == 3 ? eyp
                                   : wz == 0 ? ezm : wz == 3 ? ezp : e0;
-                        const T rj = r[j], mj = mi[j];
+                        const T rj = r[j], mj = (T)tab[kx[ux] + ky[vy] + kz[wz]];
                         rw[wz][vy][ux] = rj;
                         mw[wz][vy][ux] = mj;
                         xw[wz][vy][ux] = w * mj * rj + og * e;
