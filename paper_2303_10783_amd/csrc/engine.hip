@@ -269,13 +269,13 @@ static double row_bytes(int cls, int nd, int dim, int tsize)
     case SOL_KCLASS_CG: return (nd + 11.0) * tsize;     // A, r, w, s, M, p, x; p, s, x, r, w
     case SOL_KCLASS_BICG_A: return (nd + 11.0) * tsize; // A, r, v, t, p, M, rh, x; x, r', p', v'
     case SOL_KCLASS_BICG_B: return (nd + 5.0) * tsize;  // A, r, v, M, rh; t
-    // multigrid (the pressure operator is applied from its closed form, no
-    // matrix values are read)
+    // multigrid (the pressure operator and its Jacobi inverse diagonal are
+    // applied from their closed forms, no matrix values are read)
     case SOL_KCLASS_MG_PQ: return 4.0 * tsize;           // z, p_old; p, q
-    case SOL_KCLASS_MG_DOWN0:                            // M, r, q, x, p; x, r; level-1 rhs (2D: and x2)
-        return (7.0 + (dim == 2) + 1.0 / (1 << dim)) * tsize;
-    case SOL_KCLASS_MG_UP0:                              // M, r, level-1 correction (2D: and x2); z
-        return (3.0 + (dim == 2) + 1.0 / (1 << dim)) * tsize;
+    case SOL_KCLASS_MG_DOWN0:                            // r, q, x, p; x, r; level-1 rhs (2D: and x2)
+        return (6.0 + (dim == 2) + 1.0 / (1 << dim)) * tsize;
+    case SOL_KCLASS_MG_UP0:                              // r, level-1 correction (2D: and x2); z
+        return (2.0 + (dim == 2) + 1.0 / (1 << dim)) * tsize;
     case SOL_KCLASS_MG_COARSE: return 0.0;
     case SOL_KCLASS_ASM_MOM: return 16.0 * nd + 8.0 * dim + 48.0;
     case SOL_KCLASS_ASM_TRN: return 24.0 * nd + 8.0 * dim + 56.0;
