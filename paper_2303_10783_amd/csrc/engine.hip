@@ -503,7 +503,8 @@ static int stage2_fits(bool two5, int rpt, int sx, size_t tsize)
 
 // a one-sweep 7-point FP64 solve goes through LDS on the same terms, its halo
 // (one grid row on either side) at most the tile: at 128x128x64 the A kernel
-// of the momentum group measured 130 -> 107 us, the same arithmetic
+// of the momentum group measured 46.5 -> 41.3 us per launch, the same
+// arithmetic (FP32 inner solves measured slower staged, and stay gathered)
 static int stage1_fits(bool one7, int rpt, int sx, size_t tsize)
 {
     return one7 && 2 * sx <= rpt && (size_t)stage1_values(rpt, sx) * tsize <= (size_t)STAGE2_LDS_MAX ? 1 : 0;
