@@ -1305,12 +1305,11 @@ static int group_step_once(Group &g, bool speculate)
         for (int gi = 0; gi < 2; ++gi) launch_asm_momentum(gi ? 3 : 2, g.cases_d, g.t_mom[gi], g.n_mom[gi], s, fwd);
     });
     RCHK(group_solve(g, g.ph[0], speculate));
-    // 2: pressure correction (and the initial guesses of phi and T*)
-    for (int gi = 0; gi < 2; ++gi) {
-        launch_div_rhs(gi ? 3 : 2, g.cases_d, g.t_cell[gi], g.n_cell[gi], 1, s);
-        launch_sub_mean(g.cases_d, g.t_cell[gi], g.n_cell[gi], s);
-        launch_guess(g.cases_d, g.t_cell[gi], g.n_cell[gi], s);
-    }
+    // 2: pressure correction (and the initial guesses of phi and T*; the
+    // guess kernel removes the rhs mean)
+    for (int gi = 0; gi < 2; ++gi) launch_div_rhs(gi ? 3 : 2, g.cases_d, g.t_cell[gi], g.n_cell[gi], 1, s);
+    launch_case_mean(g.cases_d, g.cidx_d, (int)g.cs.size(), s);
+    for (int gi = 0; gi < 2; ++gi) launch_guess(g.cases_d, g.t_cell[gi], g.n_cell[gi], s);
     RCHK(group_solve(g, g.ph[1], speculate));
     // 3: projection
     for (int gi = 0; gi < 2; ++gi) launch_project(g.cases_d, g.t_mom[gi], g.n_mom[gi], s);
@@ -1793,6 +1792,7 @@ int sol_assemble(sol_handle *h, uint32_t mask)
     if (mask & 7u) launch_asm_momentum(dim, g.cases_d, g.t_mom[gi], g.n_mom[gi], s, fwd);
     if (mask & (1u << SP)) {
         launch_div_rhs(dim, g.cases_d, g.t_cell[gi], g.n_cell[gi], 0, s);
+        launch_case_mean(g.cases_d, g.cidx_d, 1, s);
         launch_sub_mean(g.cases_d, g.t_cell[gi], g.n_cell[gi], s);
     }
     if (mask & ((1u << SC) | (1u << ST))) launch_asm_transport(dim, g.cases_d, g.t_cell[gi], g.n_cell[gi], 0, s, fwd);

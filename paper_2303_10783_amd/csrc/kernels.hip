@@ -343,24 +343,32 @@ __global__ __launch_bounds__(TILE) void k_div_rhs(const CaseDev *__restrict__ ca
     put_partials<2>(v, c.red_part, off, tl.t);
 }
 
-// remove the mean of the pressure rhs (consistency of the Neumann problem);
-// workgroup 0 of each case records the mean and ||D u*||
-__global__ __launch_bounds__(TILE) void k_sub_mean(const CaseDev *__restrict__ cases, const Tile *__restrict__ tiles)
+// totals of k_div_rhs's partials, one workgroup per case: the mean of the
+// pressure rhs (removed for the consistency of the Neumann problem by k_guess
+// or k_sub_mean) and ||D u*||.  Totalled once per case: a total reads all of
+// the case's partials (4096 x 2 at 128x128x64), which every workgroup of a
+// per-tile kernel would otherwise repeat.
+__global__ __launch_bounds__(TILE) void k_case_mean(const CaseDev *__restrict__ cases, const int32_t *__restrict__ cidx)
 {
-    const Tile tl = tiles[xcd_tile(blockIdx.x, gridDim.x)];
-    const CaseDev &c = cases[tl.c];
+    const CaseDev &c = cases[cidx[blockIdx.x]];
     const int nt = c.ntile_cell;
     const int off[2] = {0, nt};
     double tot[2];
     sum_partials<2>(c.red_part, off, nt, tot);
-    const double mean = tot[0] / (double)c.ph.ncell;
-    const int ci = tl.t * TILE + threadIdx.x;
-    if (ci < c.ph.ncell) c.b[SP][ci] -= mean;
-    if (tl.t == 0 && threadIdx.x == 0) {
+    if (threadIdx.x == 0) {
         c.red[R_SUMB] = tot[0];
         c.red[R_DIVSTAR] = sqrt(tot[1]);
-        c.ks[SP].bmean = mean;
+        c.ks[SP].bmean = tot[0] / (double)c.ph.ncell;
     }
+}
+
+// remove the mean k_case_mean recorded from the pressure rhs
+__global__ __launch_bounds__(TILE) void k_sub_mean(const CaseDev *__restrict__ cases, const Tile *__restrict__ tiles)
+{
+    const Tile tl = tiles[xcd_tile(blockIdx.x, gridDim.x)];
+    const CaseDev &c = cases[tl.c];
+    const int ci = tl.t * TILE + threadIdx.x;
+    if (ci < c.ph.ncell) c.b[SP][ci] -= c.ks[SP].bmean;
 }
 
 // ------------------------------------------------------------ projection
@@ -492,7 +500,8 @@ __global__ __launch_bounds__(TILE) void k_phase_commit(const CaseDev *__restrict
 // cavity, energy BiCGSTAB iterations: step 3 linear 31 / quadratic 41,
 // step 5 27 / 27, step 6 26 / 25, step 12 22 / 19, step 18 21 / 16).  The
 // guess is written into the solution buffer, which the solve then takes as
-// its initial guess; the history shifts by one.
+// its initial guess; the history shifts by one.  The same pass removes the
+// mean k_case_mean recorded from the pressure rhs (as k_sub_mean would).
 constexpr int QUAD_GUESS_STEPS = 6;
 __global__ __launch_bounds__(TILE) void k_guess(const CaseDev *__restrict__ cases, const Tile *__restrict__ tiles)
 {
@@ -514,6 +523,7 @@ __global__ __launch_bounds__(TILE) void k_guess(const CaseDev *__restrict__ case
         tg = c.T[i];
         pg = 0.0;
     }
+    c.b[SP][i] -= c.ks[SP].bmean;
     c.Tstar[i] = tg;
     c.phi[i] = pg;
     c.Tprev2[i] = t1;
@@ -1835,6 +1845,11 @@ void launch_div_rhs(int dim, const CaseDev *c, const Tile *t, int nt, int vel_sr
     if (nt <= 0) return;
     if (dim == 2) SOL_LAUNCH(k_div_rhs<2>, GRID(nt), 0, s, c, t, vel_src);
     else SOL_LAUNCH(k_div_rhs<3>, GRID(nt), 0, s, c, t, vel_src);
+}
+void launch_case_mean(const CaseDev *c, const int32_t *cidx, int ncase, hipStream_t s)
+{
+    if (ncase <= 0) return;
+    SOL_LAUNCH(k_case_mean, GRID(ncase), 0, s, c, cidx);
 }
 void launch_sub_mean(const CaseDev *c, const Tile *t, int nt, hipStream_t s)
 {

@@ -21,6 +21,7 @@ void launch_asm_const(int dim, const CaseDev *c, const Tile *t, int nt, hipStrea
 void launch_asm_momentum(int dim, const CaseDev *c, const Tile *t, int nt, hipStream_t s, int fwd = 0);
 void launch_asm_transport(int dim, const CaseDev *c, const Tile *t, int nt, int vel_src, hipStream_t s, int fwd = 0);
 void launch_div_rhs(int dim, const CaseDev *c, const Tile *t, int nt, int vel_src, hipStream_t s);
+void launch_case_mean(const CaseDev *c, const int32_t *cidx, int ncase, hipStream_t s);
 void launch_sub_mean(const CaseDev *c, const Tile *t, int nt, hipStream_t s);
 void launch_project(const CaseDev *c, const Tile *t, int nt, hipStream_t s);
 void launch_phase_commit(int dim, const CaseDev *c, const Tile *t, int nt, hipStream_t s);
