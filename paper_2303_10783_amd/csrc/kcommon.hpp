@@ -86,15 +86,31 @@ __device__ __forceinline__ void put_partials(double (&v)[K], double *part, const
 // wave adds its lanes in the fixed DPP tree, and after one barrier every
 // thread adds the four wave totals in wave order.  (Broadcasting a total
 // from thread 0 took two more barriers, each of which also waits for every
-// load the waves have in flight.)
-template <int K>
+// load the waves have in flight.)  U > 1: the values of U consecutive q of
+// a thread are loaded together, then added in the same order (one round trip
+// per U of them), for the long per-case totals of one-workgroup kernels; the
+// Krylov kernels total a few hundred tiles and keep U = 1 (its registers).
+template <int K, int U = 1>
 __device__ __forceinline__ void sum_partials(const double *part, const int (&off)[K], int ntile, double (&out)[K])
 {
     __shared__ double sh[4 * K];
     double acc[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) acc[k] = 0.0;
-    for (int q = threadIdx.x; q < ntile; q += TILE) {
+    int q = threadIdx.x;
+    if constexpr (U > 1)
+    for (; q + (U - 1) * TILE < ntile; q += U * TILE) {
+        double v[U][K];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int k = 0; k < K; ++k) v[u][k] = part[off[k] + q + u * TILE];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int k = 0; k < K; ++k) acc[k] += v[u][k];
+    }
+    for (; q < ntile; q += TILE) {
 #pragma unroll
         for (int k = 0; k < K; ++k) acc[k] += part[off[k] + q];
     }

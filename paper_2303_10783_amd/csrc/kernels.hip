@@ -354,7 +354,7 @@ __global__ __launch_bounds__(TILE) void k_case_mean(const CaseDev *__restrict__ 
     const int nt = c.ntile_cell;
     const int off[2] = {0, nt};
     double tot[2];
-    sum_partials<2>(c.red_part, off, nt, tot);
+    sum_partials<2, 8>(c.red_part, off, nt, tot);
     if (threadIdx.x == 0) {
         c.red[R_SUMB] = tot[0];
         c.red[R_DIVSTAR] = sqrt(tot[1]);
@@ -547,7 +547,7 @@ __global__ __launch_bounds__(TILE) void k_case_stats(const CaseDev *__restrict__
     const int nt = c.ntile_cell;
     const int off[4] = {0, nt, 2 * nt, 3 * nt};
     double tot[4];
-    sum_partials<4>(c.red_part, off, nt, tot);
+    sum_partials<4, 4>(c.red_part, off, nt, tot);
     if (threadIdx.x == 0) {
         c.red[R_SUMC] = tot[0];
         c.red[R_SUMH] = tot[1];
