@@ -181,7 +181,7 @@ static size_t footprint(const Sizes &z, int precision)
     const size_t D = sizeof(double), F = sizeof(float);
     size_t nf = 0;
     for (int s = 0; s < 3; ++s) nf += std::max(z.nsys[s], 1);
-    b += 3 * (al(nf * D));                                       // u,v,w / us / un (per component)
+    b += 5 * (al(nf * D));                                       // u,v,w / us / un / 2 history of us
     b += 13 * al((size_t)z.ncell * D);                          // p T C gl Cl Cs phi Cnew Tstar, 4 history
     for (int s = 0; s < NSYS; ++s) {
         const size_t n = std::max(z.nsys[s], 1);
@@ -771,9 +771,10 @@ static int group_build(Group &g)
                 J.b = h->cd.b[s];
                 J.minv = h->cd.minv[s];
                 const int ws = p == 0 ? s : (p == 1 ? 0 : (s == SC ? 0 : 1));
-                if (p == 0) { J.x = h->cd.us[s]; J.x0 = s == SU ? h->cd.u : (s == SV ? h->cd.v : h->cd.w); }
-                // phi and T*: the initial guess is written into the solution
-                // buffer itself by k_guess before the pressure solve
+                // u*, phi and T*: the initial guess is written into the
+                // solution buffer itself (k_guess_mom before the momentum
+                // solves, k_guess before the pressure solve)
+                if (p == 0) { J.x = h->cd.us[s]; J.x0 = h->cd.us[s]; }
                 else if (p == 1) { J.x = h->cd.phi; J.x0 = h->cd.phi; }
                 else if (s == SC) { J.x = h->cd.Cnew; J.x0 = h->cd.C; }
                 else { J.x = h->cd.Tstar; J.x0 = h->cd.Tstar; }
@@ -1304,6 +1305,7 @@ static int group_step_once(Group &g, bool speculate)
     timed(g, SOL_KCLASS_ASM_MOM, [&] {
         for (int gi = 0; gi < 2; ++gi) launch_asm_momentum(gi ? 3 : 2, g.cases_d, g.t_mom[gi], g.n_mom[gi], s, fwd);
     });
+    for (int gi = 0; gi < 2; ++gi) launch_guess_mom(g.cases_d, g.t_mom[gi], g.n_mom[gi], s);
     RCHK(group_solve(g, g.ph[0], speculate));
     // 2: pressure correction (and the initial guesses of phi and T*; the
     // guess kernel removes the rhs mean)
@@ -1469,11 +1471,14 @@ static int alloc_case(sol_handle *h)
     // face arrays: one block per set, components back to back
     size_t nf[3];
     for (int s = 0; s < 3; ++s) nf[s] = std::max(z.nsys[s], 1);
-    double *fu = dal(nf[0] + nf[1] + nf[2]), *fs = dal(nf[0] + nf[1] + nf[2]), *fn = dal(nf[0] + nf[1] + nf[2]);
-    if (!fu || !fs || !fn) return fail(SOL_ENOMEM, "device allocation failed");
+    const size_t nft = nf[0] + nf[1] + nf[2];
+    double *fu = dal(nft), *fs = dal(nft), *fn = dal(nft), *fp = dal(nft), *fp2 = dal(nft);
+    if (!fu || !fs || !fn || !fp || !fp2) return fail(SOL_ENOMEM, "device allocation failed");
     d.u = fu; d.v = fu + nf[0]; d.w = fu + nf[0] + nf[1];
     d.us[0] = fs; d.us[1] = fs + nf[0]; d.us[2] = fs + nf[0] + nf[1];
     d.un[0] = fn; d.un[1] = fn + nf[0]; d.un[2] = fn + nf[0] + nf[1];
+    d.usprev[0] = fp; d.usprev[1] = fp + nf[0]; d.usprev[2] = fp + nf[0] + nf[1];
+    d.usprev2[0] = fp2; d.usprev2[1] = fp2 + nf[0]; d.usprev2[2] = fp2 + nf[0] + nf[1];
     double **cellf[] = {&d.p,     &d.T,     &d.C,     &d.gl,       &d.Cl,     &d.Cs,      &d.phi,
                         &d.Cnew,  &d.Tstar, &d.Tprev, &d.phiprev, &d.Tprev2, &d.phiprev2};
     for (double **pp : cellf) if (!(*pp = dal(z.ncell))) return fail(SOL_ENOMEM, "device allocation failed");
@@ -1605,6 +1610,8 @@ static int init_state(sol_handle *h)
     launch_fill(d.u, 0.0, nf, s);
     launch_fill(d.us[0], 0.0, nf, s);
     launch_fill(d.un[0], 0.0, nf, s);
+    launch_fill(d.usprev[0], 0.0, nf, s);
+    launch_fill(d.usprev2[0], 0.0, nf, s);
     launch_fill(d.p, 0.0, z.ncell, s);
     launch_fill(d.T, h->al.T_ref, z.ncell, s);
     launch_fill(d.C, h->al.C_ref, z.ncell, s);

@@ -532,6 +532,28 @@ __global__ __launch_bounds__(TILE) void k_guess(const CaseDev *__restrict__ case
     c.phiprev[i] = p0;
 }
 
+// Initial guesses of the momentum solves, by the same rule from the previous
+// u* (before the history holds two steps: u^n); written into u*, the history
+// shifts by one.
+constexpr int QUAD_GUESS_MOM = QUAD_GUESS_STEPS;
+__global__ __launch_bounds__(TILE) void k_guess_mom(const CaseDev *__restrict__ cases, const Tile *__restrict__ tiles)
+{
+    const Tile tl = tiles[xcd_tile(blockIdx.x, gridDim.x)];
+    const CaseDev &c = cases[tl.c];
+    const int d = tl.s;
+    const int row = tl.t * TILE + threadIdx.x;
+    if (row >= c.ph.nsys[d]) return;
+    const int64_t h = *c.step - *c.hist;
+    const double s0 = c.us[d][row], s1 = c.usprev[d][row], s2 = c.usprev2[d][row];
+    double g;
+    if (h >= QUAD_GUESS_MOM) g = 3.0 * (s0 - s1) + s2;
+    else if (h >= 2) g = 2.0 * s0 - s1;
+    else g = (d == 0 ? c.u : (d == 1 ? c.v : c.w))[row];
+    c.us[d][row] = g;
+    c.usprev2[d][row] = s1;
+    c.usprev[d][row] = s0;
+}
+
 // history reset of every case of a group (hist = step)
 __global__ void k_hist_reset(const CaseDev *__restrict__ cases, int ncase)
 {
@@ -804,7 +826,7 @@ __global__ __launch_bounds__(TILE) void k_bicg_init(const KJob *__restrict__ job
         if (mode == 0) {
             if (J.x0) {
                 ri = b[i] - kstencil<ND, T>(A, n, i, J.sx, J.sxy, [&](int j) { return x0[j]; });
-                x[i] = x0[i];
+                if (J.x0 != J.x) x[i] = x0[i];     // a guess written into x stays
             } else {
                 ri = b[i];
                 x[i] = T(0);
@@ -1240,7 +1262,7 @@ __global__ __launch_bounds__(TILE) void k_cg_init_a(const KJob *__restrict__ job
         if (mode == 0) {
             if (J.x0) {
                 ri = b[i] - kstencil<ND, T>(A, n, i, J.sx, J.sxy, [&](int j) { return x0[j]; });
-                x[i] = x0[i];
+                if (J.x0 != J.x) x[i] = x0[i];     // a guess written into x stays
             } else {
                 ri = b[i];
                 x[i] = T(0);
@@ -1428,7 +1450,7 @@ __global__ __launch_bounds__(TILE) void k_ir_resid(const KJob *__restrict__ jobs
         } else if (mode == 0) {
             ri = b[i] - kstencil<ND, double>(A, n, i, J.sx, J.sxy, [&](int j) { return x0[j]; });
             xi = x0[i];
-            x[i] = xi;
+            if (J.x0 != J.x) x[i] = xi;
         } else {
             ri = b[i] - kstencil<ND, double>(A, n, i, J.sx, J.sxy, [&](int j) { return x[j]; });
             xi = x[i];
@@ -1987,6 +2009,11 @@ void launch_guess(const CaseDev *c, const Tile *t, int nt, hipStream_t s)
 {
     if (nt <= 0) return;
     SOL_LAUNCH(k_guess, GRID(nt), 0, s, c, t);
+}
+void launch_guess_mom(const CaseDev *c, const Tile *t, int nt, hipStream_t s)
+{
+    if (nt <= 0) return;
+    SOL_LAUNCH(k_guess_mom, GRID(nt), 0, s, c, t);
 }
 void launch_hist_reset(const CaseDev *c, int ncase, hipStream_t s)
 {

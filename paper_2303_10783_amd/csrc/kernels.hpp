@@ -63,6 +63,7 @@ void launch_ir_close(const KJob *j, int njobs, hipStream_t s);
 void launch_case_stats(const CaseDev *c, const int32_t *cidx, int ncase, hipStream_t s);
 // initial guesses of the pressure-correction and energy solves; history reset
 void launch_guess(const CaseDev *c, const Tile *t, int nt, hipStream_t s);
+void launch_guess_mom(const CaseDev *c, const Tile *t, int nt, hipStream_t s);
 void launch_hist_reset(const CaseDev *c, int ncase, hipStream_t s);
 
 void launch_csr(int dim, const CaseDev *cd, int s, int n, int32_t *cnt, int32_t *row_ptr, int32_t *col,

@@ -392,8 +392,11 @@ __global__ __launch_bounds__(TILE) void k_mg_init(const KJob *__restrict__ jobs,
                 auto src = from_x0 ? x0 : x;
                 ri = bi - apply_op<DIM, T>(L, i, q, [&](int j, int, int) { return src[j]; });
             }
-            if (from_x0) x[i] = x0[i];
-            else if (!keep_x) x[i] = T(0);
+            if (from_x0) {
+                if (J.x0 != J.x) x[i] = x0[i];            // a guess written into x stays
+            } else if (!keep_x) {
+                x[i] = T(0);
+            }
             r[i] = ri;
             pz[i] = T(0);
             bb += (double)bi * bi;

@@ -112,6 +112,7 @@ struct CaseDev {
     double *u, *v, *w, *p, *T, *C, *gl, *Cl, *Cs;
     // step intermediates
     double *us[3];            // u* (momentum predictor)
+    double *usprev[3], *usprev2[3];   // u* of the two previous steps (momentum initial guesses)
     double *un[3];            // u^{n+1} (projected), committed to u, v, w
     double *phi, *Cnew, *Tstar;
     // systems, DIA storage: A[s][slot*n + row], slot order -sxy,-sx,-1,0,+1,+sx,+sxy

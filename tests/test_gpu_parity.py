@@ -234,19 +234,20 @@ def test_cavity_50x30_200_steps(sol, dev):
     therefore needs solves tight enough that the band is far below it: the
     oracle alone moves by 1.3e-9 in u between (pressure, transport)
     tolerances (1e-13, 1e-14) and (1e-14, 1e-15), and by 2.8e-12 between
-    (1e-14, 1e-15) and (5e-15, 1e-15), so both sides solve at (1e-14, 1e-15),
-    which this small grid's pressure system reaches above its FP64 floor.
-    At 1e-10 the spread (measured 1.5e-5 in p) is reported and bounded by
-    1e-4."""
-    case = W.cavity_2d(50, 30, tol=1e-14, seed=0)
+    (1e-14, 1e-15) and (5e-15, 1e-15), so both sides solve at (2e-14, 1e-15):
+    at a pressure tolerance of 1e-14 this small grid's pressure system sits
+    at its FP64 floor (one of the 200 solves ends at a true residual of
+    1.02e-14 however often it restarts).  At 1e-10 the spread (measured
+    1.5e-5 in p) is reported and bounded by 1e-4."""
+    case = W.cavity_2d(50, 30, tol=2e-14, seed=0)
     case["numerics"]["tol_t"] = 1e-15
-    print("[gpu] 50x30 cavity, 200 steps, tol_p 1e-14, tol_t 1e-15", flush=True)
+    print("[gpu] 50x30 cavity, 200 steps, tol_p 2e-14, tol_t 1e-15", flush=True)
     g = sol.Case(case, device=dev)
     o = oracle.Oracle(case, threads=8)
     st = g.step(200)
     o.step(200)
     errs = field_errors(g.read_fields(), o.fields())
-    print("rel L2 (tol 1e-14 / 1e-15):", {k: f"{v:.1e}" for k, v in errs.items()}, "redone", st["redone"])
+    print("rel L2 (tol 2e-14 / 1e-15):", {k: f"{v:.1e}" for k, v in errs.items()}, "redone", st["redone"])
     for k, e in errs.items():
         assert e < 1e-9, (k, errs)
     assert max(errs[k] for k in ("T", "C")) < 1e-12, errs
@@ -782,7 +783,7 @@ def test_speculative_handover_matches_in_order_checks(sol, dev, case):
 
 def _redo_cases():
     c1 = W.box_3d(24, 20, 16, lx=0.024, ly=0.020, lz=0.016, tol=5e-13, seed=6)
-    c1["numerics"]["tol_t"] = 1e-15
+    c1["numerics"]["tol_t"] = 5e-16
     return [("mg/jacobi", c1)]
 
 
@@ -790,7 +791,7 @@ def _redo_cases():
 def test_speculative_redo(sol, dev, precond, case):
     """A step whose speculative true-residual verdict asks for a restart is
     discarded before its commit and run again in order.  Cases at
-    tolerances near the FP64 floor (transport 1e-15) hit one such verdict
+    tolerances near the FP64 floor (transport 5e-16) hit one such verdict
     within 12 steps; the result stays within the solver tolerance band of the
     run that takes every verdict in order."""
     a = make(sol, dev, case, precond)
@@ -804,7 +805,7 @@ def test_speculative_redo(sol, dev, precond, case):
     assert sa["step"] == sb["step"] == 12
     errs = field_errors(a.read_fields(), b.read_fields())
     print("speculative with redo vs in order", {k: f"{v:.1e}" for k, v in errs.items()}, flush=True)
-    assert max(errs.values()) < 1e-9, errs      # measured 1.9e-12 (v)
+    assert max(errs.values()) < 1e-9, errs      # measured 8.5e-12 (v)
     a.close()
     b.close()
 
