@@ -1121,10 +1121,10 @@ static void record_iters(Group &g, const JobSet &S, int slot, int *mx)
 }
 
 // plain FP64 solves.  speculate: once every solve has converged by its
-// recurrence, the check of the true residual (k_kfinish, k_kdecide) is
-// queued and the call returns without waiting for its verdict; the caller
-// reads the verdict (K_DONE, or K_RESTART) from a later state copy before
-// anything is committed.
+// recurrence, the check of the true residual (k_kfinish, or k_mg_finish for
+// the multigrid solves, then k_kdecide) is queued and the call returns
+// without waiting for its verdict; the caller reads the verdict (K_DONE, or
+// K_RESTART) from a later state copy before anything is committed.
 static bool all_converged(const Group &g, const JobSet &S, int slot)
 {
     for (int idx : S.st_index) {
@@ -1148,7 +1148,10 @@ static int solve_plain(Group &g, Phase &P, bool speculate)
         // the state copy after k_kdecide below follows the chunk queued
         // ahead on the stream, so the host need not wait for that chunk
         RCHK(iterate(g, P, S, 0, round == 0 ? P.pred : std::max(2, P.pred / 8), k, nullptr, 1, &slot, false));
-        for (int gi = 0; gi < 2; ++gi) launch_kfinish(gi ? 7 : 5, S.jobs_d, S.tiles_d[gi], S.nt[gi], g.stream);
+        for (int gi = 0; gi < 2; ++gi) {
+            if (P.kind == K_MGCG) launch_mg_finish(gi ? 7 : 5, S.jobs_d, S.tiles_d[gi], S.nt[gi], g.stream);
+            else launch_kfinish(gi ? 7 : 5, S.jobs_d, S.tiles_d[gi], S.nt[gi], g.stream);
+        }
         launch_kdecide(S.jobs_d, (int)S.jobs.size(), g.stream);
         if (fast && all_converged(g, S, slot)) {
             int mx = 1;
@@ -1193,7 +1196,10 @@ static int solve_mixed(Group &g, Phase &P)
     const int nj = (int)S.jobs.size();
     const int max_outer = 60;
     P.launched = 0;
-    for (int gi = 0; gi < 2; ++gi) launch_ir_resid(gi ? 7 : 5, S.jobs_d, S.tiles_d[gi], S.nt[gi], 0, g.stream);
+    for (int gi = 0; gi < 2; ++gi) {
+        if (P.kind == K_MGCG) launch_mg_ir_resid(gi ? 7 : 5, S.jobs_d, S.tiles_d[gi], S.nt[gi], 0, g.stream);
+        else launch_ir_resid(gi ? 7 : 5, S.jobs_d, S.tiles_d[gi], S.nt[gi], 0, g.stream);
+    }
     launch_ir_decide(S.jobs_d, nj, 0, max_outer, g.stream);
     RCHK(poll_enqueue(g, 0));
     // Each sweep's inner solves are started right behind the verdict copy,
@@ -1218,7 +1224,10 @@ static int solve_mixed(Group &g, Phase &P)
             RCHK(iterate(g, P, I, 1, std::max(2, P.pred_inner / 4), k, &S, 0, &slot, false));
         }
         for (int gi = 0; gi < 2; ++gi) launch_ir_update(gi ? 7 : 5, S.jobs_d, S.tiles_d[gi], S.nt[gi], g.stream);
-        for (int gi = 0; gi < 2; ++gi) launch_ir_resid(gi ? 7 : 5, S.jobs_d, S.tiles_d[gi], S.nt[gi], 1, g.stream);
+        for (int gi = 0; gi < 2; ++gi) {
+            if (P.kind == K_MGCG) launch_mg_ir_resid(gi ? 7 : 5, S.jobs_d, S.tiles_d[gi], S.nt[gi], 1, g.stream);
+            else launch_ir_resid(gi ? 7 : 5, S.jobs_d, S.tiles_d[gi], S.nt[gi], 1, g.stream);
+        }
         launch_ir_decide(S.jobs_d, nj, 1, max_outer, g.stream);
         RCHK(poll_enqueue(g, 0));
         k = 0;

@@ -49,6 +49,8 @@ int mg_fused_bricks(int dim, const MLevel &M);
 // multigrid: start of the solves (r = b - A x, p = 0, partial (b, b)) and
 // the inverse diagonal of level l >= 1 (FP32 copy when mi32 is given)
 void launch_mg_init(int nd, int fp32, const KJob *j, const JTile *t, int nt, int k, int mode, hipStream_t s);
+void launch_mg_finish(int nd, const KJob *j, const JTile *t, int nt, hipStream_t s);
+void launch_mg_ir_resid(int nd, const KJob *j, const JTile *t, int nt, int mode, hipStream_t s);
 void launch_mg_minv(int dim, const MLevel *lev, int l, int n, double *mi, float *mi32, hipStream_t s);
 // multigrid: dense inverse of the exactly solved level l (n cells; work:
 // 4 n + 1 doubles of device scratch)

@@ -408,6 +408,83 @@ __global__ __launch_bounds__(TILE) void k_mg_init(const KJob *__restrict__ jobs,
     mark_start(tl, J.st, k, mode);
 }
 
+// ------------------------------------------------------------- finish
+
+// The true residual b - A x of the converged solves (totalled by k_kdecide)
+// and the FP64 residual sweep of a refinement (mode 0: x = x0 or 0; mode 1:
+// keep x; its FP32 copy into aux, totalled by k_ir_decide), the operator
+// from its closed form instead of the stored diagonals k_kfinish and
+// k_ir_resid read: the same rows, 16 instead of 72 bytes each; partials in
+// the same slots.
+template <int DIM>
+__global__ __launch_bounds__(TILE) void k_mg_finish(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles)
+{
+    JTile tl;
+    const KJob &J = job_of(jobs, tiles, tl);
+    const int status = J.st->status;
+    if (status != K_CONVERGED && status != K_ZERO) return;
+    const MLevel &L = J.lev[0];
+    const double icx = 1.0 / L.cnx, icxy = 1.0 / ((double)L.cnx * L.cny);
+    auto b = G<double>(J.b);
+    auto x = G<double>(J.x);
+    double v[3] = {0.0, 0.0, 0.0};
+    const int I0 = tl.t * L.cpt, I1 = min(L.cn, I0 + L.cpt);
+    for (int I = I0 + threadIdx.x; I < I1; I += TILE) {
+        const Agg<DIM> a = agg_of<DIM>(L, I, icx, icxy);
+        for_children<DIM>(L, a, [&](int i, const int *, const int *q) {
+            if (status == K_ZERO) {
+                x[i] = 0.0;
+                return;
+            }
+            const double rt = b[i] - apply_op<DIM, double>(L, i, q, [&](int j, int, int) { return x[j]; });
+            v[0] += rt * rt;
+            v[1] += rt;
+            v[2] += x[i];
+        });
+    }
+    const int off[3] = {poff(J, 0, PS_Q), poff(J, 0, PS_TS), poff(J, 0, PS_TT)};
+    put_partials<3>(v, J.part, off, tl.t);
+}
+
+template <int DIM>
+__global__ __launch_bounds__(TILE) void k_mg_ir_resid(const KJob *__restrict__ jobs, const JTile *__restrict__ tiles,
+                                                      int mode)
+{
+    JTile tl;
+    const KJob &J = job_of(jobs, tiles, tl);
+    if (mode == 1 && J.st->status != K_RUNNING) return;
+    const MLevel &L = J.lev[0];
+    const double icx = 1.0 / L.cnx, icxy = 1.0 / ((double)L.cnx * L.cny);
+    auto b = G<double>(J.b);
+    auto x = G<double>(J.x), x0 = G<double>(J.x0);
+    auto r32 = G<float>(J.aux);
+    const bool zero = mode == 0 && !J.x0;
+    const auto src = mode == 0 ? x0 : x;
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    const int I0 = tl.t * L.cpt, I1 = min(L.cn, I0 + L.cpt);
+    for (int I = I0 + threadIdx.x; I < I1; I += TILE) {
+        const Agg<DIM> a = agg_of<DIM>(L, I, icx, icxy);
+        for_children<DIM>(L, a, [&](int i, const int *, const int *q) {
+            const double bi = b[i];
+            double ri = bi, xi = 0.0;
+            if (zero) {
+                x[i] = 0.0;
+            } else {
+                ri = bi - apply_op<DIM, double>(L, i, q, [&](int j, int, int) { return src[j]; });
+                xi = src[i];
+                if (mode == 0 && J.x0 != J.x) x[i] = xi;     // a guess written into x stays
+            }
+            r32[i] = (float)ri;
+            v[0] += ri * ri;
+            v[1] += bi * bi;
+            v[2] += ri;
+            v[3] += xi;
+        });
+    }
+    const int off[4] = {poff(J, 0, PS_RR), poff(J, 0, PS_BB), poff(J, 0, PS_TS), poff(J, 0, PS_TT)};
+    put_partials<4>(v, J.part, off, tl.t);
+}
+
 // ------------------------------------------------------------- iteration
 
 // pq(k).  On a grid with an even x count the two children of a window row
@@ -1742,6 +1819,22 @@ const void *mg_fn(int which, int nd, int fp32)
 {
     if (nd == 5) return fp32 ? mg_fn_t<2, float>(which) : mg_fn_t<2, double>(which);
     return fp32 ? mg_fn_t<3, float>(which) : mg_fn_t<3, double>(which);
+}
+
+void launch_mg_finish(int nd, const KJob *j, const JTile *t, int nt, hipStream_t s)
+{
+    if (nt <= 0) return;
+    const dim3 g(nt), b(TILE);
+    if (nd == 5) SOL_LAUNCH(k_mg_finish<2>, g, b, 0, s, j, t);
+    else SOL_LAUNCH(k_mg_finish<3>, g, b, 0, s, j, t);
+}
+
+void launch_mg_ir_resid(int nd, const KJob *j, const JTile *t, int nt, int mode, hipStream_t s)
+{
+    if (nt <= 0) return;
+    const dim3 g(nt), b(TILE);
+    if (nd == 5) SOL_LAUNCH(k_mg_ir_resid<2>, g, b, 0, s, j, t, mode);
+    else SOL_LAUNCH(k_mg_ir_resid<3>, g, b, 0, s, j, t, mode);
 }
 
 void launch_mg_init(int nd, int fp32, const KJob *j, const JTile *t, int nt, int k, int mode, hipStream_t s)
