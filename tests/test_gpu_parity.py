@@ -169,6 +169,43 @@ def _step_cases():
     return out
 
 
+def _resid_cases():
+    return [("2d-37x23", W.cavity_2d(37, 23, seed=5)),
+            ("3d-13x9x6", W.box_3d(13, 9, 6, lx=0.013, ly=0.009, lz=0.006, seed=7)),
+            ("3d-40x32x24", W.box_3d(40, 32, 24, lx=0.040, ly=0.032, lz=0.024, seed=9))]
+
+
+@pytest.mark.parametrize("precision", [W.PRECISION_FP64, W.PRECISION_MIXED], ids=["fp64", "mixed"])
+@pytest.mark.parametrize("precond", ["mg", "jacobi"])
+@pytest.mark.parametrize("name,case", _resid_cases(), ids=[x[0] for x in _resid_cases()])
+def test_pressure_residual_matches_host(sol, dev, name, case, precond, precision):
+    """The residual a pressure solve reports -- its true-residual check, or in
+    mixed precision the last FP64 refinement sweep; from the operator's closed
+    form with the multigrid preconditioner, from the stored diagonals with
+    Jacobi -- equals ||b - A phi|| / ||b|| formed on the host from the
+    exported pressure system (the last step's right-hand side) and the
+    solution phi, to the rounding of a residual at the solver tolerance."""
+    import scipy.sparse as sps
+    case = dict(case, numerics=dict(case["numerics"], precision=precision))
+    g = make(sol, dev, case, precond)
+    st = g.step(3)
+    rp, ci, va, rhs = g.read_matrix(3)
+    phi = g.read_fields(("phi",))["phi"]
+    g.close()
+    A = sps.csr_matrix((va, ci, rp), shape=(rhs.size, rhs.size))
+    r = rhs - A @ phi
+    host = np.linalg.norm(r) / np.linalg.norm(rhs)
+    got = st["rel_resid"][3]
+    print(f"{name} {precond} {precision}: reported {got:.4e}, host {host:.4e}, "
+          f"sums {st['sum_resid'][3]:.2e} / {r.sum():.2e}", flush=True)
+    assert 0 < got <= case["numerics"]["tol_p"] * (1 + 1e-6)
+    assert abs(got - host) <= 1e-3 * host, (got, host)      # measured: 5 digits agree
+    # sum(b - A phi) vanishes up to rounding on both sides (zero row sums,
+    # mean-free b)
+    scale = np.abs(rhs).sum()
+    assert abs(st["sum_resid"][3]) <= 1e-12 * scale and abs(r.sum()) <= 1e-12 * scale
+
+
 @pytest.mark.parametrize("precond", PRECONDS)
 @pytest.mark.parametrize("name,case,nsteps", _step_cases(), ids=[x[0] for x in _step_cases()])
 def test_steps_match_oracle(sol, dev, name, case, nsteps, precond):
