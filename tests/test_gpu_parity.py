@@ -206,6 +206,34 @@ def test_pressure_residual_matches_host(sol, dev, name, case, precond, precision
     assert abs(st["sum_resid"][3]) <= 1e-12 * scale and abs(r.sum()) <= 1e-12 * scale
 
 
+@pytest.mark.parametrize("precision", [W.PRECISION_FP64, W.PRECISION_MIXED], ids=["fp64", "mixed"])
+@pytest.mark.parametrize("name,case", _resid_cases(), ids=[x[0] for x in _resid_cases()])
+def test_bicgstab_residuals_match_host(sol, dev, name, case, precision):
+    """The same for the BiCGSTAB systems of the last step: momentum (u*, v*,
+    w* against their assembled systems), solute (C^{n+1}) and energy (T*)."""
+    import scipy.sparse as sps
+    case = dict(case, numerics=dict(case["numerics"], precision=precision))
+    g = make(sol, dev, case)
+    st = g.step(3)
+    f = g.read_fields(("ustar", "vstar", "wstar", "C", "Tstar"))
+    sols = {0: f["ustar"], 1: f["vstar"], 2: f["wstar"], 4: f["C"], 5: f["Tstar"]}
+    out = {}
+    for s_, x in sols.items():
+        if x.size == 0:
+            continue
+        rp, ci, va, rhs = g.read_matrix(s_)
+        A = sps.csr_matrix((va, ci, rp), shape=(rhs.size, rhs.size))
+        host = np.linalg.norm(rhs - A @ x) / np.linalg.norm(rhs)
+        got = st["rel_resid"][s_]
+        out[s_] = (f"{got:.4e}", f"{host:.4e}")
+        assert 0 < got <= case["numerics"]["tol_t"] * (1 + 1e-6), (s_, got)
+        # the solute and some momentum solves end at the FP64 floor (~1e-16
+        # relative), where each side's rounding of b - A x is of order EPS
+        assert abs(got - host) <= 1e-3 * host + 2 * EPS, (s_, got, host)
+    g.close()
+    print(f"{name} {precision}: reported / host per system", out, flush=True)
+
+
 @pytest.mark.parametrize("precond", PRECONDS)
 @pytest.mark.parametrize("name,case,nsteps", _step_cases(), ids=[x[0] for x in _step_cases()])
 def test_steps_match_oracle(sol, dev, name, case, nsteps, precond):
