@@ -246,6 +246,7 @@ __device__ __forceinline__ void mark_start(const JTile &tl, KState *st, int k, i
 {
     if (tl.t == 0 && threadIdx.x == 0) {
         st->k0 = k;
+        st->half = 0;
         if (mode == 0) { st->it_base = 0; st->restarts = 0; st->status = K_RUNNING; }
         else { st->it_base = st->it; st->restarts += 1; }
     }

@@ -605,8 +605,10 @@ __global__ __launch_bounds__(TILE) void k_case_stats(const CaseDev *__restrict__
 // st->gamma by workgroup 0.  Iteration k is two launches:
 //   B(k): convergence test on ||r_k||^2 (from A(k-1); the start kernels
 //         test r_k0); alpha_k = rho_k / (rh, v_k); s = r_k - alpha_k v_k;
-//         t = A M s; partials (t,s), (t,t), (rh,s), (rh,t)
-//   A(k): omega_k = (t,s) / (t,t); x += M (alpha_k p_k + omega_k s);
+//         t = A M s; partials (t,s), (t,t), (rh,s), (rh,t), (s,s)
+//   A(k): if ||s|| already meets half the tolerance, x += alpha_k M p_k and
+//         r_(k+1) = s, tested by B(k+1) (bicg_half_exit); otherwise
+//         omega_k = (t,s) / (t,t); x += M (alpha_k p_k + omega_k s);
 //         r_(k+1) = s - omega_k t; rho_(k+1) = (rh, r_(k+1)) expanded as
 //         (rh,s) - omega_k (rh,t), so beta = (rho_(k+1)/rho_k)(alpha_k/omega_k)
 //         needs no reduction of its own; p_(k+1) = r_(k+1) + beta (p_k -
@@ -950,7 +952,7 @@ __device__ __forceinline__ void bicg_b_body(const KJob *__restrict__ jobs, const
     auto r = G<T>(pk ? J.r1 : J.r), mi = G<T>(J.minv), rh = G<T>(J.rh);
     auto vk = G<T>(pk ? J.v1 : J.v0);
     auto t = G<T>(J.t);
-    double v[4] = {0.0, 0.0, 0.0, 0.0};     // (t,s) (t,t) (rh,s) (rh,t)
+    double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};     // (t,s) (t,t) (rh,s) (rh,t) (s,s)
     const int i0 = tl.t * J.rpt, i1 = min(n, i0 + J.rpt);
     if constexpr (S1) {
         static_assert(ND == 7 && PD == 1, "one-sweep 7-point staging");
@@ -966,6 +968,7 @@ __device__ __forceinline__ void bicg_b_body(const KJob *__restrict__ jobs, const
             v[1] += td * td;
             v[2] += hd * sd;
             v[3] += hd * td;
+            v[4] += sd * sd;
         });
     } else if constexpr (PD == 2) {
         constexpr int NC = Ring2<ND>::NC;
@@ -984,6 +987,7 @@ __device__ __forceinline__ void bicg_b_body(const KJob *__restrict__ jobs, const
                     v[1] += td * td;
                     v[2] += hd * sd;
                     v[3] += hd * td;
+                    v[4] += sd * sd;
                 });
                 done = true;
             }
@@ -1006,6 +1010,7 @@ __device__ __forceinline__ void bicg_b_body(const KJob *__restrict__ jobs, const
             v[1] += td * td;
             v[2] += hd * sd;
             v[3] += hd * td;
+            v[4] += sd * sd;
         }
     } else
     for (int i = i0 + threadIdx.x; i < i1; i += 2 * TILE) {
@@ -1029,10 +1034,52 @@ __device__ __forceinline__ void bicg_b_body(const KJob *__restrict__ jobs, const
             v[1] += td * td;
             v[2] += hd * sd;
             v[3] += hd * td;
+            v[4] += sd * sd;
         }
     }
-    const int off[4] = {poff(J, pk, PS_TS), poff(J, pk, PS_TT), poff(J, pk, PS_RHS), poff(J, pk, PS_RHT)};
-    put_partials<4>(v, J.part, off, tl.t);
+    const int off[5] = {poff(J, pk, PS_TS), poff(J, pk, PS_TT), poff(J, pk, PS_RHS), poff(J, pk, PS_RHT),
+                        poff(J, pk, PS_SS)};
+    put_partials<5>(v, J.part, off, tl.t);
+}
+
+// A(k) when s_k = r_k - alpha_k v_k already meets half the tolerance (its
+// norm from B(k)): x_(k+1) = x_k + alpha_k M p_k, the update without the
+// stabilising half; r_(k+1) = s_k, whose norm B(k+1) takes for its test
+// from the tile's partial copied here, and nothing else is formed (r, p, v
+// of k+1 serve no converged solve, and a restart forms them from x).  The
+// same code for the gathering and the staged kernels.  The true residual of
+// x + alpha M p is s plus the drift of the recurrences, so half the
+// tolerance leaves room for a drift up to the other half (near the FP64
+// floor a solve that exited at the tolerance itself failed its check and
+// broke down at every restart); and only before a solve's first restart,
+// after which it takes whole iterations.
+template <int ND, int PD, class T>
+__device__ __forceinline__ void bicg_half_exit(const KJob &J, const JTile &tl, int pk, int pn, T ta)
+{
+    const int n = J.n;
+    auto x = G<T>(J.x);
+    const auto Mi = R<T>(J.minv), Pk = R<T>(pk ? J.p1 : J.p0);
+    const int i0 = tl.t * J.rpt, i1 = min(n, i0 + J.rpt);
+    if constexpr (PD == 1) {
+        for (int i = i0 + threadIdx.x; i < i1; i += TILE) x[i] = x[i] + Mi[i] * (ta * Pk[i]);
+    } else {
+        // M f = D^-1 (f - N D^-1 f) at row i
+        constexpr int C = ND / 2;
+        RO<T> Ad[ND];
+        diag_views<ND, T>(J.A, n, Ad);
+        for (int i = i0 + threadIdx.x; i < i1; i += TILE) {
+            T gs = T(0);
+#pragma unroll
+            for (int s2 = 0; s2 < ND; ++s2) {
+                if (s2 == C) continue;
+                const int j = min(max(i + slot_off<ND>(s2, J.sx, J.sxy), 0), n - 1);
+                gs += Ad[s2][i] * (Mi[j] * (ta * Pk[j]));
+            }
+            x[i] = x[i] + Mi[i] * (ta * Pk[i] - gs);
+        }
+    }
+    if (threadIdx.x == 0) J.part[poff(J, pn, PS_RR) + tl.t] = J.part[poff(J, pk, PS_SS) + tl.t];
+    if (tl.t == 0 && threadIdx.x == 0) J.st->half = 1;      // read by the host only
 }
 
 // A(k); kernels below
@@ -1045,14 +1092,18 @@ __device__ __forceinline__ void bicg_a_body(const KJob *__restrict__ jobs, const
     if (wg_status(J.st) != K_RUNNING || outer_idle(J)) return;
     KState *st = J.st;
     const int pk = k & 1, pn = (k + 1) & 1;
-    double s5[5];
+    double s5[6];
     {
-        const int off[5] = {poff(J, pk, PS_TS), poff(J, pk, PS_TT), poff(J, pk, PS_RHS), poff(J, pk, PS_RHT),
-                            poff(J, pk, PS_Q)};
-        sum_partials<5>(J.part, off, J.ntile, s5);
+        const int off[6] = {poff(J, pk, PS_TS), poff(J, pk, PS_TT), poff(J, pk, PS_RHS), poff(J, pk, PS_RHT),
+                            poff(J, pk, PS_Q), poff(J, pk, PS_SS)};
+        sum_partials<6>(J.part, off, J.ntile, s5);
     }
     const double rho = st->gamma[pk];
     const double alpha = rho / s5[4];
+    if (st->restarts == 0 && finite(alpha) && s5[5] <= 0.25 * st->tol2 * st->bb) {
+        bicg_half_exit<ND, PD, T>(J, tl, pk, pn, (T)alpha);
+        return;
+    }
     const double omega = s5[1] > 0.0 ? s5[0] / s5[1] : 0.0;
     const double rho_n = s5[2] - omega * s5[3];
     // On a breakdown nothing is written: workgroup 0 records the restart,

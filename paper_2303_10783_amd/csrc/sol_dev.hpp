@@ -83,11 +83,13 @@ struct KState {
     int32_t max_iter, restarts;
     int32_t outer;             // mixed precision: refinement sweeps done
     int32_t inner_total;       // mixed precision: inner iterations summed
+    int32_t half;              // BiCGSTAB: the last iteration stopped at its half step (x += alpha M p)
 };
 
 // Partial-sum slots of a solve: part[(par * NSLOT + slot) * ntile + tile],
 // par = parity of the iteration that produced them.
-enum PSlot { PS_Q = 0, PS_TS = 1, PS_TT = 2, PS_RHO = 3, PS_RR = 4, PS_BB = 5, PS_RHS = 6, PS_RHT = 7, NSLOT = 8 };
+enum PSlot { PS_Q = 0, PS_TS = 1, PS_TT = 2, PS_RHO = 3, PS_RR = 4, PS_BB = 5, PS_RHS = 6, PS_RHT = 7, PS_SS = 8,
+             NSLOT = 9 };
 
 // Physical / geometric constants of one case (immutable after create).
 struct Phys {
