@@ -258,7 +258,7 @@ static int rows_per_tile(int n, int nd)
 // ------------------------------------------------------------------ timing
 
 struct JobSet;
-struct TSample { int cls; int64_t iter; const JobSet *set; int tsize; hipEvent_t a, b; int count = 1; bool two = false; };
+struct TSample { int cls; int64_t iter; const JobSet *set; int tsize; hipEvent_t a, b; int count = 1; bool two = false; bool s1 = false; };
 struct TAcc { int64_t n = 0; double ms = 0.0, bytes = 0.0; };
 
 // algorithmic bytes per row of one launch: matrix values and every vector
@@ -287,6 +287,13 @@ static double row_bytes(int cls, int nd, int dim, int tsize)
 // A BiCGSTAB A launch that ended its solve at the half step (x += alpha M p):
 // x, p, M; x (two sweeps: and the nd - 1 off-diagonals of A)
 static double half_exit_bytes(int nd, bool two, int tsize) { return (two ? nd + 3.0 : 4.0) * tsize; }
+
+// A BiCGSTAB B launch that stages the solve in LDS at FP64 forms M from the
+// diagonal of A and reads no M: one value per row fewer
+static bool b_without_m(const TSample &s, const KJob &J, int nd)
+{
+    return s.cls == SOL_KCLASS_BICG_B && s.tsize == 8 && (nd == 7 ? s.s1 : J.staged != 0);
+}
 
 // ------------------------------------------------------------------ handle
 
@@ -882,20 +889,22 @@ static void collect_samples(Group &g, const KState *ks)
         double bytes = 0.0;
         bool valid = true;
         if (s.set) {
-            double rows = 0.0, rows_half = 0.0;
+            double rows = 0.0, rows_half = 0.0, rows_nom = 0.0;
             int nd = 5, dim = 2;
             for (size_t j = 0; j < s.set->jobs.size(); ++j) {
                 const KState &k = ks[s.set->st_index[j]];
                 if (k.restarts != 0) valid = false;
                 if (s.iter < k.it) {
-                    // the last A launch of a solve that stopped at its half step
-                    if (s.cls == SOL_KCLASS_BICG_A && k.half && s.iter == k.it - 1) rows_half += s.set->jobs[j].n;
-                    else rows += s.set->jobs[j].n;
                     nd = g.cs[s.set->case_of[j]]->z.nd;
                     dim = g.cs[s.set->case_of[j]]->z.dim;
+                    // the last A launch of a solve that stopped at its half step
+                    if (s.cls == SOL_KCLASS_BICG_A && k.half && s.iter == k.it - 1) rows_half += s.set->jobs[j].n;
+                    else if (b_without_m(s, s.set->jobs[j], nd)) rows_nom += s.set->jobs[j].n;
+                    else rows += s.set->jobs[j].n;
                 }
             }
-            bytes = (rows * row_bytes(s.cls, nd, dim, s.tsize) + rows_half * half_exit_bytes(nd, s.two, s.tsize)) *
+            bytes = (rows * row_bytes(s.cls, nd, dim, s.tsize) + rows_half * half_exit_bytes(nd, s.two, s.tsize) +
+                     rows_nom * (row_bytes(s.cls, nd, dim, s.tsize) - s.tsize)) *
                     s.count;
         } else {
             for (auto *c : g.cs) {
@@ -1043,7 +1052,10 @@ static int enqueue_iters(Group &g, Phase &P, JobSet &S, int fp32, int nits, int 
             hipEvent_t a = nullptr, b = nullptr;
             if (sample && (st.nt[0] <= 0 || st.nt[1] <= 0)) { a = take_event(tm); b = take_event(tm); }
             RCHK(launch_stage(g, S, st, fp32, k, a, b));
-            if (a && b) tm->samples.push_back({st.cls, (int64_t)k, &S, fp32 ? 4 : 8, a, b, 1, st.two[st.nt[0] > 0 ? 0 : 1]});
+            if (a && b) {
+                const int w = st.nt[0] > 0 ? 0 : 1;
+                tm->samples.push_back({st.cls, (int64_t)k, &S, fp32 ? 4 : 8, a, b, 1, st.two[w], st.s1[w]});
+            }
         }
         if (k == wend) {
             (void)hipEventRecord(wb, g.stream);

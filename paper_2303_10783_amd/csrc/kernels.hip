@@ -720,6 +720,35 @@ __device__ __forceinline__ void diag_views(const void *A, int n, RO<T> (&Ad)[ND]
     for (int s = 0; s < ND; ++s) Ad[s] = R<T>((const T *)A + (size_t)s * n);
 }
 
+// Jacobi inverse diagonal of row j in the staged B and first-iteration
+// kernels.  FP64: the reciprocal of the stored diagonal, which those kernels
+// read anyway (one correctly rounded division: the double the assembly
+// stores in minv, so the staged and the gathering kernels still agree bit
+// for bit), instead of streaming minv as an array of its own.  The staged A
+// kernel keeps the array: at its five waves per SIMD the divisions' latency
+// cost more than the 8 bytes per row they saved (30.7 -> 31.7 us at
+// 128x128x64), where B, at eight, gained (25.2 -> 24.0 us).  FP32 reads
+// minv32: the float reciprocal of the float diagonal is not the float of
+// that double.
+template <class T>
+struct MinvOf {
+    RO<T> dg, mi;
+    __device__ __forceinline__ T operator()(int j) const
+    {
+        if constexpr (sizeof(T) == 8) return T(1) / dg[j];
+        else return mi[j];
+    }
+};
+
+// a * b + c rounded once, spelled out where two kernels must round alike
+// and the compiler's own choice of products to fuse could differ between them
+template <class T>
+__device__ __forceinline__ T fmat(T a, T b, T c)
+{
+    if constexpr (sizeof(T) == 8) return __builtin_fma(a, b, c);
+    else return __builtin_fmaf(a, b, c);
+}
+
 // PD 2 on a 5-point FP64 system, the tile [i0, i1) staged through LDS (KJob::
 // staged; the FP32 inner solves were faster gathering per row).  The rows within two stencil steps of the tile are [i0 - 2 sx - 2,
 // i1 + 2 sx + 2).  Pass 1 writes y = D^-1 f for each of them (0 outside
@@ -728,8 +757,8 @@ __device__ __forceinline__ void diag_views(const void *A, int n, RO<T> (&Ad)[ND]
 // row to out(i, .).  Each value is loaded once per workgroup instead of once
 // per row that reaches it; the arithmetic and its order are those of
 // ring_amf.  The dynamic LDS holds stage2_values(rpt, sx) values.
-template <class T, class FY, class FO>
-__device__ __forceinline__ void stage2_amf(const KJob &J, int i0, int i1, const RO<T> (&Ad)[5], RO<T> Mi, FY fy,
+template <class T, class MI, class FY, class FO>
+__device__ __forceinline__ void stage2_amf(const KJob &J, int i0, int i1, const RO<T> (&Ad)[5], MI Mi, FY fy,
                                            FO out)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -740,7 +769,7 @@ __device__ __forceinline__ void stage2_amf(const KJob &J, int i0, int i1, const 
     T *Z = Y + yn;
     for (int q = threadIdx.x; q < yn; q += TILE) {
         const int j = ylo + q;
-        Y[q] = (j >= 0 && j < n) ? Mi[j] * fy(j) : T(0);
+        Y[q] = (j >= 0 && j < n) ? Mi(j) * fy(j) : T(0);
     }
     __syncthreads();
     for (int q = threadIdx.x; q < zn; q += TILE) {
@@ -753,7 +782,7 @@ __device__ __forceinline__ void stage2_amf(const KJob &J, int i0, int i1, const 
             ns += Ad[1][j] * Y[c - 1];
             ns += Ad[3][j] * Y[c + 1];
             ns += Ad[4][j] * Y[c + sx];
-            z = Y[c] - Mi[j] * ns;
+            z = Y[c] - Mi(j) * ns;
         }
         Z[q] = z;
     }
@@ -877,7 +906,8 @@ __global__ __launch_bounds__(TILE) void k_bicg_first(const KJob *__restrict__ jo
         if (J.staged) {
             RO<T> Ad[ND];
             diag_views<ND, T>(J.A, n, Ad);
-            const auto Mi = R<T>(J.minv), Rr = R<T>(pk ? J.r1 : J.r);
+            const MinvOf<T> Mi{Ad[2], R<T>(J.minv)};
+            const auto Rr = R<T>(pk ? J.r1 : J.r);
             stage2_amf<T>(J, i0, i1, Ad, Mi, [&](int j) { return Rr[j]; }, [&](int i, T vi) {
                 p[i] = r[i];
                 vv[i] = vi;
@@ -890,8 +920,9 @@ __global__ __launch_bounds__(TILE) void k_bicg_first(const KJob *__restrict__ jo
         static_assert(ND == 7 && PD == 1, "one-sweep 7-point staging");
         RO<T> Ad[ND];
         diag_views<ND, T>(J.A, n, Ad);
-        const auto Mi = R<T>(J.minv), Rr = R<T>(pk ? J.r1 : J.r);
-        stage1_amf7<T>(J, i0, i1, Ad, [&](int j) { return Mi[j] * Rr[j]; }, [&](int i, T vi) {
+        const MinvOf<T> Mi{Ad[3], R<T>(J.minv)};
+        const auto Rr = R<T>(pk ? J.r1 : J.r);
+        stage1_amf7<T>(J, i0, i1, Ad, [&](int j) { return Mi(j) * Rr[j]; }, [&](int i, T vi) {
             p[i] = r[i];
             vv[i] = vi;
             q += (double)rh[i] * vi;
@@ -958,8 +989,9 @@ __device__ __forceinline__ void bicg_b_body(const KJob *__restrict__ jobs, const
         static_assert(ND == 7 && PD == 1, "one-sweep 7-point staging");
         RO<T> Ad[ND];
         diag_views<ND, T>(J.A, n, Ad);
-        const auto Mi = R<T>(J.minv), Rr = R<T>(pk ? J.r1 : J.r), Vk = R<T>(pk ? J.v1 : J.v0), Rh = R<T>(J.rh);
-        stage1_amf7<T>(J, i0, i1, Ad, [&](int j) { return Mi[j] * (Rr[j] - alpha * Vk[j]); }, [&](int i, T ti) {
+        const MinvOf<T> Mi{Ad[3], R<T>(J.minv)};
+        const auto Rr = R<T>(pk ? J.r1 : J.r), Vk = R<T>(pk ? J.v1 : J.v0), Rh = R<T>(J.rh);
+        stage1_amf7<T>(J, i0, i1, Ad, [&](int j) { return Mi(j) * (Rr[j] - alpha * Vk[j]); }, [&](int i, T ti) {
             const T si = Rr[i] - alpha * Vk[i];
             const T hi = Rh[i];
             t[i] = ti;
@@ -978,7 +1010,8 @@ __device__ __forceinline__ void bicg_b_body(const KJob *__restrict__ jobs, const
         bool done = false;
         if constexpr (ND == 5 && sizeof(T) == 8) {
             if (J.staged) {
-                stage2_amf<T>(J, i0, i1, Ad, Mi, [&](int j) { return Rr[j] - alpha * Vk[j]; }, [&](int i, T ti) {
+                const MinvOf<T> Mf{Ad[2], Mi};
+                stage2_amf<T>(J, i0, i1, Ad, Mf, [&](int j) { return Rr[j] - alpha * Vk[j]; }, [&](int i, T ti) {
                     const T si = Rr[i] - alpha * Vk[i];
                     const T hi = Rh[i];
                     t[i] = ti;
@@ -1138,7 +1171,7 @@ __device__ __forceinline__ void bicg_a_body(const KJob *__restrict__ jobs, const
         const auto Mi = R<T>(J.minv);
         stage1_amf7<T>(J, i0, i1, Ad, [&](int j) { return Mi[j] * pnext(j); }, [&](int i, T vi) {
             const T si = rk[i] - ta * vk[i];
-            const T xi = x[i] + mi[i] * (ta * pkv[i] + tw * si);
+            const T xi = fmat(Mi[i], fmat(ta, pkv[i], tw * si), x[i]);     // x + M (alpha p + omega s)
             const T ri = si - tw * t[i];
             const T pi = pnext(i);
             const T hi = rh[i];
@@ -1160,7 +1193,7 @@ __device__ __forceinline__ void bicg_a_body(const KJob *__restrict__ jobs, const
         if constexpr (ND == 5 && sizeof(T) == 8) {
             if (J.staged) {
                 auto pn = [&](int j) { return ((Rk[j] - ta * Vk[j]) - tw * Tt[j]) + tb * (Pk[j] - tw * Vk[j]); };
-                stage2_amf<T>(J, i0, i1, Ad, Mi, pn, [&](int i, T vi) {
+                stage2_amf<T>(J, i0, i1, Ad, [&](int j) { return Mi[j]; }, pn, [&](int i, T vi) {
                     T gs = T(0);
 #pragma unroll
                     for (int s2 = 0; s2 < ND; ++s2) {
@@ -1227,7 +1260,7 @@ __device__ __forceinline__ void bicg_a_body(const KJob *__restrict__ jobs, const
         for (int u = 0; u < 2; ++u) {
             const int ii = iv[u];
             const T si = rk[ii] - ta * vk[ii];
-            xv[u] = x[ii] + mi[ii] * (ta * pkv[ii] + tw * si);
+            xv[u] = fmat(mi[ii], fmat(ta, pkv[ii], tw * si), x[ii]);     // x + M (alpha p + omega s)
             rv[u] = si - tw * t[ii];
             pv[u] = pnext(ii);
             vv[u] = kstencil<ND, T>(A, n, ii, J.sx, J.sxy, [&](int j) { return mi[j] * pnext(j); });
