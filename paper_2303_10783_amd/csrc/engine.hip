@@ -258,12 +258,15 @@ static int rows_per_tile(int n, int nd)
 // ------------------------------------------------------------------ timing
 
 struct JobSet;
-struct TSample { int cls; int64_t iter; const JobSet *set; int tsize; hipEvent_t a, b; int count = 1; bool two = false; bool s1 = false; };
+struct TSample { int cls; int64_t iter; const JobSet *set; int tsize; hipEvent_t a, b; int count = 1; bool two = false; bool s1 = false;
+                 bool fwd = false; };
 struct TAcc { int64_t n = 0; double ms = 0.0, bytes = 0.0; };
 
 // algorithmic bytes per row of one launch: matrix values and every vector
-// element read or written once; tsize = bytes per value (8 FP64, 4 FP32)
-static double row_bytes(int cls, int nd, int dim, int tsize)
+// element read or written once; tsize = bytes per value (8 FP64, 4 FP32);
+// fwd: the forward assembly route, which reads the stored constant part (the
+// stencil route forms it in registers)
+static double row_bytes(int cls, int nd, int dim, int tsize, bool fwd = false)
 {
     switch (cls) {
     case SOL_KCLASS_CG: return (nd + 11.0) * tsize;     // A, r, w, s, M, p, x; p, s, x, r, w
@@ -277,8 +280,8 @@ static double row_bytes(int cls, int nd, int dim, int tsize)
     case SOL_KCLASS_MG_UP0:                              // r, level-1 correction (2D: and x2); z
         return (2.0 + (dim == 2) + 1.0 / (1 << dim)) * tsize;
     case SOL_KCLASS_MG_COARSE: return 0.0;
-    case SOL_KCLASS_ASM_MOM: return 16.0 * nd + 8.0 * dim + 48.0;
-    case SOL_KCLASS_ASM_TRN: return 24.0 * nd + 8.0 * dim + 56.0;
+    case SOL_KCLASS_ASM_MOM: return (fwd ? 16.0 : 8.0) * nd + 8.0 * dim + 48.0;
+    case SOL_KCLASS_ASM_TRN: return (fwd ? 24.0 : 16.0) * nd + 8.0 * dim + 56.0;
     case SOL_KCLASS_PHASE: return 96.0 + 16.0 * dim;
     }
     return 0.0;
@@ -911,7 +914,7 @@ static void collect_samples(Group &g, const KState *ks)
                 const double rows = s.cls == SOL_KCLASS_ASM_MOM
                                         ? (double)(c->z.nsys[0] + c->z.nsys[1] + c->z.nsys[2])
                                         : (double)c->z.ncell;
-                bytes += rows * row_bytes(s.cls, c->z.nd, c->z.dim, 8);
+                bytes += rows * row_bytes(s.cls, c->z.nd, c->z.dim, 8, s.fwd);
             }
         }
         if (valid) {
@@ -1304,7 +1307,7 @@ static int phase_verdict(const Group &g, const Phase &P)
 }
 
 template <class F>
-static void timed(Group &g, int cls, F launch)
+static void timed(Group &g, int cls, F launch, bool fwd = false)
 {
     sol_handle *tm = g.timer;
     hipEvent_t a = nullptr, b = nullptr;
@@ -1313,7 +1316,7 @@ static void timed(Group &g, int cls, F launch)
     launch();
     if (a && b) {
         (void)hipEventRecord(b, g.stream);
-        tm->samples.push_back({cls, 0, nullptr, 8, a, b, 1});
+        tm->samples.push_back({cls, 0, nullptr, 8, a, b, 1, false, false, fwd});
     }
 }
 
@@ -1332,7 +1335,7 @@ static int group_step_once(Group &g, bool speculate)
     const int fwd = g.cs[0]->assembly == SOL_ASSEMBLY_FORWARD;
     timed(g, SOL_KCLASS_ASM_MOM, [&] {
         for (int gi = 0; gi < 2; ++gi) launch_asm_momentum(gi ? 3 : 2, g.cases_d, g.t_mom[gi], g.n_mom[gi], s, fwd);
-    });
+    }, fwd != 0);
     for (int gi = 0; gi < 2; ++gi) launch_guess_mom(g.cases_d, g.t_mom[gi], g.n_mom[gi], s);
     RCHK(group_solve(g, g.ph[0], speculate));
     // 2: pressure correction (and the initial guesses of phi and T*; the
@@ -1347,7 +1350,7 @@ static int group_step_once(Group &g, bool speculate)
     timed(g, SOL_KCLASS_ASM_TRN, [&] {
         for (int gi = 0; gi < 2; ++gi)
             launch_asm_transport(gi ? 3 : 2, g.cases_d, g.t_cell[gi], g.n_cell[gi], 1, s, fwd);
-    });
+    }, fwd != 0);
     RCHK(group_solve(g, g.ph[2]));
     if (g.ph[0].pending || g.ph[1].pending) {
         if (!g.ph[2].synced) {

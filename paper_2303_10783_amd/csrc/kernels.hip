@@ -62,6 +62,58 @@ __device__ __forceinline__ double wall_temp(const Phys &P, int face, double t)
     return P.thermal[face] == 2 ? P.Tw0[face] - P.Tramp[face] * t : P.Text[face];
 }
 
+// Constant (offline) coefficients of a momentum row (component s, face
+// coordinates q): I/dt + viscous diffusion, no-slip walls at half a cell
+// along the tangential axes; and of an energy row: I/dt + conduction, Robin
+// wall conductances on the diagonal.  The offline assembly stores them; the
+// per-step stencil-route kernels form them in registers with the same code
+// (56 bytes per 7-point row less to read than the stored copy, the same
+// doubles), the forward route reads the stored copy.
+template <int DIM>
+__device__ __forceinline__ void mom_const_row(const Phys &P, int s, const int *q, double (&a)[2 * DIM + 1])
+{
+#pragma unroll
+    for (int k = 0; k < 2 * DIM + 1; ++k) a[k] = 0.0;
+    a[DIM] = P.idt;
+#pragma unroll
+    for (int ax = 0; ax < DIM; ++ax) {
+        const double dif = P.nu * P.ih2[ax];
+        const bool em = q[ax] >= 1, ep = q[ax] <= P.sdim[s][ax] - 2;
+        if (ax == s) {
+            // neighbours along the normal: faces (or impermeable walls) at distance h
+            a[DIM] += 2.0 * dif;
+            a[DIM - 1 - ax] = em ? -dif : 0.0;
+            a[DIM + 1 + ax] = ep ? -dif : 0.0;
+        } else {
+            if (em) { a[DIM] += dif; a[DIM - 1 - ax] = -dif; }
+            else if (P.slip[2 * ax] == 0) a[DIM] += 2.0 * dif;
+            if (ep) { a[DIM] += dif; a[DIM + 1 + ax] = -dif; }
+            else if (P.slip[2 * ax + 1] == 0) a[DIM] += 2.0 * dif;
+        }
+    }
+}
+
+template <int DIM>
+__device__ __forceinline__ void energy_const_row(const Phys &P, const int *q, double (&a)[2 * DIM + 1])
+{
+#pragma unroll
+    for (int k = 0; k < 2 * DIM + 1; ++k) a[k] = 0.0;
+    a[DIM] = P.idt;
+#pragma unroll
+    for (int ax = 0; ax < DIM; ++ax) {
+        const double dif = P.alpha * P.ih2[ax];
+        for (int sd = 0; sd < 2; ++sd) {
+            const bool ex = sd == 0 ? q[ax] >= 1 : q[ax] <= P.sdim[ST][ax] - 2;
+            const int slot = sd == 0 ? DIM - 1 - ax : DIM + 1 + ax;
+            if (ex) { a[DIM] += dif; a[slot] = -dif; }
+            else {
+                const double U = wall_cond(P, 2 * ax + sd, P.h[ax]);
+                a[DIM] += U / (P.rcp * P.h[ax]);
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------- offline assembly
 // Constant-coefficient terms, assembled once (the term-wise split of
 // Section 4): transient 1/dt, central diffusion (eq. 3.26) with no-slip
@@ -85,41 +137,12 @@ __global__ __launch_bounds__(TILE) void k_asm_const(const CaseDev *__restrict__ 
 #pragma unroll
     for (int k = 0; k < ND; ++k) a[k] = 0.0;
     if (s <= SW) {
-        a[DIM] = P.idt;
-#pragma unroll
-        for (int ax = 0; ax < DIM; ++ax) {
-            const double dif = P.nu * P.ih2[ax];
-            const bool em = q[ax] >= 1, ep = q[ax] <= P.sdim[s][ax] - 2;
-            if (ax == s) {
-                // neighbours along the normal: faces (or impermeable walls) at distance h
-                a[DIM] += 2.0 * dif;
-                a[DIM - 1 - ax] = em ? -dif : 0.0;
-                a[DIM + 1 + ax] = ep ? -dif : 0.0;
-            } else {
-                if (em) { a[DIM] += dif; a[DIM - 1 - ax] = -dif; }
-                else if (P.slip[2 * ax] == 0) a[DIM] += 2.0 * dif;
-                if (ep) { a[DIM] += dif; a[DIM + 1 + ax] = -dif; }
-                else if (P.slip[2 * ax + 1] == 0) a[DIM] += 2.0 * dif;
-            }
-        }
+        mom_const_row<DIM>(P, s, q, a);
         double *Ac = c.Ac[s];
 #pragma unroll
         for (int k = 0; k < ND; ++k) Ac[(size_t)k * n + row] = a[k];
     } else if (s == ST) {
-        a[DIM] = P.idt;
-#pragma unroll
-        for (int ax = 0; ax < DIM; ++ax) {
-            const double dif = P.alpha * P.ih2[ax];
-            for (int sd = 0; sd < 2; ++sd) {
-                const bool ex = sd == 0 ? q[ax] >= 1 : q[ax] <= P.sdim[s][ax] - 2;
-                const int slot = sd == 0 ? DIM - 1 - ax : DIM + 1 + ax;
-                if (ex) { a[DIM] += dif; a[slot] = -dif; }
-                else {
-                    const double U = wall_cond(P, 2 * ax + sd, P.h[ax]);
-                    a[DIM] += U / (P.rcp * P.h[ax]);
-                }
-            }
-        }
+        energy_const_row<DIM>(P, q, a);
         double *Ac = c.Ac[ST];
 #pragma unroll
         for (int k = 0; k < ND; ++k) Ac[(size_t)k * n + row] = a[k];
@@ -172,10 +195,8 @@ __global__ __launch_bounds__(TILE) void k_asm_momentum(const CaseDev *__restrict
     const int clo = cell_index(P, lo[0], lo[1], lo[2]);
     const int chi = cell_index(P, hi[0], hi[1], hi[2]);
     double *const vel[3] = {c.u, c.v, c.w};
-    const double *Ac = c.Ac[d];
     double a[ND];
-#pragma unroll
-    for (int k = 0; k < ND; ++k) a[k] = Ac[(size_t)k * n + row];
+    mom_const_row<DIM>(P, d, q, a);
     const double gf = 0.5 * (c.gl[clo] + c.gl[chi]);
     const double gt = P.mom1 ? fmax(gf, P.gfloor) : 1.0;
     const double gw = P.mom1 ? gf : 1.0;
@@ -250,10 +271,10 @@ __global__ __launch_bounds__(TILE) void k_asm_transport(const CaseDev *__restric
     const double t_new = (double)(*c.step + 1) * P.dt;
     const double omk = 1.0 - P.kp;
     const double agP = 1.0 / (1.0 - omk * (1.0 - c.gl[ci]));
-    const double *AcT = c.Ac[ST];
     double aC[ND], aT[ND];
+    energy_const_row<DIM>(P, q, aT);
 #pragma unroll
-    for (int k = 0; k < ND; ++k) { aC[k] = 0.0; aT[k] = AcT[(size_t)k * n + ci]; }
+    for (int k = 0; k < ND; ++k) aC[k] = 0.0;
     double dconv = 0.0, ddif = 0.0;
     const double gP = c.gl[ci];
     double bT = c.T[ci] * P.idt;
